@@ -1,0 +1,532 @@
+/*
+ * FP64 CPU oracle for PLIC inversion and PLIC curvature.
+ *
+ * TEST INFRASTRUCTURE ONLY: the plain, slow, obviously-correct reference the
+ * GPU library is checked against.  Only the tests, the package smoke check and
+ * the benchmark's CPU-baseline leg load it.  It shares no code with the GPU
+ * library (no common headers, helpers or constants).
+ *
+ * Paper: M. Lehmann, S. Gekle, "Analytic Solution to the Piecewise Linear
+ * Interface Construction Problem and its Application in Curvature Calculation
+ * for Volume-of-Fluid Simulation Codes" (arXiv 2006.12838).
+ *
+ * What is computed, and from which passage:
+ *  - forward volume: Sec. 2.2 ("Formulating the inverse PLIC problem"), the
+ *    five-case volume in reduced symmetry space, with the symmetry reduction of
+ *    Sec. 2.1 (sorted |n|, V = min(V0, 1 - V0), d = S/2 - |d0|);
+ *  - inverse (the PLIC problem itself, Sec. 2, problem statement V0, n -> d0):
+ *    the unique root of the monotone forward volume, found by bisection.  This
+ *    is the definition the paper's closed forms reach faster;
+ *  - gradient of d0: implicit differentiation of V0(n, d0) = volume below the
+ *    plane; dV0/dd0 = A/|n| and dV0/dn = -(A/|n|) * centroid, with A and the
+ *    centroid of the plane-cube intersection polygon built explicitly;
+ *  - curvature: Sec. 5.2 (PLIC point neighbourhood, coordinate transform with
+ *    the fixed vector r), App. B.1 (Parker-Youngs normal), B.2 (paraboloid mean
+ *    curvature at the origin), B.3 (least-squares normal equations, reduced
+ *    dimension when fewer than 5 points).
+ *
+ * Readings where the paper is silent or ambiguous (each also used by the GPU
+ * library, written independently there):
+ *  - V0 outside [0,1] is clamped; NaN inputs and n = 0 give NaN;
+ *  - fit solve: symmetric LDL^T in the fixed order A,B,C,H,I; a pivot below
+ *    1e-10 * (largest diagonal entry of the leading block) drops that
+ *    parameter (kept 0); with k < 5 points the leading k x k block is solved;
+ *  - kappa is reported with the sign flipped relative to the paper's formula so
+ *    that a fluid drop (normal pointing out of the fluid) has kappa = +1/R;
+ *  - |g| < 1e-12 gives kappa = 0; if |n x r| < 1e-6 the vector r is replaced
+ *    by (r_y, r_z, r_x);
+ *  - kappa = 0 on non-interface cells and on the outer one-cell layer.
+ */
+#include "plic_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* forward volume                                                             */
+/* ------------------------------------------------------------------------- */
+
+static void sort3_asc(double *a, double *b, double *c)
+{
+    double t;
+    if (*a > *b) { t = *a; *a = *b; *b = t; }
+    if (*b > *c) { t = *b; *b = *c; *c = t; }
+    if (*a > *b) { t = *a; *a = *b; *b = t; }
+}
+
+/* Volume below the plane a1*z1 + a2*z2 + a3*z3 = u inside the unit cube [0,1]^3,
+ * for 0 <= a1 <= a2 <= a3, a3 > 0 and 0 <= u <= (a1+a2+a3)/2.
+ *
+ * Five-case volume of Sec. 2.2 with the factor 1/(6 n1 n2 n3) divided through
+ * analytically where it would otherwise cancel:
+ *   case (1) u <  a1:                      u^3 / (6 a1 a2 a3)
+ *   case (5) min(a1+a2, a3) <= u <= a3:    (u - (a1+a2)/2) / a3
+ *   cases (2)-(4):  [u^3 - (u-a1)^3 - (u-a2)+^3 - (u-a3)+^3] / (6 a1 a2 a3)
+ *                 = [3u(u-a1) + a1^2 - ((u-a2)+^3 + (u-a3)+^3)/a1] / (6 a2 a3)
+ * (the case-(2) rewrite is the one the paper's inverse-PLIC listing uses).
+ * Normals in a coordinate plane (a1 = 0) and along an axis (a2 = 0) follow the
+ * 2D and 1D special cases of Sec. 2.3. */
+double orc_reduced_volume(double a1, double a2, double a3, double u)
+{
+    if (u <= 0.0) return 0.0;
+    if (a2 == 0.0) return u / a3;                              /* 1D */
+    if (a1 == 0.0)                                             /* 2D */
+        return u <= a2 ? u * u / (2.0 * a2 * a3) : (u - 0.5 * a2) / a3;
+    if (u < a1) return u * u * u / (6.0 * a1 * a2 * a3);       /* case (1) */
+    if (u >= fmin(a1 + a2, a3) && u <= a3)                     /* case (5) */
+        return (u - 0.5 * (a1 + a2)) / a3;
+    {
+        double p2 = u > a2 ? u - a2 : 0.0;
+        double p3 = u > a3 ? u - a3 : 0.0;
+        return (3.0 * u * (u - a1) + a1 * a1 - (p2 * p2 * p2 + p3 * p3 * p3) / a1)
+               / (6.0 * a2 * a3);                              /* cases (2),(3),(4) */
+    }
+}
+
+double orc_volume1(double nx, double ny, double nz, double d0)
+{
+    double a1 = fabs(nx), a2 = fabs(ny), a3 = fabs(nz), S, u;
+    if (isnan(nx) || isnan(ny) || isnan(nz) || isnan(d0)) return NAN;
+    sort3_asc(&a1, &a2, &a3);
+    if (!(a3 > 0.0)) return NAN;                               /* n = 0 */
+    S = a1 + a2 + a3;
+    u = d0 + 0.5 * S;              /* origin moved to the cube corner (Sec. 2.1) */
+    if (u <= 0.0) return 0.0;
+    if (u >= S) return 1.0;
+    if (u <= 0.5 * S) return orc_reduced_volume(a1, a2, a3, u);
+    return 1.0 - orc_reduced_volume(a1, a2, a3, S - u);        /* V0 > 1/2 by symmetry */
+}
+
+/* ------------------------------------------------------------------------- */
+/* inverse PLIC: bisection on the forward volume                              */
+/* ------------------------------------------------------------------------- */
+
+/* reduced root u in [0, S/2] with F(u) = V, V in [0, 1/2] */
+static double reduced_root(double a1, double a2, double a3, double V)
+{
+    double lo = 0.0, hi = 0.5 * (a1 + a2 + a3), S = a1 + a2 + a3;
+    int it;
+    if (V <= 0.0) return 0.0;                  /* F is strictly increasing, F(0) = 0 */
+    if (V >= 0.5) return hi;
+    for (it = 0; it < 200; ++it) {
+        double mid = lo + 0.5 * (hi - lo);
+        if (!(mid > lo && mid < hi)) break;    /* adjacent doubles */
+        if (orc_reduced_volume(a1, a2, a3, mid) < V) lo = mid; else hi = mid;
+        if (hi - lo <= ldexp(S, -60)) break;
+    }
+    return lo + 0.5 * (hi - lo);
+}
+
+double orc_offset1(double nx, double ny, double nz, double V0)
+{
+    double a1 = fabs(nx), a2 = fabs(ny), a3 = fabs(nz), V, u, d;
+    if (isnan(nx) || isnan(ny) || isnan(nz) || isnan(V0)) return NAN;
+    sort3_asc(&a1, &a2, &a3);
+    if (!(a3 > 0.0)) return NAN;
+    if (V0 < 0.0) V0 = 0.0;
+    if (V0 > 1.0) V0 = 1.0;
+    V = V0 <= 0.5 ? V0 : 1.0 - V0;            /* reduced volume (Sec. 2.1), exact */
+    u = reduced_root(a1, a2, a3, V);
+    d = 0.5 * (a1 + a2 + a3) - u;              /* |d0| */
+    if (V0 > 0.5) return d;
+    if (V0 < 0.5) return -d;
+    return 0.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* gradient of d0 from the explicit intersection polygon                      */
+/* ------------------------------------------------------------------------- */
+
+static double dot3(const double *a, const double *b) { return a[0]*b[0] + a[1]*b[1] + a[2]*b[2]; }
+static void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1]*b[2] - a[2]*b[1];
+    c[1] = a[2]*b[0] - a[0]*b[2];
+    c[2] = a[0]*b[1] - a[1]*b[0];
+}
+
+/* vertices of { x in [-1/2,1/2]^3 : n . x = d0 } on the 12 cube edges, deduplicated */
+static int plane_cube_vertices(const double n[3], double d0, double v[16][3])
+{
+    int nv = 0, k, j, l, s1, s2, i;
+    const double eps = 1e-12;
+    for (k = 0; k < 3; ++k) {
+        j = (k + 1) % 3; l = (k + 2) % 3;
+        for (s1 = 0; s1 < 2; ++s1) for (s2 = 0; s2 < 2; ++s2) {
+            double xj = s1 ? 0.5 : -0.5, xl = s2 ? 0.5 : -0.5;
+            double cand[2][3];
+            int nc = 0, c;
+            if (n[k] != 0.0) {
+                double t = (d0 - n[j] * xj - n[l] * xl) / n[k];
+                if (t >= -0.5 - eps && t <= 0.5 + eps) {
+                    if (t < -0.5) t = -0.5;
+                    if (t > 0.5) t = 0.5;
+                    cand[0][k] = t; cand[0][j] = xj; cand[0][l] = xl; nc = 1;
+                }
+            } else if (fabs(n[j] * xj + n[l] * xl - d0) <= eps) {
+                /* the whole edge lies in the plane: both endpoints are vertices */
+                cand[0][k] = -0.5; cand[0][j] = xj; cand[0][l] = xl;
+                cand[1][k] = 0.5;  cand[1][j] = xj; cand[1][l] = xl; nc = 2;
+            }
+            for (c = 0; c < nc; ++c) {
+                int dup = 0;
+                for (i = 0; i < nv; ++i)
+                    if (fabs(v[i][0] - cand[c][0]) < 1e-10 && fabs(v[i][1] - cand[c][1]) < 1e-10 &&
+                        fabs(v[i][2] - cand[c][2]) < 1e-10) { dup = 1; break; }
+                if (!dup && nv < 16) { v[nv][0] = cand[c][0]; v[nv][1] = cand[c][1]; v[nv][2] = cand[c][2]; ++nv; }
+            }
+        }
+    }
+    return nv;
+}
+
+int orc_offset_grad1(double nx, double ny, double nz, double V0,
+                     double *d0_out, double *dd_dV0, double dd_dn[3], double *area_out)
+{
+    double n[3] = {nx, ny, nz}, v[16][3], m[3] = {0, 0, 0}, t1[3], t2[3], e[3] = {0, 0, 0};
+    double ang[16], area = 0.0, cen[3] = {0, 0, 0}, nn, d0;
+    int nv, i, j, order[16], kmin = 0;
+
+    d0 = orc_offset1(nx, ny, nz, V0);
+    if (d0_out) *d0_out = d0;
+    nn = sqrt(dot3(n, n));
+    if (isnan(d0) || !(nn > 0.0)) {
+        *dd_dV0 = NAN; dd_dn[0] = dd_dn[1] = dd_dn[2] = NAN;
+        if (area_out) *area_out = NAN;
+        return 0;
+    }
+    nv = plane_cube_vertices(n, d0, v);
+    for (i = 0; i < nv; ++i) { m[0] += v[i][0]; m[1] += v[i][1]; m[2] += v[i][2]; }
+    if (nv > 0) { m[0] /= nv; m[1] /= nv; m[2] /= nv; }
+    if (nv < 3) {
+        /* degenerate polygon (a corner or an edge): zero area, centroid = limit */
+        *dd_dV0 = INFINITY;
+        dd_dn[0] = m[0]; dd_dn[1] = m[1]; dd_dn[2] = m[2];
+        if (area_out) *area_out = 0.0;
+        return nv;
+    }
+    /* in-plane orthonormal basis t1, t2 */
+    if (fabs(n[1]) < fabs(n[kmin])) kmin = 1;
+    if (fabs(n[2]) < fabs(n[kmin])) kmin = 2;
+    e[kmin] = 1.0;
+    cross3(e, n, t1);
+    { double s = sqrt(dot3(t1, t1)); t1[0] /= s; t1[1] /= s; t1[2] /= s; }
+    { double nh[3] = {n[0] / nn, n[1] / nn, n[2] / nn}; cross3(nh, t1, t2); }
+    for (i = 0; i < nv; ++i) {
+        double w[3] = {v[i][0] - m[0], v[i][1] - m[1], v[i][2] - m[2]};
+        ang[i] = atan2(dot3(w, t2), dot3(w, t1));
+        order[i] = i;
+    }
+    for (i = 1; i < nv; ++i) {                 /* insertion sort by angle */
+        int o = order[i];
+        j = i - 1;
+        while (j >= 0 && ang[order[j]] > ang[o]) { order[j + 1] = order[j]; --j; }
+        order[j + 1] = o;
+    }
+    /* triangle fan from the first vertex: areas and centroids */
+    for (i = 1; i + 1 < nv; ++i) {
+        const double *p0 = v[order[0]], *p1 = v[order[i]], *p2 = v[order[i + 1]];
+        double a[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+        double b[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]}, c[3], at;
+        cross3(a, b, c);
+        at = 0.5 * sqrt(dot3(c, c));
+        area += at;
+        for (j = 0; j < 3; ++j) cen[j] += at * (p0[j] + p1[j] + p2[j]) / 3.0;
+    }
+    if (area > 0.0) {
+        for (j = 0; j < 3; ++j) cen[j] /= area;
+        *dd_dV0 = nn / area;
+    } else {
+        for (j = 0; j < 3; ++j) cen[j] = m[j];
+        *dd_dV0 = INFINITY;
+    }
+    dd_dn[0] = cen[0]; dd_dn[1] = cen[1]; dd_dn[2] = cen[2];
+    if (area_out) *area_out = area;
+    return nv;
+}
+
+void orc_volume(const double *nx, const double *ny, const double *nz, const double *d0,
+                double *V0, int64_t count)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < count; ++i) V0[i] = orc_volume1(nx[i], ny[i], nz[i], d0[i]);
+}
+
+void orc_offset(const double *nx, const double *ny, const double *nz, const double *V0,
+                double *d0, int64_t count)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < count; ++i) d0[i] = orc_offset1(nx[i], ny[i], nz[i], V0[i]);
+}
+
+void orc_offset_grad(const double *nx, const double *ny, const double *nz, const double *V0,
+                     double *d0, double *dd_dV0, double *dd_dnx, double *dd_dny,
+                     double *dd_dnz, int64_t count)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < count; ++i) {
+        double g[3];
+        orc_offset_grad1(nx[i], ny[i], nz[i], V0[i], &d0[i], &dd_dV0[i], g, NULL);
+        dd_dnx[i] = g[0]; dd_dny[i] = g[1]; dd_dnz[i] = g[2];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* curvature                                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* the fixed auxiliary vector r of Sec. 5.2 */
+static const double R_AUX[3] = {0.56270900, 0.32704452, 0.75921047};
+
+/* mean curvature of z = A x^2 + B y^2 + C x y + H x + I y at x = y = 0
+ * (App. B.2): (A (I^2+1) + B (H^2+1) - C H I) / (H^2 + I^2 + 1)^(3/2) */
+double orc_paraboloid_kappa(const double coef[5])
+{
+    double A = coef[0], B = coef[1], C = coef[2], H = coef[3], I = coef[4];
+    double w = H * H + I * I + 1.0;
+    return (A * (I * I + 1.0) + B * (H * H + 1.0) - C * H * I) / (w * sqrt(w));
+}
+
+/* least-squares fit of App. B.3: M = sum Q Q^T, b = sum z Q, Q = (x^2, y^2, xy, x, y),
+ * solved by LDL^T (M is symmetric) over the leading min(5, npts) parameters */
+int orc_fit_paraboloid(const double *px, const double *py, const double *pz, int npts,
+                       double coef[5], double *cond)
+{
+    double M[5][5], b[5], L[5][5], D[5], y[5], x[5], maxdiag = 0.0, tol, dmax = 0.0, dmin = 0.0;
+    int act[5], N, i, j, k, nact = 0;
+    memset(M, 0, sizeof M); memset(b, 0, sizeof b); memset(L, 0, sizeof L);
+    for (i = 0; i < npts; ++i) {
+        double Q[5] = {px[i] * px[i], py[i] * py[i], px[i] * py[i], px[i], py[i]};
+        for (j = 0; j < 5; ++j) {
+            b[j] += pz[i] * Q[j];
+            for (k = 0; k < 5; ++k) M[j][k] += Q[j] * Q[k];
+        }
+    }
+    for (j = 0; j < 5; ++j) coef[j] = 0.0;
+    if (cond) *cond = 0.0;
+    N = npts < 5 ? npts : 5;
+    if (N <= 0) return 0;
+    for (j = 0; j < N; ++j) if (M[j][j] > maxdiag) maxdiag = M[j][j];
+    tol = 1e-10 * maxdiag;
+    for (j = 0; j < N; ++j) {
+        double dj = M[j][j];
+        for (k = 0; k < j; ++k) if (act[k]) dj -= L[j][k] * L[j][k] * D[k];
+        act[j] = dj > tol && maxdiag > 0.0;
+        if (!act[j]) continue;
+        D[j] = dj;
+        if (nact == 0 || dj > dmax) dmax = dj;
+        if (nact == 0 || dj < dmin) dmin = dj;
+        ++nact;
+        for (i = j + 1; i < N; ++i) {
+            double s = M[i][j];
+            for (k = 0; k < j; ++k) if (act[k]) s -= L[i][k] * L[j][k] * D[k];
+            L[i][j] = s / dj;
+        }
+    }
+    for (j = 0; j < N; ++j) {                  /* L y = b */
+        if (!act[j]) continue;
+        y[j] = b[j];
+        for (k = 0; k < j; ++k) if (act[k]) y[j] -= L[j][k] * y[k];
+    }
+    for (j = N - 1; j >= 0; --j) {             /* D L^T x = y */
+        if (!act[j]) continue;
+        x[j] = y[j] / D[j];
+        for (i = j + 1; i < N; ++i) if (act[i]) x[j] -= L[i][j] * x[i];
+    }
+    for (j = 0; j < N; ++j) coef[j] = act[j] ? x[j] : 0.0;
+    if (cond) *cond = nact > 0 ? dmax / dmin : 0.0;
+    {
+        int bits = 0;
+        for (j = 0; j < N; ++j) if (act[j]) bits |= 1 << j;
+        return bits;
+    }
+}
+
+double orc_curv_cell_full(const double phi[27], const unsigned char mask[27], double info[3],
+                          double normal[3], double coef[5])
+{
+    return orc_curv_cell_r(phi, mask, R_AUX, info, normal, coef);
+}
+
+double orc_curv_cell_r(const double phi[27], const unsigned char mask[27], const double raux[3],
+                       double info[3], double normal[3], double coef[5])
+{
+    double g[3] = {0, 0, 0}, gn, n[3], u[3], r[3], un, by[3], bx[3], D0;
+    double px[26], py[26], pz[26], cond = 0.0;
+    int dx, dy, dz, npts = 0, bits;
+    double c5[5];
+    if (!coef) coef = c5;
+    for (int j = 0; j < 5; ++j) coef[j] = 0.0;
+    if (info) { info[0] = 0; info[1] = 0; info[2] = 0; }
+    /* Parker-Youngs gradient (App. B.1): weights 4 / 2 / 1 for |e| = 1 / sqrt2 / sqrt3 */
+    for (dz = -1; dz <= 1; ++dz) for (dy = -1; dy <= 1; ++dy) for (dx = -1; dx <= 1; ++dx) {
+        int q = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1), e2 = dx * dx + dy * dy + dz * dz;
+        double w;
+        if (e2 == 0) continue;
+        w = e2 == 1 ? 4.0 : (e2 == 2 ? 2.0 : 1.0);
+        g[0] += w * dx * phi[q];
+        g[1] += w * dy * phi[q];
+        g[2] += w * dz * phi[q];
+    }
+    gn = sqrt(dot3(g, g));
+    if (!(gn >= 1e-12)) { if (normal) normal[0] = normal[1] = normal[2] = 0; return 0.0; }
+    n[0] = -g[0] / gn; n[1] = -g[1] / gn; n[2] = -g[2] / gn;
+    if (normal) { normal[0] = n[0]; normal[1] = n[1]; normal[2] = n[2]; }
+    /* local frame (Sec. 5.2): b_z = n, b_y = n x r / |n x r|, b_x = b_y x b_z */
+    r[0] = raux[0]; r[1] = raux[1]; r[2] = raux[2];
+    cross3(n, r, u);
+    un = sqrt(dot3(u, u));
+    if (un < 1e-6) {
+        r[0] = raux[1]; r[1] = raux[2]; r[2] = raux[0];
+        cross3(n, r, u);
+        un = sqrt(dot3(u, u));
+    }
+    by[0] = u[0] / un; by[1] = u[1] / un; by[2] = u[2] / un;
+    cross3(by, n, bx);
+    /* PLIC points of the interface neighbours, centre normal for every one */
+    D0 = orc_offset1(n[0], n[1], n[2], phi[13]);
+    for (dz = -1; dz <= 1; ++dz) for (dy = -1; dy <= 1; ++dy) for (dx = -1; dx <= 1; ++dx) {
+        int q = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+        double e[3] = {(double)dx, (double)dy, (double)dz}, Di;
+        if (q == 13 || !mask[q]) continue;
+        Di = orc_offset1(n[0], n[1], n[2], phi[q]);
+        px[npts] = dot3(e, bx);
+        py[npts] = dot3(e, by);
+        pz[npts] = dot3(e, n) + Di - D0;
+        ++npts;
+    }
+    bits = orc_fit_paraboloid(px, py, pz, npts, coef, &cond);
+    if (info) { info[0] = npts; info[1] = bits; info[2] = cond; }
+    /* sign: positive for a fluid drop (the normal points out of the fluid) */
+    return -orc_paraboloid_kappa(coef);
+}
+
+double orc_curv_cell(const double phi[27], const unsigned char mask[27], double info[3])
+{
+    return orc_curv_cell_full(phi, mask, info, NULL, NULL);
+}
+
+static int is_interface(float p) { return p > 0.0f && p < 1.0f; }
+
+static void gather27(const float *phi, int64_t X, int64_t Y, int64_t x, int64_t y, int64_t z,
+                     double v[27], unsigned char m[27])
+{
+    int dx, dy, dz;
+    for (dz = -1; dz <= 1; ++dz) for (dy = -1; dy <= 1; ++dy) for (dx = -1; dx <= 1; ++dx) {
+        int q = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+        float p = phi[((z + dz) * Y + (y + dy)) * X + (x + dx)];
+        v[q] = (double)p;
+        m[q] = (unsigned char)is_interface(p);
+    }
+}
+
+void orc_curvature(const float *phi, int64_t X, int64_t Y, int64_t Z, double *kappa,
+                   uint8_t *flags)
+{
+    int64_t c, total = X * Y * Z;
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (c = 0; c < total; ++c) {
+        int64_t x = c % X, y = (c / X) % Y, z = c / (X * Y);
+        double v[27], info[3];
+        unsigned char m[27];
+        kappa[c] = 0.0;
+        if (flags) flags[c] = 0;
+        if (x < 1 || y < 1 || z < 1 || x > X - 2 || y > Y - 2 || z > Z - 2) continue;
+        if (!is_interface(phi[c])) continue;
+        gather27(phi, X, Y, x, y, z, v, m);
+        kappa[c] = orc_curv_cell(v, m, info);
+        if (flags) {
+            flags[c] = 1;
+            if (info[2] > 1e8) flags[c] |= 2;
+            if (info[0] < 5) flags[c] |= 4;
+        }
+    }
+}
+
+void orc_curvature_cells(const float *phi, int64_t X, int64_t Y, int64_t Z,
+                         const int64_t *cells, int64_t ncells, double *kappa, double *info3)
+{
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (i = 0; i < ncells; ++i) {
+        int64_t c = cells[i], x = c % X, y = (c / X) % Y, z = c / (X * Y);
+        double v[27], info[3] = {0, 0, 0};
+        unsigned char m[27];
+        kappa[i] = 0.0;
+        if (x >= 1 && y >= 1 && z >= 1 && x <= X - 2 && y <= Y - 2 && z <= Z - 2 &&
+            is_interface(phi[c])) {
+            gather27(phi, X, Y, x, y, z, v, m);
+            kappa[i] = orc_curv_cell(v, m, info);
+        }
+        if (info3) { info3[3 * i] = info[0]; info3[3 * i + 1] = info[1]; info3[3 * i + 2] = info[2]; }
+    }
+}
+
+int orc_curv_cell_fd_grad(const double phi[27], const unsigned char mask[27], double h,
+                          double grad[27])
+{
+    double base[3], ip[3], im[3], p[27];
+    int q, bad = 0;
+    orc_curv_cell(phi, mask, base);
+    for (q = 0; q < 27; ++q) {
+        double kp, km;
+        memcpy(p, phi, sizeof p);
+        if (mask[q] || q == 13) {
+            if (!(phi[q] - h > 0.0 && phi[q] + h < 1.0)) bad = 1;
+        }
+        p[q] = phi[q] + h; kp = orc_curv_cell(p, mask, ip);
+        p[q] = phi[q] - h; km = orc_curv_cell(p, mask, im);
+        if (ip[0] != base[0] || im[0] != base[0] || ip[1] != base[1] || im[1] != base[1]) bad = 1;
+        grad[q] = (kp - km) / (2.0 * h);
+    }
+    return bad;
+}
+
+int64_t orc_curvature_grad(const float *phi, int64_t X, int64_t Y, int64_t Z,
+                           const float *grad_kappa, double h, double *grad_phi,
+                           uint8_t *bad_cells)
+{
+    int64_t total = X * Y * Z, c, nif = 0, k, nbad = 0;
+    int64_t *list;
+    double *part;
+    int *bad;
+    for (c = 0; c < total; ++c) { grad_phi[c] = 0.0; if (bad_cells) bad_cells[c] = 0; }
+    for (c = 0; c < total; ++c) {
+        int64_t x = c % X, y = (c / X) % Y, z = c / (X * Y);
+        if (x >= 1 && y >= 1 && z >= 1 && x <= X - 2 && y <= Y - 2 && z <= Z - 2 &&
+            is_interface(phi[c])) ++nif;
+    }
+    list = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nif > 0 ? nif : 1));
+    part = (double *)malloc(sizeof(double) * 27 * (size_t)(nif > 0 ? nif : 1));
+    bad = (int *)malloc(sizeof(int) * (size_t)(nif > 0 ? nif : 1));
+    k = 0;
+    for (c = 0; c < total; ++c) {
+        int64_t x = c % X, y = (c / X) % Y, z = c / (X * Y);
+        if (x >= 1 && y >= 1 && z >= 1 && x <= X - 2 && y <= Y - 2 && z <= Z - 2 &&
+            is_interface(phi[c])) list[k++] = c;
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (k = 0; k < nif; ++k) {
+        int64_t cc = list[k], x = cc % X, y = (cc / X) % Y, z = cc / (X * Y);
+        double v[27];
+        unsigned char m[27];
+        gather27(phi, X, Y, x, y, z, v, m);
+        bad[k] = orc_curv_cell_fd_grad(v, m, h, part + 27 * k);
+    }
+    for (k = 0; k < nif; ++k) {                /* fixed-order scatter */
+        int64_t cc = list[k], x = cc % X, y = (cc / X) % Y, z = cc / (X * Y);
+        double gk = (double)grad_kappa[cc];
+        int dx, dy, dz;
+        for (dz = -1; dz <= 1; ++dz) for (dy = -1; dy <= 1; ++dy) for (dx = -1; dx <= 1; ++dx) {
+            int q = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+            grad_phi[((z + dz) * Y + (y + dy)) * X + (x + dx)] += gk * part[27 * k + q];
+        }
+        if (bad[k]) { ++nbad; if (bad_cells) bad_cells[cc] = 1; }
+    }
+    free(list); free(part); free(bad);
+    return nbad;
+}

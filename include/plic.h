@@ -1,0 +1,147 @@
+/*
+ * libplic — PLIC inversion and PLIC curvature on AMD Instinct MI355X (gfx950).
+ *
+ * Method: M. Lehmann, S. Gekle, "Analytic Solution to the Piecewise Linear
+ * Interface Construction Problem and its Application in Curvature Calculation
+ * for Volume-of-Fluid Simulation Codes", arXiv 2006.12838.
+ *
+ * Geometry (Sec. 2, problem statement): the unit cube [-1/2, 1/2]^3 centred at
+ * the origin, cut by the plane n . x = d0.  V0 in [0, 1] is the volume of the
+ * part with n . x <= d0; d0 lies in [-S/2, S/2] with S = |nx| + |ny| + |nz|.
+ * The paper states the problem for a unit normal; every entry point here
+ * accepts any non-zero n and describes the plane n . x = d0, so d0 is
+ * homogeneous of degree 1 in n (for |n| = 1 this is the paper's d0).
+ *
+ * Common rules for every entry point
+ *  - Array arguments are DEVICE pointers owned by the caller.  The library
+ *    allocates nothing and keeps no state between calls.
+ *  - Arrays are structure-of-arrays, one element per problem (or per lattice
+ *    cell), naturally aligned (4 bytes for float, 8 for double).  Outputs may
+ *    alias an input of the same element index only where stated.
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL is the
+ *    default stream) and the call returns without waiting.  Kernel faults are
+ *    reported by the HIP runtime at the next synchronisation, not here.
+ *  - Arguments are validated before anything is enqueued; a call that returns
+ *    an error has enqueued nothing.  count == 0 (or an empty lattice) is valid
+ *    and does nothing.  No call aborts the process or throws.
+ *  - Inputs: V0 is clamped to [0, 1]; a NaN in (n, V0) gives NaN; n = 0 gives NaN.
+ *  - Results are deterministic: the same inputs on the same device give the
+ *    same bits.
+ */
+#ifndef PLIC_H
+#define PLIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PLIC_OK 0
+#define PLIC_EINVAL (-1)  /* null / misaligned / overlapping pointer, negative size, bad enum */
+#define PLIC_EHIP (-2)    /* the HIP runtime refused the launch (see plic_last_hip_error) */
+
+/* PLIC solvers: the four inversion methods compared in Sec. 3 of the paper */
+#define PLIC_ANALYTIC 0   /* the paper's analytic solution (Sec. 2.3, trigonometric root via atan) */
+#define PLIC_SZ 1         /* optimized Scardovelli-Zaleski solution (Sec. 3.1, root via asin)      */
+#define PLIC_NEWTON 2     /* Newton-Raphson on the cubic cases (Sec. 3.2), |step| <= 1e-6 (f32)    */
+#define PLIC_NESTED 3     /* nested intervals (bisection) on the cubic cases (Sec. 3.2)            */
+
+/* arithmetic precision of the computation (independent of the storage type) */
+#define PLIC_FP32 0       /* all FP32                                                              */
+#define PLIC_MIXED 1      /* FP32 bulk; FP64 for the cubic-case root and the curvature fit solve   */
+#define PLIC_FP64 2       /* all FP64                                                              */
+
+/*
+ * plic_offset_f32 / plic_offset_f64 — the PLIC problem (Sec. 2): n, V0 -> d0.
+ *   nx, ny, nz, V0 : inputs, `count` elements each.
+ *   d0             : output, `count` elements; may alias V0 (read before write).
+ *   solver         : PLIC_ANALYTIC, PLIC_SZ, PLIC_NEWTON or PLIC_NESTED.
+ *   precision      : (f32 only) PLIC_FP32, PLIC_MIXED or PLIC_FP64; the f64 entry
+ *                    point always computes in FP64.
+ * Accuracy: |d0 - exact| <= 1e-5 (f32 storage) and <= 1e-12 (f64), absolute,
+ * for unit normals, for every solver.
+ * Returns PLIC_OK, PLIC_EINVAL or PLIC_EHIP.
+ */
+int plic_offset_f32(const float *nx, const float *ny, const float *nz, const float *V0,
+                    float *d0, int64_t count, int solver, int precision, void *stream);
+int plic_offset_f64(const double *nx, const double *ny, const double *nz, const double *V0,
+                    double *d0, int64_t count, int solver, void *stream);
+
+/*
+ * plic_volume_f32 / plic_volume_f64 — the inverse PLIC problem (Sec. 2.2,
+ * five-case volume): n, d0 -> V0.  d0 outside [-S/2, S/2] gives 0 or 1.
+ *   V0 : output, may alias d0.
+ *   precision : (f32 only) PLIC_FP32 or PLIC_FP64 (PLIC_MIXED means FP32 here).
+ */
+int plic_volume_f32(const float *nx, const float *ny, const float *nz, const float *d0,
+                    float *V0, int64_t count, int precision, void *stream);
+int plic_volume_f64(const double *nx, const double *ny, const double *nz, const double *d0,
+                    double *V0, int64_t count, void *stream);
+
+/*
+ * plic_offset_backward_f32 / _f64 — vector-Jacobian product of plic_offset.
+ * Implicit differentiation of V0 = volume{x in cube : n.x <= d0}:
+ *   dd0/dV0 = |n| / A  and  dd0/dn = c,
+ * A the area and c the centroid (cube-centred) of the polygon where the plane
+ * cuts the cube.  d0 is recomputed with `solver` (nothing is stored by the
+ * forward call).  Outputs: grad_n* = grad_d0 * c_*, grad_V0 = grad_d0 * |n| / A.
+ * Where A = 0 (V0 in {0, 1} with a corner or an edge as the polygon)
+ * dd0/dV0 is +inf.  Outputs must not alias inputs.
+ */
+int plic_offset_backward_f32(const float *nx, const float *ny, const float *nz, const float *V0,
+                             const float *grad_d0, float *grad_nx, float *grad_ny,
+                             float *grad_nz, float *grad_V0, int64_t count, int solver,
+                             int precision, void *stream);
+int plic_offset_backward_f64(const double *nx, const double *ny, const double *nz,
+                             const double *V0, const double *grad_d0, double *grad_nx,
+                             double *grad_ny, double *grad_nz, double *grad_V0, int64_t count,
+                             int solver, void *stream);
+
+/*
+ * plic_curvature_f32 — PLIC curvature of a VoF fill-level lattice (Sec. 5.1-5.2,
+ * Appendix B): for every interface cell (0 < phi < 1) away from the outer
+ * one-cell layer: Parker-Youngs normal from the 3x3x3 fill levels, local frame
+ * from the fixed vector r, PLIC points of the interface neighbours (centre
+ * normal for all), least-squares paraboloid z = Ax^2+By^2+Cxy+Hx+Iy, mean
+ * curvature at the origin.
+ *   phi   : X*Y*Z floats, x fastest (index (z*Y + y)*X + x, torch shape (Z,Y,X)).
+ *   kappa : X*Y*Z floats, written everywhere; 0 on non-interface cells and on
+ *           the outer layer.  Must not overlap phi.
+ *   solver, precision : PLIC solver for the points; PLIC_FP32 fits in FP32,
+ *           PLIC_MIXED fits in FP64 (FP32 points), PLIC_FP64 is FP64 throughout.
+ * Sign: kappa = +1/R for a fluid sphere of radius R (the normal points out of
+ * the fluid); the paper's formula is negated for this.  Fits with fewer than 5
+ * points use the leading parameters only (App. B.3); a pivot of the LDL^T
+ * factorisation below 1e-10 of the largest diagonal entry drops its parameter.
+ * X, Y, Z >= 1.  Deterministic.
+ */
+int plic_curvature_f32(const float *phi, int64_t X, int64_t Y, int64_t Z, float *kappa,
+                       int solver, int precision, void *stream);
+
+/*
+ * plic_curvature_backward_f32 — vector-Jacobian product of plic_curvature:
+ * grad_phi[j] = sum over interface cells c of grad_kappa[c] * d kappa_c / d phi_j.
+ * The neighbourhood of each cell is recomputed (nothing is stored by the
+ * forward call).  The interface mask, the case of each PLIC point and the set
+ * of fit parameters are held fixed (they are piecewise constant in phi).
+ * grad_phi is written everywhere (zero away from the interface band); it must
+ * not overlap phi or grad_kappa.  Deterministic (fixed summation order).
+ */
+int plic_curvature_backward_f32(const float *phi, int64_t X, int64_t Y, int64_t Z,
+                                const float *grad_kappa, float *grad_phi, int solver,
+                                int precision, void *stream);
+
+/* human-readable status; never NULL */
+const char *plic_status_string(int status);
+/* library version string, e.g. "plic-mi355x 0.1.0 (gfx950)" */
+const char *plic_version(void);
+/* the hipError_t value behind the last PLIC_EHIP returned on this thread (0 if none) */
+int plic_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PLIC_H */

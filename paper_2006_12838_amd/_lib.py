@@ -1,0 +1,201 @@
+"""ctypes binding of libplic.so: one Python function per C entry point, same
+names, argument marshalling only (torch tensors -> device pointers, the
+current torch stream -> hipStream_t).  Every computation runs in the library's
+HIP kernels; a missing library is an ImportError, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads torch's HIP runtime first; libplic binds to the same one
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libplic.so")
+
+PLIC_OK, PLIC_EINVAL, PLIC_EHIP = 0, -1, -2
+SOLVERS = {"analytic": 0, "sz": 1, "newton": 2, "nested": 3}
+PRECISIONS = {"fp32": 0, "mixed": 1, "fp64": 2}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(or python -m paper_2006_12838_amd._build)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _i64, _int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+
+
+def _sig(name, args):
+    f = getattr(_lib, name)
+    f.restype = ctypes.c_int
+    f.argtypes = args
+    return f
+
+
+_c = {
+    "plic_offset_f32": _sig("plic_offset_f32", [_vp] * 5 + [_i64, _int, _int, _vp]),
+    "plic_offset_f64": _sig("plic_offset_f64", [_vp] * 5 + [_i64, _int, _vp]),
+    "plic_volume_f32": _sig("plic_volume_f32", [_vp] * 5 + [_i64, _int, _vp]),
+    "plic_volume_f64": _sig("plic_volume_f64", [_vp] * 5 + [_i64, _vp]),
+    "plic_offset_backward_f32": _sig("plic_offset_backward_f32", [_vp] * 9 + [_i64, _int, _int, _vp]),
+    "plic_offset_backward_f64": _sig("plic_offset_backward_f64", [_vp] * 9 + [_i64, _int, _vp]),
+    "plic_curvature_f32": _sig("plic_curvature_f32", [_vp, _i64, _i64, _i64, _vp, _int, _int, _vp]),
+    "plic_curvature_backward_f32": _sig("plic_curvature_backward_f32",
+                                        [_vp, _i64, _i64, _i64, _vp, _vp, _int, _int, _vp]),
+}
+_lib.plic_status_string.restype = ctypes.c_char_p
+_lib.plic_status_string.argtypes = [_int]
+_lib.plic_version.restype = ctypes.c_char_p
+_lib.plic_version.argtypes = []
+_lib.plic_last_hip_error.restype = ctypes.c_int
+_lib.plic_last_hip_error.argtypes = []
+
+EXPORTED = tuple(_c) + ("plic_status_string", "plic_version", "plic_last_hip_error")
+
+
+def plic_status_string(status: int) -> str:
+    return _lib.plic_status_string(int(status)).decode()
+
+
+def plic_version() -> str:
+    return _lib.plic_version().decode()
+
+
+def plic_last_hip_error() -> int:
+    return int(_lib.plic_last_hip_error())
+
+
+def raw(name):
+    """The raw ctypes function (plain integers / pointers in, status out)."""
+    return _c[name]
+
+
+def _check(status: int, name: str):
+    if status != PLIC_OK:
+        extra = f" (hipError {plic_last_hip_error()})" if status == PLIC_EHIP else ""
+        raise RuntimeError(f"{name}: {plic_status_string(status)}{extra}")
+
+
+def _ptr(t: torch.Tensor, dtype, n: int, what: str):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: tensor must live on a GPU (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{what}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{what}: expected {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _enum(table, value, what):
+    if isinstance(value, int):
+        return value
+    try:
+        return table[value]
+    except KeyError:
+        raise ValueError(f"unknown {what} {value!r}; one of {sorted(table)}") from None
+
+
+def _same_device(*ts):
+    dev = ts[0].device
+    for t in ts[1:]:
+        if t.device != dev:
+            raise ValueError("all tensors must be on the same device")
+
+
+# ---------------------------------------------------------------- entry points
+
+def plic_offset_f32(nx, ny, nz, V0, d0, solver="analytic", precision="fp32"):
+    n = V0.numel()
+    _same_device(nx, ny, nz, V0, d0)
+    args = [_ptr(t, torch.float32, n, w) for t, w in ((nx, "nx"), (ny, "ny"), (nz, "nz"), (V0, "V0"), (d0, "d0"))]
+    _check(_c["plic_offset_f32"](*args, n, _enum(SOLVERS, solver, "solver"),
+                                 _enum(PRECISIONS, precision, "precision"), _stream(V0)), "plic_offset_f32")
+    return d0
+
+
+def plic_offset_f64(nx, ny, nz, V0, d0, solver="analytic"):
+    n = V0.numel()
+    _same_device(nx, ny, nz, V0, d0)
+    args = [_ptr(t, torch.float64, n, w) for t, w in ((nx, "nx"), (ny, "ny"), (nz, "nz"), (V0, "V0"), (d0, "d0"))]
+    _check(_c["plic_offset_f64"](*args, n, _enum(SOLVERS, solver, "solver"), _stream(V0)), "plic_offset_f64")
+    return d0
+
+
+def plic_volume_f32(nx, ny, nz, d0, V0, precision="fp32"):
+    n = d0.numel()
+    _same_device(nx, ny, nz, d0, V0)
+    args = [_ptr(t, torch.float32, n, w) for t, w in ((nx, "nx"), (ny, "ny"), (nz, "nz"), (d0, "d0"), (V0, "V0"))]
+    _check(_c["plic_volume_f32"](*args, n, _enum(PRECISIONS, precision, "precision"), _stream(d0)),
+           "plic_volume_f32")
+    return V0
+
+
+def plic_volume_f64(nx, ny, nz, d0, V0):
+    n = d0.numel()
+    _same_device(nx, ny, nz, d0, V0)
+    args = [_ptr(t, torch.float64, n, w) for t, w in ((nx, "nx"), (ny, "ny"), (nz, "nz"), (d0, "d0"), (V0, "V0"))]
+    _check(_c["plic_volume_f64"](*args, n, _stream(d0)), "plic_volume_f64")
+    return V0
+
+
+def plic_offset_backward_f32(nx, ny, nz, V0, grad_d0, grad_nx, grad_ny, grad_nz, grad_V0,
+                             solver="analytic", precision="fp32"):
+    n = V0.numel()
+    ts = (nx, ny, nz, V0, grad_d0, grad_nx, grad_ny, grad_nz, grad_V0)
+    _same_device(*ts)
+    names = ("nx", "ny", "nz", "V0", "grad_d0", "grad_nx", "grad_ny", "grad_nz", "grad_V0")
+    args = [_ptr(t, torch.float32, n, w) for t, w in zip(ts, names)]
+    _check(_c["plic_offset_backward_f32"](*args, n, _enum(SOLVERS, solver, "solver"),
+                                          _enum(PRECISIONS, precision, "precision"), _stream(V0)),
+           "plic_offset_backward_f32")
+
+
+def plic_offset_backward_f64(nx, ny, nz, V0, grad_d0, grad_nx, grad_ny, grad_nz, grad_V0,
+                             solver="analytic"):
+    n = V0.numel()
+    ts = (nx, ny, nz, V0, grad_d0, grad_nx, grad_ny, grad_nz, grad_V0)
+    _same_device(*ts)
+    names = ("nx", "ny", "nz", "V0", "grad_d0", "grad_nx", "grad_ny", "grad_nz", "grad_V0")
+    args = [_ptr(t, torch.float64, n, w) for t, w in zip(ts, names)]
+    _check(_c["plic_offset_backward_f64"](*args, n, _enum(SOLVERS, solver, "solver"), _stream(V0)),
+           "plic_offset_backward_f64")
+
+
+def _lattice_dims(phi):
+    if phi.dim() != 3:
+        raise ValueError("phi must be a 3-D tensor of shape (Z, Y, X)")
+    Z, Y, X = phi.shape
+    return X, Y, Z
+
+
+def plic_curvature_f32(phi, kappa, solver="analytic", precision="mixed"):
+    X, Y, Z = _lattice_dims(phi)
+    n = X * Y * Z
+    _same_device(phi, kappa)
+    _check(_c["plic_curvature_f32"](_ptr(phi, torch.float32, n, "phi"), X, Y, Z,
+                                    _ptr(kappa, torch.float32, n, "kappa"),
+                                    _enum(SOLVERS, solver, "solver"),
+                                    _enum(PRECISIONS, precision, "precision"), _stream(phi)),
+           "plic_curvature_f32")
+    return kappa
+
+
+def plic_curvature_backward_f32(phi, grad_kappa, grad_phi, solver="analytic", precision="mixed"):
+    X, Y, Z = _lattice_dims(phi)
+    n = X * Y * Z
+    _same_device(phi, grad_kappa, grad_phi)
+    _check(_c["plic_curvature_backward_f32"](_ptr(phi, torch.float32, n, "phi"), X, Y, Z,
+                                             _ptr(grad_kappa, torch.float32, n, "grad_kappa"),
+                                             _ptr(grad_phi, torch.float32, n, "grad_phi"),
+                                             _enum(SOLVERS, solver, "solver"),
+                                             _enum(PRECISIONS, precision, "precision"), _stream(phi)),
+           "plic_curvature_backward_f32")
+    return grad_phi

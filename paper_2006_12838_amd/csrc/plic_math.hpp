@@ -1,0 +1,419 @@
+// Device-side PLIC mathematics for gfx950: symmetry reduction, the four
+// inversion solvers, the forward volume and the derivatives of the offset.
+//
+// Paper: Lehmann & Gekle, arXiv 2006.12838.  Notation follows Sec. 2:
+// reduced space has sorted 0 <= n1 <= n2 <= n3, the reduced volume
+// V = min(V0, 1 - V0) in [0, 1/2] and the reduced offset d = S/2 - |d0| in
+// [0, S/2] (origin at the cube corner), S = n1 + n2 + n3.
+//
+// Everything is templated on the arithmetic type T (float or double).  The
+// cubic-case root recovery takes a second type U so that FP32 kernels can run
+// that part in FP64 (mixed precision).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cfloat>
+#include <cstdint>
+
+namespace plic {
+
+// ---------------------------------------------------------------------------
+// arithmetic primitives.  FP32 uses the native gfx950 instructions (v_sqrt,
+// v_rsq, v_rcp: <= 1 ulp); FP64 uses the correctly rounded library routines.
+// ---------------------------------------------------------------------------
+template <class T> struct M;
+
+template <> struct M<float> {
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float cbrt(float x) { return ::cbrtf(x); }
+    static __device__ __forceinline__ float sin(float x) { return ::sinf(x); }
+    static __device__ __forceinline__ float asin(float x) { return ::asinf(x); }
+    static __device__ __forceinline__ float atan(float x) { return ::atanf(x); }
+    static __device__ __forceinline__ float fmin(float a, float b) { return ::fminf(a, b); }
+    static __device__ __forceinline__ float fmax(float a, float b) { return ::fmaxf(a, b); }
+    static __device__ __forceinline__ float fabs(float a) { return ::fabsf(a); }
+    static __device__ __forceinline__ float med3(float a, float b, float c) {
+        return __builtin_amdgcn_fmed3f(a, b, c);
+    }
+    static constexpr float tiny = FLT_MIN;
+    static constexpr float nan_v = __builtin_nanf("");
+    // Newton step tolerance (|delta d|) and bisection halvings per bracket
+    static constexpr float newton_tol = 1e-6f;
+    static constexpr int bisect_steps = 24;
+    // relative pivot threshold of the fit (rounding noise of a zero pivot ~1e-7)
+    static constexpr float pivot_rel = 1e-5f;
+};
+
+template <> struct M<double> {
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double cbrt(double x) { return ::cbrt(x); }
+    static __device__ __forceinline__ double sin(double x) { return ::sin(x); }
+    static __device__ __forceinline__ double asin(double x) { return ::asin(x); }
+    static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
+    static __device__ __forceinline__ double fmin(double a, double b) { return ::fmin(a, b); }
+    static __device__ __forceinline__ double fmax(double a, double b) { return ::fmax(a, b); }
+    static __device__ __forceinline__ double fabs(double a) { return ::fabs(a); }
+    static __device__ __forceinline__ double med3(double a, double b, double c) {
+        return ::fmax(::fmin(a, b), ::fmin(::fmax(a, b), c));
+    }
+    static constexpr double tiny = DBL_MIN;
+    static constexpr double nan_v = __builtin_nan("");
+    static constexpr double newton_tol = 1e-13;
+    static constexpr int bisect_steps = 52;
+    static constexpr double pivot_rel = 1e-10;
+};
+
+enum Solver : int { kAnalytic = 0, kSZ = 1, kNewton = 2, kNested = 3 };
+
+// ---------------------------------------------------------------------------
+// Symmetry reduction (Sec. 2.1).  The reduced volume is taken as
+// V0 <= 1/2 ? V0 : 1 - V0, which is exact in floating point (Sterbenz), where
+// the printed 1/2 - |V0 - 1/2| rounds for V0 < 1/2 and the cube root of case
+// (1) amplifies that rounding near V0 = 0.
+// ---------------------------------------------------------------------------
+template <class T> struct Reduced {
+    T n1, n2, n3;  // sorted |n|
+    T V;           // reduced volume in [0, 1/2]
+    T V0;          // clamped input volume
+};
+
+template <class T>
+__device__ __forceinline__ Reduced<T> reduce(T nx, T ny, T nz, T V0) {
+    using m = M<T>;
+    Reduced<T> r;
+    const T ax = m::fabs(nx), ay = m::fabs(ny), az = m::fabs(nz);
+    r.n1 = m::fmin(m::fmin(ax, ay), az);
+    r.n3 = m::fmax(m::fmax(ax, ay), az);
+    r.n2 = m::med3(ax, ay, az);
+    const T v = m::fmin(m::fmax(V0, T(0)), T(1));
+    r.V0 = v;
+    r.V = v <= T(0.5) ? v : T(1) - v;
+    return r;
+}
+
+// d0 = sign(V0 - 1/2) (S/2 - d)  (Sec. 2.1); NaN inputs and n = 0 give NaN.
+template <class T>
+__device__ __forceinline__ T unreduce(const Reduced<T>& r, T d, T nx, T ny, T nz, T V0raw) {
+    T h = T(0.5) * (r.n1 + r.n2 + r.n3) - d;
+    T d0 = r.V0 > T(0.5) ? h : (r.V0 < T(0.5) ? -h : T(0));
+    if (__builtin_isnan(nx + ny + nz + V0raw) || !(r.n3 > T(0))) d0 = M<T>::nan_v;
+    return d0;
+}
+
+// ---------------------------------------------------------------------------
+// Closed-form cases shared by the analytic, Newton and nested-interval solvers
+// (a-priori conditions of Sec. 2.3): returns true and sets d for (5), (2), (1).
+// Case (2) is n1^2 <= 6 V n2 n3 and 3 n2 (2 V n3 + n1 - n2) <= n1^2, the form
+// that follows from n1 <= d2 <= n2.  Normals in a coordinate plane (n1 = 0)
+// and along an axis (n2 = 0) are covered by (2) and (5) (Sec. 2.3).
+// ---------------------------------------------------------------------------
+template <class T, bool WITH_CASE1 = true>
+__device__ __forceinline__ int closed_case(T n1, T n2, T n3, T V, T& d) {
+    using m = M<T>;
+    const T n12 = n1 + n2, n3V = n3 * V;
+    if (n12 <= T(2) * n3V) { d = n3V + T(0.5) * n12; return 5; }
+    const T V6n2n3 = T(6) * n2 * n3V, sqn1 = n1 * n1;
+    if (V6n2n3 >= sqn1 && T(3) * n2 * (T(2) * n3V + n1 - n2) <= sqn1) {
+        // d2 = n1/2 + sqrt(2 V n2 n3 - n1^2/12) = n1/2 + sqrt(24 V n2 n3 - n1^2) / sqrt(12)
+        d = T(0.5) * n1 + m::sqrt(m::fmax(T(24) * n2 * n3V - sqn1, T(0))) * T(0.28867513459481288225);
+        return 2;
+    }
+    if (V6n2n3 < sqn1) {
+        if constexpr (WITH_CASE1) d = m::cbrt(V6n2n3 * n1);
+        return 1;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Analytic solution (Sec. 2.3): the trigonometric root
+//   f(x, y, a, b, c) = c - 2 (a + b (x^2+y^2)^(1/3)) / (x^2+y^2)^(1/6)
+//                      * sin(pi/6 - atan2(y, x)/3)
+// with the printed coefficients, tried in the order (5), (2), (1), (3), (4),
+// case (3) accepted when d3 <= n3.  Two exact simplifications:
+//  * x3^2 + y3^2 = 23328 (n1 n2)^3 and x4^2 + y4^2 = 4 t4^3, so the cube roots
+//    cancel: the prefactor is 2 sqrt(2 n1 n2) in case (3) and sqrt(t4)/3 in
+//    case (4);
+//  * t4 = 9 (S^2 - 2) assumes |n| = 1 and cancels near the face diagonal; the
+//    equal (for |n| = 1), degree-2 homogeneous
+//    t4 = 9 (2 n1 (n2 + n3) - n1^2 - (n3 - n2)^2) is used instead.
+// atan(y/x) replaces atan2 with x4 clamped to the smallest normal number, as
+// the paper does; x3 > 0 holds once (5) is excluded.
+// ---------------------------------------------------------------------------
+template <class T, class U>
+__device__ __forceinline__ T solve_analytic(T n1, T n2, T n3, T V) {
+    T d;
+    if (closed_case(n1, n2, n3, V, d)) return d;
+    using m = M<U>;
+    const U u1 = n1, u2 = n2, u3 = n3, uV = V;
+    const U p = u1 * u2, s = u1 + u2;
+    const U pi6 = U(0.52359877559829887308), third = U(1) / U(3);
+    const U x3 = U(81) * p * (s - U(2) * u3 * uV);
+    const U y3 = m::sqrt(m::fmax(U(23328) * p * p * p - x3 * x3, U(0)));
+    const U d3 = s - U(2) * m::sqrt(U(2) * p) * m::sin(pi6 - third * m::atan(m::div(y3, x3)));
+    if (d3 <= u3) return T(d3);                                  // case (3)
+    const U t4 = m::fmax(U(9) * (U(2) * u1 * (u2 + u3) - u1 * u1 - (u3 - u2) * (u3 - u2)), U(0));
+    const U x4 = m::fmax(U(324) * p * u3 * (U(1) - U(2) * uV), m::tiny);
+    const U y4 = m::sqrt(m::fmax(U(4) * t4 * t4 * t4 - x4 * x4, U(0)));
+    const U d4 = U(0.5) * (s + u3) - m::sqrt(t4) * third * m::sin(pi6 - third * m::atan(m::div(y4, x4)));
+    return T(d4);                                                // case (4)
+}
+
+// ---------------------------------------------------------------------------
+// Optimized Scardovelli-Zaleski solution (Sec. 3.1), on the L1-normalized
+// normal (n1 + n2 + n3 = 1, so d in [0, 1/2]).  Cases (5), (2), (1) first;
+// the boundary between (3) and (4) is decided a priori through the volume v3
+// at d = n3; one root d = c - 2 t sin(asin(arg)/3) serves both.  The printed
+// coefficients t = sqrt(c^2 - b) and arg = (c^3 - a/2 - 3bc/2)/t^3 are 0/0 for
+// small n1; the equal cancellation-free forms are used:
+//   case (3): c = n1 + n2, t = sqrt(2 n1 n2), arg = 1.5 n1 n2 (n1 + n2 - 2 n3 V) / t^3
+//   case (4): c = 1/2,     t = sqrt(2 n1 (n2+n3) - n1^2 - (n3-n2)^2) / 2,
+//             arg = 0.75 n1 n2 n3 (1 - 2V) / t^3
+// and arg is clamped to [-1, 1] before asin.  v3 is evaluated in the divided
+// form 3 n3 (n3 - n1) + n1^2 - (n3 - n2)^3 / n1 (over 6 n2), which has no
+// cancellation either.  Returns the reduced d in L1 units.
+// ---------------------------------------------------------------------------
+template <class T, class U>
+__device__ __forceinline__ T solve_sz(T n1, T n2, T n3, T V) {
+    using mt = M<T>;
+    const T n12 = n1 + n2, n3V = n3 * V;
+    if (n12 <= T(2) * n3V) return n3V + T(0.5) * n12;                  // case (5)
+    const T sqn1 = n1 * n1, n26 = T(6) * n2, v1 = mt::div(sqn1, n26);   // n2 > 0 here
+    if (v1 <= n3V && n3V < v1 + T(0.5) * (n2 - n1))                    // case (2)
+        return T(0.5) * (n1 + mt::sqrt(sqn1 + T(8) * n2 * (n3V - v1)));
+    if (n3V < v1) return mt::cbrt(n1 * n26 * n3V);                      // case (1)
+    using m = M<U>;
+    const U u1 = n1, u2 = n2, u3 = n3, uV = V, s = u1 + u2;
+    bool case3 = true;
+    if (u3 < s) {
+        const U w = u3 - u2;
+        const U v3 = m::div(U(3) * u3 * (u3 - u1) + u1 * u1 - m::div(w * w * w, u1), U(6) * u2);
+        case3 = u3 * uV < v3;
+    }
+    U c, t, num;
+    if (case3) {
+        c = s;
+        t = m::sqrt(U(2) * u1 * u2);
+        num = U(1.5) * u1 * u2 * (s - U(2) * u3 * uV);
+    } else {
+        c = U(0.5);
+        t = U(0.5) * m::sqrt(m::fmax(U(2) * u1 * (u2 + u3) - u1 * u1 - (u3 - u2) * (u3 - u2), U(0)));
+        num = U(0.75) * u1 * u2 * u3 * (U(1) - U(2) * uV);
+    }
+    U arg = m::div(num, t * t * t);
+    arg = m::fmin(m::fmax(arg, U(-1)), U(1));
+    return T(c - U(2) * t * m::sin(m::asin(arg) * (U(1) / U(3))));
+}
+
+// ---------------------------------------------------------------------------
+// Divided volume polynomial used by the iterative solvers.  For d >= n1
+//   [d^3 - (d-n1)^3 - (d-n2)+^3 - (d-n3)+^3] / n1
+//     = 3 d (d - n1) + n1^2 - ((d-n2)+^3 + (d-n3)+^3) / n1,
+// and d^3 / n1 below n1; the reduced volume is this over 6 n2 n3 (Sec. 2.2).
+// The printed polynomials cancel catastrophically when n1 is small; this form
+// does not.  Valid for 0 <= d <= min(n1 + n2, S/2) with n1 > 0.
+// ---------------------------------------------------------------------------
+template <class U>
+__device__ __forceinline__ void divided_volume(U n1, U n2, U n3, U d, U& g, U& gp) {
+    if (d < n1) {
+        const U r = M<U>::rcp(n1);
+        g = d * d * d * r;
+        gp = U(3) * d * d * r;
+    } else {
+        const U p2 = M<U>::fmax(d - n2, U(0)), p3 = M<U>::fmax(d - n3, U(0));
+        const U r = M<U>::rcp(n1);
+        g = U(3) * d * (d - n1) + n1 * n1 - (p2 * p2 * p2 + p3 * p3 * p3) * r;
+        gp = U(6) * d - U(3) * n1 - U(3) * (p2 * p2 + p3 * p3) * r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Newton-Raphson (Sec. 3.2).  Cases (5) and (2) in closed form; the cubic
+// cases by Newton on the divided polynomial against 6 V n2 n3, on the bracket
+// [0, n1] for case (1) (start n1/2, as printed) and on [n2, min(n1+n2, S/2)]
+// for cases (3) and (4) together (start at the midpoint).  The printed fixed
+// step counts (7/4/4) do not converge for small V, so each iterate is
+// safeguarded (kept inside the shrinking bracket, bisecting when a step leaves
+// it) and iteration stops once |step| <= 1e-6 (FP32) / 1e-13 (FP64), at most
+// 40 steps.  V = 0 returns d = 0 directly.
+// ---------------------------------------------------------------------------
+template <class T, class U>
+__device__ __forceinline__ T solve_newton(T n1, T n2, T n3, T V) {
+    T d;
+    if (closed_case<T, false>(n1, n2, n3, V, d) >= 2) return d;       // (5) or (2)
+    if (V == T(0)) return T(0);
+    using m = M<U>;
+    const U u1 = n1, u2 = n2, u3 = n3;
+    const U target = U(6) * u2 * u3 * U(V);
+    U lo, hi;
+    if (target < u1 * u1) { lo = U(0); hi = u1; }                      // case (1)
+    else { lo = u2; hi = m::fmin(u1 + u2, U(0.5) * (u1 + u2 + u3)); }  // cases (3), (4)
+    U x = U(0.5) * (lo + hi);
+    for (int it = 0; it < 40; ++it) {
+        U g, gp;
+        divided_volume(u1, u2, u3, x, g, gp);
+        const U f = g - target;
+        if (f < U(0)) lo = x; else hi = x;
+        U xn = x - m::div(f, gp);
+        if (!(xn > lo && xn < hi)) xn = U(0.5) * (lo + hi);
+        const U step = m::fabs(xn - x);
+        x = xn;
+        if (step <= U(M<T>::newton_tol)) break;
+    }
+    return T(x);
+}
+
+// ---------------------------------------------------------------------------
+// Nested intervals (Sec. 3.2).  Cases (5), (2) closed form, case (1) by cube
+// root, as printed.  Cases (3) and (4) by bisection of the divided polynomial
+// on [n2, n1 + n2]: the (d-n3)+ term makes one bracket cover both cases, where
+// the printed version bisects [n2, n1+n2] and then [n3, S/2].  A fixed count of
+// halvings (24 in FP32, 52 in FP64) replaces the printed exponent-based count,
+// so all lanes of a wavefront run the same trip count.
+// ---------------------------------------------------------------------------
+template <class T, class U>
+__device__ __forceinline__ T solve_nested(T n1, T n2, T n3, T V) {
+    T d;
+    if (closed_case(n1, n2, n3, V, d)) return d;
+    const U u1 = n1, u2 = n2, u3 = n3;
+    const U target = U(6) * u2 * u3 * U(V);
+    U lo = u2, hi = u1 + u2;
+#pragma unroll 4
+    for (int i = 0; i < M<T>::bisect_steps; ++i) {
+        const U mid = U(0.5) * (lo + hi);
+        U g, gp;
+        divided_volume(u1, u2, u3, mid, g, gp);
+        if (g < target) lo = mid; else hi = mid;
+    }
+    return T(U(0.5) * (lo + hi));
+}
+
+// full problem: (n, V0) -> d0 with the chosen solver
+template <int SOLVER, class T, class U>
+__device__ __forceinline__ T offset(T nx, T ny, T nz, T V0) {
+    const Reduced<T> r = reduce(nx, ny, nz, V0);
+    T d;
+    if constexpr (SOLVER == kSZ) {
+        // L1 normalisation (Sec. 3.1): d0 = l * sign(V0 - 1/2) (1/2 - d)
+        const T l = r.n1 + r.n2 + r.n3;
+        const T il = M<T>::rcp(l);
+        d = solve_sz<T, U>(r.n1 * il, r.n2 * il, r.n3 * il, r.V) * l;
+    } else if constexpr (SOLVER == kNewton) {
+        d = solve_newton<T, U>(r.n1, r.n2, r.n3, r.V);
+    } else if constexpr (SOLVER == kNested) {
+        d = solve_nested<T, U>(r.n1, r.n2, r.n3, r.V);
+    } else {
+        d = solve_analytic<T, U>(r.n1, r.n2, r.n3, r.V);
+    }
+    return unreduce(r, d, nx, ny, nz, V0);
+}
+
+// ---------------------------------------------------------------------------
+// Forward volume (Sec. 2.2, the inverse PLIC problem), case (5) tested first
+// as in the paper's inverse listing; cases (2)-(4) in the divided form (no
+// cancellation, no division by n1 in case (2)).  d0 outside [-S/2, S/2] gives
+// 0 or 1.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T volume(T nx, T ny, T nz, T d0) {
+    using m = M<T>;
+    const T ax = m::fabs(nx), ay = m::fabs(ny), az = m::fabs(nz);
+    const T n1 = m::fmin(m::fmin(ax, ay), az), n3 = m::fmax(m::fmax(ax, ay), az);
+    const T n2 = m::med3(ax, ay, az);
+    const T n12 = n1 + n2;
+    const T d = m::fmax(T(0.5) * (n12 + n3) - m::fabs(d0), T(0));
+    T V;
+    if (m::fmin(n12, n3) <= d && d <= n3) {
+        V = m::div(d - T(0.5) * n12, n3);                                // case (5)
+    } else if (d < n1) {
+        V = m::div(d * d * d, T(6) * n1 * n2 * n3);                       // case (1)
+    } else {
+        T g = T(3) * d * (d - n1) + n1 * n1;                              // case (2)
+        if (d > n2) {                                                     // cases (3), (4)
+            const T p2 = d - n2, p3 = m::fmax(d - n3, T(0));
+            g -= m::div(p2 * p2 * p2 + p3 * p3 * p3, n1);
+        }
+        V = m::div(g, T(6) * n2 * n3);
+    }
+    T V0 = __builtin_copysign(T(0.5) - V, d0) + T(0.5);
+    if (__builtin_isnan(nx + ny + nz + d0) || !(n3 > T(0))) V0 = m::nan_v;
+    return V0;
+}
+
+// ---------------------------------------------------------------------------
+// Derivatives of d0(n, V0).  With F(a, u) the reduced volume of the corner
+// region {z in [0,1]^3 : a.z <= u} (a = sorted |n|, u = reduced d):
+//   dV/du = A/|n|  and  dV/da_j = -(A/|n|) * zbar_j,
+// A the area and zbar the centroid (corner coordinates) of the polygon, so
+//   dd0/dV0 = 1 / F_u  and  zbar_j = -F_aj / F_u.
+// F_u and F_aj come from differentiating the five-case volume of Sec. 2.2
+// (divided forms, no cancellation):
+//   case (5):  F_u = 1/a3,               zbar = (1/2, 1/2, F)
+//   case (1):  F_u = u^2 / (2 a1 a2 a3),  zbar_j = u / (3 a_j)
+//   (2)-(4):   G = 3u(u-a1) + a1^2 - (P2^3+P3^3)/a1,  Gu = 6u - 3a1 - 3(P2^2+P3^2)/a1,
+//              F_u = Gu / (6 a2 a3),
+//              zbar1 = (3u - 2a1 - (P2^3+P3^3)/a1^2) / Gu,
+//              zbar2 = (G/a2 - 3 P2^2/a1) / Gu,  zbar3 = (G/a3 - 3 P3^2/a1) / Gu,
+//              with P_j = max(u - a_j, 0) (case (2): P2 = P3 = 0, valid for a1 = 0).
+// The centroid in cube-centred coordinates is mapped back through the sort and
+// the sign of each component, and mirrored when V0 > 1/2.
+// Returns dd0/dV0 (+inf for a degenerate polygon) and writes dd0/dn.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T offset_grad_from_d0(T nx, T ny, T nz, T V0, T d0, T g[3]) {
+    using m = M<T>;
+    const T ax = m::fabs(nx), ay = m::fabs(ny), az = m::fabs(nz);
+    // sort with the permutation: rank of each component (stable on ties)
+    const int rx = (ax > ay) + (ax > az);
+    const int ry = (ay >= ax) + (ay > az);
+    const int rz = (az >= ax) + (az >= ay);
+    const T n1 = m::fmin(m::fmin(ax, ay), az), n3 = m::fmax(m::fmax(ax, ay), az);
+    const T n2 = m::med3(ax, ay, az);
+    const T u = m::fmax(T(0.5) * (n1 + n2 + n3) - m::fabs(d0), T(0));
+    T z1, z2, z3, Fu;
+    if (m::fmin(n1 + n2, n3) <= u && u <= n3) {                          // case (5)
+        Fu = m::rcp(n3);
+        z1 = T(0.5); z2 = T(0.5);
+        z3 = m::div(u - T(0.5) * (n1 + n2), n3);
+    } else if (u < n1) {                                                  // case (1)
+        Fu = m::div(u * u, T(2) * n1 * n2 * n3);
+        const T t = u * T(1.0 / 3.0);
+        z1 = m::div(t, n1); z2 = m::div(t, n2); z3 = m::div(t, n3);
+    } else if (u <= n2) {                                                 // case (2)
+        const T G = T(3) * u * (u - n1) + n1 * n1;
+        const T Gu = T(6) * u - T(3) * n1;
+        Fu = m::div(Gu, T(6) * n2 * n3);
+        if (Gu > T(0)) {
+            const T iG = m::rcp(Gu);
+            z1 = (T(3) * u - T(2) * n1) * iG;
+            z2 = m::div(G, n2) * iG;
+            z3 = m::div(G, n3) * iG;
+        } else {                                      // u = 0 with n1 = 0: an edge
+            z1 = T(0.5); z2 = T(0); z3 = T(0);
+        }
+    } else {                                                              // cases (3), (4)
+        const T P2 = u - n2, P3 = m::fmax(u - n3, T(0));
+        const T r1 = m::rcp(n1);
+        const T c3 = (P2 * P2 * P2 + P3 * P3 * P3) * r1;
+        const T G = T(3) * u * (u - n1) + n1 * n1 - c3;
+        const T Gu = T(6) * u - T(3) * n1 - T(3) * (P2 * P2 + P3 * P3) * r1;
+        Fu = m::div(Gu, T(6) * n2 * n3);
+        const T iG = m::rcp(Gu);
+        z1 = (T(3) * u - T(2) * n1 - c3 * r1) * iG;
+        z2 = (m::div(G, n2) - T(3) * P2 * P2 * r1) * iG;
+        z3 = (m::div(G, n3) - T(3) * P3 * P3 * r1) * iG;
+    }
+    // selects, not an indexed array (which would live in scratch memory)
+    auto pick = [&](int k) { return k == 0 ? z1 : (k == 1 ? z2 : z3); };
+    const T mir = V0 > T(0.5) ? T(-1) : T(1);
+    g[0] = mir * __builtin_copysign(pick(rx) - T(0.5), nx);
+    g[1] = mir * __builtin_copysign(pick(ry) - T(0.5), ny);
+    g[2] = mir * __builtin_copysign(pick(rz) - T(0.5), nz);
+    return Fu > T(0) ? m::rcp(Fu) : T(__builtin_inf());
+}
+
+}  // namespace plic

@@ -1,0 +1,315 @@
+// Batched PLIC kernels on gfx950: inversion (four solvers), forward volume and
+// the backward (vector-Jacobian) pass of the inversion.
+//
+// Layout: structure of arrays in HBM (nx, ny, nz, V0 / d0), one problem per
+// element.  Each thread handles VEC consecutive problems with 16-byte loads
+// and stores per array (4 floats or 2 doubles), so a wavefront moves 1 KiB per
+// array per access; VEC = 1 covers unaligned pointers and the ragged tail.
+// The work is arithmetic-bound: no shared memory, no reuse, one pass over HBM.
+#include <hip/hip_runtime.h>
+
+#include "plic_host.hpp"
+#include "plic_math.hpp"
+
+namespace plic {
+namespace {
+
+constexpr int kBlock = 256;
+
+template <class S, int VEC> struct Vec;
+template <> struct Vec<float, 4> { using type = float4; };
+template <> struct Vec<double, 2> { using type = double2; };
+
+template <class S, int VEC>
+__device__ __forceinline__ void load(const S* __restrict__ p, int64_t i, S (&v)[VEC]) {
+    if constexpr (VEC == 1) {
+        v[0] = p[i];
+    } else {
+        using V = typename Vec<S, VEC>::type;
+        const V t = *reinterpret_cast<const V*>(p + i);
+        if constexpr (VEC == 4) { v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w; }
+        else { v[0] = t.x; v[1] = t.y; }
+    }
+}
+
+template <class S, int VEC>
+__device__ __forceinline__ void store(S* __restrict__ p, int64_t i, const S (&v)[VEC]) {
+    if constexpr (VEC == 1) {
+        p[i] = v[0];
+    } else {
+        using V = typename Vec<S, VEC>::type;
+        V t;
+        if constexpr (VEC == 4) { t.x = v[0]; t.y = v[1]; t.z = v[2]; t.w = v[3]; }
+        else { t.x = v[0]; t.y = v[1]; }
+        *reinterpret_cast<V*>(p + i) = t;
+    }
+}
+
+// S: storage type, T: bulk arithmetic, U: cubic-case arithmetic
+template <int SOLVER, class S, class T, class U, int VEC>
+__global__ __launch_bounds__(kBlock) void k_offset(const S* __restrict__ nx, const S* __restrict__ ny,
+                                                   const S* __restrict__ nz, const S* V0, S* d0,
+                                                   int64_t count) {
+    const int64_t i = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) * VEC;
+    if (i + VEC <= count) {
+        S a[VEC], b[VEC], c[VEC], v[VEC], r[VEC];
+        load<S, VEC>(nx, i, a); load<S, VEC>(ny, i, b); load<S, VEC>(nz, i, c); load<S, VEC>(V0, i, v);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k)
+            r[k] = S(offset<SOLVER, T, U>(T(a[k]), T(b[k]), T(c[k]), T(v[k])));
+        store<S, VEC>(d0, i, r);
+    } else {
+        for (int64_t j = i; j < count; ++j)
+            d0[j] = S(offset<SOLVER, T, U>(T(nx[j]), T(ny[j]), T(nz[j]), T(V0[j])));
+    }
+}
+
+template <class S, class T, int VEC>
+__global__ __launch_bounds__(kBlock) void k_volume(const S* __restrict__ nx, const S* __restrict__ ny,
+                                                   const S* __restrict__ nz, const S* d0, S* V0,
+                                                   int64_t count) {
+    const int64_t i = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) * VEC;
+    if (i + VEC <= count) {
+        S a[VEC], b[VEC], c[VEC], v[VEC], r[VEC];
+        load<S, VEC>(nx, i, a); load<S, VEC>(ny, i, b); load<S, VEC>(nz, i, c); load<S, VEC>(d0, i, v);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) r[k] = S(volume<T>(T(a[k]), T(b[k]), T(c[k]), T(v[k])));
+        store<S, VEC>(V0, i, r);
+    } else {
+        for (int64_t j = i; j < count; ++j)
+            V0[j] = S(volume<T>(T(nx[j]), T(ny[j]), T(nz[j]), T(d0[j])));
+    }
+}
+
+template <int SOLVER, class T, class U>
+__device__ __forceinline__ void backward1(T nx, T ny, T nz, T V0, T gd, T& gx, T& gy, T& gz, T& gv) {
+    const T d0 = offset<SOLVER, T, U>(nx, ny, nz, V0);
+    T g[3];
+    const T dv = offset_grad_from_d0<T>(nx, ny, nz, V0, d0, g);
+    gx = gd * g[0];
+    gy = gd * g[1];
+    gz = gd * g[2];
+    gv = gd * dv;
+    if (__builtin_isnan(d0)) gx = gy = gz = gv = d0;
+}
+
+template <int SOLVER, class S, class T, class U, int VEC>
+__global__ __launch_bounds__(kBlock) void k_offset_bwd(const S* __restrict__ nx, const S* __restrict__ ny,
+                                                       const S* __restrict__ nz, const S* __restrict__ V0,
+                                                       const S* __restrict__ gd, S* __restrict__ gnx,
+                                                       S* __restrict__ gny, S* __restrict__ gnz,
+                                                       S* __restrict__ gV0, int64_t count) {
+    const int64_t i = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) * VEC;
+    if (i + VEC <= count) {
+        S a[VEC], b[VEC], c[VEC], v[VEC], g[VEC], ox[VEC], oy[VEC], oz[VEC], ov[VEC];
+        load<S, VEC>(nx, i, a); load<S, VEC>(ny, i, b); load<S, VEC>(nz, i, c);
+        load<S, VEC>(V0, i, v); load<S, VEC>(gd, i, g);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+            T x, y, z, w;
+            backward1<SOLVER, T, U>(T(a[k]), T(b[k]), T(c[k]), T(v[k]), T(g[k]), x, y, z, w);
+            ox[k] = S(x); oy[k] = S(y); oz[k] = S(z); ov[k] = S(w);
+        }
+        store<S, VEC>(gnx, i, ox); store<S, VEC>(gny, i, oy); store<S, VEC>(gnz, i, oz);
+        store<S, VEC>(gV0, i, ov);
+    } else {
+        for (int64_t j = i; j < count; ++j) {
+            T x, y, z, w;
+            backward1<SOLVER, T, U>(T(nx[j]), T(ny[j]), T(nz[j]), T(V0[j]), T(gd[j]), x, y, z, w);
+            gnx[j] = S(x); gny[j] = S(y); gnz[j] = S(z); gV0[j] = S(w);
+        }
+    }
+}
+
+inline unsigned grid_for(int64_t count, int vec) {
+    const int64_t per = static_cast<int64_t>(kBlock) * vec;
+    return static_cast<unsigned>((count + per - 1) / per);
+}
+
+template <class S> constexpr int kVec = 16 / sizeof(S);
+
+// ---- dispatch ------------------------------------------------------------------
+template <int SOLVER, class S, class T, class U>
+void launch_offset_t(const S* nx, const S* ny, const S* nz, const S* V0, S* d0, int64_t count,
+                     bool vec, hipStream_t st) {
+    if (vec) {
+        hipLaunchKernelGGL((k_offset<SOLVER, S, T, U, kVec<S>>), dim3(grid_for(count, kVec<S>)),
+                           dim3(kBlock), 0, st, nx, ny, nz, V0, d0, count);
+    } else {
+        hipLaunchKernelGGL((k_offset<SOLVER, S, T, U, 1>), dim3(grid_for(count, 1)), dim3(kBlock), 0,
+                           st, nx, ny, nz, V0, d0, count);
+    }
+}
+
+template <class S, class T, class U>
+void launch_offset_s(int solver, const S* nx, const S* ny, const S* nz, const S* V0, S* d0,
+                     int64_t count, bool vec, hipStream_t st) {
+    switch (solver) {
+        case kSZ: launch_offset_t<kSZ, S, T, U>(nx, ny, nz, V0, d0, count, vec, st); break;
+        case kNewton: launch_offset_t<kNewton, S, T, U>(nx, ny, nz, V0, d0, count, vec, st); break;
+        case kNested: launch_offset_t<kNested, S, T, U>(nx, ny, nz, V0, d0, count, vec, st); break;
+        default: launch_offset_t<kAnalytic, S, T, U>(nx, ny, nz, V0, d0, count, vec, st); break;
+    }
+}
+
+template <int SOLVER, class S, class T, class U>
+void launch_bwd_t(const S* nx, const S* ny, const S* nz, const S* V0, const S* gd, S* gx, S* gy,
+                  S* gz, S* gv, int64_t count, bool vec, hipStream_t st) {
+    if (vec) {
+        hipLaunchKernelGGL((k_offset_bwd<SOLVER, S, T, U, kVec<S>>), dim3(grid_for(count, kVec<S>)),
+                           dim3(kBlock), 0, st, nx, ny, nz, V0, gd, gx, gy, gz, gv, count);
+    } else {
+        hipLaunchKernelGGL((k_offset_bwd<SOLVER, S, T, U, 1>), dim3(grid_for(count, 1)),
+                           dim3(kBlock), 0, st, nx, ny, nz, V0, gd, gx, gy, gz, gv, count);
+    }
+}
+
+template <class S, class T, class U>
+void launch_bwd_s(int solver, const S* nx, const S* ny, const S* nz, const S* V0, const S* gd, S* gx,
+                  S* gy, S* gz, S* gv, int64_t count, bool vec, hipStream_t st) {
+    switch (solver) {
+        case kSZ: launch_bwd_t<kSZ, S, T, U>(nx, ny, nz, V0, gd, gx, gy, gz, gv, count, vec, st); break;
+        case kNewton: launch_bwd_t<kNewton, S, T, U>(nx, ny, nz, V0, gd, gx, gy, gz, gv, count, vec, st); break;
+        case kNested: launch_bwd_t<kNested, S, T, U>(nx, ny, nz, V0, gd, gx, gy, gz, gv, count, vec, st); break;
+        default: launch_bwd_t<kAnalytic, S, T, U>(nx, ny, nz, V0, gd, gx, gy, gz, gv, count, vec, st); break;
+    }
+}
+
+template <class S>
+bool all_aligned16(std::initializer_list<const void*> ps) {
+    for (const void* p : ps)
+        if (!aligned(p, 16)) return false;
+    return true;
+}
+
+}  // namespace
+}  // namespace plic
+
+using namespace plic;
+
+extern "C" {
+
+int plic_offset_f32(const float* nx, const float* ny, const float* nz, const float* V0, float* d0,
+                    int64_t count, int solver, int precision, void* stream) {
+    if (count < 0 || !valid_solver(solver) || !valid_precision(precision)) return PLIC_EINVAL;
+    if (!valid_array(nx, count) || !valid_array(ny, count) || !valid_array(nz, count) ||
+        !valid_array(V0, count) || !valid_array(d0, count))
+        return PLIC_EINVAL;
+    const size_t nb = static_cast<size_t>(count) * sizeof(float);
+    if ((overlap(d0, nb, nx, nb) || overlap(d0, nb, ny, nb) || overlap(d0, nb, nz, nb) ||
+         overlap(d0, nb, V0, nb)) && d0 != V0)
+        return PLIC_EINVAL;
+    if (count == 0) return PLIC_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool vec = all_aligned16<float>({nx, ny, nz, V0, d0});
+    if (precision == PLIC_FP32) launch_offset_s<float, float, float>(solver, nx, ny, nz, V0, d0, count, vec, st);
+    else if (precision == PLIC_MIXED) launch_offset_s<float, float, double>(solver, nx, ny, nz, V0, d0, count, vec, st);
+    else launch_offset_s<float, double, double>(solver, nx, ny, nz, V0, d0, count, vec, st);
+    return launch_status();
+}
+
+int plic_offset_f64(const double* nx, const double* ny, const double* nz, const double* V0, double* d0,
+                    int64_t count, int solver, void* stream) {
+    if (count < 0 || !valid_solver(solver)) return PLIC_EINVAL;
+    if (!valid_array(nx, count) || !valid_array(ny, count) || !valid_array(nz, count) ||
+        !valid_array(V0, count) || !valid_array(d0, count))
+        return PLIC_EINVAL;
+    const size_t nb = static_cast<size_t>(count) * sizeof(double);
+    if ((overlap(d0, nb, nx, nb) || overlap(d0, nb, ny, nb) || overlap(d0, nb, nz, nb) ||
+         overlap(d0, nb, V0, nb)) && d0 != V0)
+        return PLIC_EINVAL;
+    if (count == 0) return PLIC_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool vec = all_aligned16<double>({nx, ny, nz, V0, d0});
+    launch_offset_s<double, double, double>(solver, nx, ny, nz, V0, d0, count, vec, st);
+    return launch_status();
+}
+
+int plic_volume_f32(const float* nx, const float* ny, const float* nz, const float* d0, float* V0,
+                    int64_t count, int precision, void* stream) {
+    if (count < 0 || !valid_precision(precision)) return PLIC_EINVAL;
+    if (!valid_array(nx, count) || !valid_array(ny, count) || !valid_array(nz, count) ||
+        !valid_array(d0, count) || !valid_array(V0, count))
+        return PLIC_EINVAL;
+    const size_t nb = static_cast<size_t>(count) * sizeof(float);
+    if ((overlap(V0, nb, nx, nb) || overlap(V0, nb, ny, nb) || overlap(V0, nb, nz, nb) ||
+         overlap(V0, nb, d0, nb)) && V0 != d0)
+        return PLIC_EINVAL;
+    if (count == 0) return PLIC_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool vec = all_aligned16<float>({nx, ny, nz, d0, V0});
+    if (precision == PLIC_FP64) {
+        if (vec) hipLaunchKernelGGL((k_volume<float, double, 4>), dim3(grid_for(count, 4)), dim3(kBlock), 0, st, nx, ny, nz, d0, V0, count);
+        else hipLaunchKernelGGL((k_volume<float, double, 1>), dim3(grid_for(count, 1)), dim3(kBlock), 0, st, nx, ny, nz, d0, V0, count);
+    } else {
+        if (vec) hipLaunchKernelGGL((k_volume<float, float, 4>), dim3(grid_for(count, 4)), dim3(kBlock), 0, st, nx, ny, nz, d0, V0, count);
+        else hipLaunchKernelGGL((k_volume<float, float, 1>), dim3(grid_for(count, 1)), dim3(kBlock), 0, st, nx, ny, nz, d0, V0, count);
+    }
+    return launch_status();
+}
+
+int plic_volume_f64(const double* nx, const double* ny, const double* nz, const double* d0, double* V0,
+                    int64_t count, void* stream) {
+    if (count < 0) return PLIC_EINVAL;
+    if (!valid_array(nx, count) || !valid_array(ny, count) || !valid_array(nz, count) ||
+        !valid_array(d0, count) || !valid_array(V0, count))
+        return PLIC_EINVAL;
+    const size_t nb = static_cast<size_t>(count) * sizeof(double);
+    if ((overlap(V0, nb, nx, nb) || overlap(V0, nb, ny, nb) || overlap(V0, nb, nz, nb) ||
+         overlap(V0, nb, d0, nb)) && V0 != d0)
+        return PLIC_EINVAL;
+    if (count == 0) return PLIC_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (all_aligned16<double>({nx, ny, nz, d0, V0}))
+        hipLaunchKernelGGL((k_volume<double, double, 2>), dim3(grid_for(count, 2)), dim3(kBlock), 0, st, nx, ny, nz, d0, V0, count);
+    else
+        hipLaunchKernelGGL((k_volume<double, double, 1>), dim3(grid_for(count, 1)), dim3(kBlock), 0, st, nx, ny, nz, d0, V0, count);
+    return launch_status();
+}
+
+int plic_offset_backward_f32(const float* nx, const float* ny, const float* nz, const float* V0,
+                             const float* grad_d0, float* grad_nx, float* grad_ny, float* grad_nz,
+                             float* grad_V0, int64_t count, int solver, int precision, void* stream) {
+    if (count < 0 || !valid_solver(solver) || !valid_precision(precision)) return PLIC_EINVAL;
+    const float* ins[5] = {nx, ny, nz, V0, grad_d0};
+    float* outs[4] = {grad_nx, grad_ny, grad_nz, grad_V0};
+    for (const float* p : ins) if (!valid_array(p, count)) return PLIC_EINVAL;
+    for (float* p : outs) if (!valid_array(p, count)) return PLIC_EINVAL;
+    const size_t nb = static_cast<size_t>(count) * sizeof(float);
+    for (int a = 0; a < 4; ++a) {
+        for (const float* p : ins) if (overlap(outs[a], nb, p, nb)) return PLIC_EINVAL;
+        for (int b = a + 1; b < 4; ++b) if (overlap(outs[a], nb, outs[b], nb)) return PLIC_EINVAL;
+    }
+    if (count == 0) return PLIC_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool vec = all_aligned16<float>({nx, ny, nz, V0, grad_d0, grad_nx, grad_ny, grad_nz, grad_V0});
+    if (precision == PLIC_FP32)
+        launch_bwd_s<float, float, float>(solver, nx, ny, nz, V0, grad_d0, grad_nx, grad_ny, grad_nz, grad_V0, count, vec, st);
+    else if (precision == PLIC_MIXED)
+        launch_bwd_s<float, float, double>(solver, nx, ny, nz, V0, grad_d0, grad_nx, grad_ny, grad_nz, grad_V0, count, vec, st);
+    else
+        launch_bwd_s<float, double, double>(solver, nx, ny, nz, V0, grad_d0, grad_nx, grad_ny, grad_nz, grad_V0, count, vec, st);
+    return launch_status();
+}
+
+int plic_offset_backward_f64(const double* nx, const double* ny, const double* nz, const double* V0,
+                             const double* grad_d0, double* grad_nx, double* grad_ny, double* grad_nz,
+                             double* grad_V0, int64_t count, int solver, void* stream) {
+    if (count < 0 || !valid_solver(solver)) return PLIC_EINVAL;
+    const double* ins[5] = {nx, ny, nz, V0, grad_d0};
+    double* outs[4] = {grad_nx, grad_ny, grad_nz, grad_V0};
+    for (const double* p : ins) if (!valid_array(p, count)) return PLIC_EINVAL;
+    for (double* p : outs) if (!valid_array(p, count)) return PLIC_EINVAL;
+    const size_t nb = static_cast<size_t>(count) * sizeof(double);
+    for (int a = 0; a < 4; ++a) {
+        for (const double* p : ins) if (overlap(outs[a], nb, p, nb)) return PLIC_EINVAL;
+        for (int b = a + 1; b < 4; ++b) if (overlap(outs[a], nb, outs[b], nb)) return PLIC_EINVAL;
+    }
+    if (count == 0) return PLIC_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool vec = all_aligned16<double>({nx, ny, nz, V0, grad_d0, grad_nx, grad_ny, grad_nz, grad_V0});
+    launch_bwd_s<double, double, double>(solver, nx, ny, nz, V0, grad_d0, grad_nx, grad_ny, grad_nz, grad_V0, count, vec, st);
+    return launch_status();
+}
+
+}  // extern "C"

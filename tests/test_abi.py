@@ -1,0 +1,120 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/plic.h, and rejects invalid arguments before touching the
+HIP runtime (null / misaligned / overlapping pointers, negative sizes, unknown
+enums); empty inputs succeed without any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "plic.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(plic_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2006_12838_amd._lib as L
+    return L
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("plic_offset_f32", "plic_offset_f64", "plic_volume_f32", "plic_volume_f64",
+                     "plic_offset_backward_f32", "plic_offset_backward_f64", "plic_curvature_f32",
+                     "plic_curvature_backward_f32", "plic_status_string", "plic_version"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    so = ctypes.CDLL(lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(so, name), name
+    assert set(declared_functions()) == set(lib.EXPORTED)
+
+
+def test_status_and_version(lib):
+    assert "gfx950" in lib.plic_version()
+    assert lib.plic_status_string(0).startswith("PLIC_OK")
+    assert lib.plic_status_string(-1).startswith("PLIC_EINVAL")
+    assert lib.plic_status_string(-2).startswith("PLIC_EHIP")
+    assert lib.plic_status_string(12345) == "unknown PLIC status"
+    assert lib.plic_last_hip_error() == 0
+
+
+A = 0x10000      # fake, 16-byte aligned device addresses: never dereferenced,
+B = 0x20000      # every call below is rejected (or is empty) before any HIP call
+C = 0x30000
+D = 0x40000
+E = 0x50000
+
+
+def test_offset_validation(lib):
+    f = lib.raw("plic_offset_f32")
+    assert f(A, B, C, D, E, 0, 0, 0, None) == 0                       # empty: OK
+    assert f(None, None, None, None, None, 0, 0, 0, None) == 0        # empty, null: OK
+    assert f(A, B, C, D, E, -1, 0, 0, None) == -1                     # negative count
+    assert f(None, B, C, D, E, 8, 0, 0, None) == -1                   # null input
+    assert f(A, B, C, D, None, 8, 0, 0, None) == -1                   # null output
+    assert f(A + 2, B, C, D, E, 8, 0, 0, None) == -1                  # misaligned
+    assert f(A, B, C, D, E, 8, 4, 0, None) == -1                      # bad solver
+    assert f(A, B, C, D, E, 8, -1, 0, None) == -1
+    assert f(A, B, C, D, E, 8, 0, 3, None) == -1                      # bad precision
+    assert f(A, B, C, D, A + 4, 8, 0, 0, None) == -1                  # d0 overlaps nx
+    g = lib.raw("plic_offset_f64")
+    assert g(A, B, C, D, E, 0, 0, None) == 0
+    assert g(A + 4, B, C, D, E, 8, 0, None) == -1                     # 8-byte alignment
+    assert g(A, B, C, D, E, 8, 7, None) == -1
+
+
+def test_volume_validation(lib):
+    f = lib.raw("plic_volume_f32")
+    assert f(A, B, C, D, E, 0, 0, None) == 0
+    assert f(A, B, C, D, E, -5, 0, None) == -1
+    assert f(A, B, C, D, E, 8, 9, None) == -1
+    assert f(A, B, C, D, B, 8, 0, None) == -1                         # V0 overlaps ny
+    g = lib.raw("plic_volume_f64")
+    assert g(A, B, C, D, E, 0, None) == 0
+    assert g(A, B, None, D, E, 8, None) == -1
+
+
+def test_backward_validation(lib):
+    f = lib.raw("plic_offset_backward_f32")
+    F, G, H, I = 0x60000, 0x70000, 0x80000, 0x90000
+    assert f(A, B, C, D, E, F, G, H, I, 0, 0, 0, None) == 0
+    assert f(A, B, C, D, E, F, G, H, I, -1, 0, 0, None) == -1
+    assert f(A, B, C, D, E, F, F, H, I, 8, 0, 0, None) == -1         # outputs alias
+    assert f(A, B, C, D, E, A, G, H, I, 8, 0, 0, None) == -1         # output aliases input
+    assert f(A, B, C, D, E, F, G, H, I, 8, 0, 5, None) == -1
+    g = lib.raw("plic_offset_backward_f64")
+    assert g(A, B, C, D, E, F, G, H, I, 0, 0, None) == 0
+    assert g(A, B, C, D, None, F, G, H, I, 8, 0, None) == -1
+
+
+def test_curvature_validation(lib):
+    f = lib.raw("plic_curvature_f32")
+    assert f(A, 0, 5, 5, B, 0, 1, None) == 0                          # empty lattice
+    assert f(A, -1, 5, 5, B, 0, 1, None) == -1
+    assert f(None, 4, 4, 4, B, 0, 1, None) == -1
+    assert f(A, 4, 4, 4, A + 64, 0, 1, None) == -1                    # kappa overlaps phi
+    assert f(A, 4, 4, 4, B, 9, 1, None) == -1
+    assert f(A, 4, 4, 4, B, 0, 7, None) == -1
+    assert f(A, 1 << 40, 1 << 40, 4, B, 0, 1, None) == -1             # size overflow
+    g = lib.raw("plic_curvature_backward_f32")
+    assert g(A, 3, 3, 0, B, C, 0, 1, None) == 0
+    assert g(A, 3, 3, 3, B, A, 0, 1, None) == -1                      # grad_phi overlaps phi
+    assert g(A, 3, 3, 3, B, B + 4, 0, 1, None) == -1                  # grad_phi overlaps grad_kappa
+    assert g(A, 3, 3, 3, None, C, 0, 1, None) == -1
+
+
+def test_python_layer_rejects_cpu_tensors(lib):
+    import torch
+    x = torch.zeros(8)
+    with pytest.raises(ValueError):
+        lib.plic_offset_f32(x, x, x, x, x)

@@ -1,0 +1,150 @@
+"""GPU backward of plic_curvature (neighbourhood recomputation, deterministic
+gather) against the oracle's FP64 finite-difference gradient and against
+central differences of the GPU forward."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from tests.gpu_util import PRECISIONS, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2006_12838_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def case(orc):
+    """Perturbed sphere (l <= 6 harmonics, 5 % amplitude), upstream gradient
+    N(0,1) on interface cells whose fit is well conditioned and whose finite
+    differences stay inside (0,1) and keep the fit's parameter set."""
+    phi, c, _ = workloads.perturbed_sphere_lattice(N=36, R=11.0, seed=2, ss=4)
+    kref, flags = orc.curvature(phi, flags=True)
+    cells = np.flatnonzero(flags & 1)
+    _, info = orc.curvature_cells(phi, cells)
+    ok = (info[:, 0] >= 5) & (info[:, 2] <= 1e4)
+    _, bad = orc.curvature_grad(phi, np.ones_like(phi), h=1e-6)
+    gk = np.zeros(phi.size, np.float32)
+    rng = np.random.default_rng(3)
+    sel = cells[ok & ~bad.ravel()[cells]]
+    gk[sel] = rng.standard_normal(sel.size).astype(np.float32)
+    gk = gk.reshape(phi.shape)
+    gref, _ = orc.curvature_grad(phi, gk, h=1e-6)
+    return phi, gk, gref, sel
+
+
+def gpu_grad(P, phi, gk, solver="analytic", precision="mixed"):
+    tp, tg = dev(phi, gk)
+    out = torch.empty_like(tp)
+    P.plic_curvature_backward_f32(tp, tg, out, solver, precision)
+    return host(out)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_backward_matches_oracle(P, case, precision):
+    phi, gk, gref, sel = case
+    g = gpu_grad(P, phi, gk, "analytic", precision).astype(np.float64)
+    scale = np.abs(gref).max()
+    err = np.abs(g - gref).max() / scale
+    print(f"{precision}: {sel.size} cells, max |g - g_ref| / max|g_ref| = {err:.3e}")
+    tol = {"fp32": 2e-3, "mixed": 2e-3, "fp64": 1e-6}[precision]
+    assert err <= tol
+    # away from the interface band the gradient is exactly zero
+    band = np.zeros(phi.shape, bool)
+    iface = (phi > 0) & (phi < 1)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                band |= np.roll(iface, (dz, dy, dx), (0, 1, 2))
+    assert np.all(g[~band] == 0.0)
+
+
+@pytest.mark.parametrize("solver", ["sz", "newton", "nested"])
+def test_backward_other_solvers(P, case, solver):
+    phi, gk, gref, _ = case
+    g = gpu_grad(P, phi, gk, solver, "mixed").astype(np.float64)
+    assert np.abs(g - gref).max() / np.abs(gref).max() <= 2e-3
+
+
+def test_backward_against_gpu_finite_differences(P, case):
+    """d/dphi_j of sum(gk * kappa) by central differences (h = 1e-4) of the
+    GPU forward in FP64, for interface cells j (the mask stays fixed)."""
+    phi, gk, _, sel = case
+    g = gpu_grad(P, phi, gk, "analytic", "fp64").astype(np.float64)
+    rng = np.random.default_rng(4)
+    h = 1e-4
+    cand = np.flatnonzero(((phi > 2 * h) & (phi < 1 - 2 * h)).ravel())
+    js = rng.choice(cand, 40, replace=False)
+    tp = dev(phi)
+    tg = dev(gk).double()
+    k = torch.empty_like(tp)
+    worst = 0.0
+    for j in js:
+        vals = []
+        for s in (+1, -1):
+            t = tp.clone().view(-1)
+            t[j] += s * h
+            P.plic_curvature_f32(t.view(phi.shape), k, "analytic", "fp64")
+            vals.append((k.double() * tg).sum().item())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        worst = max(worst, abs(fd - g.ravel()[j]) / max(1.0, abs(g.ravel()[j])))
+    print(f"GPU FD check: worst relative error {worst:.3e}")
+    assert worst <= 2e-3
+
+
+def test_backward_determinism_and_zero(P, case):
+    phi, gk, _, _ = case
+    a = gpu_grad(P, phi, gk)
+    b = gpu_grad(P, phi, gk)
+    assert np.array_equal(a, b)
+    z = gpu_grad(P, phi, np.zeros_like(gk))
+    assert np.all(z == 0.0)
+
+
+def test_autograd_function(P, case):
+    phi, gk, gref, _ = case
+    t = dev(phi).requires_grad_(True)
+    k = P.curvature(t, "analytic", "mixed")
+    (k * dev(gk)).sum().backward()
+    g = host(t.grad).astype(np.float64)
+    assert np.abs(g - gref).max() / np.abs(gref).max() <= 2e-3
+
+
+def test_full_size_backward_runs(P, orc):
+    """Perturbed sphere R = 50 on 192^3 (the differentiation workload): the
+    backward against the oracle on a sample of interface cells' neighbourhoods."""
+    phi, _, _ = workloads.perturbed_sphere_lattice(N=192, R=50.0, seed=0)
+    kref, flags = orc.curvature(phi, flags=True)
+    cells = np.flatnonzero(flags & 1)
+    _, info = orc.curvature_cells(phi, cells)
+    ok = cells[(info[:, 0] >= 5) & (info[:, 2] <= 1e4)]
+    rng = np.random.default_rng(7)
+    # isolated upstream cells (pairwise more than 2 cells apart) so that each
+    # checked neighbourhood sees one source
+    pick = rng.choice(ok, 400, replace=False)
+    Z, Y, X = phi.shape
+    coords = np.stack([pick % X, (pick // X) % Y, pick // (X * Y)], 1)
+    keep = []
+    for i, c in enumerate(coords):
+        if all(np.abs(c - coords[j]).max() > 2 for j in keep):
+            keep.append(i)
+    pick = pick[keep][:60]
+    gk = np.zeros(phi.size, np.float32)
+    gk[pick] = 1.0
+    gk = gk.reshape(phi.shape)
+    g = gpu_grad(P, phi, gk).astype(np.float64)
+    worst = 0.0
+    for c in pick:
+        x, y, z = c % X, (c // X) % Y, c // (X * Y)
+        nb = phi[z - 1:z + 2, y - 1:y + 2, x - 1:x + 2].astype(np.float64).ravel()
+        ref, bad = orc.curv_cell_fd_grad(nb, h=1e-6)
+        if bad:
+            continue
+        got = g[z - 1:z + 2, y - 1:y + 2, x - 1:x + 2].ravel()
+        worst = max(worst, np.abs(got - ref).max() / max(1.0, np.abs(ref).max()))
+    print(f"192^3 sampled backward: worst {worst:.3e}")
+    assert worst <= 2e-3

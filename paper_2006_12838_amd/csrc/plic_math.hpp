@@ -409,10 +409,11 @@ __device__ __forceinline__ T offset_grad_from_d0(T nx, T ny, T nz, T V0, T d0, T
     }
     // selects, not an indexed array (which would live in scratch memory)
     auto pick = [&](int k) { return k == 0 ? z1 : (k == 1 ? z2 : z3); };
+    // x_k = sign(n_k) (z_rank(k) - 1/2), mirrored through the centre for V0 > 1/2
     const T mir = V0 > T(0.5) ? T(-1) : T(1);
-    g[0] = mir * __builtin_copysign(pick(rx) - T(0.5), nx);
-    g[1] = mir * __builtin_copysign(pick(ry) - T(0.5), ny);
-    g[2] = mir * __builtin_copysign(pick(rz) - T(0.5), nz);
+    g[0] = mir * __builtin_copysign(T(1), nx) * (pick(rx) - T(0.5));
+    g[1] = mir * __builtin_copysign(T(1), ny) * (pick(ry) - T(0.5));
+    g[2] = mir * __builtin_copysign(T(1), nz) * (pick(rz) - T(0.5));
     return Fu > T(0) ? m::rcp(Fu) : T(__builtin_inf());
 }
 

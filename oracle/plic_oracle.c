@@ -61,7 +61,10 @@ static void sort3_asc(double *a, double *b, double *c)
  * Five-case volume of Sec. 2.2 with the factor 1/(6 n1 n2 n3) divided through
  * analytically where it would otherwise cancel:
  *   case (1) u <  a1:                      u^3 / (6 a1 a2 a3)
- *   case (5) min(a1+a2, a3) <= u <= a3:    (u - (a1+a2)/2) / a3
+ *   case (5) a1+a2 <= u <= a3:             (u - (a1+a2)/2) / a3
+ * The printed case-(5) range min(a1+a2, a3) <= u <= a3 shrinks to the single
+ * point u = a3 when a3 < a1 + a2, where the case-(5) formula is not the volume
+ * (the general form below is); the range is therefore read as a1+a2 <= u <= a3.
  *   cases (2)-(4):  [u^3 - (u-a1)^3 - (u-a2)+^3 - (u-a3)+^3] / (6 a1 a2 a3)
  *                 = [3u(u-a1) + a1^2 - ((u-a2)+^3 + (u-a3)+^3)/a1] / (6 a2 a3)
  * (the case-(2) rewrite is the one the paper's inverse-PLIC listing uses).
@@ -74,7 +77,7 @@ double orc_reduced_volume(double a1, double a2, double a3, double u)
     if (a1 == 0.0)                                             /* 2D */
         return u <= a2 ? u * u / (2.0 * a2 * a3) : (u - 0.5 * a2) / a3;
     if (u < a1) return u * u * u / (6.0 * a1 * a2 * a3);       /* case (1) */
-    if (u >= fmin(a1 + a2, a3) && u <= a3)                     /* case (5) */
+    if (u >= a1 + a2 && u <= a3)                               /* case (5) */
         return (u - 0.5 * (a1 + a2)) / a3;
     {
         double p2 = u > a2 ? u - a2 : 0.0;

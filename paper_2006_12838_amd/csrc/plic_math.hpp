@@ -238,8 +238,9 @@ __device__ __forceinline__ void divided_volume(U n1, U n2, U n3, U d, U& g, U& g
 // for cases (3) and (4) together (start at the midpoint).  The printed fixed
 // step counts (7/4/4) do not converge for small V, so each iterate is
 // safeguarded (kept inside the shrinking bracket, bisecting when a step leaves
-// it) and iteration stops once |step| <= 1e-6 (FP32) / 1e-13 (FP64), at most
-// 40 steps.  V = 0 returns d = 0 directly.
+// it); iteration stops after a Newton step of |step| <= 1e-6 (FP32) / 1e-13
+// (FP64) or once the bracket is that narrow, at most 40 steps.  V = 0 returns
+// d = 0 directly.
 // ---------------------------------------------------------------------------
 template <class T, class U>
 __device__ __forceinline__ T solve_newton(T n1, T n2, T n3, T V) {
@@ -253,16 +254,20 @@ __device__ __forceinline__ T solve_newton(T n1, T n2, T n3, T V) {
     if (target < u1 * u1) { lo = U(0); hi = u1; }                      // case (1)
     else { lo = u2; hi = m::fmin(u1 + u2, U(0.5) * (u1 + u2 + u3)); }  // cases (3), (4)
     U x = U(0.5) * (lo + hi);
+    const U tol = U(M<T>::newton_tol);
     for (int it = 0; it < 40; ++it) {
         U g, gp;
         divided_volume(u1, u2, u3, x, g, gp);
         const U f = g - target;
         if (f < U(0)) lo = x; else hi = x;
         U xn = x - m::div(f, gp);
-        if (!(xn > lo && xn < hi)) xn = U(0.5) * (lo + hi);
+        const bool newton = xn > lo && xn < hi;
+        if (!newton) xn = U(0.5) * (lo + hi);   // safeguard: bisect
         const U step = m::fabs(xn - x);
         x = xn;
-        if (step <= U(M<T>::newton_tol)) break;
+        // a small Newton step bounds the error (quadratic convergence); a
+        // bisection step does not, so only the bracket width ends it then
+        if ((newton && step <= tol) || hi - lo <= tol) break;
     }
     return T(x);
 }
@@ -316,7 +321,9 @@ __device__ __forceinline__ T offset(T nx, T ny, T nz, T V0) {
 // Forward volume (Sec. 2.2, the inverse PLIC problem), case (5) tested first
 // as in the paper's inverse listing; cases (2)-(4) in the divided form (no
 // cancellation, no division by n1 in case (2)).  d0 outside [-S/2, S/2] gives
-// 0 or 1.
+// 0 or 1.  Case (5) is n1 + n2 <= d <= n3: the printed min(n1 + n2, n3) <= d
+// admits the single point d = n3 when n3 < n1 + n2, where the case-(5)
+// formula is wrong and the general form holds.
 // ---------------------------------------------------------------------------
 template <class T>
 __device__ __forceinline__ T volume(T nx, T ny, T nz, T d0) {
@@ -327,7 +334,7 @@ __device__ __forceinline__ T volume(T nx, T ny, T nz, T d0) {
     const T n12 = n1 + n2;
     const T d = m::fmax(T(0.5) * (n12 + n3) - m::fabs(d0), T(0));
     T V;
-    if (m::fmin(n12, n3) <= d && d <= n3) {
+    if (n12 <= d && d <= n3) {
         V = m::div(d - T(0.5) * n12, n3);                                // case (5)
     } else if (d < n1) {
         V = m::div(d * d * d, T(6) * n1 * n2 * n3);                       // case (1)
@@ -375,7 +382,7 @@ __device__ __forceinline__ T offset_grad_from_d0(T nx, T ny, T nz, T V0, T d0, T
     const T n2 = m::med3(ax, ay, az);
     const T u = m::fmax(T(0.5) * (n1 + n2 + n3) - m::fabs(d0), T(0));
     T z1, z2, z3, Fu;
-    if (m::fmin(n1 + n2, n3) <= u && u <= n3) {                          // case (5)
+    if (n1 + n2 <= u && u <= n3) {                                        // case (5)
         Fu = m::rcp(n3);
         z1 = T(0.5); z2 = T(0.5);
         z3 = m::div(u - T(0.5) * (n1 + n2), n3);

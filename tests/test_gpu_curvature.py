@@ -1,10 +1,16 @@
 """GPU parity of plic_curvature against the FP64 oracle, cell by cell.
 
-Tolerance per interface cell: |kappa - kappa_ref| <= 1e-5 + 1e-3 |kappa_ref|
-on cells with a well-conditioned fit (oracle pivot ratio <= 1e4 for the FP32
-fit, <= 1e6 for FP64 fits) and at least 5 points; the others (about 1 in 500
-on a sphere) are checked for finiteness only, their fit being decided by
-pivots near the rank threshold.  Non-interface and boundary cells are exactly 0.
+Tolerance per interface cell, on cells with a fit of 5 points or more whose
+pivot ratio (largest / smallest LDL^T pivot, the oracle's conditioning proxy)
+is at most 1e6:
+  * FP64 fit (precisions "mixed", "fp64"): |kappa - kappa_ref| <= 1e-5 + 1e-3 |kappa_ref|;
+    FP32 PLIC points carry errors of ~3e-7 in the heights, far below this;
+  * FP32 fit ("fp32"): the normal equations are solved in FP32, with an error
+    of about (pivot ratio) * 2^-23 relative to the coefficients, so the bound
+    is (1e-5 + 1e-3 |kappa_ref|) * max(1, pivot ratio / 25).
+The remaining cells (about 1 in 500 on a sphere) are checked for finiteness
+only: their fit is decided by pivots near the rank threshold.  Non-interface
+and boundary cells are exactly 0.
 """
 import numpy as np
 import pytest
@@ -33,11 +39,13 @@ def check_cells(orc, phi, k, precision, report=""):
     kref, flags = orc.curvature(phi, flags=True)
     cells = np.flatnonzero(flags & 1)
     _, info = orc.curvature_cells(phi, cells)
-    cond_max = 1e4 if precision == "fp32" else 1e6
-    good = (info[:, 0] >= 5) & (info[:, 2] <= cond_max)
+    good = (info[:, 0] >= 5) & (info[:, 2] <= 1e6)
     kr = kref.ravel()[cells]
     kg = k.ravel()[cells].astype(np.float64)
-    err = np.abs(kg - kr) / (1e-5 + 1e-3 * np.abs(kr))
+    tol = 1e-5 + 1e-3 * np.abs(kr)
+    if precision == "fp32":
+        tol *= np.maximum(1.0, info[:, 2] / 25.0)
+    err = np.abs(kg - kr) / tol
     print(f"{report}: {cells.size} interface cells, {int((~good).sum())} loose; "
           f"max err/tol {err[good].max() if good.any() else 0:.3f}")
     assert np.isfinite(kg).all()

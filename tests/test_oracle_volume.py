@@ -108,6 +108,25 @@ def test_volume_nan_and_zero_normal(orc):
     assert np.isnan(orc.volume1(0.0, 0.0, 1.0, np.nan))
 
 
+def test_volume_at_case_boundaries_exact(orc):
+    """At the case boundaries u in {a1, a2, a3, a1 + a2} (Sec. 2.2) the volume
+    must still equal the exact inclusion-exclusion value.  The printed range of
+    case (5), min(n1+n2, n3) <= d <= n3, is a single point d = n3 when
+    n3 < n1 + n2 and selects the wrong formula there."""
+    rng = np.random.default_rng(6)
+    worst = 0.0
+    for trial in range(300):
+        a = sorted(Fraction(int(rng.integers(1, 1 << 20)), 1 << 20) for _ in range(3))
+        S = sum(a)
+        for u in (a[0], a[1], a[2], a[0] + a[1]):
+            if u > S / 2:
+                continue
+            exact = float(exact_reduced_volume(a, u))
+            got = orc.volume1(float(a[0]), float(a[1]), float(a[2]), float(u - S / 2))
+            worst = max(worst, abs(got - exact))
+    assert worst <= 2e-15
+
+
 @pytest.mark.parametrize("a1", [1e-12, 1e-8, 1e-4])
 def test_reduced_volume_small_n1_is_stable(orc, a1):
     """The divided form has no cancellation when n1 -> 0: compare with the exact

@@ -1,0 +1,201 @@
+"""Throughput of the PLIC hot path on one MI355X.
+
+One step = one pass of the whole path over resident synthetic inputs:
+  * plic_offset forward on N = 2^26 problems with each of the four solvers
+    (analytic, optimized SZ, Newton-Raphson, nested intervals), FP32;
+  * plic_volume on the same problems (the round trip V0(n, d0(n, V0)));
+  * plic_offset backward (optimized SZ), upstream gradient N(0, 1);
+  * plic_curvature forward and backward on a 256^3 lattice holding a sphere of
+    radius 40 (8^3 supersampled fill levels), FP32 points with FP64 fit.
+Each kernel is bracketed by HIP events on the stream it runs on; the step time
+is taken around the whole step after a device synchronisation.
+
+Prints one JSON line: value = PLIC solves per second of step time, counting
+the 4 N forward solves and the N solves recomputed by the backward (5 N per
+step); per-kernel rates, the roofline of the dominant kernel and an oracle
+CPU baseline ride along.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+VALU_PEAK_TOPS = 39.3          # 256 CU x 64 lanes x 2.4 GHz, non-packed lane-ops / s (x1e12)
+METRIC = "PLIC solves/s + curvature cells/s at 1 GPU, fwd+bwd, err vs FP64 oracle"
+SOLVERS = ("analytic", "sz", "newton", "nested")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=26, help="log2 of the PLIC batch size")
+    ap.add_argument("--lattice", type=int, default=256)
+    ap.add_argument("--radius", type=float, default=40.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target duration of the oracle CPU baseline sample")
+    ap.add_argument("--only", default="", help="comma list of kernels to run (profiling aid)")
+    return ap.parse_args()
+
+
+def cpu_baseline(nx, ny, nz, V0, seconds):
+    """The oracle (bisection on the FP64 forward volume), timed on the host
+    cores on chunks of the same workload until `seconds` have passed."""
+    import numpy as np
+    import oracle
+
+    oracle.build(force=False)
+    chunk = 1 << 21
+    done, t0 = 0, time.perf_counter()
+    i = 0
+    while True:
+        s = slice(i * chunk, (i + 1) * chunk)
+        oracle.offset(nx[s], ny[s], nz[s], V0[s])
+        done += len(V0[s])
+        i = (i + 1) % max(1, len(V0) // chunk)
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": done / el, "unit": "PLIC solves/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{done} problems of the 2^{int(math.log2(len(V0)))} workload "
+                      f"(chunks of 2^21) through the FP64 oracle's bisection inverse, "
+                      f"{el:.1f} s, {oracle.num_threads()} OpenMP threads"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(the PLIC path has no cross-GPU step; sharding is described in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2006_12838_amd as P
+    import workloads
+
+    dev = torch.device("cuda:0")
+    N = 1 << args.log2n
+    t_gen = time.perf_counter()
+    nx, ny, nz, V0 = workloads.plic_problems(N, seed=0)
+    gd = workloads.upstream_grad(N, seed=1)
+    phi, _ = workloads.sphere_lattice(N=args.lattice, R=args.radius, seed=0)
+    gk = workloads.upstream_grad(phi.shape, seed=2)
+    print(f"bench: inputs generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+
+    tn = [torch.from_numpy(a).to(dev) for a in (nx, ny, nz, V0, gd)]
+    d0 = torch.empty_like(tn[3])
+    Vb = torch.empty_like(tn[3])
+    gout = [torch.empty_like(tn[3]) for _ in range(4)]
+    tphi = torch.from_numpy(phi).to(dev)
+    tgk = torch.from_numpy(gk).to(dev)
+    kap = torch.empty_like(tphi)
+    gphi = torch.empty_like(tphi)
+    cells = phi.size
+    n_iface = int(((phi > 0) & (phi < 1)).sum())
+
+    kernels = []  # (name, fn, units, unit_name, algorithmic bytes per unit)
+    for s in SOLVERS:
+        kernels.append((f"offset_{s}", (lambda s=s: P.plic_offset_f32(*tn[:4], d0, s, "fp32")),
+                        N, "solves", 20))
+    kernels.append(("volume", lambda: P.plic_volume_f32(tn[0], tn[1], tn[2], d0, Vb, "fp32"), N, "solves", 20))
+    kernels.append(("offset_backward_sz",
+                    lambda: P.plic_offset_backward_f32(*tn[:4], tn[4], *gout, "sz", "fp32"), N, "solves", 36))
+    kernels.append(("curvature_fwd", lambda: P.plic_curvature_f32(tphi, kap, "analytic", "mixed"),
+                    cells, "cells", 8))
+    kernels.append(("curvature_bwd",
+                    lambda: P.plic_curvature_backward_f32(tphi, tgk, gphi, "analytic", "mixed"),
+                    cells, "cells", 8))
+    if args.only:
+        keep = set(args.only.split(","))
+        kernels = [k for k in kernels if k[0] in keep]
+
+    stream = torch.cuda.current_stream(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in kernels]
+
+    def step(record):
+        for (name, fn, *_), (a, b) in zip(kernels, ev):
+            if record:
+                a.record(stream)
+            fn()
+            if record:
+                b.record(stream)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    per = {k[0]: 0.0 for k in kernels}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()   # events of this step are complete
+        for (name, *_), (a, b) in zip(kernels, ev):
+            per[name] += a.elapsed_time(b)
+        print(f"bench: step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+
+    rates = {}
+    for name, fn, units, uname, bpu in kernels:
+        ms = per[name] / args.steps
+        rates[name] = {"ms": round(ms, 4), "rate": units / (ms * 1e-3), "unit": f"{uname}/s",
+                       "GBps": units * bpu / (ms * 1e-3) / 1e9,
+                       "hbm_frac": units * bpu / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    solves = sum(N for k in kernels if k[0].startswith("offset_"))
+    value = solves / (ms_step * 1e-3)
+    dom = max(kernels, key=lambda k: per[k[0]])
+    dms = per[dom[0]] / args.steps
+    dgbs = dom[2] * dom[4] / (dms * 1e-3) / 1e9
+    roofline = {"kernel": dom[0], "bound": "hbm", "achieved": round(dgbs, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(dgbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_unit": dom[4], "units_per_launch": dom[2]}
+    fast = min((k for k in kernels if k[0].startswith("offset_") and k[0] != "offset_backward_sz"),
+               key=lambda k: per[k[0]], default=None)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "PLIC solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2^{args.log2n} plane-cube problems (unit Gaussian normals, uniform V0, "
+                               f"2% edge cases) x 4 solvers fwd + volume + SZ bwd; "
+                               f"{args.lattice}^3 sphere R={args.radius:g} curvature fwd+bwd",
+                   "problems": N, "lattice": [args.lattice] * 3, "interface_cells": n_iface,
+                   "precision": {"plic": "fp32", "curvature": "mixed (fp32 points, fp64 fit)"}},
+        "kernels": rates,
+        "curvature_cells_per_s": (cells / ((per.get("curvature_fwd", 0) + per.get("curvature_bwd", 0))
+                                           / args.steps * 1e-3)) if "curvature_fwd" in per else None,
+        "fastest_solver": None if fast is None else {"solver": fast[0][7:], "solves_per_s": rates[fast[0]]["rate"],
+                                                     "hbm_frac": rates[fast[0]]["hbm_frac"]},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(nx, ny, nz, V0, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

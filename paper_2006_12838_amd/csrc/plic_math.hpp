@@ -261,7 +261,9 @@ __device__ __forceinline__ T solve_newton(T n1, T n2, T n3, T V) {
         const U f = g - target;
         if (f < U(0)) lo = x; else hi = x;
         U xn = x - m::div(f, gp);
-        const bool newton = xn > lo && xn < hi;
+        // inclusive: at convergence the step vanishes and xn lands on the end
+        // of the bracket that x just became
+        const bool newton = xn >= lo && xn <= hi;
         if (!newton) xn = U(0.5) * (lo + hi);   // safeguard: bisect
         const U step = m::fabs(xn - x);
         x = xn;

@@ -105,6 +105,7 @@ def main():
     tgk = torch.from_numpy(gk).to(dev)
     kap = torch.empty_like(tphi)
     gphi = torch.empty_like(tphi)
+    ws = torch.empty(P.plic_curvature_workspace_bytes(*phi.shape[::-1]), dtype=torch.uint8, device=dev)
     cells = phi.size
     n_iface = int(((phi > 0) & (phi < 1)).sum())
 
@@ -115,10 +116,10 @@ def main():
     kernels.append(("volume", lambda: P.plic_volume_f32(tn[0], tn[1], tn[2], d0, Vb, "fp32"), N, "solves", 20))
     kernels.append(("offset_backward_sz",
                     lambda: P.plic_offset_backward_f32(*tn[:4], tn[4], *gout, "sz", "fp32"), N, "solves", 36))
-    kernels.append(("curvature_fwd", lambda: P.plic_curvature_f32(tphi, kap, "analytic", "mixed"),
+    kernels.append(("curvature_fwd", lambda: P.plic_curvature_f32(tphi, kap, "analytic", "mixed", ws),
                     cells, "cells", 8))
     kernels.append(("curvature_bwd",
-                    lambda: P.plic_curvature_backward_f32(tphi, tgk, gphi, "analytic", "mixed"),
+                    lambda: P.plic_curvature_backward_f32(tphi, tgk, gphi, "analytic", "mixed", ws),
                     cells, "cells", 8))
     if args.only:
         keep = set(args.only.split(","))

@@ -101,6 +101,15 @@ int plic_offset_backward_f64(const double *nx, const double *ny, const double *n
                              int solver, void *stream);
 
 /*
+ * plic_curvature_workspace_bytes — size of the device workspace that
+ * plic_curvature_f32 and plic_curvature_backward_f32 need for an X*Y*Z lattice:
+ * one 32-bit flag per 64x4x4 tile, rounded up to 256 bytes (16 KiB at 256^3).
+ * 0 for an empty or invalid lattice.  The workspace is caller-owned device
+ * memory; its contents need no initialisation and are scratch after the call.
+ */
+size_t plic_curvature_workspace_bytes(int64_t X, int64_t Y, int64_t Z);
+
+/*
  * plic_curvature_f32 — PLIC curvature of a VoF fill-level lattice (Sec. 5.1-5.2,
  * Appendix B): for every interface cell (0 < phi < 1) away from the outer
  * one-cell layer: Parker-Youngs normal from the 3x3x3 fill levels, local frame
@@ -109,17 +118,22 @@ int plic_offset_backward_f64(const double *nx, const double *ny, const double *n
  * curvature at the origin.
  *   phi   : X*Y*Z floats, x fastest (index (z*Y + y)*X + x, torch shape (Z,Y,X)).
  *   kappa : X*Y*Z floats, written everywhere; 0 on non-interface cells and on
- *           the outer layer.  Must not overlap phi.
+ *           the outer layer.  Must not overlap phi or the workspace.
  *   solver, precision : PLIC solver for the points; PLIC_FP32 fits in FP32,
  *           PLIC_MIXED fits in FP64 (FP32 points), PLIC_FP64 is FP64 throughout.
+ *   workspace, workspace_bytes : device scratch of at least
+ *           plic_curvature_workspace_bytes(X, Y, Z) bytes, 4-byte aligned, not
+ *           overlapping phi or kappa.  Calls that overlap in time must use
+ *           distinct workspaces.
  * Sign: kappa = +1/R for a fluid sphere of radius R (the normal points out of
  * the fluid); the paper's formula is negated for this.  Fits with fewer than 5
  * points use the leading parameters only (App. B.3); a pivot of the LDL^T
- * factorisation below 1e-10 of the largest diagonal entry drops its parameter.
- * X, Y, Z >= 1.  Deterministic.
+ * factorisation below 1e-10 (FP64 fit) / 1e-5 (FP32 fit) of the largest
+ * diagonal entry drops its parameter.  X, Y, Z >= 1.  Deterministic.
  */
 int plic_curvature_f32(const float *phi, int64_t X, int64_t Y, int64_t Z, float *kappa,
-                       int solver, int precision, void *stream);
+                       int solver, int precision, void *workspace, size_t workspace_bytes,
+                       void *stream);
 
 /*
  * plic_curvature_backward_f32 — vector-Jacobian product of plic_curvature:
@@ -128,11 +142,13 @@ int plic_curvature_f32(const float *phi, int64_t X, int64_t Y, int64_t Z, float 
  * forward call).  The interface mask, the case of each PLIC point and the set
  * of fit parameters are held fixed (they are piecewise constant in phi).
  * grad_phi is written everywhere (zero away from the interface band); it must
- * not overlap phi or grad_kappa.  Deterministic (fixed summation order).
+ * not overlap phi, grad_kappa or the workspace.  Workspace as for the forward
+ * call.  Deterministic (fixed summation order).
  */
 int plic_curvature_backward_f32(const float *phi, int64_t X, int64_t Y, int64_t Z,
                                 const float *grad_kappa, float *grad_phi, int solver,
-                                int precision, void *stream);
+                                int precision, void *workspace, size_t workspace_bytes,
+                                void *stream);
 
 /* human-readable status; never NULL */
 const char *plic_status_string(int status);

@@ -22,6 +22,7 @@ from ._lib import (  # noqa: F401  (re-exported: the C ABI by name)
     SOLVERS,
     plic_curvature_backward_f32,
     plic_curvature_f32,
+    plic_curvature_workspace_bytes,
     plic_last_hip_error,
     plic_offset_backward_f32,
     plic_offset_backward_f64,

@@ -19,7 +19,7 @@ PRECISIONS = {"fp32": 0, "mixed": 1, "fp64": 2}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
-                      "(or python -m paper_2006_12838_amd._build)")
+                      "(or python paper_2006_12838_amd/_build.py)")
 
 _lib = ctypes.CDLL(LIB_PATH)
 _vp, _i64, _int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
@@ -39,10 +39,14 @@ _c = {
     "plic_volume_f64": _sig("plic_volume_f64", [_vp] * 5 + [_i64, _vp]),
     "plic_offset_backward_f32": _sig("plic_offset_backward_f32", [_vp] * 9 + [_i64, _int, _int, _vp]),
     "plic_offset_backward_f64": _sig("plic_offset_backward_f64", [_vp] * 9 + [_i64, _int, _vp]),
-    "plic_curvature_f32": _sig("plic_curvature_f32", [_vp, _i64, _i64, _i64, _vp, _int, _int, _vp]),
+    "plic_curvature_f32": _sig("plic_curvature_f32",
+                               [_vp, _i64, _i64, _i64, _vp, _int, _int, _vp, ctypes.c_size_t, _vp]),
     "plic_curvature_backward_f32": _sig("plic_curvature_backward_f32",
-                                        [_vp, _i64, _i64, _i64, _vp, _vp, _int, _int, _vp]),
+                                        [_vp, _i64, _i64, _i64, _vp, _vp, _int, _int, _vp,
+                                         ctypes.c_size_t, _vp]),
 }
+_lib.plic_curvature_workspace_bytes.restype = ctypes.c_size_t
+_lib.plic_curvature_workspace_bytes.argtypes = [_i64, _i64, _i64]
 _lib.plic_status_string.restype = ctypes.c_char_p
 _lib.plic_status_string.argtypes = [_int]
 _lib.plic_version.restype = ctypes.c_char_p
@@ -50,7 +54,12 @@ _lib.plic_version.argtypes = []
 _lib.plic_last_hip_error.restype = ctypes.c_int
 _lib.plic_last_hip_error.argtypes = []
 
-EXPORTED = tuple(_c) + ("plic_status_string", "plic_version", "plic_last_hip_error")
+EXPORTED = tuple(_c) + ("plic_status_string", "plic_version", "plic_last_hip_error",
+                        "plic_curvature_workspace_bytes")
+
+
+def plic_curvature_workspace_bytes(X: int, Y: int, Z: int) -> int:
+    return int(_lib.plic_curvature_workspace_bytes(int(X), int(Y), int(Z)))
 
 
 def plic_status_string(status: int) -> str:
@@ -176,26 +185,44 @@ def _lattice_dims(phi):
     return X, Y, Z
 
 
-def plic_curvature_f32(phi, kappa, solver="analytic", precision="mixed"):
+def _workspace(phi, workspace, X, Y, Z):
+    need = plic_curvature_workspace_bytes(X, Y, Z)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=phi.device)
+    if not (workspace.is_cuda and workspace.is_contiguous() and workspace.dtype == torch.uint8):
+        raise ValueError("workspace must be a contiguous uint8 GPU tensor")
+    if workspace.numel() < need:
+        raise ValueError(f"workspace holds {workspace.numel()} bytes, {need} needed")
+    return workspace
+
+
+def plic_curvature_f32(phi, kappa, solver="analytic", precision="mixed", workspace=None):
+    """workspace: optional uint8 device tensor of plic_curvature_workspace_bytes
+    bytes (allocated through torch's caching allocator when omitted)."""
     X, Y, Z = _lattice_dims(phi)
     n = X * Y * Z
     _same_device(phi, kappa)
+    ws = _workspace(phi, workspace, X, Y, Z)
     _check(_c["plic_curvature_f32"](_ptr(phi, torch.float32, n, "phi"), X, Y, Z,
                                     _ptr(kappa, torch.float32, n, "kappa"),
                                     _enum(SOLVERS, solver, "solver"),
-                                    _enum(PRECISIONS, precision, "precision"), _stream(phi)),
+                                    _enum(PRECISIONS, precision, "precision"),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
            "plic_curvature_f32")
     return kappa
 
 
-def plic_curvature_backward_f32(phi, grad_kappa, grad_phi, solver="analytic", precision="mixed"):
+def plic_curvature_backward_f32(phi, grad_kappa, grad_phi, solver="analytic", precision="mixed",
+                                workspace=None):
     X, Y, Z = _lattice_dims(phi)
     n = X * Y * Z
     _same_device(phi, grad_kappa, grad_phi)
+    ws = _workspace(phi, workspace, X, Y, Z)
     _check(_c["plic_curvature_backward_f32"](_ptr(phi, torch.float32, n, "phi"), X, Y, Z,
                                              _ptr(grad_kappa, torch.float32, n, "grad_kappa"),
                                              _ptr(grad_phi, torch.float32, n, "grad_phi"),
                                              _enum(SOLVERS, solver, "solver"),
-                                             _enum(PRECISIONS, precision, "precision"), _stream(phi)),
+                                             _enum(PRECISIONS, precision, "precision"),
+                                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
            "plic_curvature_backward_f32")
     return grad_phi

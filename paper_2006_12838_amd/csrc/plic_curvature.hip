@@ -1,15 +1,21 @@
 // PLIC curvature of a VoF fill-level lattice on gfx950 (Sec. 5.1-5.2 and
 // Appendix B of Lehmann & Gekle, arXiv 2006.12838), forward and backward.
 //
-// Layout: phi, kappa, grad_kappa, grad_phi are X*Y*Z floats, x fastest.
-// Both kernels are fused tile kernels: a workgroup owns a 64x4x4 tile, stages
-// the tile plus a halo of fill levels in LDS, writes the zeros of every
-// non-interface cell, and computes the interface cells of the tile from LDS.
+// Layout: phi, kappa, grad_kappa, grad_phi are X*Y*Z floats, x fastest.  The
+// lattice is cut into 64x4x4 tiles.  Each call runs two kernels:
+//  1. a streaming scan over the whole lattice (float4 loads and stores, no LDS,
+//     low register use, full occupancy): writes the zero result everywhere and
+//     one flag per tile telling whether the tile holds an interface cell
+//     (0 < phi < 1, away from the outer layer).  Every flag is written, so the
+//     workspace needs no clearing.
+//  2. a persistent tile kernel over the flagged tiles (their neighbours too for
+//     the backward): stages the tile's fill levels plus a halo in LDS and
+//     computes each interface cell with a group of 32 lanes, lane j taking
+//     neighbour j of the 3x3x3 neighbourhood (lane 26 the centre).  The
+//     Parker-Youngs sum and the normal equations are butterfly reductions
+//     over the group, which give every lane the same bits.
 // The interface is one cell thick (about 0.2 % of a 256^3 sphere lattice), so
-// the kernels stream at HBM speed over the bulk and spend their arithmetic in
-// the few tiles the interface crosses.  Workgroups are mapped to tiles so that
-// each XCD (own L2) works on one contiguous slab and the halo re-reads of
-// neighbouring tiles hit in its L2.
+// the scan carries the HBM traffic and the tile kernel the arithmetic.
 #include <hip/hip_runtime.h>
 
 #include "plic_host.hpp"
@@ -20,18 +26,14 @@ namespace {
 
 constexpr int TX = 64, TY = 4, TZ = 4;       // tile
 constexpr int kTile = TX * TY * TZ;           // 1024 cells
-constexpr int kThreads = 256;                 // 4 wave64, 4 cells per thread
+constexpr int kThreads = 256;                 // 4 wave64
 constexpr int kCellsPerThread = kTile / kThreads;
+constexpr int kGroup = 32;                    // lanes per interface cell
+constexpr int kGroups = kThreads / kGroup;    // 8 cells in flight per workgroup
+constexpr int kPersistentBlocks = 2048;
 
 // fixed auxiliary vector r of Sec. 5.2 (non-collinear with the normal)
 constexpr double kR0 = 0.56270900, kR1 = 0.32704452, kR2 = 0.75921047;
-
-// Workgroup -> tile: XCD k (workgroups dispatched round-robin, b % 8) takes a
-// contiguous run of tiles; a ragged tail keeps the identity mapping.
-__device__ __forceinline__ int tile_of_block(int b, int nb) {
-    const int q = nb >> 3;
-    return b < (q << 3) ? (b & 7) * q + (b >> 3) : b;
-}
 
 // neighbour q = (dz+1)*9 + (dy+1)*3 + (dx+1); centre q = 13
 __host__ __device__ constexpr int q_dx(int q) { return q % 3 - 1; }
@@ -39,6 +41,18 @@ __host__ __device__ constexpr int q_dy(int q) { return (q / 3) % 3 - 1; }
 __host__ __device__ constexpr int q_dz(int q) { return q / 9 - 1; }
 
 __device__ __forceinline__ bool is_iface(float p) { return p > 0.0f && p < 1.0f; }
+
+template <class F>
+__device__ __forceinline__ F group_sum(F v) {
+#pragma unroll
+    for (int m = kGroup / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kGroup);
+    return v;
+}
+
+template <class F>
+__device__ __forceinline__ F group_bcast(F v, int src_in_group) {
+    return __shfl(v, src_in_group, kGroup);
+}
 
 // ---------------------------------------------------------------------------
 // LDL^T factorisation and solve of the symmetric 5x5 normal equations
@@ -92,104 +106,6 @@ __device__ __forceinline__ void ldlt_solve(const F (&m)[5][5], const bool (&act)
     }
 }
 
-// ---------------------------------------------------------------------------
-// Per-cell state of the forward computation, shared by both kernels.
-// s: LDS fill levels, c: centre index, sy/sz: LDS strides.
-// ---------------------------------------------------------------------------
-template <class T, class F>
-struct CellState {
-    T n[3], bx[3], by[3], r[3];
-    T ign, iun, D0;
-    unsigned mask;          // interface neighbours (bit q)
-    int npts;
-    F m[5][5];              // factorised normal equations
-    F a[5];                 // A, B, C, H, I
-    bool act[5];
-    bool valid;             // |g| large enough
-};
-
-template <int SOLVER, class T, class U, class F>
-__device__ __forceinline__ void cell_forward(const float* __restrict__ s, int c, int sy, int sz,
-                                             CellState<T, F>& st) {
-    using mt = M<T>;
-    // Parker-Youngs gradient (App. B.1): weights 4 / 2 / 1 for |e|^2 = 1 / 2 / 3
-    T gx = T(0), gy = T(0), gz = T(0);
-    unsigned mask = 0;
-#pragma unroll
-    for (int q = 0; q < 27; ++q) {
-        if (q == 13) continue;
-        constexpr int dummy = 0;
-        (void)dummy;
-        const int dx = q_dx(q), dy = q_dy(q), dz = q_dz(q);
-        const float p = s[c + dz * sz + dy * sy + dx];
-        const int e2 = dx * dx + dy * dy + dz * dz;
-        const T w = T(e2 == 1 ? 4 : (e2 == 2 ? 2 : 1)) * T(p);
-        gx += T(dx) * w;
-        gy += T(dy) * w;
-        gz += T(dz) * w;
-        mask |= is_iface(p) ? (1u << q) : 0u;
-    }
-    st.mask = mask;
-    for (int j = 0; j < 5; ++j) st.a[j] = F(0);
-    const T gn2 = gx * gx + gy * gy + gz * gz;
-    st.valid = gn2 >= T(1e-24);
-    if (!st.valid) { st.npts = 0; return; }
-    const T gn = mt::sqrt(gn2);
-    st.ign = mt::rcp(gn);
-    st.n[0] = -gx * st.ign; st.n[1] = -gy * st.ign; st.n[2] = -gz * st.ign;
-    // local frame (Sec. 5.2): b_z = n, b_y = n x r / |n x r|, b_x = b_y x b_z
-    st.r[0] = T(kR0); st.r[1] = T(kR1); st.r[2] = T(kR2);
-    T u0 = st.n[1] * st.r[2] - st.n[2] * st.r[1];
-    T u1 = st.n[2] * st.r[0] - st.n[0] * st.r[2];
-    T u2 = st.n[0] * st.r[1] - st.n[1] * st.r[0];
-    T un2 = u0 * u0 + u1 * u1 + u2 * u2;
-    if (un2 < T(1e-12)) {            // n parallel to r: use (r_y, r_z, r_x)
-        st.r[0] = T(kR1); st.r[1] = T(kR2); st.r[2] = T(kR0);
-        u0 = st.n[1] * st.r[2] - st.n[2] * st.r[1];
-        u1 = st.n[2] * st.r[0] - st.n[0] * st.r[2];
-        u2 = st.n[0] * st.r[1] - st.n[1] * st.r[0];
-        un2 = u0 * u0 + u1 * u1 + u2 * u2;
-    }
-    st.iun = mt::rcp(mt::sqrt(un2));
-    st.by[0] = u0 * st.iun; st.by[1] = u1 * st.iun; st.by[2] = u2 * st.iun;
-    st.bx[0] = st.by[1] * st.n[2] - st.by[2] * st.n[1];
-    st.bx[1] = st.by[2] * st.n[0] - st.by[0] * st.n[2];
-    st.bx[2] = st.by[0] * st.n[1] - st.by[1] * st.n[0];
-    // PLIC points (eq. of the coordinate transformation, Sec. 5.2), centre normal for all
-    st.D0 = offset<SOLVER, T, U>(st.n[0], st.n[1], st.n[2], T(s[c]));
-    F (&m)[5][5] = st.m;
-    F b[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        b[i] = F(0);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) m[i][j] = F(0);
-    }
-    int npts = 0;
-    unsigned mm = mask;
-    while (mm) {
-        const int q = __builtin_ctz(mm);
-        mm &= mm - 1u;
-        const int dx = q_dx(q), dy = q_dy(q), dz = q_dz(q);
-        const T D = offset<SOLVER, T, U>(st.n[0], st.n[1], st.n[2], T(s[c + dz * sz + dy * sy + dx]));
-        const T ex = T(dx), ey = T(dy), ez = T(dz);
-        const F x = F(ex * st.bx[0] + ey * st.bx[1] + ez * st.bx[2]);
-        const F y = F(ex * st.by[0] + ey * st.by[1] + ez * st.by[2]);
-        const F z = F(ex * st.n[0] + ey * st.n[1] + ez * st.n[2] + (D - st.D0));
-        const F Q[5] = {x * x, y * y, x * y, x, y};
-#pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            b[i] += z * Q[i];
-#pragma unroll
-            for (int j = 0; j <= i; ++j) m[i][j] += Q[i] * Q[j];
-        }
-        ++npts;
-    }
-    st.npts = npts;
-    ldlt_factor<F>(m, npts < 5 ? npts : 5, st.act);
-    ldlt_solve<F>(m, st.act, b, st.a);
-}
-
 // mean curvature of the paraboloid at the origin (App. B.2), negated so that a
 // fluid drop (normal pointing out of the fluid) is positive
 template <class F>
@@ -200,162 +116,249 @@ __device__ __forceinline__ F kappa_of(const F (&a)[5]) {
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint of one cell: out[q] = gk * d kappa / d phi_q for the 27 fill levels
-// of the neighbourhood (interface mask, active fit parameters and PLIC cases
-// held fixed).  Recomputes the forward state, then reverses: kappa -> fit
-// coefficients -> lambda = M^-1 abar -> points -> (PLIC offsets: dd/dV = 1/A,
-// dd/dn = polygon centroid) and (local frame) -> normal -> Parker-Youngs sums.
-// out must hold 27 floats owned by this thread.
+// One interface cell on a group of 32 lanes.  s: LDS fill levels, c: centre
+// index, sy/sz: LDS strides, j: lane in the group (0..31), gbase: lane index
+// of the group's lane 0 within the wave.  Every lane of the group must call
+// it.  Returns kappa (same value on every lane).  With ADJ, also writes
+// out[q] = gk * d kappa / d phi_q (q = 0..26) from the lanes that own q, with
+// the interface mask, PLIC cases and active fit parameters held fixed.
 // ---------------------------------------------------------------------------
-template <int SOLVER, class T, class U, class F>
-__device__ __forceinline__ void cell_adjoint(const float* __restrict__ s, int c, int sy, int sz, float gk,
-                                             float* out) {
-#pragma unroll
-    for (int q = 0; q < 27; ++q) out[q] = 0.0f;
-    CellState<T, F> st;
-    cell_forward<SOLVER, T, U, F>(s, c, sy, sz, st);
-    if (!st.valid || gk == 0.0f) return;
+template <int SOLVER, class T, class U, class F, bool ADJ>
+__device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, int sy, int sz, int j,
+                                            float gk, float* __restrict__ out) {
     using mt = M<T>;
-    // d kappa / d(A, B, C, H, I) with kappa = -(A(I^2+1) + B(H^2+1) - CHI) / W^(3/2)
-    const F A = st.a[0], B = st.a[1], C = st.a[2], H = st.a[3], I = st.a[4];
-    const F W = H * H + I * I + F(1);
-    const F iW32 = F(1) / (W * M<F>::sqrt(W));
-    const F num = A * (I * I + F(1)) + B * (H * H + F(1)) - C * H * I;
-    const F g = -F(gk);
-    F abar[5];
-    abar[0] = g * (I * I + F(1)) * iW32;
-    abar[1] = g * (H * H + F(1)) * iW32;
-    abar[2] = g * (-H * I) * iW32;
-    abar[3] = g * ((F(2) * B * H - C * I) * iW32 - F(3) * num * H * iW32 / W);
-    abar[4] = g * ((F(2) * A * I - C * H) * iW32 - F(3) * num * I * iW32 / W);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) abar[j] = st.act[j] ? abar[j] : F(0);
-    F lam[5];
-    ldlt_solve<F>(st.m, st.act, abar, lam);
-    // reverse over the points: zbar = lam.Q, Qbar = lam (z - a.Q) - a (lam.Q)
-    T bxb[3] = {T(0), T(0), T(0)}, byb[3] = {T(0), T(0), T(0)}, nb[3] = {T(0), T(0), T(0)};
-    T sumz = T(0);
-    unsigned mm = st.mask;
-    while (mm) {
-        const int q = __builtin_ctz(mm);
-        mm &= mm - 1u;
-        const int dx = q_dx(q), dy = q_dy(q), dz = q_dz(q);
-        const T phq = T(s[c + dz * sz + dy * sy + dx]);
-        const T D = offset<SOLVER, T, U>(st.n[0], st.n[1], st.n[2], phq);
-        T cq[3];
-        const T dv = offset_grad_from_d0<T>(st.n[0], st.n[1], st.n[2], phq, D, cq);
-        const T ex = T(dx), ey = T(dy), ez = T(dz);
-        const F x = F(ex * st.bx[0] + ey * st.bx[1] + ez * st.bx[2]);
-        const F y = F(ex * st.by[0] + ey * st.by[1] + ez * st.by[2]);
-        const F z = F(ex * st.n[0] + ey * st.n[1] + ez * st.n[2] + (D - st.D0));
-        const F Q[5] = {x * x, y * y, x * y, x, y};
-        F zb = F(0), aQ = F(0);
-#pragma unroll
-        for (int i = 0; i < 5; ++i) { zb += lam[i] * Q[i]; aQ += st.a[i] * Q[i]; }
-        F Qb[5];
-#pragma unroll
-        for (int i = 0; i < 5; ++i) Qb[i] = lam[i] * (z - aQ) - st.a[i] * zb;
-        const T xb = T(F(2) * x * Qb[0] + y * Qb[2] + Qb[3]);
-        const T yb = T(F(2) * y * Qb[1] + x * Qb[2] + Qb[4]);
-        const T zt = T(zb);
-        bxb[0] += xb * ex; bxb[1] += xb * ey; bxb[2] += xb * ez;
-        byb[0] += yb * ex; byb[1] += yb * ey; byb[2] += yb * ez;
-        nb[0] += zt * (ex + cq[0]); nb[1] += zt * (ey + cq[1]); nb[2] += zt * (ez + cq[2]);
-        out[q] += float(zt * dv);
-        sumz += zt;
+    const bool nbr = j < 26;                      // lane owns neighbour q
+    const bool centre = j == 26;                  // lane owns the centre
+    const int q = nbr ? (j < 13 ? j : j + 1) : 13;
+    const int dx = nbr ? q_dx(q) : 0, dy = nbr ? q_dy(q) : 0, dz = nbr ? q_dz(q) : 0;
+    const float p = (nbr || centre) ? s[c + dz * sz + dy * sy + dx] : 0.0f;
+    const T ex = T(dx), ey = T(dy), ez = T(dz);
+    const int e2 = dx * dx + dy * dy + dz * dz;
+    const T w = nbr ? T(e2 == 1 ? 4 : (e2 == 2 ? 2 : 1)) : T(0);
+    // Parker-Youngs gradient (App. B.1): weights 4 / 2 / 1 for |e|^2 = 1 / 2 / 3
+    const T gx = group_sum<T>(w * ex * T(p));
+    const T gy = group_sum<T>(w * ey * T(p));
+    const T gz = group_sum<T>(w * ez * T(p));
+    const bool iface = nbr && is_iface(p);
+    const unsigned long long bal = __ballot(iface);
+    const int npts = __popcll(bal & (0xffffffffull << (threadIdx.x & 32)));
+    const T gn2 = gx * gx + gy * gy + gz * gz;
+    if (!(gn2 >= T(1e-24))) {                     // no usable normal: kappa = 0
+        if constexpr (ADJ) {
+            if (nbr) out[q] = 0.0f;
+            if (centre) out[13] = 0.0f;
+        }
+        return 0.0f;
     }
-    {   // centre offset D0 enters every z with a minus sign
-        const T ph0 = T(s[c]);
-        T c0[3];
-        const T dv0 = offset_grad_from_d0<T>(st.n[0], st.n[1], st.n[2], ph0, st.D0, c0);
-        out[13] += float(-sumz * dv0);
-        nb[0] -= sumz * c0[0]; nb[1] -= sumz * c0[1]; nb[2] -= sumz * c0[2];
+    const T ign = mt::rcp(mt::sqrt(gn2));
+    const T n0 = -gx * ign, n1 = -gy * ign, n2 = -gz * ign;
+    // local frame (Sec. 5.2): b_z = n, b_y = n x r / |n x r|, b_x = b_y x b_z
+    T r0 = T(kR0), r1 = T(kR1), r2 = T(kR2);
+    T u0 = n1 * r2 - n2 * r1, u1 = n2 * r0 - n0 * r2, u2 = n0 * r1 - n1 * r0;
+    T un2 = u0 * u0 + u1 * u1 + u2 * u2;
+    if (un2 < T(1e-12)) {                         // n parallel to r: use (r_y, r_z, r_x)
+        r0 = T(kR1); r1 = T(kR2); r2 = T(kR0);
+        u0 = n1 * r2 - n2 * r1; u1 = n2 * r0 - n0 * r2; u2 = n0 * r1 - n1 * r0;
+        un2 = u0 * u0 + u1 * u1 + u2 * u2;
     }
-    // b_x = b_y x n
-    byb[0] += st.n[1] * bxb[2] - st.n[2] * bxb[1];
-    byb[1] += st.n[2] * bxb[0] - st.n[0] * bxb[2];
-    byb[2] += st.n[0] * bxb[1] - st.n[1] * bxb[0];
-    nb[0] += bxb[1] * st.by[2] - bxb[2] * st.by[1];
-    nb[1] += bxb[2] * st.by[0] - bxb[0] * st.by[2];
-    nb[2] += bxb[0] * st.by[1] - bxb[1] * st.by[0];
-    // b_y = u / |u|, u = n x r
-    const T bdot = st.by[0] * byb[0] + st.by[1] * byb[1] + st.by[2] * byb[2];
-    const T ub0 = (byb[0] - st.by[0] * bdot) * st.iun;
-    const T ub1 = (byb[1] - st.by[1] * bdot) * st.iun;
-    const T ub2 = (byb[2] - st.by[2] * bdot) * st.iun;
-    nb[0] += st.r[1] * ub2 - st.r[2] * ub1;
-    nb[1] += st.r[2] * ub0 - st.r[0] * ub2;
-    nb[2] += st.r[0] * ub1 - st.r[1] * ub0;
-    // n = -g / |g|
-    const T ndot = st.n[0] * nb[0] + st.n[1] * nb[1] + st.n[2] * nb[2];
-    const T gb0 = -(nb[0] - st.n[0] * ndot) * st.ign;
-    const T gb1 = -(nb[1] - st.n[1] * ndot) * st.ign;
-    const T gb2 = -(nb[2] - st.n[2] * ndot) * st.ign;
+    const T iun = mt::rcp(mt::sqrt(un2));
+    const T by0 = u0 * iun, by1 = u1 * iun, by2 = u2 * iun;
+    const T bx0 = by1 * n2 - by2 * n1, bx1 = by2 * n0 - by0 * n2, bx2 = by0 * n1 - by1 * n0;
+    // PLIC offsets: the neighbour lanes and the centre lane in parallel, all
+    // with the centre normal (Sec. 5.2)
+    T D = T(0);
+    if (iface || centre) D = offset<SOLVER, T, U>(n0, n1, n2, T(p));
+    const int gl = threadIdx.x & 32;              // lane 0 of this group in the wave
+    const T D0 = group_bcast<T>(D, 26);
+    // this lane's point (eq. of the coordinate transformation, Sec. 5.2)
+    F x = F(0), y = F(0), z = F(0);
+    if (iface) {
+        x = F(ex * bx0 + ey * bx1 + ez * bx2);
+        y = F(ex * by0 + ey * by1 + ez * by2);
+        z = F(ex * n0 + ey * n1 + ez * n2 + (D - D0));
+    }
+    const F Q[5] = {x * x, y * y, x * y, x, y};
+    F m[5][5], b[5];
 #pragma unroll
-    for (int q = 0; q < 27; ++q) {
-        if (q == 13) continue;
-        const int dx = q_dx(q), dy = q_dy(q), dz = q_dz(q);
-        const int e2 = dx * dx + dy * dy + dz * dz;
-        const T w = T(e2 == 1 ? 4 : (e2 == 2 ? 2 : 1));
-        out[q] += float(w * (T(dx) * gb0 + T(dy) * gb1 + T(dz) * gb2));
+    for (int i = 0; i < 5; ++i) {
+        b[i] = group_sum<F>(z * Q[i]);
+#pragma unroll
+        for (int k = 0; k <= i; ++k) m[i][k] = group_sum<F>(Q[i] * Q[k]);
     }
-    (void)mt::fabs(T(0));
+    bool act[5];
+    F a[5];
+    ldlt_factor<F>(m, npts < 5 ? npts : 5, act);
+    ldlt_solve<F>(m, act, b, a);
+    const float kappa = float(kappa_of<F>(a));
+    if constexpr (ADJ) {
+        // d kappa / d(A,B,C,H,I), kappa = -(A(I^2+1) + B(H^2+1) - CHI) / W^(3/2)
+        const F A = a[0], B = a[1], C = a[2], H = a[3], I = a[4];
+        const F W = H * H + I * I + F(1);
+        const F iW32 = F(1) / (W * M<F>::sqrt(W));
+        const F num = A * (I * I + F(1)) + B * (H * H + F(1)) - C * H * I;
+        const F g = -F(gk);
+        F abar[5];
+        abar[0] = g * (I * I + F(1)) * iW32;
+        abar[1] = g * (H * H + F(1)) * iW32;
+        abar[2] = g * (-H * I) * iW32;
+        abar[3] = g * ((F(2) * B * H - C * I) * iW32 - F(3) * num * H * iW32 / W);
+        abar[4] = g * ((F(2) * A * I - C * H) * iW32 - F(3) * num * I * iW32 / W);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) abar[i] = act[i] ? abar[i] : F(0);
+        F lam[5];
+        ldlt_solve<F>(m, act, abar, lam);          // M symmetric: lambda = M^-1 abar
+        // this lane's point: zbar = lam.Q, Qbar = lam (z - a.Q) - a (lam.Q)
+        T phib = T(0), bxb[3] = {T(0), T(0), T(0)}, byb[3] = {T(0), T(0), T(0)};
+        T nbv[3] = {T(0), T(0), T(0)}, zsum = T(0);
+        T dvc = T(0), cc[3] = {T(0), T(0), T(0)};
+        if (iface) {
+            F zb = F(0), aQ = F(0);
+#pragma unroll
+            for (int i = 0; i < 5; ++i) { zb += lam[i] * Q[i]; aQ += a[i] * Q[i]; }
+            F Qb[5];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) Qb[i] = lam[i] * (z - aQ) - a[i] * zb;
+            const T xb = T(F(2) * x * Qb[0] + y * Qb[2] + Qb[3]);
+            const T yb = T(F(2) * y * Qb[1] + x * Qb[2] + Qb[4]);
+            const T zt = T(zb);
+            T cq[3];
+            const T dv = offset_grad_from_d0<T>(n0, n1, n2, T(p), D, cq);   // 1/A, centroid
+            phib = zt * dv;
+            bxb[0] = xb * ex; bxb[1] = xb * ey; bxb[2] = xb * ez;
+            byb[0] = yb * ex; byb[1] = yb * ey; byb[2] = yb * ez;
+            nbv[0] = zt * (ex + cq[0]); nbv[1] = zt * (ey + cq[1]); nbv[2] = zt * (ez + cq[2]);
+            zsum = zt;
+        }
+        if (centre) dvc = offset_grad_from_d0<T>(n0, n1, n2, T(p), D, cc);
+        const T sz_ = group_sum<T>(zsum);
+        T sbx[3], sby[3], snb[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            sbx[i] = group_sum<T>(bxb[i]);
+            sby[i] = group_sum<T>(byb[i]);
+            snb[i] = group_sum<T>(nbv[i]);
+        }
+        const T c0[3] = {group_bcast<T>(cc[0], 26), group_bcast<T>(cc[1], 26), group_bcast<T>(cc[2], 26)};
+        // the centre offset D0 enters every z with a minus sign
+        T nb0 = snb[0] - sz_ * c0[0], nb1 = snb[1] - sz_ * c0[1], nb2 = snb[2] - sz_ * c0[2];
+        // b_x = b_y x n
+        T yb0 = sby[0] + (n1 * sbx[2] - n2 * sbx[1]);
+        T yb1 = sby[1] + (n2 * sbx[0] - n0 * sbx[2]);
+        T yb2 = sby[2] + (n0 * sbx[1] - n1 * sbx[0]);
+        nb0 += sbx[1] * by2 - sbx[2] * by1;
+        nb1 += sbx[2] * by0 - sbx[0] * by2;
+        nb2 += sbx[0] * by1 - sbx[1] * by0;
+        // b_y = u / |u|, u = n x r
+        const T bd = by0 * yb0 + by1 * yb1 + by2 * yb2;
+        const T ub0 = (yb0 - by0 * bd) * iun, ub1 = (yb1 - by1 * bd) * iun, ub2 = (yb2 - by2 * bd) * iun;
+        nb0 += r1 * ub2 - r2 * ub1;
+        nb1 += r2 * ub0 - r0 * ub2;
+        nb2 += r0 * ub1 - r1 * ub0;
+        // n = -g / |g|
+        const T nd = n0 * nb0 + n1 * nb1 + n2 * nb2;
+        const T gb0 = -(nb0 - n0 * nd) * ign, gb1 = -(nb1 - n1 * nd) * ign, gb2 = -(nb2 - n2 * nd) * ign;
+        if (nbr) out[q] = float(phib + w * (ex * gb0 + ey * gb1 + ez * gb2));
+        if (centre) out[13] = float(-sz_ * dvc);
+        (void)gl;
+    }
+    (void)gl;
+    return kappa;
 }
 
 // ---------------------------------------------------------------------------
-// forward kernel: halo 1
+// 1. streaming scan: zero output everywhere, one interface flag per tile.
+// Thread t of the workgroup handles 4 consecutive cells along x.
+// ---------------------------------------------------------------------------
+template <bool VEC>
+__global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict__ phi, float* __restrict__ out,
+                                                        unsigned* __restrict__ flags, int X, int Y, int Z,
+                                                        int ntx, int nty) {
+    const int tile = blockIdx.x;
+    const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
+    const int t = threadIdx.x;
+    const int x = x0 + (t % 16) * 4, y = y0 + (t / 16) % TY, z = z0 + t / (16 * TY);
+    int any = 0;
+    if (y < Y && z < Z) {
+        const bool yz_in = y >= 1 && y <= Y - 2 && z >= 1 && z <= Z - 2;
+        const int64_t row = (static_cast<int64_t>(z) * Y + y) * X;
+        if (VEC && x + 4 <= X) {
+            const float4 v = *reinterpret_cast<const float4*>(phi + row + x);
+            *reinterpret_cast<float4*>(out + row + x) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                any |= yz_in && x + k >= 1 && x + k <= X - 2 && is_iface(vv[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (x + k < X) {
+                    const float v = phi[row + x + k];
+                    out[row + x + k] = 0.0f;
+                    any |= yz_in && x + k >= 1 && x + k <= X - 2 && is_iface(v);
+                }
+            }
+        }
+    }
+    any = __syncthreads_or(any);
+    if (t == 0) flags[tile] = any ? 1u : 0u;
+}
+
+// ---------------------------------------------------------------------------
+// 2a. forward tile kernel: halo 1
 // ---------------------------------------------------------------------------
 constexpr int F_RX = TX + 2, F_RY = TY + 2, F_RZ = TZ + 2, F_REGION = F_RX * F_RY * F_RZ;
 
 template <int SOLVER, class T, class U, class F>
-__global__ __launch_bounds__(kThreads) void k_curv_fwd(const float* __restrict__ phi, float* __restrict__ kappa,
-                                                        int X, int Y, int Z, int ntx, int nty) {
+__global__ __launch_bounds__(kThreads) void k_curv_fwd_tiles(const float* __restrict__ phi,
+                                                              float* __restrict__ kappa,
+                                                              const unsigned* __restrict__ flags, int X, int Y,
+                                                              int Z, int ntx, int nty, int ntiles) {
     __shared__ float s[F_REGION];
     __shared__ unsigned short list[kTile];
     __shared__ int nlist;
-    const int tile = tile_of_block(blockIdx.x, gridDim.x);
-    const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
-    const int tid = threadIdx.x;
-    if (tid == 0) nlist = 0;
-    for (int i = tid; i < F_REGION; i += kThreads) {
-        const int lx = i % F_RX, ly = (i / F_RX) % F_RY, lz = i / (F_RX * F_RY);
-        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-        float v = 0.0f;
-        if (gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z)
-            v = phi[(static_cast<int64_t>(gz) * Y + gy) * X + gx];
-        s[i] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kCellsPerThread; ++k) {
-        const int cl = tid + k * kThreads;
-        const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-        const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
-        if (gx < X && gy < Y && gz < Z) {
-            const float p = s[((cz + 1) * F_RY + (cy + 1)) * F_RX + (cx + 1)];
-            const bool interior = gx >= 1 && gy >= 1 && gz >= 1 && gx <= X - 2 && gy <= Y - 2 && gz <= Z - 2;
-            if (interior && is_iface(p)) list[atomicAdd(&nlist, 1)] = static_cast<unsigned short>(cl);
-            else kappa[(static_cast<int64_t>(gz) * Y + gy) * X + gx] = 0.0f;
+    const int tid = threadIdx.x, grp = tid / kGroup, j = tid % kGroup;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        if (!flags[tile]) continue;                                  // uniform per workgroup
+        const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
+        if (tid == 0) nlist = 0;
+        for (int i = tid; i < F_REGION; i += kThreads) {
+            const int lx = i % F_RX, ly = (i / F_RX) % F_RY, lz = i / (F_RX * F_RY);
+            const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
+            float v = 0.0f;
+            if (gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z)
+                v = phi[(static_cast<int64_t>(gz) * Y + gy) * X + gx];
+            s[i] = v;
         }
-    }
-    __syncthreads();
-    const int n = nlist;
-    for (int i = tid; i < n; i += kThreads) {
-        const int cl = list[i];
-        const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-        CellState<T, F> st;
-        cell_forward<SOLVER, T, U, F>(s, ((cz + 1) * F_RY + (cy + 1)) * F_RX + (cx + 1), F_RX, F_RX * F_RY, st);
-        const float kv = st.valid ? float(kappa_of<F>(st.a)) : 0.0f;
-        kappa[(static_cast<int64_t>(z0 + cz) * Y + (y0 + cy)) * X + (x0 + cx)] = kv;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kCellsPerThread; ++k) {
+            const int cl = tid + k * kThreads;
+            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
+            const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
+            const bool interior = gx >= 1 && gy >= 1 && gz >= 1 && gx <= X - 2 && gy <= Y - 2 && gz <= Z - 2;
+            if (interior && is_iface(s[((cz + 1) * F_RY + (cy + 1)) * F_RX + (cx + 1)]))
+                list[atomicAdd(&nlist, 1)] = static_cast<unsigned short>(cl);
+        }
+        __syncthreads();
+        const int n = nlist;
+        for (int i = grp; i < n; i += kGroups) {
+            const int cl = list[i];
+            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
+            const float kv = group_cell<SOLVER, T, U, F, false>(
+                s, ((cz + 1) * F_RY + (cy + 1)) * F_RX + (cx + 1), F_RX, F_RX * F_RY, j, 0.0f, nullptr);
+            if (j == 0) kappa[(static_cast<int64_t>(z0 + cz) * Y + (y0 + cy)) * X + (x0 + cx)] = kv;
+        }
+        __syncthreads();                                             // LDS reused by the next tile
     }
 }
 
 // ---------------------------------------------------------------------------
-// backward kernel: halo 2.  Candidates are the interface cells of the tile
-// grown by one cell (every cell whose neighbourhood touches the tile); they are
-// listed in region order (ordered wave compaction), processed in chunks of
-// kChunk, and each target cell of the tile gathers the contributions of its 27
-// neighbours chunk by chunk in a fixed order, so the result is deterministic.
+// 2b. backward tile kernel: halo 2.  A tile is processed when it or one of
+// its 26 neighbour tiles holds an interface cell.  Candidates are the
+// interface cells of the tile grown by one cell, listed in region order
+// (ordered wave compaction) and processed in chunks of kChunk; each target
+// cell of the tile then gathers the contributions of its 27 neighbours chunk
+// by chunk in a fixed order, so the result is deterministic.
 // ---------------------------------------------------------------------------
 constexpr int B_RX = TX + 4, B_RY = TY + 4, B_RZ = TZ + 4, B_REGION = B_RX * B_RY * B_RZ;
 constexpr int C_RX = TX + 2, C_RY = TY + 2, C_RZ = TZ + 2, C_REGION = C_RX * C_RY * C_RZ;
@@ -363,122 +366,117 @@ constexpr int kChunk = 128;
 constexpr unsigned short kNoSlot = 0xFFFFu;
 
 template <int SOLVER, class T, class U, class F>
-__global__ __launch_bounds__(kThreads) void k_curv_bwd(const float* __restrict__ phi,
-                                                        const float* __restrict__ gkap,
-                                                        float* __restrict__ gphi, int X, int Y, int Z,
-                                                        int ntx, int nty) {
+__global__ __launch_bounds__(kThreads) void k_curv_bwd_tiles(const float* __restrict__ phi,
+                                                              const float* __restrict__ gkap,
+                                                              float* __restrict__ gphi,
+                                                              const unsigned* __restrict__ flags, int X, int Y,
+                                                              int Z, int ntx, int nty, int ntz, int ntiles) {
     __shared__ float s[B_REGION];
     __shared__ unsigned short cand[C_REGION];
     __shared__ unsigned short slot[C_REGION];
     __shared__ float contrib[kChunk][27];
     __shared__ int wcount[kThreads / 64];
-    const int tile = tile_of_block(blockIdx.x, gridDim.x);
-    const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = tid; i < B_REGION; i += kThreads) {
-        const int lx = i % B_RX, ly = (i / B_RX) % B_RY, lz = i / (B_RX * B_RY);
-        const int gx = x0 - 2 + lx, gy = y0 - 2 + ly, gz = z0 - 2 + lz;
-        float v = 0.0f;
-        if (gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z)
-            v = phi[(static_cast<int64_t>(gz) * Y + gy) * X + gx];
-        s[i] = v;
-    }
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, grp = tid / kGroup, j = tid % kGroup;
     for (int i = tid; i < C_REGION; i += kThreads) slot[i] = kNoSlot;
-    __syncthreads();
-    // ordered compaction of the candidate cells (region order)
-    int ncand = 0;
-    for (int base = 0; base < C_REGION; base += kThreads) {
-        const int i = base + tid;
-        bool is = false;
-        if (i < C_REGION) {
-            const int lx = i % C_RX, ly = (i / C_RX) % C_RY, lz = i / (C_RX * C_RY);
-            const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-            const bool interior = gx >= 1 && gy >= 1 && gz >= 1 && gx <= X - 2 && gy <= Y - 2 && gz <= Z - 2;
-            is = interior && is_iface(s[((lz + 1) * B_RY + (ly + 1)) * B_RX + (lx + 1)]);
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+        int act = 0;
+        if (tid < 27) {
+            const int ax = tx + q_dx(tid), ay = ty + q_dy(tid), az = tz + q_dz(tid);
+            if (ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz)
+                act = flags[(az * nty + ay) * ntx + ax] != 0u;
         }
-        const unsigned long long bal = __ballot(is);
-        if (lane == 0) wcount[wave] = __popcll(bal);
+        if (!__syncthreads_or(act)) continue;                        // uniform per workgroup
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+        for (int i = tid; i < B_REGION; i += kThreads) {
+            const int lx = i % B_RX, ly = (i / B_RX) % B_RY, lz = i / (B_RX * B_RY);
+            const int gx = x0 - 2 + lx, gy = y0 - 2 + ly, gz = z0 - 2 + lz;
+            float v = 0.0f;
+            if (gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z)
+                v = phi[(static_cast<int64_t>(gz) * Y + gy) * X + gx];
+            s[i] = v;
+        }
         __syncthreads();
-        int before = 0, total = 0;
+        // ordered compaction of the candidate cells (region order)
+        int ncand = 0;
+        for (int base = 0; base < C_REGION; base += kThreads) {
+            const int i = base + tid;
+            bool is = false;
+            if (i < C_REGION) {
+                const int lx = i % C_RX, ly = (i / C_RX) % C_RY, lz = i / (C_RX * C_RY);
+                const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
+                const bool interior = gx >= 1 && gy >= 1 && gz >= 1 && gx <= X - 2 && gy <= Y - 2 && gz <= Z - 2;
+                is = interior && is_iface(s[((lz + 1) * B_RY + (ly + 1)) * B_RX + (lx + 1)]);
+            }
+            const unsigned long long bal = __ballot(is);
+            if (lane == 0) wcount[wave] = __popcll(bal);
+            __syncthreads();
+            int before = 0, total = 0;
 #pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) {
-            before += w < wave ? wcount[w] : 0;
-            total += wcount[w];
+            for (int w = 0; w < kThreads / 64; ++w) {
+                before += w < wave ? wcount[w] : 0;
+                total += wcount[w];
+            }
+            if (is) {
+                const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
+                cand[ncand + before + __popcll(below)] = static_cast<unsigned short>(i);
+            }
+            ncand += total;
+            __syncthreads();
         }
-        if (is) {
-            const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
-            cand[ncand + before + __popcll(below)] = static_cast<unsigned short>(i);
-        }
-        ncand += total;
-        __syncthreads();
-    }
-    float acc[kCellsPerThread];
+        float acc[kCellsPerThread];
 #pragma unroll
-    for (int k = 0; k < kCellsPerThread; ++k) acc[k] = 0.0f;
-    for (int c0 = 0; c0 < ncand; c0 += kChunk) {
-        const int nc = min(kChunk, ncand - c0);
-        for (int i = tid; i < nc; i += kThreads) slot[cand[c0 + i]] = static_cast<unsigned short>(i);
-        for (int i = tid; i < nc; i += kThreads) {
-            const int ci = cand[c0 + i];
-            const int lx = ci % C_RX, ly = (ci / C_RX) % C_RY, lz = ci / (C_RX * C_RY);
-            const float gk = gkap[(static_cast<int64_t>(z0 - 1 + lz) * Y + (y0 - 1 + ly)) * X + (x0 - 1 + lx)];
-            cell_adjoint<SOLVER, T, U, F>(s, ((lz + 1) * B_RY + (ly + 1)) * B_RX + (lx + 1), B_RX,
-                                          B_RX * B_RY, gk, contrib[i]);
+        for (int k = 0; k < kCellsPerThread; ++k) acc[k] = 0.0f;
+        for (int c0 = 0; c0 < ncand; c0 += kChunk) {
+            const int nc = min(kChunk, ncand - c0);
+            for (int i = tid; i < nc; i += kThreads) slot[cand[c0 + i]] = static_cast<unsigned short>(i);
+            for (int i = grp; i < nc; i += kGroups) {
+                const int ci = cand[c0 + i];
+                const int lx = ci % C_RX, ly = (ci / C_RX) % C_RY, lz = ci / (C_RX * C_RY);
+                const float gk =
+                    gkap[(static_cast<int64_t>(z0 - 1 + lz) * Y + (y0 - 1 + ly)) * X + (x0 - 1 + lx)];
+                group_cell<SOLVER, T, U, F, true>(s, ((lz + 1) * B_RY + (ly + 1)) * B_RX + (lx + 1), B_RX,
+                                                  B_RX * B_RY, j, gk, contrib[i]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kCellsPerThread; ++k) {
+                const int cl = tid + k * kThreads;
+                const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
+                // the target sits at candidate-region coordinates (cx+1, cy+1, cz+1);
+                // the neighbour owning offset q is at target - e_q
+                float a = acc[k];
+#pragma unroll
+                for (int q = 0; q < 27; ++q) {
+                    const int ci = ((cz + 1 - q_dz(q)) * C_RY + (cy + 1 - q_dy(q))) * C_RX + (cx + 1 - q_dx(q));
+                    const unsigned short sl = slot[ci];
+                    if (sl != kNoSlot) a += contrib[sl][q];
+                }
+                acc[k] = a;
+            }
+            __syncthreads();
+            for (int i = tid; i < nc; i += kThreads) slot[cand[c0 + i]] = kNoSlot;
+            __syncthreads();
         }
-        __syncthreads();
 #pragma unroll
         for (int k = 0; k < kCellsPerThread; ++k) {
             const int cl = tid + k * kThreads;
             const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-            // the target sits at candidate-region coordinates (cx+1, cy+1, cz+1);
-            // the neighbour owning offset q is at target - e_q
-            float a = acc[k];
-#pragma unroll
-            for (int q = 0; q < 27; ++q) {
-                const int ci = ((cz + 1 - q_dz(q)) * C_RY + (cy + 1 - q_dy(q))) * C_RX + (cx + 1 - q_dx(q));
-                const unsigned short sl = slot[ci];
-                if (sl != kNoSlot) a += contrib[sl][q];
-            }
-            acc[k] = a;
+            const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
+            if (gx < X && gy < Y && gz < Z) gphi[(static_cast<int64_t>(gz) * Y + gy) * X + gx] = acc[k];
         }
-        __syncthreads();
-        for (int i = tid; i < nc; i += kThreads) slot[cand[c0 + i]] = kNoSlot;
-        __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < kCellsPerThread; ++k) {
-        const int cl = tid + k * kThreads;
-        const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-        const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
-        if (gx < X && gy < Y && gz < Z) gphi[(static_cast<int64_t>(gz) * Y + gy) * X + gx] = acc[k];
+        __syncthreads();                                             // LDS reused by the next tile
     }
 }
 
-// ---- dispatch -----------------------------------------------------------------
-template <int SOLVER>
-void launch_fwd(int precision, const float* phi, float* kappa, int X, int Y, int Z, int ntx, int nty,
-                unsigned nblk, hipStream_t st) {
-    if (precision == PLIC_FP32)
-        hipLaunchKernelGGL((k_curv_fwd<SOLVER, float, float, float>), dim3(nblk), dim3(kThreads), 0, st, phi, kappa, X, Y, Z, ntx, nty);
-    else if (precision == PLIC_MIXED)
-        hipLaunchKernelGGL((k_curv_fwd<SOLVER, float, double, double>), dim3(nblk), dim3(kThreads), 0, st, phi, kappa, X, Y, Z, ntx, nty);
-    else
-        hipLaunchKernelGGL((k_curv_fwd<SOLVER, double, double, double>), dim3(nblk), dim3(kThreads), 0, st, phi, kappa, X, Y, Z, ntx, nty);
-}
+// ---- launch helpers -----------------------------------------------------------
+struct Grid {
+    int ntx, nty, ntz;
+    int ntiles;
+};
 
-template <int SOLVER>
-void launch_bwd(int precision, const float* phi, const float* gk, float* gp, int X, int Y, int Z, int ntx,
-                int nty, unsigned nblk, hipStream_t st) {
-    if (precision == PLIC_FP32)
-        hipLaunchKernelGGL((k_curv_bwd<SOLVER, float, float, float>), dim3(nblk), dim3(kThreads), 0, st, phi, gk, gp, X, Y, Z, ntx, nty);
-    else if (precision == PLIC_MIXED)
-        hipLaunchKernelGGL((k_curv_bwd<SOLVER, float, double, double>), dim3(nblk), dim3(kThreads), 0, st, phi, gk, gp, X, Y, Z, ntx, nty);
-    else
-        hipLaunchKernelGGL((k_curv_bwd<SOLVER, double, double, double>), dim3(nblk), dim3(kThreads), 0, st, phi, gk, gp, X, Y, Z, ntx, nty);
-}
-
-// validates the lattice; returns PLIC_OK with *empty set when nothing to do
-int check_lattice(int64_t X, int64_t Y, int64_t Z, bool* empty, int* ntx, int* nty, unsigned* nblk) {
+// validates the lattice; *empty when there is nothing to do
+int check_lattice(int64_t X, int64_t Y, int64_t Z, bool* empty, Grid* g) {
     if (X < 0 || Y < 0 || Z < 0) return PLIC_EINVAL;
     *empty = X == 0 || Y == 0 || Z == 0;
     if (*empty) return PLIC_OK;
@@ -487,9 +485,64 @@ int check_lattice(int64_t X, int64_t Y, int64_t Z, bool* empty, int* ntx, int* n
     if (X > (int64_t(1) << 62) / Y / Z) return PLIC_EINVAL;
     const int64_t tx = (X + TX - 1) / TX, ty = (Y + TY - 1) / TY, tz = (Z + TZ - 1) / TZ;
     if (tx > lim / ty || tx * ty > lim / tz) return PLIC_EINVAL;   // grid limit
-    *ntx = static_cast<int>(tx);
-    *nty = static_cast<int>(ty);
-    *nblk = static_cast<unsigned>(tx * ty * tz);
+    g->ntx = static_cast<int>(tx);
+    g->nty = static_cast<int>(ty);
+    g->ntz = static_cast<int>(tz);
+    g->ntiles = static_cast<int>(tx * ty * tz);
+    return PLIC_OK;
+}
+
+size_t workspace_for(const Grid& g) { return (static_cast<size_t>(g.ntiles) * sizeof(unsigned) + 255) & ~size_t(255); }
+
+void launch_scan(const float* phi, float* out, unsigned* flags, int X, int Y, int Z, const Grid& g,
+                 hipStream_t st) {
+    const bool vec = X % 4 == 0 && aligned(phi, 16) && aligned(out, 16);
+    if (vec)
+        hipLaunchKernelGGL((k_curv_scan<true>), dim3(g.ntiles), dim3(kThreads), 0, st, phi, out, flags, X, Y, Z, g.ntx, g.nty);
+    else
+        hipLaunchKernelGGL((k_curv_scan<false>), dim3(g.ntiles), dim3(kThreads), 0, st, phi, out, flags, X, Y, Z, g.ntx, g.nty);
+}
+
+unsigned persistent_grid(const Grid& g) {
+    return static_cast<unsigned>(g.ntiles < kPersistentBlocks ? g.ntiles : kPersistentBlocks);
+}
+
+template <int SOLVER>
+void launch_fwd(int precision, const float* phi, float* kappa, const unsigned* flags, int X, int Y, int Z,
+                const Grid& g, hipStream_t st) {
+    const dim3 grid(persistent_grid(g)), block(kThreads);
+    if (precision == PLIC_FP32)
+        hipLaunchKernelGGL((k_curv_fwd_tiles<SOLVER, float, float, float>), grid, block, 0, st, phi, kappa, flags, X, Y, Z, g.ntx, g.nty, g.ntiles);
+    else if (precision == PLIC_MIXED)
+        hipLaunchKernelGGL((k_curv_fwd_tiles<SOLVER, float, double, double>), grid, block, 0, st, phi, kappa, flags, X, Y, Z, g.ntx, g.nty, g.ntiles);
+    else
+        hipLaunchKernelGGL((k_curv_fwd_tiles<SOLVER, double, double, double>), grid, block, 0, st, phi, kappa, flags, X, Y, Z, g.ntx, g.nty, g.ntiles);
+}
+
+template <int SOLVER>
+void launch_bwd(int precision, const float* phi, const float* gk, float* gp, const unsigned* flags, int X,
+                int Y, int Z, const Grid& g, hipStream_t st) {
+    const dim3 grid(persistent_grid(g)), block(kThreads);
+    if (precision == PLIC_FP32)
+        hipLaunchKernelGGL((k_curv_bwd_tiles<SOLVER, float, float, float>), grid, block, 0, st, phi, gk, gp, flags, X, Y, Z, g.ntx, g.nty, g.ntz, g.ntiles);
+    else if (precision == PLIC_MIXED)
+        hipLaunchKernelGGL((k_curv_bwd_tiles<SOLVER, float, double, double>), grid, block, 0, st, phi, gk, gp, flags, X, Y, Z, g.ntx, g.nty, g.ntz, g.ntiles);
+    else
+        hipLaunchKernelGGL((k_curv_bwd_tiles<SOLVER, double, double, double>), grid, block, 0, st, phi, gk, gp, flags, X, Y, Z, g.ntx, g.nty, g.ntz, g.ntiles);
+}
+
+// shared argument checks of the two entry points
+int check_common(const float* phi, int64_t X, int64_t Y, int64_t Z, int solver, int precision,
+                 const void* ws, size_t ws_bytes, bool* empty, Grid* g, int64_t* n) {
+    if (!valid_solver(solver) || !valid_precision(precision)) return PLIC_EINVAL;
+    if (check_lattice(X, Y, Z, empty, g) != PLIC_OK) return PLIC_EINVAL;
+    *n = *empty ? 0 : X * Y * Z;
+    if (!valid_array(phi, *n)) return PLIC_EINVAL;
+    if (!*empty) {
+        const size_t need = workspace_for(*g);
+        if (ws == nullptr || !aligned(ws, 4) || ws_bytes < need) return PLIC_EINVAL;
+        if (overlap(ws, need, phi, static_cast<size_t>(*n) * sizeof(float))) return PLIC_EINVAL;
+    }
     return PLIC_OK;
 }
 
@@ -500,48 +553,62 @@ using namespace plic;
 
 extern "C" {
 
-int plic_curvature_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float* kappa, int solver,
-                       int precision, void* stream) {
-    if (!valid_solver(solver) || !valid_precision(precision)) return PLIC_EINVAL;
+size_t plic_curvature_workspace_bytes(int64_t X, int64_t Y, int64_t Z) {
     bool empty;
-    int ntx = 0, nty = 0;
-    unsigned nblk = 0;
-    if (check_lattice(X, Y, Z, &empty, &ntx, &nty, &nblk) != PLIC_OK) return PLIC_EINVAL;
-    const int64_t n = empty ? 0 : X * Y * Z;
-    if (!valid_array(phi, n) || !valid_array(kappa, n)) return PLIC_EINVAL;
+    Grid g;
+    if (check_lattice(X, Y, Z, &empty, &g) != PLIC_OK || empty) return 0;
+    return workspace_for(g);
+}
+
+int plic_curvature_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float* kappa, int solver,
+                       int precision, void* workspace, size_t workspace_bytes, void* stream) {
+    bool empty;
+    Grid g{};
+    int64_t n = 0;
+    if (check_common(phi, X, Y, Z, solver, precision, workspace, workspace_bytes, &empty, &g, &n) != PLIC_OK)
+        return PLIC_EINVAL;
+    if (!valid_array(kappa, n)) return PLIC_EINVAL;
     const size_t nb = static_cast<size_t>(n) * sizeof(float);
     if (overlap(phi, nb, kappa, nb)) return PLIC_EINVAL;
+    if (!empty && overlap(workspace, workspace_for(g), kappa, nb)) return PLIC_EINVAL;
     if (empty) return PLIC_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned* flags = static_cast<unsigned*>(workspace);
     const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
+    launch_scan(phi, kappa, flags, x, y, z, g, st);
     switch (solver) {
-        case kSZ: launch_fwd<kSZ>(precision, phi, kappa, x, y, z, ntx, nty, nblk, st); break;
-        case kNewton: launch_fwd<kNewton>(precision, phi, kappa, x, y, z, ntx, nty, nblk, st); break;
-        case kNested: launch_fwd<kNested>(precision, phi, kappa, x, y, z, ntx, nty, nblk, st); break;
-        default: launch_fwd<kAnalytic>(precision, phi, kappa, x, y, z, ntx, nty, nblk, st); break;
+        case kSZ: launch_fwd<kSZ>(precision, phi, kappa, flags, x, y, z, g, st); break;
+        case kNewton: launch_fwd<kNewton>(precision, phi, kappa, flags, x, y, z, g, st); break;
+        case kNested: launch_fwd<kNested>(precision, phi, kappa, flags, x, y, z, g, st); break;
+        default: launch_fwd<kAnalytic>(precision, phi, kappa, flags, x, y, z, g, st); break;
     }
     return launch_status();
 }
 
 int plic_curvature_backward_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, const float* grad_kappa,
-                                float* grad_phi, int solver, int precision, void* stream) {
-    if (!valid_solver(solver) || !valid_precision(precision)) return PLIC_EINVAL;
+                                float* grad_phi, int solver, int precision, void* workspace,
+                                size_t workspace_bytes, void* stream) {
     bool empty;
-    int ntx = 0, nty = 0;
-    unsigned nblk = 0;
-    if (check_lattice(X, Y, Z, &empty, &ntx, &nty, &nblk) != PLIC_OK) return PLIC_EINVAL;
-    const int64_t n = empty ? 0 : X * Y * Z;
-    if (!valid_array(phi, n) || !valid_array(grad_kappa, n) || !valid_array(grad_phi, n)) return PLIC_EINVAL;
+    Grid g{};
+    int64_t n = 0;
+    if (check_common(phi, X, Y, Z, solver, precision, workspace, workspace_bytes, &empty, &g, &n) != PLIC_OK)
+        return PLIC_EINVAL;
+    if (!valid_array(grad_kappa, n) || !valid_array(grad_phi, n)) return PLIC_EINVAL;
     const size_t nb = static_cast<size_t>(n) * sizeof(float);
     if (overlap(grad_phi, nb, phi, nb) || overlap(grad_phi, nb, grad_kappa, nb)) return PLIC_EINVAL;
+    if (!empty && (overlap(workspace, workspace_for(g), grad_phi, nb) ||
+                   overlap(workspace, workspace_for(g), grad_kappa, nb)))
+        return PLIC_EINVAL;
     if (empty) return PLIC_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned* flags = static_cast<unsigned*>(workspace);
     const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
+    launch_scan(phi, grad_phi, flags, x, y, z, g, st);
     switch (solver) {
-        case kSZ: launch_bwd<kSZ>(precision, phi, grad_kappa, grad_phi, x, y, z, ntx, nty, nblk, st); break;
-        case kNewton: launch_bwd<kNewton>(precision, phi, grad_kappa, grad_phi, x, y, z, ntx, nty, nblk, st); break;
-        case kNested: launch_bwd<kNested>(precision, phi, grad_kappa, grad_phi, x, y, z, ntx, nty, nblk, st); break;
-        default: launch_bwd<kAnalytic>(precision, phi, grad_kappa, grad_phi, x, y, z, ntx, nty, nblk, st); break;
+        case kSZ: launch_bwd<kSZ>(precision, phi, grad_kappa, grad_phi, flags, x, y, z, g, st); break;
+        case kNewton: launch_bwd<kNewton>(precision, phi, grad_kappa, grad_phi, flags, x, y, z, g, st); break;
+        case kNested: launch_bwd<kNested>(precision, phi, grad_kappa, grad_phi, flags, x, y, z, g, st); break;
+        default: launch_bwd<kAnalytic>(precision, phi, grad_kappa, grad_phi, flags, x, y, z, g, st); break;
     }
     return launch_status();
 }

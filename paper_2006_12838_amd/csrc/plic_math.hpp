@@ -245,13 +245,16 @@ __device__ __forceinline__ void divided_volume(U n1, U n2, U n3, U d, U& g, U& g
 template <class T, class U>
 __device__ __forceinline__ T solve_newton(T n1, T n2, T n3, T V) {
     T d;
-    if (closed_case<T, false>(n1, n2, n3, V, d) >= 2) return d;       // (5) or (2)
+    const int c = closed_case<T, false>(n1, n2, n3, V, d);
+    if (c >= 2) return d;                                               // (5) or (2)
     if (V == T(0)) return T(0);
     using m = M<U>;
     const U u1 = n1, u2 = n2, u3 = n3;
     const U target = U(6) * u2 * u3 * U(V);
+    // the bracket follows the classifier's own decision, so that rounding
+    // cannot place the root in a skipped case-(2) interval
     U lo, hi;
-    if (target < u1 * u1) { lo = U(0); hi = u1; }                      // case (1)
+    if (c == 1) { lo = U(0); hi = u1; }                                // case (1)
     else { lo = u2; hi = m::fmin(u1 + u2, U(0.5) * (u1 + u2 + u3)); }  // cases (3), (4)
     U x = U(0.5) * (lo + hi);
     const U tol = U(M<T>::newton_tol);

@@ -98,19 +98,30 @@ def test_backward_validation(lib):
 
 
 def test_curvature_validation(lib):
+    assert lib.plic_curvature_workspace_bytes(256, 256, 256) == 16384 * 4
+    assert lib.plic_curvature_workspace_bytes(65, 5, 5) == 256          # 8 tiles, rounded up
+    assert lib.plic_curvature_workspace_bytes(0, 5, 5) == 0
+    assert lib.plic_curvature_workspace_bytes(-1, 5, 5) == 0
+    W = 0xA0000
     f = lib.raw("plic_curvature_f32")
-    assert f(A, 0, 5, 5, B, 0, 1, None) == 0                          # empty lattice
-    assert f(A, -1, 5, 5, B, 0, 1, None) == -1
-    assert f(None, 4, 4, 4, B, 0, 1, None) == -1
-    assert f(A, 4, 4, 4, A + 64, 0, 1, None) == -1                    # kappa overlaps phi
-    assert f(A, 4, 4, 4, B, 9, 1, None) == -1
-    assert f(A, 4, 4, 4, B, 0, 7, None) == -1
-    assert f(A, 1 << 40, 1 << 40, 4, B, 0, 1, None) == -1             # size overflow
+    ws = lib.plic_curvature_workspace_bytes(4, 4, 4)
+    assert f(A, 0, 5, 5, B, 0, 1, None, 0, None) == 0                 # empty lattice
+    assert f(A, -1, 5, 5, B, 0, 1, W, ws, None) == -1
+    assert f(None, 4, 4, 4, B, 0, 1, W, ws, None) == -1
+    assert f(A, 4, 4, 4, A + 64, 0, 1, W, ws, None) == -1             # kappa overlaps phi
+    assert f(A, 4, 4, 4, B, 9, 1, W, ws, None) == -1
+    assert f(A, 4, 4, 4, B, 0, 7, W, ws, None) == -1
+    assert f(A, 4, 4, 4, B, 0, 1, None, ws, None) == -1               # no workspace
+    assert f(A, 4, 4, 4, B, 0, 1, W, ws - 1, None) == -1              # workspace too small
+    assert f(A, 4, 4, 4, B, 0, 1, W + 2, ws, None) == -1              # misaligned workspace
+    assert f(A, 4, 4, 4, B, 0, 1, B, ws, None) == -1                  # workspace overlaps kappa
+    assert f(A, 1 << 40, 1 << 40, 4, B, 0, 1, W, ws, None) == -1      # size overflow
     g = lib.raw("plic_curvature_backward_f32")
-    assert g(A, 3, 3, 0, B, C, 0, 1, None) == 0
-    assert g(A, 3, 3, 3, B, A, 0, 1, None) == -1                      # grad_phi overlaps phi
-    assert g(A, 3, 3, 3, B, B + 4, 0, 1, None) == -1                  # grad_phi overlaps grad_kappa
-    assert g(A, 3, 3, 3, None, C, 0, 1, None) == -1
+    assert g(A, 3, 3, 0, B, C, 0, 1, None, 0, None) == 0
+    assert g(A, 3, 3, 3, B, A, 0, 1, W, ws, None) == -1               # grad_phi overlaps phi
+    assert g(A, 3, 3, 3, B, B + 4, 0, 1, W, ws, None) == -1           # grad_phi overlaps grad_kappa
+    assert g(A, 3, 3, 3, None, C, 0, 1, W, ws, None) == -1
+    assert g(A, 3, 3, 3, B, C, 0, 1, C, ws, None) == -1               # workspace overlaps grad_phi
 
 
 def test_python_layer_rejects_cpu_tensors(lib):

@@ -103,9 +103,12 @@ int plic_offset_backward_f64(const double *nx, const double *ny, const double *n
 /*
  * plic_curvature_workspace_bytes — size of the device workspace that
  * plic_curvature_f32 and plic_curvature_backward_f32 need for an X*Y*Z lattice:
- * one 32-bit flag per 64x4x4 tile, rounded up to 256 bytes (16 KiB at 256^3).
- * 0 for an empty or invalid lattice.  The workspace is caller-owned device
- * memory; its contents need no initialisation and are scratch after the call.
+ * a work-list counter, one flag per 64x4x4 tile and a work list of at most
+ * 128 entries per tile: 256 + 516 * tiles bytes (8.5 MB at 256^3, about 0.5
+ * byte per cell).  0 for an empty or invalid lattice (more than 2^25 tiles is
+ * invalid).  The workspace is caller-owned device memory; its contents need
+ * no initialisation (each call clears what it uses with a kernel) and are
+ * scratch after the call.
  */
 size_t plic_curvature_workspace_bytes(int64_t X, int64_t Y, int64_t Z);
 

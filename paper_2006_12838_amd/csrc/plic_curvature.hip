@@ -2,20 +2,23 @@
 // Appendix B of Lehmann & Gekle, arXiv 2006.12838), forward and backward.
 //
 // Layout: phi, kappa, grad_kappa, grad_phi are X*Y*Z floats, x fastest.  The
-// lattice is cut into 64x4x4 tiles.  Each call runs two kernels:
-//  1. a streaming scan over the whole lattice (float4 loads and stores, no LDS,
-//     low register use, full occupancy): writes the zero result everywhere and
-//     one flag per tile telling whether the tile holds an interface cell
-//     (0 < phi < 1, away from the outer layer).  Every flag is written, so the
-//     workspace needs no clearing.
-//  2. a persistent tile kernel over the flagged tiles (their neighbours too for
-//     the backward): stages the tile's fill levels plus a halo in LDS and
-//     computes each interface cell with a group of 32 lanes, lane j taking
-//     neighbour j of the 3x3x3 neighbourhood (lane 26 the centre).  The
-//     Parker-Youngs sum and the normal equations are butterfly reductions
-//     over the group, which give every lane the same bits.
+// lattice is cut into 64x4x4 tiles.  A call runs:
+//  1. a one-thread kernel that zeroes the work-list counter in the workspace
+//     (a kernel, not a memset, so the call can be captured in a graph);
+//  2. a streaming scan over the whole lattice (float4 loads and stores, no
+//     LDS, low register use, full occupancy) that writes the zero result
+//     everywhere and records the interface cells (0 < phi < 1, away from the
+//     outer layer): forward, one work item per 8 interface cells of a tile;
+//     backward, one flag per tile, then a small kernel lists every tile whose
+//     3x3x3 tile neighbourhood is flagged;
+//  3. a persistent kernel over the work list that stages the fill levels of a
+//     tile plus a halo in LDS and computes each interface cell with a group of
+//     32 lanes: lane j takes neighbour j of the 3x3x3 neighbourhood (its PLIC
+//     offset, its row of the normal equations), lane 26 the centre.  Sums over
+//     the neighbours go through a small LDS tile and are added in a fixed
+//     order, so results are bitwise reproducible.
 // The interface is one cell thick (about 0.2 % of a 256^3 sphere lattice), so
-// the scan carries the HBM traffic and the tile kernel the arithmetic.
+// the scan carries the HBM traffic and the list kernels the arithmetic.
 #include <hip/hip_runtime.h>
 
 #include "plic_host.hpp"
@@ -41,18 +44,6 @@ __host__ __device__ constexpr int q_dy(int q) { return (q / 3) % 3 - 1; }
 __host__ __device__ constexpr int q_dz(int q) { return q / 9 - 1; }
 
 __device__ __forceinline__ bool is_iface(float p) { return p > 0.0f && p < 1.0f; }
-
-template <class F>
-__device__ __forceinline__ F group_sum(F v) {
-#pragma unroll
-    for (int m = kGroup / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kGroup);
-    return v;
-}
-
-template <class F>
-__device__ __forceinline__ F group_bcast(F v, int src_in_group) {
-    return __shfl(v, src_in_group, kGroup);
-}
 
 // ---------------------------------------------------------------------------
 // LDL^T factorisation and solve of the symmetric 5x5 normal equations
@@ -116,17 +107,64 @@ __device__ __forceinline__ F kappa_of(const F (&a)[5]) {
 }
 
 // ---------------------------------------------------------------------------
+// Per-group LDS scratch.  Reductions over the 26 neighbour lanes go through a
+// [26][20] staging tile: every lane writes its row, lane k sums column k in
+// the fixed order l = 0..25 (so every call gives the same bits), lanes read
+// the column sums back.
+// ---------------------------------------------------------------------------
+template <class F>
+struct alignas(16) GroupLds {
+    F stage[26][20];
+    F res[32];
+};
+
+template <class F, int NV>
+__device__ __forceinline__ void group_colsum(GroupLds<F>& L, int j, const F (&row)[NV], F (&sum)[NV]) {
+    if (j < 26) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) L.stage[j][k] = row[k];
+    }
+    __syncwarp();
+    if (j < NV) {
+        F acc = F(0);
+#pragma unroll
+        for (int l = 0; l < 26; ++l) acc += L.stage[l][j];
+        L.res[j] = acc;
+    }
+    __syncwarp();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sum[k] = L.res[k];
+    __syncwarp();
+}
+
+// lower-triangle index of the 5x5 normal matrix
+__host__ __device__ constexpr int tri(int i, int k) { return i * (i + 1) / 2 + k; }
+
+// ---------------------------------------------------------------------------
 // One interface cell on a group of 32 lanes.  s: LDS fill levels, c: centre
-// index, sy/sz: LDS strides, j: lane in the group (0..31), gbase: lane index
-// of the group's lane 0 within the wave.  Every lane of the group must call
-// it.  Returns kappa (same value on every lane).  With ADJ, also writes
-// out[q] = gk * d kappa / d phi_q (q = 0..26) from the lanes that own q, with
-// the interface mask, PLIC cases and active fit parameters held fixed.
+// index, sy/sz: LDS strides, j: lane in the group (0..31).  Lane j < 26 owns
+// neighbour q(j) (the 26 offsets other than the centre), lane 26 the centre.
+// Every lane of the group must call it.  Returns kappa (same bits on every
+// lane).  With ADJ, also writes out[q] = gk * d kappa / d phi_q (q = 0..26)
+// from the lane that owns q, with the interface mask, the PLIC cases and the
+// active fit parameters held fixed.
 // ---------------------------------------------------------------------------
 template <int SOLVER, class T, class U, class F, bool ADJ>
 __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, int sy, int sz, int j,
-                                            float gk, float* __restrict__ out) {
+                                            float gk, float* __restrict__ out, GroupLds<F>& L) {
     using mt = M<T>;
+    // Parker-Youngs gradient (App. B.1), weights 4 / 2 / 1 for |e|^2 = 1 / 2 / 3;
+    // every lane forms the same sum from the staged fill levels
+    T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+        if (q == 13) continue;
+        const int e2 = q_dx(q) * q_dx(q) + q_dy(q) * q_dy(q) + q_dz(q) * q_dz(q);
+        const T w = T(e2 == 1 ? 4 : (e2 == 2 ? 2 : 1)) * T(s[c + q_dz(q) * sz + q_dy(q) * sy + q_dx(q)]);
+        gx += T(q_dx(q)) * w;
+        gy += T(q_dy(q)) * w;
+        gz += T(q_dz(q)) * w;
+    }
     const bool nbr = j < 26;                      // lane owns neighbour q
     const bool centre = j == 26;                  // lane owns the centre
     const int q = nbr ? (j < 13 ? j : j + 1) : 13;
@@ -135,10 +173,6 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
     const T ex = T(dx), ey = T(dy), ez = T(dz);
     const int e2 = dx * dx + dy * dy + dz * dz;
     const T w = nbr ? T(e2 == 1 ? 4 : (e2 == 2 ? 2 : 1)) : T(0);
-    // Parker-Youngs gradient (App. B.1): weights 4 / 2 / 1 for |e|^2 = 1 / 2 / 3
-    const T gx = group_sum<T>(w * ex * T(p));
-    const T gy = group_sum<T>(w * ey * T(p));
-    const T gz = group_sum<T>(w * ez * T(p));
     const bool iface = nbr && is_iface(p);
     const unsigned long long bal = __ballot(iface);
     const int npts = __popcll(bal & (0xffffffffull << (threadIdx.x & 32)));
@@ -164,13 +198,15 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
     const T iun = mt::rcp(mt::sqrt(un2));
     const T by0 = u0 * iun, by1 = u1 * iun, by2 = u2 * iun;
     const T bx0 = by1 * n2 - by2 * n1, bx1 = by2 * n0 - by0 * n2, bx2 = by0 * n1 - by1 * n0;
-    // PLIC offsets: the neighbour lanes and the centre lane in parallel, all
-    // with the centre normal (Sec. 5.2)
+    // PLIC offsets: neighbour lanes and the centre lane in parallel, all with
+    // the centre normal (Sec. 5.2)
     T D = T(0);
     if (iface || centre) D = offset<SOLVER, T, U>(n0, n1, n2, T(p));
-    const int gl = threadIdx.x & 32;              // lane 0 of this group in the wave
-    const T D0 = group_bcast<T>(D, 26);
-    // this lane's point (eq. of the coordinate transformation, Sec. 5.2)
+    if (centre) L.res[24] = F(D);
+    __syncwarp();
+    const T D0 = T(L.res[24]);
+    // this lane's point (coordinate transformation of Sec. 5.2) and its row of
+    // the normal equations: Q Q^T (lower triangle) and z Q
     F x = F(0), y = F(0), z = F(0);
     if (iface) {
         x = F(ex * bx0 + ey * bx1 + ez * bx2);
@@ -178,12 +214,20 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
         z = F(ex * n0 + ey * n1 + ez * n2 + (D - D0));
     }
     const F Q[5] = {x * x, y * y, x * y, x, y};
+    F row[20], sum[20];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+#pragma unroll
+        for (int k = 0; k <= i; ++k) row[tri(i, k)] = Q[i] * Q[k];
+        row[15 + i] = z * Q[i];
+    }
+    group_colsum<F, 20>(L, j, row, sum);
     F m[5][5], b[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        b[i] = group_sum<F>(z * Q[i]);
+        b[i] = sum[15 + i];
 #pragma unroll
-        for (int k = 0; k <= i; ++k) m[i][k] = group_sum<F>(Q[i] * Q[k]);
+        for (int k = 0; k <= i; ++k) m[i][k] = sum[tri(i, k)];
     }
     bool act[5];
     F a[5];
@@ -208,9 +252,10 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
         F lam[5];
         ldlt_solve<F>(m, act, abar, lam);          // M symmetric: lambda = M^-1 abar
         // this lane's point: zbar = lam.Q, Qbar = lam (z - a.Q) - a (lam.Q)
-        T phib = T(0), bxb[3] = {T(0), T(0), T(0)}, byb[3] = {T(0), T(0), T(0)};
-        T nbv[3] = {T(0), T(0), T(0)}, zsum = T(0);
-        T dvc = T(0), cc[3] = {T(0), T(0), T(0)};
+        T phib = T(0);
+        F arow[10];
+#pragma unroll
+        for (int i = 0; i < 10; ++i) arow[i] = F(0);
         if (iface) {
             F zb = F(0), aQ = F(0);
 #pragma unroll
@@ -224,30 +269,31 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
             T cq[3];
             const T dv = offset_grad_from_d0<T>(n0, n1, n2, T(p), D, cq);   // 1/A, centroid
             phib = zt * dv;
-            bxb[0] = xb * ex; bxb[1] = xb * ey; bxb[2] = xb * ez;
-            byb[0] = yb * ex; byb[1] = yb * ey; byb[2] = yb * ez;
-            nbv[0] = zt * (ex + cq[0]); nbv[1] = zt * (ey + cq[1]); nbv[2] = zt * (ez + cq[2]);
-            zsum = zt;
+            arow[0] = F(xb * ex); arow[1] = F(xb * ey); arow[2] = F(xb * ez);
+            arow[3] = F(yb * ex); arow[4] = F(yb * ey); arow[5] = F(yb * ez);
+            arow[6] = F(zt * (ex + cq[0])); arow[7] = F(zt * (ey + cq[1])); arow[8] = F(zt * (ez + cq[2]));
+            arow[9] = F(zt);
         }
-        if (centre) dvc = offset_grad_from_d0<T>(n0, n1, n2, T(p), D, cc);
-        const T sz_ = group_sum<T>(zsum);
-        T sbx[3], sby[3], snb[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            sbx[i] = group_sum<T>(bxb[i]);
-            sby[i] = group_sum<T>(byb[i]);
-            snb[i] = group_sum<T>(nbv[i]);
+        T dvc = T(0);
+        if (centre) {
+            T cc[3];
+            dvc = offset_grad_from_d0<T>(n0, n1, n2, T(p), D, cc);
+            L.res[25] = F(cc[0]); L.res[26] = F(cc[1]); L.res[27] = F(cc[2]);
         }
-        const T c0[3] = {group_bcast<T>(cc[0], 26), group_bcast<T>(cc[1], 26), group_bcast<T>(cc[2], 26)};
+        F asum[10];
+        group_colsum<F, 10>(L, j, arow, asum);     // its barriers also publish res[25..27]
+        const T c00 = T(L.res[25]), c01 = T(L.res[26]), c02 = T(L.res[27]);
+        const T sbx0 = T(asum[0]), sbx1 = T(asum[1]), sbx2 = T(asum[2]);
+        const T sz_ = T(asum[9]);
         // the centre offset D0 enters every z with a minus sign
-        T nb0 = snb[0] - sz_ * c0[0], nb1 = snb[1] - sz_ * c0[1], nb2 = snb[2] - sz_ * c0[2];
+        T nb0 = T(asum[6]) - sz_ * c00, nb1 = T(asum[7]) - sz_ * c01, nb2 = T(asum[8]) - sz_ * c02;
         // b_x = b_y x n
-        T yb0 = sby[0] + (n1 * sbx[2] - n2 * sbx[1]);
-        T yb1 = sby[1] + (n2 * sbx[0] - n0 * sbx[2]);
-        T yb2 = sby[2] + (n0 * sbx[1] - n1 * sbx[0]);
-        nb0 += sbx[1] * by2 - sbx[2] * by1;
-        nb1 += sbx[2] * by0 - sbx[0] * by2;
-        nb2 += sbx[0] * by1 - sbx[1] * by0;
+        const T yb0 = T(asum[3]) + (n1 * sbx2 - n2 * sbx1);
+        const T yb1 = T(asum[4]) + (n2 * sbx0 - n0 * sbx2);
+        const T yb2 = T(asum[5]) + (n0 * sbx1 - n1 * sbx0);
+        nb0 += sbx1 * by2 - sbx2 * by1;
+        nb1 += sbx2 * by0 - sbx0 * by2;
+        nb2 += sbx0 * by1 - sbx1 * by0;
         // b_y = u / |u|, u = n x r
         const T bd = by0 * yb0 + by1 * yb1 + by2 * yb2;
         const T ub0 = (yb0 - by0 * bd) * iun, ub1 = (yb1 - by1 * bd) * iun, ub2 = (yb2 - by2 * bd) * iun;
@@ -259,25 +305,90 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
         const T gb0 = -(nb0 - n0 * nd) * ign, gb1 = -(nb1 - n1 * nd) * ign, gb2 = -(nb2 - n2 * nd) * ign;
         if (nbr) out[q] = float(phib + w * (ex * gb0 + ey * gb1 + ez * gb2));
         if (centre) out[13] = float(-sz_ * dvc);
-        (void)gl;
+        __syncwarp();                              // res is reused by the next cell
     }
-    (void)gl;
     return kappa;
 }
 
 // ---------------------------------------------------------------------------
-// 1. streaming scan: zero output everywhere, one interface flag per tile.
-// Thread t of the workgroup handles 4 consecutive cells along x.
+// Fill levels of a box [x0-H, x0+TX+H) x ... into LDS, every load issued
+// before the first store (out-of-lattice cells read as 0).
 // ---------------------------------------------------------------------------
-template <bool VEC>
+template <int RX, int RY, int RZ>
+__device__ __forceinline__ void load_region(float* __restrict__ s, const float* __restrict__ phi, int gx0,
+                                            int gy0, int gz0, int X, int Y, int Z) {
+    constexpr int R = RX * RY * RZ, IT = (R + kThreads - 1) / kThreads;
+    float v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int i = threadIdx.x + it * kThreads;
+        const int lx = i % RX, ly = (i / RX) % RY, lz = i / (RX * RY);
+        const int gx = gx0 + lx, gy = gy0 + ly, gz = gz0 + lz;
+        v[it] = 0.0f;
+        if (i < R && gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z)
+            v[it] = phi[(static_cast<int64_t>(gz) * Y + gy) * X + gx];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int i = threadIdx.x + it * kThreads;
+        if (i < R) s[i] = v[it];
+    }
+}
+
+// Ordered compaction: appends every i in [0, n) with pred(i) to out, in
+// increasing i; returns the count (same on every thread).  Block-wide.
+template <class Pred>
+__device__ __forceinline__ int ordered_compact(int n, Pred pred, unsigned short* out, int* wcount) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int cnt = 0;
+    for (int base = 0; base < n; base += kThreads) {
+        const int i = base + tid;
+        const bool is = i < n && pred(i);
+        const unsigned long long bal = __ballot(is);
+        if (lane == 0) wcount[wave] = __popcll(bal);
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) {
+            before += w < wave ? wcount[w] : 0;
+            total += wcount[w];
+        }
+        if (is) {
+            const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
+            out[cnt + before + __popcll(below)] = static_cast<unsigned short>(i);
+        }
+        cnt += total;
+        __syncthreads();
+    }
+    return cnt;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace: [0, 256) counter; then one flag per tile; then the work list.
+// ---------------------------------------------------------------------------
+constexpr int kPartCells = kGroups;           // interface cells per forward work item
+constexpr int kMaxParts = kTile / kPartCells; // 128
+struct Workspace {
+    unsigned* counter;
+    unsigned* flags;
+    unsigned* list;
+};
+
+__global__ void k_curv_zero(unsigned* counter) { *counter = 0u; }
+
+// ---------------------------------------------------------------------------
+// 1. streaming scan: zero output everywhere.  Forward: append one work item
+// (tile << 7 | part) per kPartCells interface cells of the tile.  Backward:
+// one flag per tile.  Thread t handles 4 consecutive cells along x.
+// ---------------------------------------------------------------------------
+template <bool VEC, bool FWD>
 __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict__ phi, float* __restrict__ out,
-                                                        unsigned* __restrict__ flags, int X, int Y, int Z,
-                                                        int ntx, int nty) {
+                                                        Workspace ws, int X, int Y, int Z, int ntx, int nty) {
     const int tile = blockIdx.x;
     const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
     const int t = threadIdx.x;
     const int x = x0 + (t % 16) * 4, y = y0 + (t / 16) % TY, z = z0 + t / (16 * TY);
-    int any = 0;
+    int cnt = 0;
     if (y < Y && z < Z) {
         const bool yz_in = y >= 1 && y <= Y - 2 && z >= 1 && z <= Z - 2;
         const int64_t row = (static_cast<int64_t>(z) * Y + y) * X;
@@ -287,78 +398,113 @@ __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict_
             const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                any |= yz_in && x + k >= 1 && x + k <= X - 2 && is_iface(vv[k]);
+                cnt += (yz_in && x + k >= 1 && x + k <= X - 2 && is_iface(vv[k])) ? 1 : 0;
         } else {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (x + k < X) {
                     const float v = phi[row + x + k];
                     out[row + x + k] = 0.0f;
-                    any |= yz_in && x + k >= 1 && x + k <= X - 2 && is_iface(v);
+                    cnt += (yz_in && x + k >= 1 && x + k <= X - 2 && is_iface(v)) ? 1 : 0;
                 }
             }
         }
     }
-    any = __syncthreads_or(any);
-    if (t == 0) flags[tile] = any ? 1u : 0u;
+    // block sum of the interface count (wave butterflies, then 4 waves)
+    __shared__ int wsum[kThreads / 64];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
+    if ((t & 63) == 0) wsum[t >> 6] = cnt;
+    __syncthreads();
+    if (t == 0) {
+        int total = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) total += wsum[w];
+        if constexpr (FWD) {
+            const unsigned parts = (total + kPartCells - 1) / kPartCells;
+            if (parts) {
+                const unsigned base = atomicAdd(ws.counter, parts);
+                for (unsigned p = 0; p < parts; ++p) ws.list[base + p] = (static_cast<unsigned>(tile) << 7) | p;
+            }
+        } else {
+            ws.flags[tile] = total ? 1u : 0u;
+        }
+    }
 }
 
-// ---------------------------------------------------------------------------
-// 2a. forward tile kernel: halo 1
-// ---------------------------------------------------------------------------
-constexpr int F_RX = TX + 2, F_RY = TY + 2, F_RZ = TZ + 2, F_REGION = F_RX * F_RY * F_RZ;
-
-template <int SOLVER, class T, class U, class F>
-__global__ __launch_bounds__(kThreads) void k_curv_fwd_tiles(const float* __restrict__ phi,
-                                                              float* __restrict__ kappa,
-                                                              const unsigned* __restrict__ flags, int X, int Y,
-                                                              int Z, int ntx, int nty, int ntiles) {
-    __shared__ float s[F_REGION];
-    __shared__ unsigned short list[kTile];
-    __shared__ int nlist;
-    const int tid = threadIdx.x, grp = tid / kGroup, j = tid % kGroup;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        if (!flags[tile]) continue;                                  // uniform per workgroup
-        const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
-        if (tid == 0) nlist = 0;
-        for (int i = tid; i < F_REGION; i += kThreads) {
-            const int lx = i % F_RX, ly = (i / F_RX) % F_RY, lz = i / (F_RX * F_RY);
-            const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-            float v = 0.0f;
-            if (gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z)
-                v = phi[(static_cast<int64_t>(gz) * Y + gy) * X + gx];
-            s[i] = v;
-        }
-        __syncthreads();
+// backward work list: every tile whose 3x3x3 tile neighbourhood holds an
+// interface cell (its targets can receive a contribution)
+__global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx, int nty, int ntz, int ntiles) {
+    const int tile = blockIdx.x * kThreads + threadIdx.x;
+    bool act = false;
+    if (tile < ntiles) {
+        const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
 #pragma unroll
-        for (int k = 0; k < kCellsPerThread; ++k) {
-            const int cl = tid + k * kThreads;
-            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-            const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
-            const bool interior = gx >= 1 && gy >= 1 && gz >= 1 && gx <= X - 2 && gy <= Y - 2 && gz <= Z - 2;
-            if (interior && is_iface(s[((cz + 1) * F_RY + (cy + 1)) * F_RX + (cx + 1)]))
-                list[atomicAdd(&nlist, 1)] = static_cast<unsigned short>(cl);
+        for (int q = 0; q < 27; ++q) {
+            const int ax = tx + q_dx(q), ay = ty + q_dy(q), az = tz + q_dz(q);
+            if (ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz)
+                act |= ws.flags[(az * nty + ay) * ntx + ax] != 0u;
         }
-        __syncthreads();
-        const int n = nlist;
-        for (int i = grp; i < n; i += kGroups) {
-            const int cl = list[i];
-            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-            const float kv = group_cell<SOLVER, T, U, F, false>(
-                s, ((cz + 1) * F_RY + (cy + 1)) * F_RX + (cx + 1), F_RX, F_RX * F_RY, j, 0.0f, nullptr);
-            if (j == 0) kappa[(static_cast<int64_t>(z0 + cz) * Y + (y0 + cy)) * X + (x0 + cx)] = kv;
-        }
-        __syncthreads();                                             // LDS reused by the next tile
+    }
+    const unsigned long long bal = __ballot(act);
+    const int lane = threadIdx.x & 63;
+    unsigned base = 0;
+    if (lane == 0 && bal) base = atomicAdd(ws.counter, static_cast<unsigned>(__popcll(bal)));
+    base = __shfl(base, 0, 64);
+    if (act) {
+        const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
+        ws.list[base + __popcll(below)] = static_cast<unsigned>(tile);
     }
 }
 
 // ---------------------------------------------------------------------------
-// 2b. backward tile kernel: halo 2.  A tile is processed when it or one of
-// its 26 neighbour tiles holds an interface cell.  Candidates are the
-// interface cells of the tile grown by one cell, listed in region order
-// (ordered wave compaction) and processed in chunks of kChunk; each target
-// cell of the tile then gathers the contributions of its 27 neighbours chunk
-// by chunk in a fixed order, so the result is deterministic.
+// 2a. forward: one work item = up to kPartCells interface cells of a tile,
+// one group of 32 lanes per cell.  The tile's interface cells are listed in
+// cell order, so the part of a work item is well defined.
+// ---------------------------------------------------------------------------
+constexpr int F_RX = TX + 2, F_RY = TY + 2, F_RZ = TZ + 2, F_REGION = F_RX * F_RY * F_RZ;
+
+template <int SOLVER, class T, class U, class F>
+__global__ __launch_bounds__(kThreads) void k_curv_fwd_parts(const float* __restrict__ phi,
+                                                              float* __restrict__ kappa, Workspace ws, int X,
+                                                              int Y, int Z, int ntx, int nty) {
+    __shared__ float s[F_REGION];
+    __shared__ unsigned short list[kTile];
+    __shared__ int wcount[kThreads / 64];
+    __shared__ GroupLds<F> glds[kGroups];
+    const int tid = threadIdx.x, grp = tid / kGroup, j = tid % kGroup;
+    const unsigned nitems = *static_cast<volatile unsigned*>(ws.counter);
+    for (unsigned item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const unsigned e = ws.list[item];
+        const int tile = static_cast<int>(e >> 7), part = static_cast<int>(e & 127u);
+        const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
+        load_region<F_RX, F_RY, F_RZ>(s, phi, x0 - 1, y0 - 1, z0 - 1, X, Y, Z);
+        __syncthreads();
+        const int n = ordered_compact(kTile, [&](int cl) {
+            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
+            const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
+            return gx >= 1 && gy >= 1 && gz >= 1 && gx <= X - 2 && gy <= Y - 2 && gz <= Z - 2 &&
+                   is_iface(s[((cz + 1) * F_RY + (cy + 1)) * F_RX + (cx + 1)]);
+        }, list, wcount);
+        const int i = part * kPartCells + grp;
+        if (i < n) {
+            const int cl = list[i];
+            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
+            const float kv = group_cell<SOLVER, T, U, F, false>(
+                s, ((cz + 1) * F_RY + (cy + 1)) * F_RX + (cx + 1), F_RX, F_RX * F_RY, j, 0.0f, nullptr,
+                glds[grp]);
+            if (j == 0) kappa[(static_cast<int64_t>(z0 + cz) * Y + (y0 + cy)) * X + (x0 + cx)] = kv;
+        }
+        __syncthreads();                                             // LDS reused by the next item
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2b. backward tile kernel: halo 2.  Candidates are the interface cells of the
+// tile grown by one cell, listed in region order and processed in chunks of
+// kChunk; each target cell of the tile then gathers the contributions of its
+// 27 neighbours chunk by chunk in a fixed order, so the result is
+// deterministic.
 // ---------------------------------------------------------------------------
 constexpr int B_RX = TX + 4, B_RY = TY + 4, B_RZ = TZ + 4, B_REGION = B_RX * B_RY * B_RZ;
 constexpr int C_RX = TX + 2, C_RY = TY + 2, C_RZ = TZ + 2, C_REGION = C_RX * C_RY * C_RZ;
@@ -368,62 +514,28 @@ constexpr unsigned short kNoSlot = 0xFFFFu;
 template <int SOLVER, class T, class U, class F>
 __global__ __launch_bounds__(kThreads) void k_curv_bwd_tiles(const float* __restrict__ phi,
                                                               const float* __restrict__ gkap,
-                                                              float* __restrict__ gphi,
-                                                              const unsigned* __restrict__ flags, int X, int Y,
-                                                              int Z, int ntx, int nty, int ntz, int ntiles) {
+                                                              float* __restrict__ gphi, Workspace ws, int X,
+                                                              int Y, int Z, int ntx, int nty) {
     __shared__ float s[B_REGION];
     __shared__ unsigned short cand[C_REGION];
     __shared__ unsigned short slot[C_REGION];
     __shared__ float contrib[kChunk][27];
     __shared__ int wcount[kThreads / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, grp = tid / kGroup, j = tid % kGroup;
+    __shared__ GroupLds<F> glds[kGroups];
+    const int tid = threadIdx.x, grp = tid / kGroup, j = tid % kGroup;
     for (int i = tid; i < C_REGION; i += kThreads) slot[i] = kNoSlot;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
-        int act = 0;
-        if (tid < 27) {
-            const int ax = tx + q_dx(tid), ay = ty + q_dy(tid), az = tz + q_dz(tid);
-            if (ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz)
-                act = flags[(az * nty + ay) * ntx + ax] != 0u;
-        }
-        if (!__syncthreads_or(act)) continue;                        // uniform per workgroup
-        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
-        for (int i = tid; i < B_REGION; i += kThreads) {
-            const int lx = i % B_RX, ly = (i / B_RX) % B_RY, lz = i / (B_RX * B_RY);
-            const int gx = x0 - 2 + lx, gy = y0 - 2 + ly, gz = z0 - 2 + lz;
-            float v = 0.0f;
-            if (gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z)
-                v = phi[(static_cast<int64_t>(gz) * Y + gy) * X + gx];
-            s[i] = v;
-        }
+    const unsigned nitems = *static_cast<volatile unsigned*>(ws.counter);
+    for (unsigned item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int tile = static_cast<int>(ws.list[item]);
+        const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
+        load_region<B_RX, B_RY, B_RZ>(s, phi, x0 - 2, y0 - 2, z0 - 2, X, Y, Z);
         __syncthreads();
-        // ordered compaction of the candidate cells (region order)
-        int ncand = 0;
-        for (int base = 0; base < C_REGION; base += kThreads) {
-            const int i = base + tid;
-            bool is = false;
-            if (i < C_REGION) {
-                const int lx = i % C_RX, ly = (i / C_RX) % C_RY, lz = i / (C_RX * C_RY);
-                const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-                const bool interior = gx >= 1 && gy >= 1 && gz >= 1 && gx <= X - 2 && gy <= Y - 2 && gz <= Z - 2;
-                is = interior && is_iface(s[((lz + 1) * B_RY + (ly + 1)) * B_RX + (lx + 1)]);
-            }
-            const unsigned long long bal = __ballot(is);
-            if (lane == 0) wcount[wave] = __popcll(bal);
-            __syncthreads();
-            int before = 0, total = 0;
-#pragma unroll
-            for (int w = 0; w < kThreads / 64; ++w) {
-                before += w < wave ? wcount[w] : 0;
-                total += wcount[w];
-            }
-            if (is) {
-                const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
-                cand[ncand + before + __popcll(below)] = static_cast<unsigned short>(i);
-            }
-            ncand += total;
-            __syncthreads();
-        }
+        const int ncand = ordered_compact(C_REGION, [&](int ci) {
+            const int lx = ci % C_RX, ly = (ci / C_RX) % C_RY, lz = ci / (C_RX * C_RY);
+            const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
+            return gx >= 1 && gy >= 1 && gz >= 1 && gx <= X - 2 && gy <= Y - 2 && gz <= Z - 2 &&
+                   is_iface(s[((lz + 1) * B_RY + (ly + 1)) * B_RX + (lx + 1)]);
+        }, cand, wcount);
         float acc[kCellsPerThread];
 #pragma unroll
         for (int k = 0; k < kCellsPerThread; ++k) acc[k] = 0.0f;
@@ -436,7 +548,7 @@ __global__ __launch_bounds__(kThreads) void k_curv_bwd_tiles(const float* __rest
                 const float gk =
                     gkap[(static_cast<int64_t>(z0 - 1 + lz) * Y + (y0 - 1 + ly)) * X + (x0 - 1 + lx)];
                 group_cell<SOLVER, T, U, F, true>(s, ((lz + 1) * B_RY + (ly + 1)) * B_RX + (lx + 1), B_RX,
-                                                  B_RX * B_RY, j, gk, contrib[i]);
+                                                  B_RX * B_RY, j, gk, contrib[i], glds[grp]);
             }
             __syncthreads();
 #pragma unroll
@@ -485,6 +597,7 @@ int check_lattice(int64_t X, int64_t Y, int64_t Z, bool* empty, Grid* g) {
     if (X > (int64_t(1) << 62) / Y / Z) return PLIC_EINVAL;
     const int64_t tx = (X + TX - 1) / TX, ty = (Y + TY - 1) / TY, tz = (Z + TZ - 1) / TZ;
     if (tx > lim / ty || tx * ty > lim / tz) return PLIC_EINVAL;   // grid limit
+    if (tx * ty * tz >= (int64_t(1) << 25)) return PLIC_EINVAL;    // work items hold a 25-bit tile index
     g->ntx = static_cast<int>(tx);
     g->nty = static_cast<int>(ty);
     g->ntz = static_cast<int>(tz);
@@ -492,43 +605,59 @@ int check_lattice(int64_t X, int64_t Y, int64_t Z, bool* empty, Grid* g) {
     return PLIC_OK;
 }
 
-size_t workspace_for(const Grid& g) { return (static_cast<size_t>(g.ntiles) * sizeof(unsigned) + 255) & ~size_t(255); }
+size_t workspace_for(const Grid& g) {
+    return 256 + static_cast<size_t>(g.ntiles) * sizeof(unsigned) * (1 + kMaxParts);
+}
 
-void launch_scan(const float* phi, float* out, unsigned* flags, int X, int Y, int Z, const Grid& g,
+Workspace carve(void* base, const Grid& g) {
+    char* p = static_cast<char*>(base);
+    Workspace w;
+    w.counter = reinterpret_cast<unsigned*>(p);
+    w.flags = reinterpret_cast<unsigned*>(p + 256);
+    w.list = w.flags + g.ntiles;
+    return w;
+}
+
+template <bool FWD>
+void launch_scan(const float* phi, float* out, Workspace ws, int X, int Y, int Z, const Grid& g,
                  hipStream_t st) {
+    hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(1), 0, st, ws.counter);
     const bool vec = X % 4 == 0 && aligned(phi, 16) && aligned(out, 16);
     if (vec)
-        hipLaunchKernelGGL((k_curv_scan<true>), dim3(g.ntiles), dim3(kThreads), 0, st, phi, out, flags, X, Y, Z, g.ntx, g.nty);
+        hipLaunchKernelGGL((k_curv_scan<true, FWD>), dim3(g.ntiles), dim3(kThreads), 0, st, phi, out, ws, X, Y, Z, g.ntx, g.nty);
     else
-        hipLaunchKernelGGL((k_curv_scan<false>), dim3(g.ntiles), dim3(kThreads), 0, st, phi, out, flags, X, Y, Z, g.ntx, g.nty);
+        hipLaunchKernelGGL((k_curv_scan<false, FWD>), dim3(g.ntiles), dim3(kThreads), 0, st, phi, out, ws, X, Y, Z, g.ntx, g.nty);
 }
 
-unsigned persistent_grid(const Grid& g) {
-    return static_cast<unsigned>(g.ntiles < kPersistentBlocks ? g.ntiles : kPersistentBlocks);
+unsigned persistent_grid(int items_max) {
+    return static_cast<unsigned>(items_max < kPersistentBlocks ? items_max : kPersistentBlocks);
 }
 
 template <int SOLVER>
-void launch_fwd(int precision, const float* phi, float* kappa, const unsigned* flags, int X, int Y, int Z,
+void launch_fwd(int precision, const float* phi, float* kappa, Workspace ws, int X, int Y, int Z,
                 const Grid& g, hipStream_t st) {
-    const dim3 grid(persistent_grid(g)), block(kThreads);
+    const dim3 grid(persistent_grid(g.ntiles * kMaxParts)), block(kThreads);
     if (precision == PLIC_FP32)
-        hipLaunchKernelGGL((k_curv_fwd_tiles<SOLVER, float, float, float>), grid, block, 0, st, phi, kappa, flags, X, Y, Z, g.ntx, g.nty, g.ntiles);
+        hipLaunchKernelGGL((k_curv_fwd_parts<SOLVER, float, float, float>), grid, block, 0, st, phi, kappa, ws, X, Y, Z, g.ntx, g.nty);
     else if (precision == PLIC_MIXED)
-        hipLaunchKernelGGL((k_curv_fwd_tiles<SOLVER, float, double, double>), grid, block, 0, st, phi, kappa, flags, X, Y, Z, g.ntx, g.nty, g.ntiles);
+        hipLaunchKernelGGL((k_curv_fwd_parts<SOLVER, float, double, double>), grid, block, 0, st, phi, kappa, ws, X, Y, Z, g.ntx, g.nty);
     else
-        hipLaunchKernelGGL((k_curv_fwd_tiles<SOLVER, double, double, double>), grid, block, 0, st, phi, kappa, flags, X, Y, Z, g.ntx, g.nty, g.ntiles);
+        hipLaunchKernelGGL((k_curv_fwd_parts<SOLVER, double, double, double>), grid, block, 0, st, phi, kappa, ws, X, Y, Z, g.ntx, g.nty);
 }
 
 template <int SOLVER>
-void launch_bwd(int precision, const float* phi, const float* gk, float* gp, const unsigned* flags, int X,
-                int Y, int Z, const Grid& g, hipStream_t st) {
-    const dim3 grid(persistent_grid(g)), block(kThreads);
+void launch_bwd(int precision, const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y,
+                int Z, const Grid& g, hipStream_t st) {
+    hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(1), 0, st, ws.counter);
+    hipLaunchKernelGGL(k_curv_dilate, dim3((g.ntiles + kThreads - 1) / kThreads), dim3(kThreads), 0, st, ws,
+                       g.ntx, g.nty, g.ntz, g.ntiles);
+    const dim3 grid(persistent_grid(g.ntiles)), block(kThreads);
     if (precision == PLIC_FP32)
-        hipLaunchKernelGGL((k_curv_bwd_tiles<SOLVER, float, float, float>), grid, block, 0, st, phi, gk, gp, flags, X, Y, Z, g.ntx, g.nty, g.ntz, g.ntiles);
+        hipLaunchKernelGGL((k_curv_bwd_tiles<SOLVER, float, float, float>), grid, block, 0, st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
     else if (precision == PLIC_MIXED)
-        hipLaunchKernelGGL((k_curv_bwd_tiles<SOLVER, float, double, double>), grid, block, 0, st, phi, gk, gp, flags, X, Y, Z, g.ntx, g.nty, g.ntz, g.ntiles);
+        hipLaunchKernelGGL((k_curv_bwd_tiles<SOLVER, float, double, double>), grid, block, 0, st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
     else
-        hipLaunchKernelGGL((k_curv_bwd_tiles<SOLVER, double, double, double>), grid, block, 0, st, phi, gk, gp, flags, X, Y, Z, g.ntx, g.nty, g.ntz, g.ntiles);
+        hipLaunchKernelGGL((k_curv_bwd_tiles<SOLVER, double, double, double>), grid, block, 0, st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
 }
 
 // shared argument checks of the two entry points
@@ -573,14 +702,14 @@ int plic_curvature_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float*
     if (!empty && overlap(workspace, workspace_for(g), kappa, nb)) return PLIC_EINVAL;
     if (empty) return PLIC_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    unsigned* flags = static_cast<unsigned*>(workspace);
+    const Workspace ws = carve(workspace, g);
     const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
-    launch_scan(phi, kappa, flags, x, y, z, g, st);
+    launch_scan<true>(phi, kappa, ws, x, y, z, g, st);
     switch (solver) {
-        case kSZ: launch_fwd<kSZ>(precision, phi, kappa, flags, x, y, z, g, st); break;
-        case kNewton: launch_fwd<kNewton>(precision, phi, kappa, flags, x, y, z, g, st); break;
-        case kNested: launch_fwd<kNested>(precision, phi, kappa, flags, x, y, z, g, st); break;
-        default: launch_fwd<kAnalytic>(precision, phi, kappa, flags, x, y, z, g, st); break;
+        case kSZ: launch_fwd<kSZ>(precision, phi, kappa, ws, x, y, z, g, st); break;
+        case kNewton: launch_fwd<kNewton>(precision, phi, kappa, ws, x, y, z, g, st); break;
+        case kNested: launch_fwd<kNested>(precision, phi, kappa, ws, x, y, z, g, st); break;
+        default: launch_fwd<kAnalytic>(precision, phi, kappa, ws, x, y, z, g, st); break;
     }
     return launch_status();
 }
@@ -601,14 +730,14 @@ int plic_curvature_backward_f32(const float* phi, int64_t X, int64_t Y, int64_t 
         return PLIC_EINVAL;
     if (empty) return PLIC_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    unsigned* flags = static_cast<unsigned*>(workspace);
+    const Workspace ws = carve(workspace, g);
     const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
-    launch_scan(phi, grad_phi, flags, x, y, z, g, st);
+    launch_scan<false>(phi, grad_phi, ws, x, y, z, g, st);
     switch (solver) {
-        case kSZ: launch_bwd<kSZ>(precision, phi, grad_kappa, grad_phi, flags, x, y, z, g, st); break;
-        case kNewton: launch_bwd<kNewton>(precision, phi, grad_kappa, grad_phi, flags, x, y, z, g, st); break;
-        case kNested: launch_bwd<kNested>(precision, phi, grad_kappa, grad_phi, flags, x, y, z, g, st); break;
-        default: launch_bwd<kAnalytic>(precision, phi, grad_kappa, grad_phi, flags, x, y, z, g, st); break;
+        case kSZ: launch_bwd<kSZ>(precision, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
+        case kNewton: launch_bwd<kNewton>(precision, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
+        case kNested: launch_bwd<kNested>(precision, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
+        default: launch_bwd<kAnalytic>(precision, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
     }
     return launch_status();
 }

@@ -98,8 +98,8 @@ def test_backward_validation(lib):
 
 
 def test_curvature_validation(lib):
-    assert lib.plic_curvature_workspace_bytes(256, 256, 256) == 16384 * 4
-    assert lib.plic_curvature_workspace_bytes(65, 5, 5) == 256          # 8 tiles, rounded up
+    assert lib.plic_curvature_workspace_bytes(256, 256, 256) == 256 + 16384 * 4 * 129
+    assert lib.plic_curvature_workspace_bytes(65, 5, 5) == 256 + 8 * 4 * 129   # 2x2x2 tiles
     assert lib.plic_curvature_workspace_bytes(0, 5, 5) == 0
     assert lib.plic_curvature_workspace_bytes(-1, 5, 5) == 0
     W = 0xA0000

@@ -621,7 +621,7 @@ Workspace carve(void* base, const Grid& g) {
 template <bool FWD>
 void launch_scan(const float* phi, float* out, Workspace ws, int X, int Y, int Z, const Grid& g,
                  hipStream_t st) {
-    hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(1), 0, st, ws.counter);
+    if (FWD) hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(1), 0, st, ws.counter);
     const bool vec = X % 4 == 0 && aligned(phi, 16) && aligned(out, 16);
     if (vec)
         hipLaunchKernelGGL((k_curv_scan<true, FWD>), dim3(g.ntiles), dim3(kThreads), 0, st, phi, out, ws, X, Y, Z, g.ntx, g.nty);

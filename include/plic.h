@@ -101,13 +101,18 @@ int plic_offset_backward_f64(const double *nx, const double *ny, const double *n
                              int solver, void *stream);
 
 /*
- * plic_curvature_workspace_bytes — size of the device workspace that
- * plic_curvature_f32 and plic_curvature_backward_f32 need for an X*Y*Z lattice:
- * a work-list counter, one flag per 64x4x4 tile and a work list of at most
- * 128 entries per tile: 256 + 516 * tiles bytes (8.5 MB at 256^3, about 0.5
- * byte per cell).  0 for an empty or invalid lattice (more than 2^25 tiles is
- * invalid).  The workspace is caller-owned device memory; its contents need
- * no initialisation (each call clears what it uses with a kernel) and are
+ * plic_curvature_workspace_bytes — recommended size of the device workspace of
+ * plic_curvature_f32 and plic_curvature_backward_f32 for an X*Y*Z lattice.
+ * The workspace holds a fixed part of 256 + 784 * tiles bytes (64x4x4 tiles:
+ * work-list counters, per-tile interface flags, bitmasks and work lists;
+ * about 0.8 byte per cell) and, for the backward pass, a store of 108 bytes
+ * (27 floats) per interface cell.  The recommended size budgets 16 interface
+ * cells per tile (41 MB at 256^3); any size of at least the fixed part is
+ * valid: interface cells beyond the store's capacity are recomputed by the
+ * backward pass (slower, same result).  The forward pass uses only the fixed
+ * part.  0 for an empty or invalid lattice (more than 2^25 tiles is invalid).
+ * The workspace is caller-owned device memory; its contents need no
+ * initialisation (each call clears what it uses with a kernel) and are
  * scratch after the call.
  */
 size_t plic_curvature_workspace_bytes(int64_t X, int64_t Y, int64_t Z);
@@ -124,10 +129,10 @@ size_t plic_curvature_workspace_bytes(int64_t X, int64_t Y, int64_t Z);
  *           the outer layer.  Must not overlap phi or the workspace.
  *   solver, precision : PLIC solver for the points; PLIC_FP32 fits in FP32,
  *           PLIC_MIXED fits in FP64 (FP32 points), PLIC_FP64 is FP64 throughout.
- *   workspace, workspace_bytes : device scratch of at least
- *           plic_curvature_workspace_bytes(X, Y, Z) bytes, 4-byte aligned, not
- *           overlapping phi or kappa.  Calls that overlap in time must use
- *           distinct workspaces.
+ *   workspace, workspace_bytes : device scratch, 4-byte aligned, not
+ *           overlapping phi or kappa, of at least the fixed part (see
+ *           plic_curvature_workspace_bytes).  Calls that overlap in time must
+ *           use distinct workspaces.
  * Sign: kappa = +1/R for a fluid sphere of radius R (the normal points out of
  * the fluid); the paper's formula is negated for this.  Fits with fewer than 5
  * points use the leading parameters only (App. B.3); a pivot of the LDL^T

@@ -364,31 +364,69 @@ __device__ __forceinline__ int ordered_compact(int n, Pred pred, unsigned short*
 }
 
 // ---------------------------------------------------------------------------
-// Workspace: [0, 256) counter; then one flag per tile; then the work list.
+// Workspace (caller device memory, 4-byte aligned):
+//   [0, 256)  counters: [0] work items, [1] gather tiles, [2] overflow tiles
+//   flags     ntiles      tile holds an interface cell (backward)
+//   cbase     ntiles      first contribution row of the tile's interface cells
+//   mask      32 ntiles   interface bit of each of the tile's 1024 cells
+//   prefix    32 ntiles   set bits of mask before word w
+//   items     128 ntiles  work items (tile << 7 | part), 8 interface cells each
+//   tiles     ntiles      backward gather tiles
+//   over      ntiles      gather tiles holding a cell without a stored row
+//   contrib   the rest:   27 floats per row (backward contributions)
+// The fixed part (everything but contrib) is 784 bytes per tile.  The
+// backward stores the 27 contributions of an interface cell in row
+// cbase[tile] + rank when that row fits; cells beyond the capacity are
+// recomputed by the gather kernel, so every workspace size >= the fixed part
+// is correct and a larger one is faster.
 // ---------------------------------------------------------------------------
-constexpr int kPartCells = kGroups;           // interface cells per forward work item
+constexpr int kPartCells = kGroups;           // interface cells per work item
 constexpr int kMaxParts = kTile / kPartCells; // 128
+constexpr int kWords = kTile / 32;            // mask words per tile
+constexpr size_t kFixedPerTile = sizeof(unsigned) * (1 + 1 + kWords + kWords + kMaxParts + 1 + 1);
+constexpr size_t kRowBytes = 27 * sizeof(float);
+constexpr size_t kDefaultRowsPerTile = 16;    // contribution rows budgeted per tile by default
+// rows are 32-bit indices: capacity and first rows saturate here, so that a
+// first row plus a rank (< kTile) never wraps and a saturated tile recomputes
+constexpr unsigned kRowCap = 0xF0000000u;
+
 struct Workspace {
-    unsigned* counter;
+    unsigned* counter;  // [0] items, [1] gather tiles, [2] overflow tiles
     unsigned* flags;
-    unsigned* list;
+    unsigned* cbase;
+    unsigned* mask;
+    unsigned* prefix;
+    unsigned* items;
+    unsigned* tiles;
+    unsigned* over;
+    float* contrib;
+    unsigned rows;      // contribution capacity
 };
 
-__global__ void k_curv_zero(unsigned* counter) { *counter = 0u; }
+__global__ void k_curv_zero(unsigned* counter) {
+    counter[0] = 0u;
+    counter[1] = 0u;
+    counter[2] = 0u;
+}
 
 // ---------------------------------------------------------------------------
-// 1. streaming scan: zero output everywhere.  Forward: append one work item
-// (tile << 7 | part) per kPartCells interface cells of the tile.  Backward:
-// one flag per tile.  Thread t handles 4 consecutive cells along x.
+// 1. streaming scan: zero output everywhere; one work item (tile << 7 | part)
+// per kPartCells interface cells of the tile.  The backward also records the
+// tile's flag, interface bitmask, its prefix counts and its first
+// contribution row.  Thread t handles 4 consecutive cells along x, which are
+// the cells 4t .. 4t+3 of the tile in cell order (x fastest, then y, z).
 // ---------------------------------------------------------------------------
 template <bool VEC, bool FWD>
 __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict__ phi, float* __restrict__ out,
                                                         Workspace ws, int X, int Y, int Z, int ntx, int nty) {
+    __shared__ int wsum[kThreads / 64];
+    __shared__ unsigned smask[kWords];
     const int tile = blockIdx.x;
     const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
     const int t = threadIdx.x;
     const int x = x0 + (t % 16) * 4, y = y0 + (t / 16) % TY, z = z0 + t / (16 * TY);
-    int cnt = 0;
+    if (!FWD && t < kWords) smask[t] = 0u;
+    unsigned nib = 0u;
     if (y < Y && z < Z) {
         const bool yz_in = y >= 1 && y <= Y - 2 && z >= 1 && z <= Z - 2;
         const int64_t row = (static_cast<int64_t>(z) * Y + y) * X;
@@ -398,41 +436,54 @@ __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict_
             const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                cnt += (yz_in && x + k >= 1 && x + k <= X - 2 && is_iface(vv[k])) ? 1 : 0;
+                nib |= (yz_in && x + k >= 1 && x + k <= X - 2 && is_iface(vv[k])) ? (1u << k) : 0u;
         } else {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (x + k < X) {
                     const float v = phi[row + x + k];
                     out[row + x + k] = 0.0f;
-                    cnt += (yz_in && x + k >= 1 && x + k <= X - 2 && is_iface(v)) ? 1 : 0;
+                    nib |= (yz_in && x + k >= 1 && x + k <= X - 2 && is_iface(v)) ? (1u << k) : 0u;
                 }
             }
         }
     }
-    // block sum of the interface count (wave butterflies, then 4 waves)
-    __shared__ int wsum[kThreads / 64];
+    // block count of interface cells (wave butterflies, then 4 waves)
+    int cnt = __popc(nib);
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
     if ((t & 63) == 0) wsum[t >> 6] = cnt;
+    if constexpr (!FWD) {
+        __syncthreads();                                  // smask cleared
+        if (nib) atomicOr(&smask[t / 8], nib << ((t % 8) * 4));
+    }
     __syncthreads();
-    if (t == 0) {
-        int total = 0;
+    int total = 0;
 #pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) total += wsum[w];
-        if constexpr (FWD) {
-            const unsigned parts = (total + kPartCells - 1) / kPartCells;
-            if (parts) {
-                const unsigned base = atomicAdd(ws.counter, parts);
-                for (unsigned p = 0; p < parts; ++p) ws.list[base + p] = (static_cast<unsigned>(tile) << 7) | p;
-            }
-        } else {
-            ws.flags[tile] = total ? 1u : 0u;
+    for (int w = 0; w < kThreads / 64; ++w) total += wsum[w];
+    const unsigned parts = (total + kPartCells - 1) / kPartCells;
+    if (t == 0) {
+        unsigned base = 0u;
+        if (parts) {
+            base = atomicAdd(ws.counter, parts);
+            for (unsigned p = 0; p < parts; ++p) ws.items[base + p] = (static_cast<unsigned>(tile) << 7) | p;
         }
+        if constexpr (!FWD) {
+            ws.flags[tile] = total ? 1u : 0u;
+            ws.cbase[tile] = base < kRowCap / kPartCells ? base * kPartCells : kRowCap;
+            unsigned acc = 0u;
+            for (int w = 0; w < kWords; ++w) {
+                ws.prefix[tile * kWords + w] = acc;
+                acc += __popc(smask[w]);
+            }
+        }
+    }
+    if constexpr (!FWD) {
+        if (t < kWords) ws.mask[tile * kWords + t] = smask[t];
     }
 }
 
-// backward work list: every tile whose 3x3x3 tile neighbourhood holds an
+// backward gather list: every tile whose 3x3x3 tile neighbourhood holds an
 // interface cell (its targets can receive a contribution)
 __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx, int nty, int ntz, int ntiles) {
     const int tile = blockIdx.x * kThreads + threadIdx.x;
@@ -449,25 +500,28 @@ __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx,
     const unsigned long long bal = __ballot(act);
     const int lane = threadIdx.x & 63;
     unsigned base = 0;
-    if (lane == 0 && bal) base = atomicAdd(ws.counter, static_cast<unsigned>(__popcll(bal)));
+    if (lane == 0 && bal) base = atomicAdd(ws.counter + 1, static_cast<unsigned>(__popcll(bal)));
     base = __shfl(base, 0, 64);
     if (act) {
         const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
-        ws.list[base + __popcll(below)] = static_cast<unsigned>(tile);
+        ws.tiles[base + __popcll(below)] = static_cast<unsigned>(tile);
     }
 }
 
 // ---------------------------------------------------------------------------
-// 2a. forward: one work item = up to kPartCells interface cells of a tile,
-// one group of 32 lanes per cell.  The tile's interface cells are listed in
-// cell order, so the part of a work item is well defined.
+// 2. work items: up to kPartCells interface cells of a tile, one group of 32
+// lanes per cell, the tile's fill levels plus a one-cell halo in LDS.  The
+// tile's interface cells are listed in cell order, so the part of an item is
+// well defined.  Forward: kappa.  Backward: the cell's 27 contributions
+// gk * d kappa / d phi_q into its contribution row (when it fits).
 // ---------------------------------------------------------------------------
 constexpr int F_RX = TX + 2, F_RY = TY + 2, F_RZ = TZ + 2, F_REGION = F_RX * F_RY * F_RZ;
 
-template <int SOLVER, class T, class U, class F>
-__global__ __launch_bounds__(kThreads) void k_curv_fwd_parts(const float* __restrict__ phi,
-                                                              float* __restrict__ kappa, Workspace ws, int X,
-                                                              int Y, int Z, int ntx, int nty) {
+template <int SOLVER, class T, class U, class F, bool ADJ>
+__global__ __launch_bounds__(kThreads) void k_curv_items(const float* __restrict__ phi,
+                                                          const float* __restrict__ gkap,
+                                                          float* __restrict__ kappa, Workspace ws, int X, int Y,
+                                                          int Z, int ntx, int nty) {
     __shared__ float s[F_REGION];
     __shared__ unsigned short list[kTile];
     __shared__ int wcount[kThreads / 64];
@@ -475,8 +529,13 @@ __global__ __launch_bounds__(kThreads) void k_curv_fwd_parts(const float* __rest
     const int tid = threadIdx.x, grp = tid / kGroup, j = tid % kGroup;
     const unsigned nitems = *static_cast<volatile unsigned*>(ws.counter);
     for (unsigned item = blockIdx.x; item < nitems; item += gridDim.x) {
-        const unsigned e = ws.list[item];
+        const unsigned e = ws.items[item];
         const int tile = static_cast<int>(e >> 7), part = static_cast<int>(e & 127u);
+        unsigned row0 = 0u;
+        if constexpr (ADJ) {
+            row0 = ws.cbase[tile] + static_cast<unsigned>(part * kPartCells);
+            if (row0 >= ws.rows) continue;                       // uniform; the gather recomputes
+        }
         const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
         load_region<F_RX, F_RY, F_RZ>(s, phi, x0 - 1, y0 - 1, z0 - 1, X, Y, Z);
         __syncthreads();
@@ -490,52 +549,90 @@ __global__ __launch_bounds__(kThreads) void k_curv_fwd_parts(const float* __rest
         if (i < n) {
             const int cl = list[i];
             const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-            const float kv = group_cell<SOLVER, T, U, F, false>(
-                s, ((cz + 1) * F_RY + (cy + 1)) * F_RX + (cx + 1), F_RX, F_RX * F_RY, j, 0.0f, nullptr,
-                glds[grp]);
-            if (j == 0) kappa[(static_cast<int64_t>(z0 + cz) * Y + (y0 + cy)) * X + (x0 + cx)] = kv;
+            const int64_t g = (static_cast<int64_t>(z0 + cz) * Y + (y0 + cy)) * X + (x0 + cx);
+            const int c = ((cz + 1) * F_RY + (cy + 1)) * F_RX + (cx + 1);
+            if constexpr (ADJ) {
+                const unsigned r = row0 + static_cast<unsigned>(grp);
+                if (r < ws.rows)                                 // uniform per group
+                    group_cell<SOLVER, T, U, F, true>(s, c, F_RX, F_RX * F_RY, j, gkap[g],
+                                                      ws.contrib + static_cast<size_t>(r) * 27, glds[grp]);
+            } else {
+                const float kv = group_cell<SOLVER, T, U, F, false>(s, c, F_RX, F_RX * F_RY, j, 0.0f, nullptr,
+                                                                     glds[grp]);
+                if (j == 0) kappa[g] = kv;
+            }
         }
-        __syncthreads();                                             // LDS reused by the next item
+        __syncthreads();                                         // LDS reused by the next item
     }
 }
 
 // ---------------------------------------------------------------------------
-// 2b. backward tile kernel: halo 2.  Candidates are the interface cells of the
-// tile grown by one cell, listed in region order and processed in chunks of
-// kChunk; each target cell of the tile then gathers the contributions of its
-// 27 neighbours chunk by chunk in a fixed order, so the result is
-// deterministic.
+// 3. backward gather: per tile of the gather list, the candidates are the
+// interface cells of the tile grown by one cell, in region order, processed in
+// chunks of kChunk.  A candidate's 27 contributions are copied from its
+// contribution row, or recomputed (halo 2 in LDS) when the row did not fit.
+// Each target cell of the tile then adds the contributions of its 27
+// neighbours chunk by chunk in a fixed order: deterministic, no atomics.
 // ---------------------------------------------------------------------------
 constexpr int B_RX = TX + 4, B_RY = TY + 4, B_RZ = TZ + 4, B_REGION = B_RX * B_RY * B_RZ;
 constexpr int C_RX = TX + 2, C_RY = TY + 2, C_RZ = TZ + 2, C_REGION = C_RX * C_RY * C_RZ;
 constexpr int kChunk = 128;
 constexpr unsigned short kNoSlot = 0xFFFFu;
 
-template <int SOLVER, class T, class U, class F>
-__global__ __launch_bounds__(kThreads) void k_curv_bwd_tiles(const float* __restrict__ phi,
-                                                              const float* __restrict__ gkap,
-                                                              float* __restrict__ gphi, Workspace ws, int X,
-                                                              int Y, int Z, int ntx, int nty) {
-    __shared__ float s[B_REGION];
+// contribution row of an interior interface cell: cbase of its tile plus its
+// rank among the tile's interface cells in cell order
+__device__ __forceinline__ unsigned contrib_row(const Workspace& ws, int gx, int gy, int gz, int ntx, int nty) {
+    const int ctile = ((gz / TZ) * nty + gy / TY) * ntx + gx / TX;
+    const int l = ((gz % TZ) * TY + gy % TY) * TX + gx % TX;
+    const unsigned w = ws.mask[ctile * kWords + l / 32];
+    return ws.cbase[ctile] + ws.prefix[ctile * kWords + l / 32] + __popc(w & ((1u << (l % 32)) - 1u));
+}
+
+// FALLBACK = false: tiles of the gather list; a tile with a candidate whose row
+// did not fit is passed on to the overflow list untouched.  FALLBACK = true:
+// the overflow list, candidates without a row recomputed here.  Splitting keeps
+// the register-heavy recomputation out of the common kernel.
+template <int SOLVER, class T, class U, class F, bool FALLBACK>
+__global__ __launch_bounds__(kThreads) void k_curv_gather(const float* __restrict__ phi,
+                                                           const float* __restrict__ gkap,
+                                                           float* __restrict__ gphi, Workspace ws, int X, int Y,
+                                                           int Z, int ntx, int nty) {
+    // the lean kernel only tests interface status (halo 1); recomputation needs halo 2
+    constexpr int RX = FALLBACK ? B_RX : F_RX, RY = FALLBACK ? B_RY : F_RY, RZ = FALLBACK ? B_RZ : F_RZ;
+    constexpr int H = FALLBACK ? 2 : 1;
+    __shared__ float s[RX * RY * RZ];
     __shared__ unsigned short cand[C_REGION];
     __shared__ unsigned short slot[C_REGION];
     __shared__ float contrib[kChunk][27];
     __shared__ int wcount[kThreads / 64];
-    __shared__ GroupLds<F> glds[kGroups];
+    __shared__ GroupLds<F> glds[FALLBACK ? kGroups : 1];
     const int tid = threadIdx.x, grp = tid / kGroup, j = tid % kGroup;
     for (int i = tid; i < C_REGION; i += kThreads) slot[i] = kNoSlot;
-    const unsigned nitems = *static_cast<volatile unsigned*>(ws.counter);
-    for (unsigned item = blockIdx.x; item < nitems; item += gridDim.x) {
-        const int tile = static_cast<int>(ws.list[item]);
+    const unsigned ntl = *static_cast<volatile unsigned*>(ws.counter + (FALLBACK ? 2 : 1));
+    const unsigned* tiles = FALLBACK ? ws.over : ws.tiles;
+    for (unsigned it = blockIdx.x; it < ntl; it += gridDim.x) {
+        const int tile = static_cast<int>(tiles[it]);
         const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
-        load_region<B_RX, B_RY, B_RZ>(s, phi, x0 - 2, y0 - 2, z0 - 2, X, Y, Z);
+        load_region<RX, RY, RZ>(s, phi, x0 - H, y0 - H, z0 - H, X, Y, Z);
         __syncthreads();
         const int ncand = ordered_compact(C_REGION, [&](int ci) {
             const int lx = ci % C_RX, ly = (ci / C_RX) % C_RY, lz = ci / (C_RX * C_RY);
             const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
             return gx >= 1 && gy >= 1 && gz >= 1 && gx <= X - 2 && gy <= Y - 2 && gz <= Z - 2 &&
-                   is_iface(s[((lz + 1) * B_RY + (ly + 1)) * B_RX + (lx + 1)]);
+                   is_iface(s[((lz + H - 1) * RY + (ly + H - 1)) * RX + (lx + H - 1)]);
         }, cand, wcount);
+        if constexpr (!FALLBACK) {
+            int miss = 0;
+            for (int i = tid; i < ncand; i += kThreads) {
+                const int ci = cand[i];
+                const int lx = ci % C_RX, ly = (ci / C_RX) % C_RY, lz = ci / (C_RX * C_RY);
+                miss |= contrib_row(ws, x0 - 1 + lx, y0 - 1 + ly, z0 - 1 + lz, ntx, nty) >= ws.rows;
+            }
+            if (__syncthreads_or(miss)) {                            // uniform per workgroup
+                if (tid == 0) ws.over[atomicAdd(ws.counter + 2, 1u)] = static_cast<unsigned>(tile);
+                continue;
+            }
+        }
         float acc[kCellsPerThread];
 #pragma unroll
         for (int k = 0; k < kCellsPerThread; ++k) acc[k] = 0.0f;
@@ -545,13 +642,18 @@ __global__ __launch_bounds__(kThreads) void k_curv_bwd_tiles(const float* __rest
             for (int i = grp; i < nc; i += kGroups) {
                 const int ci = cand[c0 + i];
                 const int lx = ci % C_RX, ly = (ci / C_RX) % C_RY, lz = ci / (C_RX * C_RY);
-                const float gk =
-                    gkap[(static_cast<int64_t>(z0 - 1 + lz) * Y + (y0 - 1 + ly)) * X + (x0 - 1 + lx)];
-                group_cell<SOLVER, T, U, F, true>(s, ((lz + 1) * B_RY + (ly + 1)) * B_RX + (lx + 1), B_RX,
-                                                  B_RX * B_RY, j, gk, contrib[i], glds[grp]);
+                const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
+                const unsigned r = contrib_row(ws, gx, gy, gz, ntx, nty);
+                if (r < ws.rows) {                                   // uniform per group
+                    if (j < 27) contrib[i][j] = ws.contrib[static_cast<size_t>(r) * 27 + j];
+                } else if constexpr (FALLBACK) {
+                    const float gk = gkap[(static_cast<int64_t>(gz) * Y + gy) * X + gx];
+                    group_cell<SOLVER, T, U, F, true>(s, ((lz + 1) * RY + (ly + 1)) * RX + (lx + 1), RX,
+                                                      RX * RY, j, gk, contrib[i], glds[grp]);
+                }
             }
             __syncthreads();
-#pragma unroll
+#pragma unroll 1
             for (int k = 0; k < kCellsPerThread; ++k) {
                 const int cl = tid + k * kThreads;
                 const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
@@ -605,23 +707,30 @@ int check_lattice(int64_t X, int64_t Y, int64_t Z, bool* empty, Grid* g) {
     return PLIC_OK;
 }
 
-size_t workspace_for(const Grid& g) {
-    return 256 + static_cast<size_t>(g.ntiles) * sizeof(unsigned) * (1 + kMaxParts);
-}
+size_t fixed_bytes(const Grid& g) { return 256 + static_cast<size_t>(g.ntiles) * kFixedPerTile; }
 
-Workspace carve(void* base, const Grid& g) {
+Workspace carve(void* base, size_t bytes, const Grid& g) {
     char* p = static_cast<char*>(base);
+    const size_t nt = static_cast<size_t>(g.ntiles);
     Workspace w;
     w.counter = reinterpret_cast<unsigned*>(p);
     w.flags = reinterpret_cast<unsigned*>(p + 256);
-    w.list = w.flags + g.ntiles;
+    w.cbase = w.flags + nt;
+    w.mask = w.cbase + nt;
+    w.prefix = w.mask + nt * kWords;
+    w.items = w.prefix + nt * kWords;
+    w.tiles = w.items + nt * kMaxParts;
+    w.over = w.tiles + nt;
+    w.contrib = reinterpret_cast<float*>(w.over + nt);
+    const size_t rows = (bytes - fixed_bytes(g)) / kRowBytes;
+    w.rows = static_cast<unsigned>(rows < kRowCap ? rows : kRowCap);
     return w;
 }
 
 template <bool FWD>
 void launch_scan(const float* phi, float* out, Workspace ws, int X, int Y, int Z, const Grid& g,
                  hipStream_t st) {
-    if (FWD) hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(1), 0, st, ws.counter);
+    hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(1), 0, st, ws.counter);
     const bool vec = X % 4 == 0 && aligned(phi, 16) && aligned(out, 16);
     if (vec)
         hipLaunchKernelGGL((k_curv_scan<true, FWD>), dim3(g.ntiles), dim3(kThreads), 0, st, phi, out, ws, X, Y, Z, g.ntx, g.nty);
@@ -629,35 +738,46 @@ void launch_scan(const float* phi, float* out, Workspace ws, int X, int Y, int Z
         hipLaunchKernelGGL((k_curv_scan<false, FWD>), dim3(g.ntiles), dim3(kThreads), 0, st, phi, out, ws, X, Y, Z, g.ntx, g.nty);
 }
 
-unsigned persistent_grid(int items_max) {
+unsigned persistent_grid(int64_t items_max) {
     return static_cast<unsigned>(items_max < kPersistentBlocks ? items_max : kPersistentBlocks);
+}
+
+template <int SOLVER, class T, class U, class F>
+void launch_items(bool adj, const float* phi, const float* gk, float* kappa, Workspace ws, int X, int Y,
+                  int Z, const Grid& g, hipStream_t st) {
+    const dim3 grid(persistent_grid(static_cast<int64_t>(g.ntiles) * kMaxParts)), block(kThreads);
+    if (adj)
+        hipLaunchKernelGGL((k_curv_items<SOLVER, T, U, F, true>), grid, block, 0, st, phi, gk, kappa, ws, X, Y, Z, g.ntx, g.nty);
+    else
+        hipLaunchKernelGGL((k_curv_items<SOLVER, T, U, F, false>), grid, block, 0, st, phi, gk, kappa, ws, X, Y, Z, g.ntx, g.nty);
 }
 
 template <int SOLVER>
 void launch_fwd(int precision, const float* phi, float* kappa, Workspace ws, int X, int Y, int Z,
                 const Grid& g, hipStream_t st) {
-    const dim3 grid(persistent_grid(g.ntiles * kMaxParts)), block(kThreads);
-    if (precision == PLIC_FP32)
-        hipLaunchKernelGGL((k_curv_fwd_parts<SOLVER, float, float, float>), grid, block, 0, st, phi, kappa, ws, X, Y, Z, g.ntx, g.nty);
-    else if (precision == PLIC_MIXED)
-        hipLaunchKernelGGL((k_curv_fwd_parts<SOLVER, float, double, double>), grid, block, 0, st, phi, kappa, ws, X, Y, Z, g.ntx, g.nty);
-    else
-        hipLaunchKernelGGL((k_curv_fwd_parts<SOLVER, double, double, double>), grid, block, 0, st, phi, kappa, ws, X, Y, Z, g.ntx, g.nty);
+    if (precision == PLIC_FP32) launch_items<SOLVER, float, float, float>(false, phi, nullptr, kappa, ws, X, Y, Z, g, st);
+    else if (precision == PLIC_MIXED) launch_items<SOLVER, float, double, double>(false, phi, nullptr, kappa, ws, X, Y, Z, g, st);
+    else launch_items<SOLVER, double, double, double>(false, phi, nullptr, kappa, ws, X, Y, Z, g, st);
+}
+
+template <int SOLVER, class T, class U, class F>
+void launch_bwd_t(const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y, int Z,
+                  const Grid& g, hipStream_t st) {
+    if (ws.rows > 0) launch_items<SOLVER, T, U, F>(true, phi, gk, nullptr, ws, X, Y, Z, g, st);
+    hipLaunchKernelGGL(k_curv_dilate, dim3((g.ntiles + kThreads - 1) / kThreads), dim3(kThreads), 0, st, ws,
+                       g.ntx, g.nty, g.ntz, g.ntiles);
+    hipLaunchKernelGGL((k_curv_gather<SOLVER, T, U, F, false>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0,
+                       st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
+    hipLaunchKernelGGL((k_curv_gather<SOLVER, T, U, F, true>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0,
+                       st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
 }
 
 template <int SOLVER>
 void launch_bwd(int precision, const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y,
                 int Z, const Grid& g, hipStream_t st) {
-    hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(1), 0, st, ws.counter);
-    hipLaunchKernelGGL(k_curv_dilate, dim3((g.ntiles + kThreads - 1) / kThreads), dim3(kThreads), 0, st, ws,
-                       g.ntx, g.nty, g.ntz, g.ntiles);
-    const dim3 grid(persistent_grid(g.ntiles)), block(kThreads);
-    if (precision == PLIC_FP32)
-        hipLaunchKernelGGL((k_curv_bwd_tiles<SOLVER, float, float, float>), grid, block, 0, st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
-    else if (precision == PLIC_MIXED)
-        hipLaunchKernelGGL((k_curv_bwd_tiles<SOLVER, float, double, double>), grid, block, 0, st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
-    else
-        hipLaunchKernelGGL((k_curv_bwd_tiles<SOLVER, double, double, double>), grid, block, 0, st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
+    if (precision == PLIC_FP32) launch_bwd_t<SOLVER, float, float, float>(phi, gk, gp, ws, X, Y, Z, g, st);
+    else if (precision == PLIC_MIXED) launch_bwd_t<SOLVER, float, double, double>(phi, gk, gp, ws, X, Y, Z, g, st);
+    else launch_bwd_t<SOLVER, double, double, double>(phi, gk, gp, ws, X, Y, Z, g, st);
 }
 
 // shared argument checks of the two entry points
@@ -668,9 +788,8 @@ int check_common(const float* phi, int64_t X, int64_t Y, int64_t Z, int solver, 
     *n = *empty ? 0 : X * Y * Z;
     if (!valid_array(phi, *n)) return PLIC_EINVAL;
     if (!*empty) {
-        const size_t need = workspace_for(*g);
-        if (ws == nullptr || !aligned(ws, 4) || ws_bytes < need) return PLIC_EINVAL;
-        if (overlap(ws, need, phi, static_cast<size_t>(*n) * sizeof(float))) return PLIC_EINVAL;
+        if (ws == nullptr || !aligned(ws, 4) || ws_bytes < fixed_bytes(*g)) return PLIC_EINVAL;
+        if (overlap(ws, ws_bytes, phi, static_cast<size_t>(*n) * sizeof(float))) return PLIC_EINVAL;
     }
     return PLIC_OK;
 }
@@ -686,7 +805,7 @@ size_t plic_curvature_workspace_bytes(int64_t X, int64_t Y, int64_t Z) {
     bool empty;
     Grid g;
     if (check_lattice(X, Y, Z, &empty, &g) != PLIC_OK || empty) return 0;
-    return workspace_for(g);
+    return fixed_bytes(g) + static_cast<size_t>(g.ntiles) * kDefaultRowsPerTile * kRowBytes;
 }
 
 int plic_curvature_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float* kappa, int solver,
@@ -699,10 +818,10 @@ int plic_curvature_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float*
     if (!valid_array(kappa, n)) return PLIC_EINVAL;
     const size_t nb = static_cast<size_t>(n) * sizeof(float);
     if (overlap(phi, nb, kappa, nb)) return PLIC_EINVAL;
-    if (!empty && overlap(workspace, workspace_for(g), kappa, nb)) return PLIC_EINVAL;
+    if (!empty && overlap(workspace, workspace_bytes, kappa, nb)) return PLIC_EINVAL;
     if (empty) return PLIC_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const Workspace ws = carve(workspace, g);
+    const Workspace ws = carve(workspace, workspace_bytes, g);
     const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
     launch_scan<true>(phi, kappa, ws, x, y, z, g, st);
     switch (solver) {
@@ -725,12 +844,12 @@ int plic_curvature_backward_f32(const float* phi, int64_t X, int64_t Y, int64_t 
     if (!valid_array(grad_kappa, n) || !valid_array(grad_phi, n)) return PLIC_EINVAL;
     const size_t nb = static_cast<size_t>(n) * sizeof(float);
     if (overlap(grad_phi, nb, phi, nb) || overlap(grad_phi, nb, grad_kappa, nb)) return PLIC_EINVAL;
-    if (!empty && (overlap(workspace, workspace_for(g), grad_phi, nb) ||
-                   overlap(workspace, workspace_for(g), grad_kappa, nb)))
+    if (!empty && (overlap(workspace, workspace_bytes, grad_phi, nb) ||
+                   overlap(workspace, workspace_bytes, grad_kappa, nb)))
         return PLIC_EINVAL;
     if (empty) return PLIC_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const Workspace ws = carve(workspace, g);
+    const Workspace ws = carve(workspace, workspace_bytes, g);
     const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
     launch_scan<false>(phi, grad_phi, ws, x, y, z, g, st);
     switch (solver) {

@@ -98,8 +98,9 @@ def test_backward_validation(lib):
 
 
 def test_curvature_validation(lib):
-    assert lib.plic_curvature_workspace_bytes(256, 256, 256) == 256 + 16384 * 4 * 129
-    assert lib.plic_curvature_workspace_bytes(65, 5, 5) == 256 + 8 * 4 * 129   # 2x2x2 tiles
+    per_tile = 784 + 16 * 108                     # fixed part + 16 contribution rows
+    assert lib.plic_curvature_workspace_bytes(256, 256, 256) == 256 + 16384 * per_tile
+    assert lib.plic_curvature_workspace_bytes(65, 5, 5) == 256 + 8 * per_tile   # 2x2x2 tiles
     assert lib.plic_curvature_workspace_bytes(0, 5, 5) == 0
     assert lib.plic_curvature_workspace_bytes(-1, 5, 5) == 0
     W = 0xA0000
@@ -112,7 +113,8 @@ def test_curvature_validation(lib):
     assert f(A, 4, 4, 4, B, 9, 1, W, ws, None) == -1
     assert f(A, 4, 4, 4, B, 0, 7, W, ws, None) == -1
     assert f(A, 4, 4, 4, B, 0, 1, None, ws, None) == -1               # no workspace
-    assert f(A, 4, 4, 4, B, 0, 1, W, ws - 1, None) == -1              # workspace too small
+    assert f(A, 4, 4, 4, B, 0, 1, W, 256 + 783, None) == -1           # below the fixed part
+    assert f(A, 4, 4, 4, B, 0, 1, W + 2, 256 + 784, None) == -1       # misaligned
     assert f(A, 4, 4, 4, B, 0, 1, W + 2, ws, None) == -1              # misaligned workspace
     assert f(A, 4, 4, 4, B, 0, 1, B, ws, None) == -1                  # workspace overlaps kappa
     assert f(A, 1 << 40, 1 << 40, 4, B, 0, 1, W, ws, None) == -1      # size overflow

@@ -105,6 +105,32 @@ def test_backward_determinism_and_zero(P, case):
     assert np.all(z == 0.0)
 
 
+def test_workspace_capacity_fallback(P, case):
+    """Cells beyond the contribution store are recomputed by the gather: a
+    workspace of only the fixed part, or with room for a few cells, gives the
+    same bits as the recommended size."""
+    phi, gk, _, _ = case
+    ref = gpu_grad(P, phi, gk)
+    Z, Y, X = phi.shape
+    full = P.plic_curvature_workspace_bytes(X, Y, Z)
+    ntiles = ((X + 63) // 64) * ((Y + 3) // 4) * ((Z + 3) // 4)
+    fixed = 256 + 784 * ntiles
+    assert full == fixed + ntiles * 16 * 108
+    tp, tg = dev(phi, gk)
+    for nbytes in (fixed, fixed + 108 * 37, fixed + 108 * 500):
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        out = torch.empty_like(tp)
+        P.plic_curvature_backward_f32(tp, tg, out, "analytic", "mixed", ws)
+        assert np.array_equal(host(out), ref), nbytes
+    # the forward needs only the fixed part
+    ws = torch.empty(fixed, dtype=torch.uint8, device="cuda")
+    k = torch.empty_like(tp)
+    P.plic_curvature_f32(tp, k, "analytic", "mixed", ws)
+    k2 = torch.empty_like(tp)
+    P.plic_curvature_f32(tp, k2, "analytic", "mixed")
+    assert torch.equal(k, k2)
+
+
 def test_autograd_function(P, case):
     phi, gk, gref, _ = case
     t = dev(phi).requires_grad_(True)

@@ -186,19 +186,21 @@ def _lattice_dims(phi):
 
 
 def _workspace(phi, workspace, X, Y, Z):
-    need = plic_curvature_workspace_bytes(X, Y, Z)
+    """The recommended workspace when none is given; a caller's workspace may
+    be smaller (down to the fixed part, which the library checks: interface
+    cells beyond its contribution store are recomputed)."""
     if workspace is None:
+        need = plic_curvature_workspace_bytes(X, Y, Z)
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=phi.device)
     if not (workspace.is_cuda and workspace.is_contiguous() and workspace.dtype == torch.uint8):
         raise ValueError("workspace must be a contiguous uint8 GPU tensor")
-    if workspace.numel() < need:
-        raise ValueError(f"workspace holds {workspace.numel()} bytes, {need} needed")
     return workspace
 
 
 def plic_curvature_f32(phi, kappa, solver="analytic", precision="mixed", workspace=None):
-    """workspace: optional uint8 device tensor of plic_curvature_workspace_bytes
-    bytes (allocated through torch's caching allocator when omitted)."""
+    """workspace: optional uint8 device tensor, at least the fixed part and
+    best plic_curvature_workspace_bytes bytes (allocated through torch's
+    caching allocator when omitted)."""
     X, Y, Z = _lattice_dims(phi)
     n = X * Y * Z
     _same_device(phi, kappa)

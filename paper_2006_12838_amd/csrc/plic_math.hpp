@@ -130,6 +130,18 @@ __device__ __forceinline__ int closed_case(T n1, T n2, T n3, T V, T& d) {
 }
 
 // ---------------------------------------------------------------------------
+// Each solver runs in two stages.  The closed stage settles the closed-form
+// cases and otherwise hands over an Open problem; the cubic stage solves that
+// (cases (3) and (4), and case (1) for Newton-Raphson).  offset() chains the
+// two per thread; the batched kernels pack the open problems of a workgroup
+// densely before the cubic stage, so the costly part runs on full wavefronts.
+// ---------------------------------------------------------------------------
+template <class T> struct Open {
+    T n1, n2, n3;  // sorted normal in the solver's units (L1 for SZ)
+    T V;           // reduced volume; negative marks Newton's case (1)
+};
+
+// ---------------------------------------------------------------------------
 // Analytic solution (Sec. 2.3): the trigonometric root
 //   f(x, y, a, b, c) = c - 2 (a + b (x^2+y^2)^(1/3)) / (x^2+y^2)^(1/6)
 //                      * sin(pi/6 - atan2(y, x)/3)
@@ -145,11 +157,9 @@ __device__ __forceinline__ int closed_case(T n1, T n2, T n3, T V, T& d) {
 // the paper does; x3 > 0 holds once (5) is excluded.
 // ---------------------------------------------------------------------------
 template <class T, class U>
-__device__ __forceinline__ T solve_analytic(T n1, T n2, T n3, T V) {
-    T d;
-    if (closed_case(n1, n2, n3, V, d)) return d;
+__device__ __forceinline__ T cubic_analytic(const Open<T>& o) {
     using m = M<U>;
-    const U u1 = n1, u2 = n2, u3 = n3, uV = V;
+    const U u1 = o.n1, u2 = o.n2, u3 = o.n3, uV = o.V;
     const U p = u1 * u2, s = u1 + u2;
     const U pi6 = U(0.52359877559829887308), third = U(1) / U(3);
     const U x3 = U(81) * p * (s - U(2) * u3 * uV);
@@ -175,19 +185,26 @@ __device__ __forceinline__ T solve_analytic(T n1, T n2, T n3, T V) {
 //             arg = 0.75 n1 n2 n3 (1 - 2V) / t^3
 // and arg is clamped to [-1, 1] before asin.  v3 is evaluated in the divided
 // form 3 n3 (n3 - n1) + n1^2 - (n3 - n2)^3 / n1 (over 6 n2), which has no
-// cancellation either.  Returns the reduced d in L1 units.
+// cancellation either.  d is in L1 units.
 // ---------------------------------------------------------------------------
-template <class T, class U>
-__device__ __forceinline__ T solve_sz(T n1, T n2, T n3, T V) {
+template <class T>
+__device__ __forceinline__ bool closed_sz(T n1, T n2, T n3, T V, T& d) {
     using mt = M<T>;
     const T n12 = n1 + n2, n3V = n3 * V;
-    if (n12 <= T(2) * n3V) return n3V + T(0.5) * n12;                  // case (5)
-    const T sqn1 = n1 * n1, n26 = T(6) * n2, v1 = mt::div(sqn1, n26);   // n2 > 0 here
-    if (v1 <= n3V && n3V < v1 + T(0.5) * (n2 - n1))                    // case (2)
-        return T(0.5) * (n1 + mt::sqrt(sqn1 + T(8) * n2 * (n3V - v1)));
-    if (n3V < v1) return mt::cbrt(n1 * n26 * n3V);                      // case (1)
+    if (n12 <= T(2) * n3V) { d = n3V + T(0.5) * n12; return true; }        // case (5)
+    const T sqn1 = n1 * n1, n26 = T(6) * n2, v1 = mt::div(sqn1, n26);     // n2 > 0 here
+    if (v1 <= n3V && n3V < v1 + T(0.5) * (n2 - n1)) {                     // case (2)
+        d = T(0.5) * (n1 + mt::sqrt(sqn1 + T(8) * n2 * (n3V - v1)));
+        return true;
+    }
+    if (n3V < v1) { d = mt::cbrt(n1 * n26 * n3V); return true; }          // case (1)
+    return false;
+}
+
+template <class T, class U>
+__device__ __forceinline__ T cubic_sz(const Open<T>& o) {
     using m = M<U>;
-    const U u1 = n1, u2 = n2, u3 = n3, uV = V, s = u1 + u2;
+    const U u1 = o.n1, u2 = o.n2, u3 = o.n3, uV = o.V, s = u1 + u2;
     bool case3 = true;
     if (u3 < s) {
         const U w = u3 - u2;
@@ -210,60 +227,88 @@ __device__ __forceinline__ T solve_sz(T n1, T n2, T n3, T V) {
 }
 
 // ---------------------------------------------------------------------------
-// Divided volume polynomial used by the iterative solvers.  For d >= n1
-//   [d^3 - (d-n1)^3 - (d-n2)+^3 - (d-n3)+^3] / n1
-//     = 3 d (d - n1) + n1^2 - ((d-n2)+^3 + (d-n3)+^3) / n1,
-// and d^3 / n1 below n1; the reduced volume is this over 6 n2 n3 (Sec. 2.2).
-// The printed polynomials cancel catastrophically when n1 is small; this form
-// does not.  Valid for 0 <= d <= min(n1 + n2, S/2) with n1 > 0.
+// The cubic cases for the iterative solvers, shifted to t = d - n2 and
+// multiplied by n1 (the volume of Sec. 2.2 without a division by n1):
+//   n1 * 6 n2 n3 (V(n2 + t) - V(n2))
+//     = H3(t) = ((3 n1 - t) t + b) t,     b = n1 (6 n2 - 3 n1),  t <= delta
+//     = H4(t) = H3(t) - (t - delta)^3,    delta = n3 - n2,       t >= delta
+// and the root solves H(t) = c with c = n1 (6 n2 n3 V - 3 n2 (n2 - n1) - n1^2).
+// Case (4) holds when delta < n1 and H3(delta) < c; its bracket is
+// [delta, (n1 + delta) / 2] (up to d = S/2), that of case (3) is
+// [0, min(n1, delta)].  Both are cubics a3 t^3 + a2 t^2 + a1 t in Horner form:
+// case (3): (-1, 3 n1, b); case (4): (-2, 3 (n1 + delta), b - 3 delta^2) with
+// c - delta^3 on the right.  Newton's case (1) (d < n1) is t = d, the cubic
+// t^3 = 6 n1 n2 n3 V on [0, n1].
 // ---------------------------------------------------------------------------
-template <class U>
-__device__ __forceinline__ void divided_volume(U n1, U n2, U n3, U d, U& g, U& gp) {
-    if (d < n1) {
-        const U r = M<U>::rcp(n1);
-        g = d * d * d * r;
-        gp = U(3) * d * d * r;
-    } else {
-        const U p2 = M<U>::fmax(d - n2, U(0)), p3 = M<U>::fmax(d - n3, U(0));
-        const U r = M<U>::rcp(n1);
-        g = U(3) * d * (d - n1) + n1 * n1 - (p2 * p2 * p2 + p3 * p3 * p3) * r;
-        gp = U(6) * d - U(3) * n1 - U(3) * (p2 * p2 + p3 * p3) * r;
+template <class U> struct Cubic {
+    U base;            // d = base + t
+    U a3, a2, a1, c;   // a3 t^3 + a2 t^2 + a1 t = c
+    U lo, hi;          // bracket of t
+};
+
+template <class T, class U>
+__device__ __forceinline__ Cubic<U> cubic_setup(const Open<T>& o) {
+    using m = M<U>;
+    const U n1 = o.n1, n2 = o.n2, n3 = o.n3;
+    Cubic<U> q;
+    if (o.V < T(0)) {                                            // Newton's case (1)
+        q.base = U(0); q.a3 = U(1); q.a2 = U(0); q.a1 = U(0);
+        q.c = U(6) * n1 * n2 * n3 * U(-o.V);
+        q.lo = U(0); q.hi = n1;
+        return q;
     }
+    const U target = U(6) * n2 * n3 * U(o.V);
+    const U c = n1 * (target - (U(3) * n2 * (n2 - n1) + n1 * n1));
+    const U b = n1 * (U(6) * n2 - U(3) * n1);
+    const U de = n3 - n2;
+    const U h3 = ((U(3) * n1 - de) * de + b) * de;
+    const bool case4 = de < n1 && h3 < c;
+    q.base = n2;
+    if (case4) {
+        q.a3 = U(-2); q.a2 = U(3) * (n1 + de); q.a1 = b - U(3) * de * de; q.c = c - de * de * de;
+        q.lo = de; q.hi = U(0.5) * (n1 + de);
+    } else {
+        q.a3 = U(-1); q.a2 = U(3) * n1; q.a1 = b; q.c = c;
+        q.lo = U(0); q.hi = m::fmin(n1, de);
+    }
+    return q;
 }
 
 // ---------------------------------------------------------------------------
-// Newton-Raphson (Sec. 3.2).  Cases (5) and (2) in closed form; the cubic
-// cases by Newton on the divided polynomial against 6 V n2 n3, on the bracket
-// [0, n1] for case (1) (start n1/2, as printed) and on [n2, min(n1+n2, S/2)]
-// for cases (3) and (4) together (start at the midpoint).  The printed fixed
+// Newton-Raphson (Sec. 3.2).  Cases (5) and (2) in closed form; case (1) and
+// the cubic cases by Newton on the shifted cubic above, starting at the middle
+// of the case's bracket (n1/2 for case (1), as printed).  The printed fixed
 // step counts (7/4/4) do not converge for small V, so each iterate is
 // safeguarded (kept inside the shrinking bracket, bisecting when a step leaves
 // it); iteration stops after a Newton step of |step| <= 1e-6 (FP32) / 1e-13
 // (FP64) or once the bracket is that narrow, at most 40 steps.  V = 0 returns
 // d = 0 directly.
 // ---------------------------------------------------------------------------
-template <class T, class U>
-__device__ __forceinline__ T solve_newton(T n1, T n2, T n3, T V) {
-    T d;
+template <class T>
+__device__ __forceinline__ bool closed_newton(T n1, T n2, T n3, T V, T& d, Open<T>& o) {
     const int c = closed_case<T, false>(n1, n2, n3, V, d);
-    if (c >= 2) return d;                                               // (5) or (2)
-    if (V == T(0)) return T(0);
-    using m = M<U>;
-    const U u1 = n1, u2 = n2, u3 = n3;
-    const U target = U(6) * u2 * u3 * U(V);
-    // the bracket follows the classifier's own decision, so that rounding
+    if (c >= 2) return true;                                            // (5) or (2)
+    if (V == T(0)) { d = T(0); return true; }
+    // the case follows the classifier's own decision, so that rounding
     // cannot place the root in a skipped case-(2) interval
-    U lo, hi;
-    if (c == 1) { lo = U(0); hi = u1; }                                // case (1)
-    else { lo = u2; hi = m::fmin(u1 + u2, U(0.5) * (u1 + u2 + u3)); }  // cases (3), (4)
+    o = Open<T>{n1, n2, n3, c == 1 ? -V : V};
+    return false;
+}
+
+template <class T, class U>
+__device__ __forceinline__ T cubic_newton(const Open<T>& o) {
+    using m = M<U>;
+    const Cubic<U> q = cubic_setup<T, U>(o);
+    U lo = q.lo, hi = q.hi;
     U x = U(0.5) * (lo + hi);
     const U tol = U(M<T>::newton_tol);
+    const U a3x3 = U(3) * q.a3, a2x2 = U(2) * q.a2;
+#pragma unroll 1
     for (int it = 0; it < 40; ++it) {
-        U g, gp;
-        divided_volume(u1, u2, u3, x, g, gp);
-        const U f = g - target;
+        const U f = ((q.a3 * x + q.a2) * x + q.a1) * x - q.c;
+        const U fp = (a3x3 * x + a2x2) * x + q.a1;
         if (f < U(0)) lo = x; else hi = x;
-        U xn = x - m::div(f, gp);
+        U xn = x - m::div(f, fp);
         // inclusive: at convergence the step vanishes and xn lands on the end
         // of the bracket that x just became
         const bool newton = xn >= lo && xn <= hi;
@@ -274,52 +319,86 @@ __device__ __forceinline__ T solve_newton(T n1, T n2, T n3, T V) {
         // bisection step does not, so only the bracket width ends it then
         if ((newton && step <= tol) || hi - lo <= tol) break;
     }
-    return T(x);
+    return T(q.base + x);
 }
 
 // ---------------------------------------------------------------------------
 // Nested intervals (Sec. 3.2).  Cases (5), (2) closed form, case (1) by cube
-// root, as printed.  Cases (3) and (4) by bisection of the divided polynomial
-// on [n2, n1 + n2]: the (d-n3)+ term makes one bracket cover both cases, where
-// the printed version bisects [n2, n1+n2] and then [n3, S/2].  A fixed count of
-// halvings (24 in FP32, 52 in FP64) replaces the printed exponent-based count,
-// so all lanes of a wavefront run the same trip count.
+// root, as printed.  Cases (3) and (4) by bisection of the shifted cubic on
+// the case's own bracket ([n2, min(n3, n1 + n2)] or [n3, S/2] in d; the case
+// is decided by one evaluation at d = n3, where the printed version bisects
+// the first bracket and then the second).  A fixed count of halvings (24 in
+// FP32, 52 in FP64) replaces the printed exponent-based count, so all lanes of
+// a wavefront run the same trip count; the midpoint of the last interval is
+// returned.
 // ---------------------------------------------------------------------------
-template <class T, class U>
-__device__ __forceinline__ T solve_nested(T n1, T n2, T n3, T V) {
-    T d;
-    if (closed_case(n1, n2, n3, V, d)) return d;
-    const U u1 = n1, u2 = n2, u3 = n3;
-    const U target = U(6) * u2 * u3 * U(V);
-    U lo = u2, hi = u1 + u2;
-#pragma unroll 4
-    for (int i = 0; i < M<T>::bisect_steps; ++i) {
-        const U mid = U(0.5) * (lo + hi);
-        U g, gp;
-        divided_volume(u1, u2, u3, mid, g, gp);
-        if (g < target) lo = mid; else hi = mid;
-    }
-    return T(U(0.5) * (lo + hi));
+template <class T>
+__device__ __forceinline__ bool closed_nested(T n1, T n2, T n3, T V, T& d, Open<T>& o) {
+    if (closed_case(n1, n2, n3, V, d)) return true;
+    o = Open<T>{n1, n2, n3, V};
+    return false;
 }
 
-// full problem: (n, V0) -> d0 with the chosen solver
+template <class T, class U>
+__device__ __forceinline__ T cubic_nested(const Open<T>& o) {
+    const Cubic<U> q = cubic_setup<T, U>(o);
+    U lo = q.lo;
+    U w = U(0.5) * (q.hi - q.lo);
+#pragma unroll
+    for (int i = 0; i < M<T>::bisect_steps; ++i) {
+        const U mid = lo + w;
+        const U h = ((q.a3 * mid + q.a2) * mid + q.a1) * mid;
+        lo = h < q.c ? mid : lo;
+        w *= U(0.5);                 // exact: the widths are w0 2^-i
+    }
+    return T(q.base + (lo + w));
+}
+
+// ---- the two stages per solver --------------------------------------------------
+// Units of the solver: SZ works on the L1-normalized normal, the others on |n|.
+template <int SOLVER, class T>
+__device__ __forceinline__ T solver_scale(const Reduced<T>& r) {
+    if constexpr (SOLVER == kSZ) return r.n1 + r.n2 + r.n3;
+    else return T(1);
+}
+
+// closed stage on the reduced problem: true with d (solver units) set, or
+// false with the open problem in o
+template <int SOLVER, class T>
+__device__ __forceinline__ bool closed_stage(const Reduced<T>& r, T& d, Open<T>& o) {
+    if constexpr (SOLVER == kSZ) {
+        const T l = r.n1 + r.n2 + r.n3, il = M<T>::rcp(l);
+        const T n1 = r.n1 * il, n2 = r.n2 * il, n3 = r.n3 * il;
+        if (closed_sz(n1, n2, n3, r.V, d)) return true;
+        o = Open<T>{n1, n2, n3, r.V};
+        return false;
+    } else if constexpr (SOLVER == kNewton) {
+        return closed_newton(r.n1, r.n2, r.n3, r.V, d, o);
+    } else if constexpr (SOLVER == kNested) {
+        return closed_nested(r.n1, r.n2, r.n3, r.V, d, o);
+    } else {
+        if (closed_case(r.n1, r.n2, r.n3, r.V, d)) return true;
+        o = Open<T>{r.n1, r.n2, r.n3, r.V};
+        return false;
+    }
+}
+
+template <int SOLVER, class T, class U>
+__device__ __forceinline__ T cubic_stage(const Open<T>& o) {
+    if constexpr (SOLVER == kSZ) return cubic_sz<T, U>(o);
+    else if constexpr (SOLVER == kNewton) return cubic_newton<T, U>(o);
+    else if constexpr (SOLVER == kNested) return cubic_nested<T, U>(o);
+    else return cubic_analytic<T, U>(o);
+}
+
+// full problem: (n, V0) -> d0 with the chosen solver, one thread per problem
 template <int SOLVER, class T, class U>
 __device__ __forceinline__ T offset(T nx, T ny, T nz, T V0) {
     const Reduced<T> r = reduce(nx, ny, nz, V0);
     T d;
-    if constexpr (SOLVER == kSZ) {
-        // L1 normalisation (Sec. 3.1): d0 = l * sign(V0 - 1/2) (1/2 - d)
-        const T l = r.n1 + r.n2 + r.n3;
-        const T il = M<T>::rcp(l);
-        d = solve_sz<T, U>(r.n1 * il, r.n2 * il, r.n3 * il, r.V) * l;
-    } else if constexpr (SOLVER == kNewton) {
-        d = solve_newton<T, U>(r.n1, r.n2, r.n3, r.V);
-    } else if constexpr (SOLVER == kNested) {
-        d = solve_nested<T, U>(r.n1, r.n2, r.n3, r.V);
-    } else {
-        d = solve_analytic<T, U>(r.n1, r.n2, r.n3, r.V);
-    }
-    return unreduce(r, d, nx, ny, nz, V0);
+    Open<T> o;
+    if (!closed_stage<SOLVER>(r, d, o)) d = cubic_stage<SOLVER, T, U>(o);
+    return unreduce(r, d * solver_scale<SOLVER>(r), nx, ny, nz, V0);
 }
 
 // ---------------------------------------------------------------------------

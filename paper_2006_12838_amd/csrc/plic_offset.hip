@@ -4,8 +4,12 @@
 // Layout: structure of arrays in HBM (nx, ny, nz, V0 / d0), one problem per
 // element.  Each thread handles VEC consecutive problems with 16-byte loads
 // and stores per array (4 floats or 2 doubles), so a wavefront moves 1 KiB per
-// array per access; VEC = 1 covers unaligned pointers and the ragged tail.
-// The work is arithmetic-bound: no shared memory, no reuse, one pass over HBM.
+// array per access; VEC = 1 covers unaligned pointers, and the last thread's
+// partial vector is loaded element by element.  One pass over HBM, no reuse.
+// The inversion kernels settle the closed-form cases in registers and pack the
+// rest (the cubic cases, about 40 % of uniformly random problems) densely in
+// LDS before the iterative / trigonometric stage, so that stage runs on full
+// wavefronts.
 #include <hip/hip_runtime.h>
 
 #include "plic_host.hpp"
@@ -45,23 +49,107 @@ __device__ __forceinline__ void store(S* __restrict__ p, int64_t i, const S (&v)
     }
 }
 
-// S: storage type, T: bulk arithmetic, U: cubic-case arithmetic
+// Loads VEC consecutive elements at i, or those below count (others 0).
+template <class S, int VEC>
+__device__ __forceinline__ void load_part(const S* p, int64_t i, int64_t count, S (&v)[VEC]) {
+    if (i + VEC <= count) {
+        load<S, VEC>(p, i, v);
+    } else {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) v[k] = i + k < count ? p[i + k] : S(0);
+    }
+}
+
+template <class S, int VEC>
+__device__ __forceinline__ void store_part(S* p, int64_t i, int64_t count, const S (&v)[VEC]) {
+    if (i + VEC <= count) {
+        store<S, VEC>(p, i, v);
+    } else {
+#pragma unroll
+        for (int k = 0; k < VEC; ++k)
+            if (i + k < count) p[i + k] = v[k];
+    }
+}
+
+// LDS of one workgroup: its open problems packed densely, and their roots
+template <class T, int VEC> struct PackLds {
+    Open<T> q[kBlock * VEC];
+    T root[kBlock * VEC];
+    int count[VEC][kBlock / 64];
+};
+
+// Reduced offsets d (solver units) of the VEC problems of every thread of the
+// workgroup; every thread must call it.  The closed-form cases finish in
+// registers; the open ones are packed into LDS in (k, wave, lane) order and
+// solved one per lane, so the iterative or trigonometric stage runs on full
+// wavefronts instead of on the fraction of lanes that need it.  The result of
+// each problem does not depend on the packing (the same stages run on the
+// same values), so it equals the one-thread-per-problem offset().
+template <int SOLVER, class T, class U, int VEC>
+__device__ __forceinline__ void solve_packed(const Reduced<T> (&r)[VEC], const bool (&valid)[VEC], T (&d)[VEC],
+                                             PackLds<T, VEC>& sm) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    Open<T> o[VEC];
+    bool open[VEC];
+    unsigned long long bal[VEC];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+        open[k] = valid[k] && !closed_stage<SOLVER>(r[k], d[k], o[k]);
+        bal[k] = __ballot(open[k]);
+        if (lane == 0) sm.count[k][wave] = __popcll(bal[k]);
+    }
+    __syncthreads();
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int slot[VEC];
+    int total = 0;
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+        int before = 0, all = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            const int c = sm.count[k][w];
+            before += w < wave ? c : 0;
+            all += c;
+        }
+        slot[k] = total + before + __popcll(bal[k] & below);
+        total += all;
+        if (open[k]) sm.q[slot[k]] = o[k];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int e = tid; e < total; e += kBlock) sm.root[e] = cubic_stage<SOLVER, T, U>(sm.q[e]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < VEC; ++k)
+        if (open[k]) d[k] = sm.root[slot[k]];
+}
+
+// S: storage type, T: bulk arithmetic, U: cubic-case arithmetic.  d0 may be
+// V0 (each element is read and written by the same thread).
 template <int SOLVER, class S, class T, class U, int VEC>
 __global__ __launch_bounds__(kBlock) void k_offset(const S* __restrict__ nx, const S* __restrict__ ny,
                                                    const S* __restrict__ nz, const S* V0, S* d0,
                                                    int64_t count) {
+    __shared__ PackLds<T, VEC> sm;
     const int64_t i = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) * VEC;
-    if (i + VEC <= count) {
-        S a[VEC], b[VEC], c[VEC], v[VEC], r[VEC];
-        load<S, VEC>(nx, i, a); load<S, VEC>(ny, i, b); load<S, VEC>(nz, i, c); load<S, VEC>(V0, i, v);
+    S a[VEC], b[VEC], c[VEC], v[VEC];
+    load_part<S, VEC>(nx, i, count, a); load_part<S, VEC>(ny, i, count, b);
+    load_part<S, VEC>(nz, i, count, c); load_part<S, VEC>(V0, i, count, v);
+    Reduced<T> r[VEC];
+    bool valid[VEC];
+    T d[VEC];
 #pragma unroll
-        for (int k = 0; k < VEC; ++k)
-            r[k] = S(offset<SOLVER, T, U>(T(a[k]), T(b[k]), T(c[k]), T(v[k])));
-        store<S, VEC>(d0, i, r);
-    } else {
-        for (int64_t j = i; j < count; ++j)
-            d0[j] = S(offset<SOLVER, T, U>(T(nx[j]), T(ny[j]), T(nz[j]), T(V0[j])));
+    for (int k = 0; k < VEC; ++k) {
+        r[k] = reduce(T(a[k]), T(b[k]), T(c[k]), T(v[k]));
+        valid[k] = i + k < count;
+        d[k] = T(0);
     }
+    solve_packed<SOLVER, T, U, VEC>(r, valid, d, sm);
+    S out[VEC];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k)
+        out[k] = S(unreduce(r[k], d[k] * solver_scale<SOLVER>(r[k]), T(a[k]), T(b[k]), T(c[k]), T(v[k])));
+    store_part<S, VEC>(d0, i, count, out);
 }
 
 template <class S, class T, int VEC>
@@ -81,9 +169,9 @@ __global__ __launch_bounds__(kBlock) void k_volume(const S* __restrict__ nx, con
     }
 }
 
-template <int SOLVER, class T, class U>
-__device__ __forceinline__ void backward1(T nx, T ny, T nz, T V0, T gd, T& gx, T& gy, T& gz, T& gv) {
-    const T d0 = offset<SOLVER, T, U>(nx, ny, nz, V0);
+// vector-Jacobian product of one problem given its offset d0
+template <class T>
+__device__ __forceinline__ void backward1(T nx, T ny, T nz, T V0, T d0, T gd, T& gx, T& gy, T& gz, T& gv) {
     T g[3];
     const T dv = offset_grad_from_d0<T>(nx, ny, nz, V0, d0, g);
     gx = gd * g[0];
@@ -99,26 +187,32 @@ __global__ __launch_bounds__(kBlock) void k_offset_bwd(const S* __restrict__ nx,
                                                        const S* __restrict__ gd, S* __restrict__ gnx,
                                                        S* __restrict__ gny, S* __restrict__ gnz,
                                                        S* __restrict__ gV0, int64_t count) {
+    __shared__ PackLds<T, VEC> sm;
     const int64_t i = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) * VEC;
-    if (i + VEC <= count) {
-        S a[VEC], b[VEC], c[VEC], v[VEC], g[VEC], ox[VEC], oy[VEC], oz[VEC], ov[VEC];
-        load<S, VEC>(nx, i, a); load<S, VEC>(ny, i, b); load<S, VEC>(nz, i, c);
-        load<S, VEC>(V0, i, v); load<S, VEC>(gd, i, g);
+    S a[VEC], b[VEC], c[VEC], v[VEC];
+    load_part<S, VEC>(nx, i, count, a); load_part<S, VEC>(ny, i, count, b);
+    load_part<S, VEC>(nz, i, count, c); load_part<S, VEC>(V0, i, count, v);
+    Reduced<T> r[VEC];
+    bool valid[VEC];
+    T d[VEC];
 #pragma unroll
-        for (int k = 0; k < VEC; ++k) {
-            T x, y, z, w;
-            backward1<SOLVER, T, U>(T(a[k]), T(b[k]), T(c[k]), T(v[k]), T(g[k]), x, y, z, w);
-            ox[k] = S(x); oy[k] = S(y); oz[k] = S(z); ov[k] = S(w);
-        }
-        store<S, VEC>(gnx, i, ox); store<S, VEC>(gny, i, oy); store<S, VEC>(gnz, i, oz);
-        store<S, VEC>(gV0, i, ov);
-    } else {
-        for (int64_t j = i; j < count; ++j) {
-            T x, y, z, w;
-            backward1<SOLVER, T, U>(T(nx[j]), T(ny[j]), T(nz[j]), T(V0[j]), T(gd[j]), x, y, z, w);
-            gnx[j] = S(x); gny[j] = S(y); gnz[j] = S(z); gV0[j] = S(w);
-        }
+    for (int k = 0; k < VEC; ++k) {
+        r[k] = reduce(T(a[k]), T(b[k]), T(c[k]), T(v[k]));
+        valid[k] = i + k < count;
+        d[k] = T(0);
     }
+    solve_packed<SOLVER, T, U, VEC>(r, valid, d, sm);
+    S g[VEC], ox[VEC], oy[VEC], oz[VEC], ov[VEC];
+    load_part<S, VEC>(gd, i, count, g);
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+        const T d0 = unreduce(r[k], d[k] * solver_scale<SOLVER>(r[k]), T(a[k]), T(b[k]), T(c[k]), T(v[k]));
+        T x, y, z, w;
+        backward1<T>(T(a[k]), T(b[k]), T(c[k]), T(v[k]), d0, T(g[k]), x, y, z, w);
+        ox[k] = S(x); oy[k] = S(y); oz[k] = S(z); ov[k] = S(w);
+    }
+    store_part<S, VEC>(gnx, i, count, ox); store_part<S, VEC>(gny, i, count, oy);
+    store_part<S, VEC>(gnz, i, count, oz); store_part<S, VEC>(gV0, i, count, ov);
 }
 
 inline unsigned grid_for(int64_t count, int vec) {

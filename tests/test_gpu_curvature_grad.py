@@ -122,6 +122,10 @@ def test_workspace_capacity_fallback(P, case):
         out = torch.empty_like(tp)
         P.plic_curvature_backward_f32(tp, tg, out, "analytic", "mixed", ws)
         assert np.array_equal(host(out), ref), nbytes
+    # below the fixed part the library refuses before launching anything
+    ws = torch.empty(fixed - 4, dtype=torch.uint8, device="cuda")
+    with pytest.raises(RuntimeError, match="EINVAL"):
+        P.plic_curvature_backward_f32(tp, tg, out, "analytic", "mixed", ws)
     # the forward needs only the fixed part
     ws = torch.empty(fixed, dtype=torch.uint8, device="cuda")
     k = torch.empty_like(tp)

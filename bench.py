@@ -124,6 +124,12 @@ def main():
     if args.only:
         keep = set(args.only.split(","))
         kernels = [k for k in kernels if k[0] in keep]
+        if "copy" in keep:
+            # plain device copy of N floats (4 N bytes read, 4 N written): the
+            # reference for scaling the HBM byte counters of a profiler run
+            csrc = torch.empty(N, dtype=torch.float32, device=dev).uniform_()
+            cdst = torch.empty_like(csrc)
+            kernels.append(("copy", lambda: cdst.copy_(csrc), N, "floats", 8))
 
     stream = torch.cuda.current_stream(dev)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in kernels]

@@ -577,6 +577,7 @@ __global__ __launch_bounds__(kThreads) void k_curv_items(const float* __restrict
 constexpr int B_RX = TX + 4, B_RY = TY + 4, B_RZ = TZ + 4, B_REGION = B_RX * B_RY * B_RZ;
 constexpr int C_RX = TX + 2, C_RY = TY + 2, C_RZ = TZ + 2, C_REGION = C_RX * C_RY * C_RZ;
 constexpr int kChunk = 128;
+constexpr int kCopyBatch = 8;                 // contribution loads in flight per thread
 constexpr unsigned short kNoSlot = 0xFFFFu;
 
 // contribution row of an interior interface cell: cbase of its tile plus its
@@ -604,6 +605,7 @@ __global__ __launch_bounds__(kThreads) void k_curv_gather(const float* __restric
     __shared__ unsigned short cand[C_REGION];
     __shared__ unsigned short slot[C_REGION];
     __shared__ float contrib[kChunk][27];
+    __shared__ unsigned crow[kChunk];
     __shared__ int wcount[kThreads / 64];
     __shared__ GroupLds<F> glds[FALLBACK ? kGroups : 1];
     const int tid = threadIdx.x, grp = tid / kGroup, j = tid % kGroup;
@@ -638,15 +640,38 @@ __global__ __launch_bounds__(kThreads) void k_curv_gather(const float* __restric
         for (int k = 0; k < kCellsPerThread; ++k) acc[k] = 0.0f;
         for (int c0 = 0; c0 < ncand; c0 += kChunk) {
             const int nc = min(kChunk, ncand - c0);
-            for (int i = tid; i < nc; i += kThreads) slot[cand[c0 + i]] = static_cast<unsigned short>(i);
-            for (int i = grp; i < nc; i += kGroups) {
+            // one thread per candidate: slot and contribution row
+            for (int i = tid; i < nc; i += kThreads) {
                 const int ci = cand[c0 + i];
                 const int lx = ci % C_RX, ly = (ci / C_RX) % C_RY, lz = ci / (C_RX * C_RY);
-                const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-                const unsigned r = contrib_row(ws, gx, gy, gz, ntx, nty);
-                if (r < ws.rows) {                                   // uniform per group
-                    if (j < 27) contrib[i][j] = ws.contrib[static_cast<size_t>(r) * 27 + j];
-                } else if constexpr (FALLBACK) {
+                slot[ci] = static_cast<unsigned short>(i);
+                crow[i] = contrib_row(ws, x0 - 1 + lx, y0 - 1 + ly, z0 - 1 + lz, ntx, nty);
+            }
+            __syncthreads();
+            // stored rows: all threads, independent loads issued in batches
+            const int nv = nc * 27;
+            for (int b0 = 0; b0 < nv; b0 += kThreads * kCopyBatch) {
+                float v[kCopyBatch];
+                unsigned at[kCopyBatch];
+#pragma unroll
+                for (int u = 0; u < kCopyBatch; ++u) {
+                    const int idx = b0 + u * kThreads + tid;
+                    const int i = min(idx, nv - 1) / 27;
+                    const unsigned r = idx < nv ? crow[i] : ws.rows;
+                    at[u] = r < ws.rows ? static_cast<unsigned>(idx) : 0xFFFFFFFFu;
+                    v[u] = r < ws.rows ? ws.contrib[static_cast<size_t>(r) * 27 + (idx - i * 27)] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < kCopyBatch; ++u)
+                    if (at[u] != 0xFFFFFFFFu) contrib[at[u] / 27][at[u] % 27] = v[u];
+            }
+            if constexpr (FALLBACK) {
+                // rows that did not fit: recomputed, one group of lanes per cell
+                for (int i = grp; i < nc; i += kGroups) {
+                    if (crow[i] < ws.rows) continue;                     // uniform per group
+                    const int ci = cand[c0 + i];
+                    const int lx = ci % C_RX, ly = (ci / C_RX) % C_RY, lz = ci / (C_RX * C_RY);
+                    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
                     const float gk = gkap[(static_cast<int64_t>(gz) * Y + gy) * X + gx];
                     group_cell<SOLVER, T, U, F, true>(s, ((lz + 1) * RY + (ly + 1)) * RX + (lx + 1), RX,
                                                       RX * RY, j, gk, contrib[i], glds[grp]);

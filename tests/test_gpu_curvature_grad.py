@@ -1,6 +1,7 @@
-"""GPU backward of plic_curvature (neighbourhood recomputation, deterministic
-gather) against the oracle's FP64 finite-difference gradient and against
-central differences of the GPU forward."""
+"""GPU backward of plic_curvature (adjoint per interface cell, stored
+contributions, deterministic gather) against the oracle's FP64
+finite-difference gradient and against central differences of the GPU
+forward."""
 import numpy as np
 import pytest
 import torch

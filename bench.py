@@ -46,7 +46,121 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle CPU baseline sample")
     ap.add_argument("--only", default="", help="comma list of kernels to run (profiling aid)")
+    ap.add_argument("--write-traffic-profile", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic summary from two rocprofv3 --pmc runs and exit (no GPU); "
+                         "run it on the tree that was profiled, since it records that tree's kernel source hash")
+    ap.add_argument("--traffic-out", default=TRAFFIC_PROFILE, help="where --write-traffic-profile writes")
     return ap.parse_args()
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_2p26_problems_256cube_sphere_pmc.md")
+KERNEL_SOURCES = ("plic_math.hpp", "plic_host.hpp", "plic_offset.hip", "plic_curvature.hip")
+
+
+def kernel_source_hash():
+    """sha256 over the device sources, in a fixed order."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2006_12838_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of a bench kernel from the committed profiler
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counters), or
+    None when the summary is missing or the kernel sources changed since."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    import re
+    m = re.search(r"kernel source sha256: `([0-9a-f]{64})`", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(r"^\| " + re.escape(kernel) + r" \| [^|]* \| ([0-9,]+) \|", text, flags=re.M)
+    return int(m.group(1).replace(",", "")) if m else None
+
+
+# bench kernel -> dispatch names (demangled prefixes) that make up one launch
+PMC_DISPATCHES = {
+    "offset_analytic": ("k_offset<0, float, float, float, 4>",),
+    "offset_sz": ("k_offset<1, float, float, float, 4>",),
+    "offset_newton": ("k_offset<2, float, float, float, 4>",),
+    "offset_nested": ("k_offset<3, float, float, float, 4>",),
+    "volume": ("k_volume<float, float, 4>",),
+    "offset_backward_sz": ("k_offset_bwd<1, float, float, float, 4>",),
+    "curvature_fwd": ("k_curv_scan<true, true>", "k_curv_items<0, float, double, double, false>"),
+    "curvature_bwd": ("k_curv_scan<true, false>", "k_curv_items<0, float, double, double, true>", "k_curv_dilate",
+                      "k_curv_gather<0, float, double, double, false>", "k_curv_gather<0, float, double, double, true>"),
+    "copy": ("__amd_rocclr_copyBuffer",),
+}
+ALGORITHMIC_BYTES = {"offset_analytic": 20, "offset_sz": 20, "offset_newton": 20, "offset_nested": 20,
+                     "volume": 20, "offset_backward_sz": 36, "curvature_fwd": 8, "curvature_bwd": 8, "copy": 8}
+
+
+def write_traffic_profile(fetch_csv, write_csv, log2n, lattice, out=TRAFFIC_PROFILE):
+    """Summary of two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, in KiB
+    per dispatch) of `bench.py --only <kernels>,copy --steps 1 --warmup 0`:
+    HBM bytes per launch of each bench kernel, both counters scaled by what
+    they read for a plain copy of 4 * 2^log2n bytes."""
+    import csv
+
+    def per_dispatch(path):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"].replace("plic::(anonymous namespace)::", "").replace("void ", "")
+            for k, pats in PMC_DISPATCHES.items():
+                for pat in pats:
+                    if name.startswith(pat):
+                        acc.setdefault((k, pat), []).append(float(r["Counter_Value"]))
+        return {key: sum(v) / len(v) for key, v in acc.items()}
+
+    fetch, write = per_dispatch(fetch_csv), per_dispatch(write_csv)
+    n = 1 << log2n
+    cp = ("copy", PMC_DISPATCHES["copy"][0])
+    ff, fw = 4 * n / 1024 / fetch[cp], 4 * n / 1024 / write[cp]
+    units = {k: (lattice ** 3 if k.startswith("curvature") else n) for k in PMC_DISPATCHES}
+    lines = [
+        f"# HBM traffic per launch: 2^{log2n} PLIC problems and a {lattice}^3 sphere lattice (R = 40)",
+        "",
+        "Commands (from the repository root on an MI355X, ROCm 7.2), one counter per run:",
+        "",
+        "```",
+        "cd /tmp && export TMPDIR=/tmp",
+        "K=" + ",".join(PMC_DISPATCHES),
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/pmc_FETCH_SIZE -o pmc -- "
+        "python3 $REPO/bench.py --only $K --steps 1 --warmup 0 --no-cpu-baseline",
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/pmc_WRITE_SIZE -o pmc -- "
+        "python3 $REPO/bench.py --only $K --steps 1 --warmup 0 --no-cpu-baseline",
+        "python3 $REPO/bench.py --write-traffic-profile $REPO/gpurun_out/pmc_FETCH_SIZE/pmc_counter_collection.csv "
+        "$REPO/gpurun_out/pmc_WRITE_SIZE/pmc_counter_collection.csv --traffic-out <this file>",
+        "```",
+        "",
+        f"Calibration: a plain device copy of {4 * n:,} bytes (`copy`, torch's `copy_`) reads "
+        f"FETCH_SIZE = {fetch[cp]:,.1f} KiB and WRITE_SIZE = {write[cp]:,.1f} KiB, so FETCH_SIZE is scaled "
+        f"by {ff:.4f} and WRITE_SIZE by {fw:.4f}.  HBM bytes = 1024 (FETCH_SIZE * {ff:.4f} + "
+        f"WRITE_SIZE * {fw:.4f}), summed over the dispatches of one launch.",
+        "",
+        f"kernel source sha256: `{kernel_source_hash()}` (bench.py reports these bytes as "
+        "`roofline.traffic` only while the device sources hash to this value)",
+        "",
+        "| bench kernel | dispatches | HBM bytes per launch | FETCH_SIZE KiB | WRITE_SIZE KiB | algorithmic bytes | ratio |",
+        "|---|---|---:|---:|---:|---:|---:|",
+    ]
+    for k, pats in PMC_DISPATCHES.items():
+        if not all((k, p) in fetch and (k, p) in write for p in pats):
+            continue
+        f = sum(fetch[(k, p)] for p in pats)
+        w = sum(write[(k, p)] for p in pats)
+        hbm = int(round(1024 * (f * ff + w * fw)))
+        alg = ALGORITHMIC_BYTES[k] * units[k]
+        lines.append(f"| {k} | {' + '.join('`' + p + '`' for p in pats)} | {hbm:,} | {f:,.1f} | {w:,.1f} | "
+                     f"{alg:,} | {hbm / alg:.3f} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return out
 
 
 def cpu_baseline(nx, ny, nz, V0, seconds):
@@ -76,6 +190,9 @@ def cpu_baseline(nx, ny, nz, V0, seconds):
 
 def main():
     args = parse()
+    if args.write_traffic_profile:
+        print(write_traffic_profile(*args.write_traffic_profile, args.log2n, args.lattice, args.traffic_out))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(the PLIC path has no cross-GPU step; sharding is described in DESIGN.md)",
@@ -170,7 +287,7 @@ def main():
     dms = per[dom[0]] / args.steps
     dgbs = dom[2] * dom[4] / (dms * 1e-3) / 1e9
     roofline = {"kernel": dom[0], "bound": "hbm", "achieved": round(dgbs, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(dgbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(dgbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom[0]),
                 "bytes_per_unit": dom[4], "units_per_launch": dom[2]}
     fast = min((k for k in kernels if k[0].startswith("offset_") and k[0] != "offset_backward_sz"),
                key=lambda k: per[k[0]], default=None)

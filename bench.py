@@ -50,6 +50,9 @@ def parse():
                     help="write the HBM traffic summary from two rocprofv3 --pmc runs and exit (no GPU); "
                          "run it on the tree that was profiled, since it records that tree's kernel source hash")
     ap.add_argument("--traffic-out", default=TRAFFIC_PROFILE, help="where --write-traffic-profile writes")
+    ap.add_argument("--write-issue-profile", metavar="SQ_CSV",
+                    help="write the instruction-issue summary from a rocprofv3 --pmc run and exit (no GPU)")
+    ap.add_argument("--issue-out", default=ISSUE_PROFILE, help="where --write-issue-profile writes")
     return ap.parse_args()
 
 
@@ -163,6 +166,66 @@ def write_traffic_profile(fetch_csv, write_csv, log2n, lattice, out=TRAFFIC_PROF
     return out
 
 
+ISSUE_PROFILE = os.path.join(ROOT, "profiles", "valu_issue_2p26_problems_256cube_sphere_pmc.md")
+ISSUE_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_VALU_TRANS_F64",
+                  "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES")
+
+
+def write_issue_profile(sq_csv, log2n, lattice, out=ISSUE_PROFILE):
+    """Summary of one rocprofv3 --pmc run with ISSUE_COUNTERS over
+    `bench.py --only <kernels> --steps 1 --warmup 0`: instructions issued per
+    wavefront and VALU lane-instructions per unit of work for each bench kernel."""
+    import csv
+
+    acc = {}
+    for r in csv.DictReader(open(sq_csv)):
+        name = r["Kernel_Name"].replace("plic::(anonymous namespace)::", "").replace("void ", "")
+        for k, pats in PMC_DISPATCHES.items():
+            for pat in pats:
+                if name.startswith(pat):
+                    d = acc.setdefault(k, {})
+                    d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    n = 1 << log2n
+    lines = [
+        f"# Instruction issue per launch: 2^{log2n} PLIC problems and a {lattice}^3 sphere lattice (R = 40)",
+        "",
+        "Command (from the repository root on an MI355X, ROCm 7.2):",
+        "",
+        "```",
+        "cd /tmp && export TMPDIR=/tmp",
+        "K=" + ",".join(k for k in PMC_DISPATCHES if k != "copy"),
+        "rocprofv3 --pmc " + " ".join(ISSUE_COUNTERS) + " --output-format csv -d $REPO/gpurun_out/pmc_sq -o pmc -- "
+        "python3 $REPO/bench.py --only $K --steps 1 --warmup 0 --no-cpu-baseline",
+        "python3 $REPO/bench.py --write-issue-profile $REPO/gpurun_out/pmc_sq/pmc_counter_collection.csv "
+        "--issue-out <this file>",
+        "```",
+        "",
+        f"kernel source sha256: `{kernel_source_hash()}`",
+        "",
+        "Counts are per wavefront (64 lanes), summed over the dispatches of one launch; `VALU lane-instr per "
+        "unit` = SQ_INSTS_VALU x 64 / units (problems, or lattice cells for the curvature), an upper bound on "
+        "the work per unit since inactive lanes count.",
+        "",
+        "| bench kernel | waves | VALU / wave | of which trans. F32 | trans. F64 | SALU / wave | LDS / wave | "
+        "VALU lane-instr per unit | ACTIVE_INST_VALU | BUSY_CYCLES |",
+        "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|",
+    ]
+    for k in PMC_DISPATCHES:
+        if k not in acc:
+            continue
+        c = acc[k]
+        w = c.get("SQ_WAVES", 0.0) or 1.0
+        units = lattice ** 3 if k.startswith("curvature") else n
+        lines.append(f"| {k} | {c.get('SQ_WAVES', 0):,.0f} | {c.get('SQ_INSTS_VALU', 0) / w:.1f} | "
+                     f"{c.get('SQ_INSTS_VALU_TRANS_F32', 0) / w:.1f} | {c.get('SQ_INSTS_VALU_TRANS_F64', 0) / w:.1f} | "
+                     f"{c.get('SQ_INSTS_SALU', 0) / w:.1f} | {c.get('SQ_INSTS_LDS', 0) / w:.1f} | "
+                     f"{c.get('SQ_INSTS_VALU', 0) * 64 / units:.1f} | {c.get('SQ_ACTIVE_INST_VALU', 0):,.0f} | "
+                     f"{c.get('SQ_BUSY_CYCLES', 0):,.0f} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return out
+
+
 def cpu_baseline(nx, ny, nz, V0, seconds):
     """The oracle (bisection on the FP64 forward volume), timed on the host
     cores on chunks of the same workload until `seconds` have passed."""
@@ -192,6 +255,9 @@ def main():
     args = parse()
     if args.write_traffic_profile:
         print(write_traffic_profile(*args.write_traffic_profile, args.log2n, args.lattice, args.traffic_out))
+        return
+    if args.write_issue_profile:
+        print(write_issue_profile(args.write_issue_profile, args.log2n, args.lattice, args.issue_out))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "

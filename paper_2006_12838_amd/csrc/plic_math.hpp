@@ -29,6 +29,16 @@ template <> struct M<float> {
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     static __device__ __forceinline__ float cbrt(float x) { return ::cbrtf(x); }
     static __device__ __forceinline__ float sin(float x) { return ::sinf(x); }
+    // sin on |x| <= pi/6 by its Maclaurin series through x^9 (first omitted
+    // term x^11/11! < 2e-11 there, far below FP32 rounding)
+    static __device__ __forceinline__ float sin_small(float x) {
+        const float x2 = x * x;
+        float p = 1.0f / 362880.0f;
+        p = p * x2 - 1.0f / 5040.0f;
+        p = p * x2 + 1.0f / 120.0f;
+        p = p * x2 - 1.0f / 6.0f;
+        return x + x * x2 * p;
+    }
     static __device__ __forceinline__ float asin(float x) { return ::asinf(x); }
     static __device__ __forceinline__ float atan(float x) { return ::atanf(x); }
     static __device__ __forceinline__ float fmin(float a, float b) { return ::fminf(a, b); }
@@ -52,6 +62,20 @@ template <> struct M<double> {
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
     static __device__ __forceinline__ double cbrt(double x) { return ::cbrt(x); }
     static __device__ __forceinline__ double sin(double x) { return ::sin(x); }
+    // sin on |x| <= pi/6 by its Maclaurin series through x^17 (first omitted
+    // term x^19/19! < 4e-23 there)
+    static __device__ __forceinline__ double sin_small(double x) {
+        const double x2 = x * x;
+        double p = 1.0 / 355687428096000.0;         // 1/17!
+        p = p * x2 - 1.0 / 1307674368000.0;         // 1/15!
+        p = p * x2 + 1.0 / 6227020800.0;            // 1/13!
+        p = p * x2 - 1.0 / 39916800.0;              // 1/11!
+        p = p * x2 + 1.0 / 362880.0;                // 1/9!
+        p = p * x2 - 1.0 / 5040.0;                  // 1/7!
+        p = p * x2 + 1.0 / 120.0;                   // 1/5!
+        p = p * x2 - 1.0 / 6.0;                     // 1/3!
+        return x + x * x2 * p;
+    }
     static __device__ __forceinline__ double asin(double x) { return ::asin(x); }
     static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
     static __device__ __forceinline__ double fmin(double a, double b) { return ::fmin(a, b); }
@@ -142,19 +166,37 @@ template <class T> struct Open {
 };
 
 // ---------------------------------------------------------------------------
+// Volume at d = n3 in the divided form (times n3 / V): case (3) holds for
+// n3 V < v3n3 when n3 < n1 + n2, always otherwise.  Scale-invariant, no
+// cancellation for small n1 (the (n3 - n2)^3 / n1 term is at most n1^2).
+// ---------------------------------------------------------------------------
+template <class U>
+__device__ __forceinline__ bool cubic_case3(U u1, U u2, U u3, U uV) {
+    using m = M<U>;
+    if (!(u3 < u1 + u2)) return true;
+    const U w = u3 - u2;
+    const U v3 = m::div(U(3) * u3 * (u3 - u1) + u1 * u1 - m::div(w * w * w, u1), U(6) * u2);
+    return u3 * uV < v3;
+}
+
+// ---------------------------------------------------------------------------
 // Analytic solution (Sec. 2.3): the trigonometric root
 //   f(x, y, a, b, c) = c - 2 (a + b (x^2+y^2)^(1/3)) / (x^2+y^2)^(1/6)
 //                      * sin(pi/6 - atan2(y, x)/3)
-// with the printed coefficients, tried in the order (5), (2), (1), (3), (4),
-// case (3) accepted when d3 <= n3.  Two exact simplifications:
+// with the printed coefficients of cases (3) and (4).  Two exact
+// simplifications:
 //  * x3^2 + y3^2 = 23328 (n1 n2)^3 and x4^2 + y4^2 = 4 t4^3, so the cube roots
 //    cancel: the prefactor is 2 sqrt(2 n1 n2) in case (3) and sqrt(t4)/3 in
 //    case (4);
 //  * t4 = 9 (S^2 - 2) assumes |n| = 1 and cancels near the face diagonal; the
 //    equal (for |n| = 1), degree-2 homogeneous
 //    t4 = 9 (2 n1 (n2 + n3) - n1^2 - (n3 - n2)^2) is used instead.
-// atan(y/x) replaces atan2 with x4 clamped to the smallest normal number, as
-// the paper does; x3 > 0 holds once (5) is excluded.
+// The paper evaluates case (3) and keeps it when d3 <= n3, else evaluates
+// case (4).  Here the case is decided first by the volume at d = n3 (the same
+// case; at the boundary both roots equal n3), so that each lane evaluates a
+// single root: one atan and one sin, with the case's (x, y, prefactor, c).
+// atan(y/x) replaces atan2 with x clamped to the smallest normal number, as
+// the paper does for x4; x3 > 0 holds once (5) is excluded.
 // ---------------------------------------------------------------------------
 template <class T, class U>
 __device__ __forceinline__ T cubic_analytic(const Open<T>& o) {
@@ -162,15 +204,23 @@ __device__ __forceinline__ T cubic_analytic(const Open<T>& o) {
     const U u1 = o.n1, u2 = o.n2, u3 = o.n3, uV = o.V;
     const U p = u1 * u2, s = u1 + u2;
     const U pi6 = U(0.52359877559829887308), third = U(1) / U(3);
-    const U x3 = U(81) * p * (s - U(2) * u3 * uV);
-    const U y3 = m::sqrt(m::fmax(U(23328) * p * p * p - x3 * x3, U(0)));
-    const U d3 = s - U(2) * m::sqrt(U(2) * p) * m::sin(pi6 - third * m::atan(m::div(y3, x3)));
-    if (d3 <= u3) return T(d3);                                  // case (3)
-    const U t4 = m::fmax(U(9) * (U(2) * u1 * (u2 + u3) - u1 * u1 - (u3 - u2) * (u3 - u2)), U(0));
-    const U x4 = m::fmax(U(324) * p * u3 * (U(1) - U(2) * uV), m::tiny);
-    const U y4 = m::sqrt(m::fmax(U(4) * t4 * t4 * t4 - x4 * x4, U(0)));
-    const U d4 = U(0.5) * (s + u3) - m::sqrt(t4) * third * m::sin(pi6 - third * m::atan(m::div(y4, x4)));
-    return T(d4);                                                // case (4)
+    U x, r2, pref, c;
+    if (cubic_case3(u1, u2, u3, uV)) {                           // case (3)
+        x = U(81) * p * (s - U(2) * u3 * uV);
+        r2 = U(23328) * p * p * p;
+        pref = U(2) * m::sqrt(U(2) * p);
+        c = s;
+    } else {                                                     // case (4)
+        const U t4 = m::fmax(U(9) * (U(2) * u1 * (u2 + u3) - u1 * u1 - (u3 - u2) * (u3 - u2)), U(0));
+        x = U(324) * p * u3 * (U(1) - U(2) * uV);
+        r2 = U(4) * t4 * t4 * t4;
+        pref = m::sqrt(t4) * third;
+        c = U(0.5) * (s + u3);
+    }
+    x = m::fmax(x, m::tiny);
+    const U y = m::sqrt(m::fmax(r2 - x * x, U(0)));
+    // the sine's argument lies in (0, pi/6]: atan(y/x) is in [0, pi/2)
+    return T(c - pref * m::sin_small(pi6 - third * m::atan(m::div(y, x))));
 }
 
 // ---------------------------------------------------------------------------
@@ -205,12 +255,7 @@ template <class T, class U>
 __device__ __forceinline__ T cubic_sz(const Open<T>& o) {
     using m = M<U>;
     const U u1 = o.n1, u2 = o.n2, u3 = o.n3, uV = o.V, s = u1 + u2;
-    bool case3 = true;
-    if (u3 < s) {
-        const U w = u3 - u2;
-        const U v3 = m::div(U(3) * u3 * (u3 - u1) + u1 * u1 - m::div(w * w * w, u1), U(6) * u2);
-        case3 = u3 * uV < v3;
-    }
+    const bool case3 = cubic_case3(u1, u2, u3, uV);
     U c, t, num;
     if (case3) {
         c = s;
@@ -223,7 +268,8 @@ __device__ __forceinline__ T cubic_sz(const Open<T>& o) {
     }
     U arg = m::div(num, t * t * t);
     arg = m::fmin(m::fmax(arg, U(-1)), U(1));
-    return T(c - U(2) * t * m::sin(m::asin(arg) * (U(1) / U(3))));
+    // asin(arg) / 3 lies in [-pi/6, pi/6]
+    return T(c - U(2) * t * m::sin_small(m::asin(arg) * (U(1) / U(3))));
 }
 
 // ---------------------------------------------------------------------------

@@ -50,9 +50,10 @@ __device__ __forceinline__ void store(S* __restrict__ p, int64_t i, const S (&v)
 }
 
 // Loads VEC consecutive elements at i, or those below count (others 0).
-template <class S, int VEC>
+// FULL: the launch covers whole blocks only, no bounds checks.
+template <class S, int VEC, bool FULL>
 __device__ __forceinline__ void load_part(const S* p, int64_t i, int64_t count, S (&v)[VEC]) {
-    if (i + VEC <= count) {
+    if (FULL || i + VEC <= count) {
         load<S, VEC>(p, i, v);
     } else {
 #pragma unroll
@@ -60,9 +61,9 @@ __device__ __forceinline__ void load_part(const S* p, int64_t i, int64_t count, 
     }
 }
 
-template <class S, int VEC>
+template <class S, int VEC, bool FULL>
 __device__ __forceinline__ void store_part(S* p, int64_t i, int64_t count, const S (&v)[VEC]) {
-    if (i + VEC <= count) {
+    if (FULL || i + VEC <= count) {
         store<S, VEC>(p, i, v);
     } else {
 #pragma unroll
@@ -125,23 +126,25 @@ __device__ __forceinline__ void solve_packed(const Reduced<T> (&r)[VEC], const b
 }
 
 // S: storage type, T: bulk arithmetic, U: cubic-case arithmetic.  d0 may be
-// V0 (each element is read and written by the same thread).
-template <int SOLVER, class S, class T, class U, int VEC>
+// V0 (each element is read and written by the same thread).  FULL launches
+// cover whole blocks (kBlock * VEC problems each) and skip the bounds checks;
+// the remainder goes to one checked block.
+template <int SOLVER, class S, class T, class U, int VEC, bool FULL>
 __global__ __launch_bounds__(kBlock) void k_offset(const S* __restrict__ nx, const S* __restrict__ ny,
                                                    const S* __restrict__ nz, const S* V0, S* d0,
                                                    int64_t count) {
     __shared__ PackLds<T, VEC> sm;
     const int64_t i = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) * VEC;
     S a[VEC], b[VEC], c[VEC], v[VEC];
-    load_part<S, VEC>(nx, i, count, a); load_part<S, VEC>(ny, i, count, b);
-    load_part<S, VEC>(nz, i, count, c); load_part<S, VEC>(V0, i, count, v);
+    load_part<S, VEC, FULL>(nx, i, count, a); load_part<S, VEC, FULL>(ny, i, count, b);
+    load_part<S, VEC, FULL>(nz, i, count, c); load_part<S, VEC, FULL>(V0, i, count, v);
     Reduced<T> r[VEC];
     bool valid[VEC];
     T d[VEC];
 #pragma unroll
     for (int k = 0; k < VEC; ++k) {
         r[k] = reduce(T(a[k]), T(b[k]), T(c[k]), T(v[k]));
-        valid[k] = i + k < count;
+        valid[k] = FULL || i + k < count;
         d[k] = T(0);
     }
     solve_packed<SOLVER, T, U, VEC>(r, valid, d, sm);
@@ -149,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_offset(const S* __restrict__ nx, con
 #pragma unroll
     for (int k = 0; k < VEC; ++k)
         out[k] = S(unreduce(r[k], d[k] * solver_scale<SOLVER>(r[k]), T(a[k]), T(b[k]), T(c[k]), T(v[k])));
-    store_part<S, VEC>(d0, i, count, out);
+    store_part<S, VEC, FULL>(d0, i, count, out);
 }
 
 template <class S, class T, int VEC>
@@ -181,38 +184,30 @@ __device__ __forceinline__ void backward1(T nx, T ny, T nz, T V0, T d0, T gd, T&
     if (__builtin_isnan(d0)) gx = gy = gz = gv = d0;
 }
 
-template <int SOLVER, class S, class T, class U, int VEC>
+// The backward solves one problem per thread (no packing): its gradient stage
+// is as long as the solve, and the packing's LDS and barriers cost more
+// occupancy than they save there.  grad_d0 is loaded with the other inputs.
+template <int SOLVER, class S, class T, class U, int VEC, bool FULL>
 __global__ __launch_bounds__(kBlock) void k_offset_bwd(const S* __restrict__ nx, const S* __restrict__ ny,
                                                        const S* __restrict__ nz, const S* __restrict__ V0,
                                                        const S* __restrict__ gd, S* __restrict__ gnx,
                                                        S* __restrict__ gny, S* __restrict__ gnz,
                                                        S* __restrict__ gV0, int64_t count) {
-    __shared__ PackLds<T, VEC> sm;
     const int64_t i = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) * VEC;
-    S a[VEC], b[VEC], c[VEC], v[VEC];
-    load_part<S, VEC>(nx, i, count, a); load_part<S, VEC>(ny, i, count, b);
-    load_part<S, VEC>(nz, i, count, c); load_part<S, VEC>(V0, i, count, v);
-    Reduced<T> r[VEC];
-    bool valid[VEC];
-    T d[VEC];
+    S a[VEC], b[VEC], c[VEC], v[VEC], g[VEC];
+    load_part<S, VEC, FULL>(nx, i, count, a); load_part<S, VEC, FULL>(ny, i, count, b);
+    load_part<S, VEC, FULL>(nz, i, count, c); load_part<S, VEC, FULL>(V0, i, count, v);
+    load_part<S, VEC, FULL>(gd, i, count, g);
+    S ox[VEC], oy[VEC], oz[VEC], ov[VEC];
 #pragma unroll
     for (int k = 0; k < VEC; ++k) {
-        r[k] = reduce(T(a[k]), T(b[k]), T(c[k]), T(v[k]));
-        valid[k] = i + k < count;
-        d[k] = T(0);
-    }
-    solve_packed<SOLVER, T, U, VEC>(r, valid, d, sm);
-    S g[VEC], ox[VEC], oy[VEC], oz[VEC], ov[VEC];
-    load_part<S, VEC>(gd, i, count, g);
-#pragma unroll
-    for (int k = 0; k < VEC; ++k) {
-        const T d0 = unreduce(r[k], d[k] * solver_scale<SOLVER>(r[k]), T(a[k]), T(b[k]), T(c[k]), T(v[k]));
+        const T d0 = offset<SOLVER, T, U>(T(a[k]), T(b[k]), T(c[k]), T(v[k]));
         T x, y, z, w;
         backward1<T>(T(a[k]), T(b[k]), T(c[k]), T(v[k]), d0, T(g[k]), x, y, z, w);
         ox[k] = S(x); oy[k] = S(y); oz[k] = S(z); ov[k] = S(w);
     }
-    store_part<S, VEC>(gnx, i, count, ox); store_part<S, VEC>(gny, i, count, oy);
-    store_part<S, VEC>(gnz, i, count, oz); store_part<S, VEC>(gV0, i, count, ov);
+    store_part<S, VEC, FULL>(gnx, i, count, ox); store_part<S, VEC, FULL>(gny, i, count, oy);
+    store_part<S, VEC, FULL>(gnz, i, count, oz); store_part<S, VEC, FULL>(gV0, i, count, ov);
 }
 
 inline unsigned grid_for(int64_t count, int vec) {
@@ -223,16 +218,23 @@ inline unsigned grid_for(int64_t count, int vec) {
 template <class S> constexpr int kVec = 16 / sizeof(S);
 
 // ---- dispatch ------------------------------------------------------------------
+// whole blocks unchecked, then the remainder in one checked block
+template <int SOLVER, class S, class T, class U, int VEC>
+void launch_offset_v(const S* nx, const S* ny, const S* nz, const S* V0, S* d0, int64_t count, hipStream_t st) {
+    const int64_t per = static_cast<int64_t>(kBlock) * VEC, full = count / per * per, rem = count - full;
+    if (full)
+        hipLaunchKernelGGL((k_offset<SOLVER, S, T, U, VEC, true>), dim3(grid_for(full, VEC)), dim3(kBlock), 0, st,
+                           nx, ny, nz, V0, d0, full);
+    if (rem)
+        hipLaunchKernelGGL((k_offset<SOLVER, S, T, U, VEC, false>), dim3(1), dim3(kBlock), 0, st,
+                           nx + full, ny + full, nz + full, V0 + full, d0 + full, rem);
+}
+
 template <int SOLVER, class S, class T, class U>
 void launch_offset_t(const S* nx, const S* ny, const S* nz, const S* V0, S* d0, int64_t count,
                      bool vec, hipStream_t st) {
-    if (vec) {
-        hipLaunchKernelGGL((k_offset<SOLVER, S, T, U, kVec<S>>), dim3(grid_for(count, kVec<S>)),
-                           dim3(kBlock), 0, st, nx, ny, nz, V0, d0, count);
-    } else {
-        hipLaunchKernelGGL((k_offset<SOLVER, S, T, U, 1>), dim3(grid_for(count, 1)), dim3(kBlock), 0,
-                           st, nx, ny, nz, V0, d0, count);
-    }
+    if (vec) launch_offset_v<SOLVER, S, T, U, kVec<S>>(nx, ny, nz, V0, d0, count, st);
+    else launch_offset_v<SOLVER, S, T, U, 1>(nx, ny, nz, V0, d0, count, st);
 }
 
 template <class S, class T, class U>
@@ -246,16 +248,24 @@ void launch_offset_s(int solver, const S* nx, const S* ny, const S* nz, const S*
     }
 }
 
+template <int SOLVER, class S, class T, class U, int VEC>
+void launch_bwd_v(const S* nx, const S* ny, const S* nz, const S* V0, const S* gd, S* gx, S* gy, S* gz, S* gv,
+                  int64_t count, hipStream_t st) {
+    const int64_t per = static_cast<int64_t>(kBlock) * VEC, full = count / per * per, rem = count - full;
+    if (full)
+        hipLaunchKernelGGL((k_offset_bwd<SOLVER, S, T, U, VEC, true>), dim3(grid_for(full, VEC)), dim3(kBlock), 0,
+                           st, nx, ny, nz, V0, gd, gx, gy, gz, gv, full);
+    if (rem)
+        hipLaunchKernelGGL((k_offset_bwd<SOLVER, S, T, U, VEC, false>), dim3(1), dim3(kBlock), 0, st,
+                           nx + full, ny + full, nz + full, V0 + full, gd + full, gx + full, gy + full, gz + full,
+                           gv + full, rem);
+}
+
 template <int SOLVER, class S, class T, class U>
 void launch_bwd_t(const S* nx, const S* ny, const S* nz, const S* V0, const S* gd, S* gx, S* gy,
                   S* gz, S* gv, int64_t count, bool vec, hipStream_t st) {
-    if (vec) {
-        hipLaunchKernelGGL((k_offset_bwd<SOLVER, S, T, U, kVec<S>>), dim3(grid_for(count, kVec<S>)),
-                           dim3(kBlock), 0, st, nx, ny, nz, V0, gd, gx, gy, gz, gv, count);
-    } else {
-        hipLaunchKernelGGL((k_offset_bwd<SOLVER, S, T, U, 1>), dim3(grid_for(count, 1)),
-                           dim3(kBlock), 0, st, nx, ny, nz, V0, gd, gx, gy, gz, gv, count);
-    }
+    if (vec) launch_bwd_v<SOLVER, S, T, U, kVec<S>>(nx, ny, nz, V0, gd, gx, gy, gz, gv, count, st);
+    else launch_bwd_v<SOLVER, S, T, U, 1>(nx, ny, nz, V0, gd, gx, gy, gz, gv, count, st);
 }
 
 template <class S, class T, class U>

@@ -35,12 +35,17 @@ def gpu_kappa(P, phi, solver="analytic", precision="mixed"):
     return host(k)
 
 
-def check_cells(orc, phi, k, precision, report=""):
+def cell_reference(orc, phi):
+    """Oracle kappa on the interface cells and their conditioning info."""
     kref, flags = orc.curvature(phi, flags=True)
     cells = np.flatnonzero(flags & 1)
     _, info = orc.curvature_cells(phi, cells)
+    return cells, kref.ravel()[cells], info
+
+
+def check_against(ref, phi, k, precision, report=""):
+    cells, kr, info = ref
     good = (info[:, 0] >= 5) & (info[:, 2] <= 1e6)
-    kr = kref.ravel()[cells]
     kg = k.ravel()[cells].astype(np.float64)
     tol = 1e-5 + 1e-3 * np.abs(kr)
     if precision == "fp32":
@@ -55,6 +60,10 @@ def check_cells(orc, phi, k, precision, report=""):
     off[cells] = False
     assert np.all(k.ravel()[off] == 0.0)
     return kg, kr, good
+
+
+def check_cells(orc, phi, k, precision, report=""):
+    return check_against(cell_reference(orc, phi), phi, k, precision, report)
 
 
 @pytest.fixture(scope="module")

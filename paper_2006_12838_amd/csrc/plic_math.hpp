@@ -41,6 +41,8 @@ template <> struct M<float> {
     }
     static __device__ __forceinline__ float asin(float x) { return ::asinf(x); }
     static __device__ __forceinline__ float atan(float x) { return ::atanf(x); }
+    // atan(y / x) for y >= 0, x > 0
+    static __device__ __forceinline__ float atan2_pos(float y, float x) { return ::atanf(y * __builtin_amdgcn_rcpf(x)); }
     static __device__ __forceinline__ float fmin(float a, float b) { return ::fminf(a, b); }
     static __device__ __forceinline__ float fmax(float a, float b) { return ::fmaxf(a, b); }
     static __device__ __forceinline__ float fabs(float a) { return ::fabsf(a); }
@@ -78,6 +80,33 @@ template <> struct M<double> {
     }
     static __device__ __forceinline__ double asin(double x) { return ::asin(x); }
     static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
+    // atan(y / x) for y >= 0, x > 0 (within 3 ulp).  With a <= b the smaller
+    // and larger of y and x, u = a / b in [0, 1] is reduced about tan(k pi/8),
+    // k = 0, 1, 2, by atan(u) = k pi/8 + atan(v), v = (a - t b) / (b + t a),
+    // |v| <= tan(pi/16); atan(v) by its Maclaurin series through v^21 (first
+    // omitted term below 2^-53 |v|); y > x reflects through pi/2.
+    static __device__ __forceinline__ double atan2_pos(double y, double x) {
+        const bool sw = y > x;
+        const double a = sw ? x : y, b = sw ? y : x;
+        const bool k1 = a >= 0.19891236737965800691 * b;                // tan(pi/16)
+        const bool k2 = a >= 0.66817863791929891999 * b;                // tan(3 pi/16)
+        const double t = k2 ? 1.0 : (k1 ? 0.41421356237309504880 : 0.0);  // tan(k pi/8)
+        const double c = k2 ? 0.78539816339744830962 : (k1 ? 0.39269908169872415481 : 0.0);
+        const double v = (a - t * b) / (b + t * a);
+        const double v2 = v * v;
+        double p = 1.0 / 21.0;
+        p = p * v2 - 1.0 / 19.0;
+        p = p * v2 + 1.0 / 17.0;
+        p = p * v2 - 1.0 / 15.0;
+        p = p * v2 + 1.0 / 13.0;
+        p = p * v2 - 1.0 / 11.0;
+        p = p * v2 + 1.0 / 9.0;
+        p = p * v2 - 1.0 / 7.0;
+        p = p * v2 + 1.0 / 5.0;
+        p = p * v2 - 1.0 / 3.0;
+        const double r = c + (v + v * v2 * p);
+        return sw ? 1.57079632679489661923 - r : r;
+    }
     static __device__ __forceinline__ double fmin(double a, double b) { return ::fmin(a, b); }
     static __device__ __forceinline__ double fmax(double a, double b) { return ::fmax(a, b); }
     static __device__ __forceinline__ double fabs(double a) { return ::fabs(a); }
@@ -220,7 +249,7 @@ __device__ __forceinline__ T cubic_analytic(const Open<T>& o) {
     x = m::fmax(x, m::tiny);
     const U y = m::sqrt(m::fmax(r2 - x * x, U(0)));
     // the sine's argument lies in (0, pi/6]: atan(y/x) is in [0, pi/2)
-    return T(c - pref * m::sin_small(pi6 - third * m::atan(m::div(y, x))));
+    return T(c - pref * m::sin_small(pi6 - third * m::atan2_pos(y, x)));
 }
 
 // ---------------------------------------------------------------------------

@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--lattice", type=int, default=256)
     ap.add_argument("--radius", type=float, default=40.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-paper-isolated", action="store_true",
+                    help="skip the compute-isolated timing after the paper's Table 3 method")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle CPU baseline sample")
     ap.add_argument("--only", default="", help="comma list of kernels to run (profiling aid)")
@@ -226,6 +228,48 @@ def write_issue_profile(sq_csv, log2n, lattice, out=ISSUE_PROFILE):
     return out
 
 
+# Table 3 of the paper (Nvidia Titan Xp, OpenCL, FP32): ps per isolated PLIC and E_avg
+PAPER_TABLE3 = {"sz": (12.8, 6.58e-8), "analytic": (19.0, 5.73e-8), "newton": (19.2, 5.47e-8),
+                "nested": (106.4, 2.86e-8)}
+
+
+def paper_isolated(P, torch, dev, log2n, L=256, reps=5):
+    """The paper's GPU benchmark method (Sec. 3.5): 2^log2n normals of its mix
+    (one axis, one face diagonal, 1/8 random 2D, the rest random 3D), each
+    thread sweeping L equally spaced V0 in series with a round trip through the
+    forward volume; the blank run (d0 = V0 - 1/2) is subtracted and the time
+    divided by the N L evaluations.  Context for the paper's Table 3, not the
+    headline (which streams inputs from HBM)."""
+    import workloads
+
+    n = 1 << log2n
+    t = [torch.from_numpy(a).to(dev) for a in workloads.paper_mix_normals(n, seed=3)]
+    err = torch.empty_like(t[0])
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    blank_ms = timed(lambda: P.plic_bench_isolated_f32(*t, err, L, "sz", True))
+    out = {"normals": n, "L": L, "reps": reps, "blank_ms": round(blank_ms, 4), "solvers": {}}
+    for s in SOLVERS:
+        ms = timed(lambda: P.plic_bench_isolated_f32(*t, err, L, s, False))
+        e_avg = err.double().sum().item() / (n * L)
+        ps = (ms - blank_ms) * 1e9 / (n * L)
+        out["solvers"][s] = {"ms": round(ms, 4), "ps_per_plic": round(ps, 3), "E_avg": e_avg,
+                             "paper_titan_xp_ps": PAPER_TABLE3[s][0], "paper_E_avg": PAPER_TABLE3[s][1]}
+        print(f"bench: isolated {s}: {ps:.2f} ps/PLIC", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(nx, ny, nz, V0, seconds):
     """The oracle (bisection on the FP64 forward volume), timed on the host
     cores on chunks of the same workload until `seconds` have passed."""
@@ -382,6 +426,8 @@ def main():
                                                      "hbm_frac": rates[fast[0]]["hbm_frac"]},
         "roofline": roofline,
     }
+    if not args.no_paper_isolated and not args.only:
+        out["paper_isolated"] = paper_isolated(P, torch, dev, args.log2n)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nx, ny, nz, V0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

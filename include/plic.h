@@ -110,7 +110,8 @@ int plic_offset_backward_f64(const double *nx, const double *ny, const double *n
  * cells per tile (41 MB at 256^3); any size of at least the fixed part is
  * valid: interface cells beyond the store's capacity are recomputed by the
  * backward pass (slower, same result).  The forward pass uses only the fixed
- * part.  0 for an empty or invalid lattice (more than 2^25 tiles is invalid).
+ * part.  0 for an empty or invalid lattice (2^24 tiles or more, i.e. about
+ * 1.7e10 cells, is invalid).
  * The workspace is caller-owned device memory; its contents need no
  * initialisation (each call clears what it uses with a kernel) and are
  * scratch after the call.

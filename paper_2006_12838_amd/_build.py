@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libplic.so")
 BUILD = os.path.join(os.path.dirname(PKG), "_build")
-SOURCES = ["plic_offset.hip", "plic_curvature.hip", "plic_abi.cpp"]
+SOURCES = ["plic_offset.hip", "plic_curvature.hip", "plic_bench.hip", "plic_abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # Packed FP32 (v_pk_*_f32) is disabled for all device code.

@@ -44,6 +44,7 @@ _c = {
     "plic_curvature_backward_f32": _sig("plic_curvature_backward_f32",
                                         [_vp, _i64, _i64, _i64, _vp, _vp, _int, _int, _vp,
                                          ctypes.c_size_t, _vp]),
+    "plic_bench_isolated_f32": _sig("plic_bench_isolated_f32", [_vp, _vp, _vp, _i64, _int, _int, _int, _vp, _vp]),
 }
 _lib.plic_curvature_workspace_bytes.restype = ctypes.c_size_t
 _lib.plic_curvature_workspace_bytes.argtypes = [_i64, _i64, _i64]
@@ -228,3 +229,16 @@ def plic_curvature_backward_f32(phi, grad_kappa, grad_phi, solver="analytic", pr
                                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
            "plic_curvature_backward_f32")
     return grad_phi
+
+
+def plic_bench_isolated_f32(nx, ny, nz, err, L=256, solver="sz", blank=False):
+    """Compute-isolated timing kernel (include/plic_bench.h): err[i] = sum over
+    V0 = j/(L-1), j < L, of |V(n_i, d0(n_i, V0)) - V0|; blank=True swaps the
+    inversion for d0 = V0 - 1/2."""
+    n = err.numel()
+    _same_device(nx, ny, nz, err)
+    args = [_ptr(t, torch.float32, n, w) for t, w in zip((nx, ny, nz), ("nx", "ny", "nz"))]
+    _check(_c["plic_bench_isolated_f32"](*args, n, int(L), _enum(SOLVERS, solver, "solver"), int(bool(blank)),
+                                         _ptr(err, torch.float32, n, "err"), _stream(err)),
+           "plic_bench_isolated_f32")
+    return err

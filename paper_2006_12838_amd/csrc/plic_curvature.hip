@@ -724,7 +724,9 @@ int check_lattice(int64_t X, int64_t Y, int64_t Z, bool* empty, Grid* g) {
     if (X > (int64_t(1) << 62) / Y / Z) return PLIC_EINVAL;
     const int64_t tx = (X + TX - 1) / TX, ty = (Y + TY - 1) / TY, tz = (Z + TZ - 1) / TZ;
     if (tx > lim / ty || tx * ty > lim / tz) return PLIC_EINVAL;   // grid limit
-    if (tx * ty * tz >= (int64_t(1) << 25)) return PLIC_EINVAL;    // work items hold a 25-bit tile index
+    // the scan launches 256 work-items per tile (a dispatch holds < 2^32), and
+    // work items hold a 25-bit tile index
+    if (tx * ty * tz >= (int64_t(1) << 24)) return PLIC_EINVAL;
     g->ntx = static_cast<int>(tx);
     g->nty = static_cast<int>(ty);
     g->ntz = static_cast<int>(tz);

@@ -217,14 +217,29 @@ inline unsigned grid_for(int64_t count, int vec) {
 
 template <class S> constexpr int kVec = 16 / sizeof(S);
 
+// A dispatch holds at most 2^32 - 1 work-items; batches are launched in
+// chunks of 2^30 problems (a multiple of every block's problem count).
+constexpr int64_t kChunkProblems = int64_t(1) << 30;
+
+template <class S, class T, int VEC>
+void launch_volume_v(const S* nx, const S* ny, const S* nz, const S* d0, S* V0, int64_t count, hipStream_t st) {
+    for (int64_t base = 0; base < count; base += kChunkProblems) {
+        const int64_t n = count - base < kChunkProblems ? count - base : kChunkProblems;
+        hipLaunchKernelGGL((k_volume<S, T, VEC>), dim3(grid_for(n, VEC)), dim3(kBlock), 0, st, nx + base, ny + base,
+                           nz + base, d0 + base, V0 + base, n);
+    }
+}
+
 // ---- dispatch ------------------------------------------------------------------
 // whole blocks unchecked, then the remainder in one checked block
 template <int SOLVER, class S, class T, class U, int VEC>
 void launch_offset_v(const S* nx, const S* ny, const S* nz, const S* V0, S* d0, int64_t count, hipStream_t st) {
     const int64_t per = static_cast<int64_t>(kBlock) * VEC, full = count / per * per, rem = count - full;
-    if (full)
-        hipLaunchKernelGGL((k_offset<SOLVER, S, T, U, VEC, true>), dim3(grid_for(full, VEC)), dim3(kBlock), 0, st,
-                           nx, ny, nz, V0, d0, full);
+    for (int64_t base = 0; base < full; base += kChunkProblems) {
+        const int64_t n = full - base < kChunkProblems ? full - base : kChunkProblems;
+        hipLaunchKernelGGL((k_offset<SOLVER, S, T, U, VEC, true>), dim3(grid_for(n, VEC)), dim3(kBlock), 0, st,
+                           nx + base, ny + base, nz + base, V0 + base, d0 + base, n);
+    }
     if (rem)
         hipLaunchKernelGGL((k_offset<SOLVER, S, T, U, VEC, false>), dim3(1), dim3(kBlock), 0, st,
                            nx + full, ny + full, nz + full, V0 + full, d0 + full, rem);
@@ -252,9 +267,12 @@ template <int SOLVER, class S, class T, class U, int VEC>
 void launch_bwd_v(const S* nx, const S* ny, const S* nz, const S* V0, const S* gd, S* gx, S* gy, S* gz, S* gv,
                   int64_t count, hipStream_t st) {
     const int64_t per = static_cast<int64_t>(kBlock) * VEC, full = count / per * per, rem = count - full;
-    if (full)
-        hipLaunchKernelGGL((k_offset_bwd<SOLVER, S, T, U, VEC, true>), dim3(grid_for(full, VEC)), dim3(kBlock), 0,
-                           st, nx, ny, nz, V0, gd, gx, gy, gz, gv, full);
+    for (int64_t base = 0; base < full; base += kChunkProblems) {
+        const int64_t n = full - base < kChunkProblems ? full - base : kChunkProblems;
+        hipLaunchKernelGGL((k_offset_bwd<SOLVER, S, T, U, VEC, true>), dim3(grid_for(n, VEC)), dim3(kBlock), 0,
+                           st, nx + base, ny + base, nz + base, V0 + base, gd + base, gx + base, gy + base, gz + base,
+                           gv + base, n);
+    }
     if (rem)
         hipLaunchKernelGGL((k_offset_bwd<SOLVER, S, T, U, VEC, false>), dim3(1), dim3(kBlock), 0, st,
                            nx + full, ny + full, nz + full, V0 + full, gd + full, gx + full, gy + full, gz + full,
@@ -343,11 +361,11 @@ int plic_volume_f32(const float* nx, const float* ny, const float* nz, const flo
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool vec = all_aligned16<float>({nx, ny, nz, d0, V0});
     if (precision == PLIC_FP64) {
-        if (vec) hipLaunchKernelGGL((k_volume<float, double, 4>), dim3(grid_for(count, 4)), dim3(kBlock), 0, st, nx, ny, nz, d0, V0, count);
-        else hipLaunchKernelGGL((k_volume<float, double, 1>), dim3(grid_for(count, 1)), dim3(kBlock), 0, st, nx, ny, nz, d0, V0, count);
+        if (vec) launch_volume_v<float, double, 4>(nx, ny, nz, d0, V0, count, st);
+        else launch_volume_v<float, double, 1>(nx, ny, nz, d0, V0, count, st);
     } else {
-        if (vec) hipLaunchKernelGGL((k_volume<float, float, 4>), dim3(grid_for(count, 4)), dim3(kBlock), 0, st, nx, ny, nz, d0, V0, count);
-        else hipLaunchKernelGGL((k_volume<float, float, 1>), dim3(grid_for(count, 1)), dim3(kBlock), 0, st, nx, ny, nz, d0, V0, count);
+        if (vec) launch_volume_v<float, float, 4>(nx, ny, nz, d0, V0, count, st);
+        else launch_volume_v<float, float, 1>(nx, ny, nz, d0, V0, count, st);
     }
     return launch_status();
 }
@@ -364,10 +382,8 @@ int plic_volume_f64(const double* nx, const double* ny, const double* nz, const 
         return PLIC_EINVAL;
     if (count == 0) return PLIC_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (all_aligned16<double>({nx, ny, nz, d0, V0}))
-        hipLaunchKernelGGL((k_volume<double, double, 2>), dim3(grid_for(count, 2)), dim3(kBlock), 0, st, nx, ny, nz, d0, V0, count);
-    else
-        hipLaunchKernelGGL((k_volume<double, double, 1>), dim3(grid_for(count, 1)), dim3(kBlock), 0, st, nx, ny, nz, d0, V0, count);
+    if (all_aligned16<double>({nx, ny, nz, d0, V0})) launch_volume_v<double, double, 2>(nx, ny, nz, d0, V0, count, st);
+    else launch_volume_v<double, double, 1>(nx, ny, nz, d0, V0, count, st);
     return launch_status();
 }
 

@@ -3,19 +3,22 @@ declared in include/plic.h, and rejects invalid arguments before touching the
 HIP runtime (null / misaligned / overlapping pointers, negative sizes, unknown
 enums); empty inputs succeed without any HIP call."""
 import ctypes
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "plic.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(plic_\w+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(plic_\w+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -101,6 +104,8 @@ def test_curvature_validation(lib):
     per_tile = 784 + 16 * 108                     # fixed part + 16 contribution rows
     assert lib.plic_curvature_workspace_bytes(256, 256, 256) == 256 + 16384 * per_tile
     assert lib.plic_curvature_workspace_bytes(65, 5, 5) == 256 + 8 * per_tile   # 2x2x2 tiles
+    assert lib.plic_curvature_workspace_bytes(64 * 4096, 4 * 4096, 4) == 0        # 2^24 tiles: too many
+    assert lib.plic_curvature_workspace_bytes(64 * 4096, 4 * 4095, 4) > 0
     assert lib.plic_curvature_workspace_bytes(0, 5, 5) == 0
     assert lib.plic_curvature_workspace_bytes(-1, 5, 5) == 0
     W = 0xA0000
@@ -124,6 +129,19 @@ def test_curvature_validation(lib):
     assert g(A, 3, 3, 3, B, B + 4, 0, 1, W, ws, None) == -1           # grad_phi overlaps grad_kappa
     assert g(A, 3, 3, 3, None, C, 0, 1, W, ws, None) == -1
     assert g(A, 3, 3, 3, B, C, 0, 1, C, ws, None) == -1               # workspace overlaps grad_phi
+
+
+def test_bench_validation(lib):
+    f = lib.raw("plic_bench_isolated_f32")
+    assert f(A, B, C, 0, 256, 0, 0, D, None) == 0                     # empty
+    assert f(A, B, C, -1, 256, 0, 0, D, None) == -1
+    assert f(A, B, C, 8, 1, 0, 0, D, None) == -1                      # L < 2
+    assert f(A, B, C, 8, 256, 4, 0, D, None) == -1                    # bad solver
+    assert f(A, B, C, 8, 256, 0, 2, D, None) == -1                    # bad blank flag
+    assert f(A, B, C, 8, 256, 0, 0, A + 4, None) == -1                # err overlaps nx
+    assert f(A + 2, B, C, 8, 256, 0, 0, D, None) == -1                # misaligned
+    far = [k << 40 for k in (1, 2, 3, 4)]                               # disjoint 8 GiB ranges
+    assert f(*far[:3], (1 << 31) + 1, 256, 0, 0, far[3], None) == -1    # grid limit
 
 
 def test_python_layer_rejects_cpu_tensors(lib):

@@ -1,0 +1,66 @@
+"""The compute-isolated benchmark kernel (the paper's GPU test method,
+Sec. 3.5): its per-normal error sums equal the same round trip computed with
+the library's batched inversion and forward volume, summed in the same order,
+and its average round-trip error is at FP32 rounding level."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from tests.gpu_util import SOLVERS, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2006_12838_amd as P
+    return P
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_isolated_matches_batched_round_trip(P, solver):
+    n, L = 2048, 64
+    nx, ny, nz = workloads.paper_mix_normals(n, seed=5)
+    V0 = (np.arange(L, dtype=np.float32) / np.float32(L - 1)).astype(np.float32)
+    assert V0[0] == 0.0 and V0[-1] == 1.0
+    tx, ty, tz = dev(nx, ny, nz)
+    err = torch.empty_like(tx)
+    P.plic_bench_isolated_f32(tx, ty, tz, err, L, solver, False)
+    got = host(err)
+    # the same n L problems through the batched kernels
+    bx, by, bz = (np.repeat(a, L) for a in (nx, ny, nz))
+    bv = np.tile(V0, n)
+    cx, cy, cz, cv = dev(bx, by, bz, bv)
+    d0 = torch.empty_like(cv)
+    P.plic_offset_f32(cx, cy, cz, cv, d0, solver, "fp32")
+    V = torch.empty_like(cv)
+    P.plic_volume_f32(cx, cy, cz, d0, V, "fp32")
+    E = np.abs(host(V) - bv).reshape(n, L)
+    ref = np.zeros(n, np.float32)
+    for j in range(L):                     # the kernel's summation order, in FP32
+        ref = (ref + E[:, j]).astype(np.float32)
+    assert np.allclose(got, ref, rtol=1e-5, atol=1e-9)
+    e_avg = float(got.astype(np.float64).sum() / (n * L))
+    print(f"{solver}: E_avg {e_avg:.3e}")
+    assert e_avg < 2e-7
+
+
+def test_blank_run(P):
+    """The blank run inverts nothing: d0 = V0 - 1/2 through the forward volume."""
+    n, L = 1024, 32
+    nx, ny, nz = workloads.paper_mix_normals(n, seed=6)
+    tx, ty, tz = dev(nx, ny, nz)
+    err = torch.empty_like(tx)
+    P.plic_bench_isolated_f32(tx, ty, tz, err, L, "sz", True)
+    V0 = (np.arange(L, dtype=np.float32) / np.float32(L - 1)).astype(np.float32)
+    bx, by, bz = (np.repeat(a, L) for a in (nx, ny, nz))
+    bd = np.tile(V0 - np.float32(0.5), n).astype(np.float32)
+    cx, cy, cz, cd = dev(bx, by, bz, bd)
+    V = torch.empty_like(cd)
+    P.plic_volume_f32(cx, cy, cz, cd, V, "fp32")
+    E = np.abs(host(V) - np.tile(V0, n)).reshape(n, L)
+    ref = np.zeros(n, np.float32)
+    for j in range(L):
+        ref = (ref + E[:, j]).astype(np.float32)
+    assert np.allclose(host(err), ref, rtol=1e-5, atol=1e-9)

@@ -73,6 +73,17 @@ def _load():
     lib.orc_curv_cell_fd_grad.argtypes = [_D, _U8, c_d, _D]
     lib.orc_curvature_grad.restype = c_i64
     lib.orc_curvature_grad.argtypes = [_F, c_i64, c_i64, c_i64, _F, c_d, _D, _U8]
+    lib.orc_curv_cell_k.restype = c_d
+    lib.orc_curv_cell_k.argtypes = [_D, _U8, ctypes.c_int, _D, _D]
+    lib.orc_curv_cell_nbr.restype = c_d
+    lib.orc_curv_cell_nbr.argtypes = [_D, _U8, ctypes.c_int, _D]
+    lib.orc_curvature_ex.argtypes = [_F, c_i64, c_i64, c_i64, ctypes.c_int, ctypes.c_int, _D, _U8]
+    lib.orc_curvature_cells_ex.argtypes = [_F, c_i64, c_i64, c_i64, ctypes.c_int, ctypes.c_int, _I64, c_i64,
+                                           _D, _D]
+    lib.orc_curv_cell_fd_grad_k.restype = ctypes.c_int
+    lib.orc_curv_cell_fd_grad_k.argtypes = [_D, _U8, ctypes.c_int, c_d, _D]
+    lib.orc_curvature_grad_ex.restype = c_i64
+    lib.orc_curvature_grad_ex.argtypes = [_F, c_i64, c_i64, c_i64, ctypes.c_int, _F, c_d, _D, _U8]
     _lib = lib
     return lib
 
@@ -183,18 +194,29 @@ def paraboloid_kappa(coef):
     return _load().orc_paraboloid_kappa(_p(c))
 
 
-def curvature(phi, flags=False):
-    """kappa over a (Z, Y, X) float32 lattice, float64 out (and per-cell flags)."""
+NORMALS = {"py": 0, "cm": 1}
+
+
+def _kind(normal):
+    if normal not in NORMALS:
+        raise ValueError(f"normal must be one of {sorted(NORMALS)}")
+    return NORMALS[normal]
+
+
+def curvature(phi, flags=False, normal="py", neighbour_normals=False):
+    """kappa over a (Z, Y, X) float32 lattice, float64 out (and per-cell flags).
+    normal: "py" (Parker-Youngs) or "cm" (centre of mass), App. B.1;
+    neighbour_normals: each interface neighbour's plane uses its own normal."""
     lib = _load()
     phi = np.ascontiguousarray(np.asarray(phi, dtype=np.float32))
     Z, Y, X = phi.shape
     k = np.empty(phi.shape, dtype=np.float64)
     fl = np.empty(phi.shape, dtype=np.uint8)
-    lib.orc_curvature(_p(phi, _F), X, Y, Z, _p(k), _p(fl, _U8))
+    lib.orc_curvature_ex(_p(phi, _F), X, Y, Z, _kind(normal), int(bool(neighbour_normals)), _p(k), _p(fl, _U8))
     return (k, fl) if flags else k
 
 
-def curvature_cells(phi, cells):
+def curvature_cells(phi, cells, normal="py", neighbour_normals=False):
     """kappa at selected linear cell indices, plus info[ncells, 3]."""
     lib = _load()
     phi = np.ascontiguousarray(np.asarray(phi, dtype=np.float32))
@@ -202,22 +224,46 @@ def curvature_cells(phi, cells):
     cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64))
     k = np.empty(cells.size)
     info = np.empty((cells.size, 3))
-    lib.orc_curvature_cells(_p(phi, _F), X, Y, Z, _p(cells, _I64), cells.size, _p(k), _p(info))
+    lib.orc_curvature_cells_ex(_p(phi, _F), X, Y, Z, _kind(normal), int(bool(neighbour_normals)),
+                               _p(cells, _I64), cells.size, _p(k), _p(info))
     return k, info
 
 
-def curv_cell_fd_grad(phi27, mask27=None, h=1e-6):
+def curv_cell_k(phi27, normal="py", mask27=None):
+    """one cell with the chosen normal; returns (kappa, info[3], normal[3])"""
+    lib = _load()
+    p = _d(phi27).ravel()
+    if mask27 is None:
+        mask27 = (p > 0) & (p < 1)
+    m = np.ascontiguousarray(np.asarray(mask27, dtype=np.uint8).ravel())
+    info, n = np.zeros(3), np.zeros(3)
+    k = lib.orc_curv_cell_k(_p(p), _p(m, _U8), _kind(normal), _p(info), _p(n))
+    return k, info, n
+
+
+def curv_cell_nbr(phi125, normal="py", inside27=None):
+    """neighbour-normal variant on a 5^3 neighbourhood [dz+2][dy+2][dx+2];
+    inside27[q] = 0 makes neighbour q keep the centre normal"""
+    lib = _load()
+    p = _d(phi125).ravel()
+    assert p.size == 125
+    ins = np.ones(27, np.uint8) if inside27 is None else np.ascontiguousarray(np.asarray(inside27, np.uint8).ravel())
+    info = np.zeros(3)
+    return lib.orc_curv_cell_nbr(_p(p), _p(ins, _U8), _kind(normal), _p(info)), info
+
+
+def curv_cell_fd_grad(phi27, mask27=None, h=1e-6, normal="py"):
     lib = _load()
     p = _d(phi27).ravel()
     if mask27 is None:
         mask27 = (p > 0) & (p < 1)
     m = np.ascontiguousarray(np.asarray(mask27, dtype=np.uint8).ravel())
     g = np.zeros(27)
-    bad = lib.orc_curv_cell_fd_grad(_p(p), _p(m, _U8), float(h), _p(g))
+    bad = lib.orc_curv_cell_fd_grad_k(_p(p), _p(m, _U8), _kind(normal), float(h), _p(g))
     return g, bool(bad)
 
 
-def curvature_grad(phi, grad_kappa, h=1e-6):
+def curvature_grad(phi, grad_kappa, h=1e-6, normal="py"):
     """grad_phi (float64) of sum(grad_kappa * kappa) by finite differences of the
     oracle's curvature with the interface mask fixed; also the bad-cell mask."""
     lib = _load()
@@ -226,7 +272,7 @@ def curvature_grad(phi, grad_kappa, h=1e-6):
     Z, Y, X = phi.shape
     out = np.empty(phi.shape, dtype=np.float64)
     bad = np.empty(phi.shape, dtype=np.uint8)
-    lib.orc_curvature_grad(_p(phi, _F), X, Y, Z, _p(gk, _F), float(h), _p(out), _p(bad, _U8))
+    lib.orc_curvature_grad_ex(_p(phi, _F), X, Y, Z, _kind(normal), _p(gk, _F), float(h), _p(out), _p(bad, _U8))
     return out, bad.astype(bool)
 
 

@@ -21,9 +21,11 @@
  *    plane; dV0/dd0 = A/|n| and dV0/dn = -(A/|n|) * centroid, with A and the
  *    centroid of the plane-cube intersection polygon built explicitly;
  *  - curvature: Sec. 5.2 (PLIC point neighbourhood, coordinate transform with
- *    the fixed vector r), App. B.1 (Parker-Youngs normal), B.2 (paraboloid mean
- *    curvature at the origin), B.3 (least-squares normal equations, reduced
- *    dimension when fewer than 5 points).
+ *    the fixed vector r), App. B.1 (Parker-Youngs normal, or the centre-of-mass
+ *    normal as an option), B.2 (paraboloid mean curvature at the origin), B.3
+ *    (least-squares normal equations, reduced dimension when fewer than 5
+ *    points); as an option, the variant of Sec. 5.2 and Sec. 5.3 in which each
+ *    interface neighbour's PLIC plane uses that neighbour's own normal.
  *
  * Readings where the paper is silent or ambiguous (each also used by the GPU
  * library, written independently there):
@@ -35,7 +37,11 @@
  *    that a fluid drop (normal pointing out of the fluid) has kappa = +1/R;
  *  - |g| < 1e-12 gives kappa = 0; if |n x r| < 1e-6 the vector r is replaced
  *    by (r_y, r_z, r_x);
- *  - kappa = 0 on non-interface cells and on the outer one-cell layer.
+ *  - kappa = 0 on non-interface cells and on the outer one-cell layer;
+ *  - neighbour-normal variant: neighbour q's point is the foot of its own
+ *    plane, e_q + d0(phi_q, n_q) n_q - d0(phi_0, n) n, in the centre frame; a
+ *    neighbour on the outer lattice layer (its 3^3 neighbourhood leaves the
+ *    lattice) or with |g| < 1e-12 keeps the centre normal.
  */
 #include "plic_oracle.h"
 
@@ -349,35 +355,48 @@ int orc_fit_paraboloid(const double *px, const double *py, const double *pz, int
     }
 }
 
-double orc_curv_cell_full(const double phi[27], const unsigned char mask[27], double info[3],
-                          double normal[3], double coef[5])
+/* fill-level gradient of a 3^3 neighbourhood (App. B.1): Parker-Youngs
+ * weights 4 / 2 / 1 for |e| = 1 / sqrt2 / sqrt3 (kind 0), or the centre-of-mass
+ * method with equal weights (kind 1); returns |g|, n = -g / |g| */
+static double normal_of(const double p27[27], int kind, double n[3])
 {
-    return orc_curv_cell_r(phi, mask, R_AUX, info, normal, coef);
+    double g[3] = {0, 0, 0}, gn;
+    int dx, dy, dz;
+    for (dz = -1; dz <= 1; ++dz) for (dy = -1; dy <= 1; ++dy) for (dx = -1; dx <= 1; ++dx) {
+        int q = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1), e2 = dx * dx + dy * dy + dz * dz;
+        double w;
+        if (e2 == 0) continue;
+        w = kind == 1 ? 1.0 : (e2 == 1 ? 4.0 : (e2 == 2 ? 2.0 : 1.0));
+        g[0] += w * dx * p27[q];
+        g[1] += w * dy * p27[q];
+        g[2] += w * dz * p27[q];
+    }
+    gn = sqrt(dot3(g, g));
+    if (gn > 0.0) { n[0] = -g[0] / gn; n[1] = -g[1] / gn; n[2] = -g[2] / gn; }
+    else { n[0] = n[1] = n[2] = 0.0; }
+    return gn;
 }
 
-double orc_curv_cell_r(const double phi[27], const unsigned char mask[27], const double raux[3],
-                       double info[3], double normal[3], double coef[5])
+/* One interface cell (Sec. 5.2 and App. B).  nbrn == NULL: every neighbour's
+ * PLIC plane uses the centre normal n, the point of neighbour i is
+ * (e_i.b_x, e_i.b_y, e_i.n + d0(phi_i, n) - d0(phi_0, n)).  Otherwise nbrn[q]
+ * is neighbour q's own normal n_q and its point is the foot of its own plane,
+ * P_q = e_q + d0(phi_q, n_q) n_q - d0(phi_0, n) n, in the centre frame
+ * (x, y, z) = (P_q.b_x, P_q.b_y, P_q.n); this reduces to the first form when
+ * n_q = n. */
+static double cell_core(const double phi[27], const unsigned char mask[27], const double raux[3],
+                        int kind, const double (*nbrn)[3], double info[3], double normal[3],
+                        double coef[5])
 {
-    double g[3] = {0, 0, 0}, gn, n[3], u[3], r[3], un, by[3], bx[3], D0;
+    double gn, n[3], u[3], r[3], un, by[3], bx[3], D0;
     double px[26], py[26], pz[26], cond = 0.0;
     int dx, dy, dz, npts = 0, bits;
     double c5[5];
     if (!coef) coef = c5;
     for (int j = 0; j < 5; ++j) coef[j] = 0.0;
     if (info) { info[0] = 0; info[1] = 0; info[2] = 0; }
-    /* Parker-Youngs gradient (App. B.1): weights 4 / 2 / 1 for |e| = 1 / sqrt2 / sqrt3 */
-    for (dz = -1; dz <= 1; ++dz) for (dy = -1; dy <= 1; ++dy) for (dx = -1; dx <= 1; ++dx) {
-        int q = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1), e2 = dx * dx + dy * dy + dz * dz;
-        double w;
-        if (e2 == 0) continue;
-        w = e2 == 1 ? 4.0 : (e2 == 2 ? 2.0 : 1.0);
-        g[0] += w * dx * phi[q];
-        g[1] += w * dy * phi[q];
-        g[2] += w * dz * phi[q];
-    }
-    gn = sqrt(dot3(g, g));
+    gn = normal_of(phi, kind, n);
     if (!(gn >= 1e-12)) { if (normal) normal[0] = normal[1] = normal[2] = 0; return 0.0; }
-    n[0] = -g[0] / gn; n[1] = -g[1] / gn; n[2] = -g[2] / gn;
     if (normal) { normal[0] = n[0]; normal[1] = n[1]; normal[2] = n[2]; }
     /* local frame (Sec. 5.2): b_z = n, b_y = n x r / |n x r|, b_x = b_y x b_z */
     r[0] = raux[0]; r[1] = raux[1]; r[2] = raux[2];
@@ -390,16 +409,23 @@ double orc_curv_cell_r(const double phi[27], const unsigned char mask[27], const
     }
     by[0] = u[0] / un; by[1] = u[1] / un; by[2] = u[2] / un;
     cross3(by, n, bx);
-    /* PLIC points of the interface neighbours, centre normal for every one */
+    /* PLIC points of the interface neighbours */
     D0 = orc_offset1(n[0], n[1], n[2], phi[13]);
     for (dz = -1; dz <= 1; ++dz) for (dy = -1; dy <= 1; ++dy) for (dx = -1; dx <= 1; ++dx) {
         int q = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
-        double e[3] = {(double)dx, (double)dy, (double)dz}, Di;
+        double e[3] = {(double)dx, (double)dy, (double)dz}, P[3];
         if (q == 13 || !mask[q]) continue;
-        Di = orc_offset1(n[0], n[1], n[2], phi[q]);
-        px[npts] = dot3(e, bx);
-        py[npts] = dot3(e, by);
-        pz[npts] = dot3(e, n) + Di - D0;
+        if (nbrn) {
+            const double *nq = nbrn[q];
+            double Di = orc_offset1(nq[0], nq[1], nq[2], phi[q]);
+            for (int k = 0; k < 3; ++k) P[k] = e[k] + Di * nq[k] - D0 * n[k];
+        } else {
+            double Di = orc_offset1(n[0], n[1], n[2], phi[q]);
+            for (int k = 0; k < 3; ++k) P[k] = e[k] + (Di - D0) * n[k];
+        }
+        px[npts] = dot3(P, bx);
+        py[npts] = dot3(P, by);
+        pz[npts] = dot3(P, n);
         ++npts;
     }
     bits = orc_fit_paraboloid(px, py, pz, npts, coef, &cond);
@@ -408,9 +434,58 @@ double orc_curv_cell_r(const double phi[27], const unsigned char mask[27], const
     return -orc_paraboloid_kappa(coef);
 }
 
+double orc_curv_cell_full(const double phi[27], const unsigned char mask[27], double info[3],
+                          double normal[3], double coef[5])
+{
+    return cell_core(phi, mask, R_AUX, 0, NULL, info, normal, coef);
+}
+
+double orc_curv_cell_r(const double phi[27], const unsigned char mask[27], const double raux[3],
+                       double info[3], double normal[3], double coef[5])
+{
+    return cell_core(phi, mask, raux, 0, NULL, info, normal, coef);
+}
+
 double orc_curv_cell(const double phi[27], const unsigned char mask[27], double info[3])
 {
-    return orc_curv_cell_full(phi, mask, info, NULL, NULL);
+    return cell_core(phi, mask, R_AUX, 0, NULL, info, NULL, NULL);
+}
+
+double orc_curv_cell_k(const double phi[27], const unsigned char mask[27], int kind, double info[3],
+                       double normal[3])
+{
+    return cell_core(phi, mask, R_AUX, kind, NULL, info, normal, NULL);
+}
+
+/* neighbour-normal variant on a 5^3 neighbourhood p125[(dz+2)*25 + (dy+2)*5 + (dx+2)];
+ * a neighbour keeps the centre normal when its own 3^3 neighbourhood is not
+ * inside the lattice (inside27[q] == 0; NULL: all inside) or its gradient
+ * vanishes (|g| < 1e-12) */
+double orc_curv_cell_nbr(const double p125[125], const unsigned char inside27[27], int kind, double info[3])
+{
+    double p27[27], nbrn[27][3], nc[3];
+    unsigned char mask[27];
+    int dx, dy, dz;
+    for (dz = -1; dz <= 1; ++dz) for (dy = -1; dy <= 1; ++dy) for (dx = -1; dx <= 1; ++dx) {
+        int q = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+        double v = p125[(dz + 2) * 25 + (dy + 2) * 5 + (dx + 2)];
+        p27[q] = v;
+        mask[q] = (unsigned char)(v > 0.0 && v < 1.0);
+    }
+    if (!(normal_of(p27, kind, nc) >= 1e-12)) {
+        if (info) { info[0] = 0; info[1] = 0; info[2] = 0; }
+        return 0.0;
+    }
+    for (dz = -1; dz <= 1; ++dz) for (dy = -1; dy <= 1; ++dy) for (dx = -1; dx <= 1; ++dx) {
+        int q = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1), a, b, c;
+        double s27[27];
+        for (c = -1; c <= 1; ++c) for (b = -1; b <= 1; ++b) for (a = -1; a <= 1; ++a)
+            s27[(c + 1) * 9 + (b + 1) * 3 + (a + 1)] = p125[(dz + c + 2) * 25 + (dy + b + 2) * 5 + (dx + a + 2)];
+        if ((inside27 && !inside27[q]) || !(normal_of(s27, kind, nbrn[q]) >= 1e-12)) {
+            nbrn[q][0] = nc[0]; nbrn[q][1] = nc[1]; nbrn[q][2] = nc[2];
+        }
+    }
+    return cell_core(p27, mask, R_AUX, kind, (const double (*)[3])nbrn, info, NULL, NULL);
 }
 
 static int is_interface(float p) { return p > 0.0f && p < 1.0f; }
@@ -427,21 +502,55 @@ static void gather27(const float *phi, int64_t X, int64_t Y, int64_t x, int64_t 
     }
 }
 
-void orc_curvature(const float *phi, int64_t X, int64_t Y, int64_t Z, double *kappa,
-                   uint8_t *flags)
+/* 5^3 neighbourhood (outside the lattice: 0, never used), and per neighbour
+ * whether its own 3^3 neighbourhood lies inside the lattice */
+static void gather125(const float *phi, int64_t X, int64_t Y, int64_t Z, int64_t x, int64_t y, int64_t z,
+                      double v[125], unsigned char inside27[27])
+{
+    int dx, dy, dz;
+    for (dz = -2; dz <= 2; ++dz) for (dy = -2; dy <= 2; ++dy) for (dx = -2; dx <= 2; ++dx) {
+        int64_t gx = x + dx, gy = y + dy, gz = z + dz;
+        int k = (dz + 2) * 25 + (dy + 2) * 5 + (dx + 2);
+        v[k] = (gx >= 0 && gy >= 0 && gz >= 0 && gx < X && gy < Y && gz < Z) ?
+               (double)phi[(gz * Y + gy) * X + gx] : 0.0;
+    }
+    for (dz = -1; dz <= 1; ++dz) for (dy = -1; dy <= 1; ++dy) for (dx = -1; dx <= 1; ++dx) {
+        int64_t gx = x + dx, gy = y + dy, gz = z + dz;
+        inside27[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] =
+            (unsigned char)(gx >= 1 && gy >= 1 && gz >= 1 && gx <= X - 2 && gy <= Y - 2 && gz <= Z - 2);
+    }
+}
+
+/* one interior interface cell with the options; info may be NULL */
+static double lattice_cell(const float *phi, int64_t X, int64_t Y, int64_t Z, int64_t x, int64_t y,
+                           int64_t z, int kind, int nbr, double info[3])
+{
+    if (nbr) {
+        double v[125];
+        unsigned char inside[27];
+        gather125(phi, X, Y, Z, x, y, z, v, inside);
+        return orc_curv_cell_nbr(v, inside, kind, info);
+    } else {
+        double v[27];
+        unsigned char m[27];
+        gather27(phi, X, Y, x, y, z, v, m);
+        return cell_core(v, m, R_AUX, kind, NULL, info, NULL, NULL);
+    }
+}
+
+void orc_curvature_ex(const float *phi, int64_t X, int64_t Y, int64_t Z, int kind, int nbr,
+                      double *kappa, uint8_t *flags)
 {
     int64_t c, total = X * Y * Z;
 #pragma omp parallel for schedule(dynamic, 4096)
     for (c = 0; c < total; ++c) {
         int64_t x = c % X, y = (c / X) % Y, z = c / (X * Y);
-        double v[27], info[3];
-        unsigned char m[27];
+        double info[3];
         kappa[c] = 0.0;
         if (flags) flags[c] = 0;
         if (x < 1 || y < 1 || z < 1 || x > X - 2 || y > Y - 2 || z > Z - 2) continue;
         if (!is_interface(phi[c])) continue;
-        gather27(phi, X, Y, x, y, z, v, m);
-        kappa[c] = orc_curv_cell(v, m, info);
+        kappa[c] = lattice_cell(phi, X, Y, Z, x, y, z, kind, nbr, info);
         if (flags) {
             flags[c] = 1;
             if (info[2] > 1e8) flags[c] |= 2;
@@ -450,48 +559,63 @@ void orc_curvature(const float *phi, int64_t X, int64_t Y, int64_t Z, double *ka
     }
 }
 
-void orc_curvature_cells(const float *phi, int64_t X, int64_t Y, int64_t Z,
-                         const int64_t *cells, int64_t ncells, double *kappa, double *info3)
+void orc_curvature(const float *phi, int64_t X, int64_t Y, int64_t Z, double *kappa,
+                   uint8_t *flags)
+{
+    orc_curvature_ex(phi, X, Y, Z, 0, 0, kappa, flags);
+}
+
+void orc_curvature_cells_ex(const float *phi, int64_t X, int64_t Y, int64_t Z, int kind, int nbr,
+                            const int64_t *cells, int64_t ncells, double *kappa, double *info3)
 {
     int64_t i;
 #pragma omp parallel for schedule(dynamic, 64)
     for (i = 0; i < ncells; ++i) {
         int64_t c = cells[i], x = c % X, y = (c / X) % Y, z = c / (X * Y);
-        double v[27], info[3] = {0, 0, 0};
-        unsigned char m[27];
+        double info[3] = {0, 0, 0};
         kappa[i] = 0.0;
         if (x >= 1 && y >= 1 && z >= 1 && x <= X - 2 && y <= Y - 2 && z <= Z - 2 &&
-            is_interface(phi[c])) {
-            gather27(phi, X, Y, x, y, z, v, m);
-            kappa[i] = orc_curv_cell(v, m, info);
-        }
+            is_interface(phi[c]))
+            kappa[i] = lattice_cell(phi, X, Y, Z, x, y, z, kind, nbr, info);
         if (info3) { info3[3 * i] = info[0]; info3[3 * i + 1] = info[1]; info3[3 * i + 2] = info[2]; }
     }
 }
 
-int orc_curv_cell_fd_grad(const double phi[27], const unsigned char mask[27], double h,
-                          double grad[27])
+void orc_curvature_cells(const float *phi, int64_t X, int64_t Y, int64_t Z,
+                         const int64_t *cells, int64_t ncells, double *kappa, double *info3)
+{
+    orc_curvature_cells_ex(phi, X, Y, Z, 0, 0, cells, ncells, kappa, info3);
+}
+
+int orc_curv_cell_fd_grad_k(const double phi[27], const unsigned char mask[27], int kind, double h,
+                            double grad[27])
 {
     double base[3], ip[3], im[3], p[27];
     int q, bad = 0;
-    orc_curv_cell(phi, mask, base);
+    orc_curv_cell_k(phi, mask, kind, base, NULL);
     for (q = 0; q < 27; ++q) {
         double kp, km;
         memcpy(p, phi, sizeof p);
         if (mask[q] || q == 13) {
             if (!(phi[q] - h > 0.0 && phi[q] + h < 1.0)) bad = 1;
         }
-        p[q] = phi[q] + h; kp = orc_curv_cell(p, mask, ip);
-        p[q] = phi[q] - h; km = orc_curv_cell(p, mask, im);
+        p[q] = phi[q] + h; kp = orc_curv_cell_k(p, mask, kind, ip, NULL);
+        p[q] = phi[q] - h; km = orc_curv_cell_k(p, mask, kind, im, NULL);
         if (ip[0] != base[0] || im[0] != base[0] || ip[1] != base[1] || im[1] != base[1]) bad = 1;
         grad[q] = (kp - km) / (2.0 * h);
     }
     return bad;
 }
 
-int64_t orc_curvature_grad(const float *phi, int64_t X, int64_t Y, int64_t Z,
-                           const float *grad_kappa, double h, double *grad_phi,
-                           uint8_t *bad_cells)
+int orc_curv_cell_fd_grad(const double phi[27], const unsigned char mask[27], double h,
+                          double grad[27])
+{
+    return orc_curv_cell_fd_grad_k(phi, mask, 0, h, grad);
+}
+
+int64_t orc_curvature_grad_ex(const float *phi, int64_t X, int64_t Y, int64_t Z, int kind,
+                              const float *grad_kappa, double h, double *grad_phi,
+                              uint8_t *bad_cells)
 {
     int64_t total = X * Y * Z, c, nif = 0, k, nbad = 0;
     int64_t *list;
@@ -518,7 +642,7 @@ int64_t orc_curvature_grad(const float *phi, int64_t X, int64_t Y, int64_t Z,
         double v[27];
         unsigned char m[27];
         gather27(phi, X, Y, x, y, z, v, m);
-        bad[k] = orc_curv_cell_fd_grad(v, m, h, part + 27 * k);
+        bad[k] = orc_curv_cell_fd_grad_k(v, m, kind, h, part + 27 * k);
     }
     for (k = 0; k < nif; ++k) {                /* fixed-order scatter */
         int64_t cc = list[k], x = cc % X, y = (cc / X) % Y, z = cc / (X * Y);
@@ -532,4 +656,11 @@ int64_t orc_curvature_grad(const float *phi, int64_t X, int64_t Y, int64_t Z,
     }
     free(list); free(part); free(bad);
     return nbad;
+}
+
+int64_t orc_curvature_grad(const float *phi, int64_t X, int64_t Y, int64_t Z,
+                           const float *grad_kappa, double h, double *grad_phi,
+                           uint8_t *bad_cells)
+{
+    return orc_curvature_grad_ex(phi, X, Y, Z, 0, grad_kappa, h, grad_phi, bad_cells);
 }

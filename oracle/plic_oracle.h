@@ -84,6 +84,28 @@ int64_t orc_curvature_grad(const float *phi, int64_t X, int64_t Y, int64_t Z,
                            const float *grad_kappa, double h, double *grad_phi,
                            uint8_t *bad_cells);
 
+/* ---- curvature options ----
+ * kind: 0 = Parker-Youngs normal (weights 4/2/1), 1 = centre-of-mass normal
+ * (equal weights), App. B.1.  nbr: 0 = every neighbour's PLIC plane uses the
+ * centre normal (Sec. 5.2), 1 = each interface neighbour uses its own normal
+ * (needs the 5^3 neighbourhood; neighbours on the outer lattice layer keep the
+ * centre normal). */
+double orc_curv_cell_k(const double phi[27], const unsigned char mask[27], int kind, double info[3],
+                       double normal[3]);
+/* neighbour-normal variant on p125[(dz+2)*25 + (dy+2)*5 + (dx+2)]; inside27[q]
+ * (NULL: all 1) says whether neighbour q's 3^3 neighbourhood is in the lattice;
+ * a neighbour outside, or with a vanishing gradient, keeps the centre normal */
+double orc_curv_cell_nbr(const double p125[125], const unsigned char inside27[27], int kind, double info[3]);
+void orc_curvature_ex(const float *phi, int64_t X, int64_t Y, int64_t Z, int kind, int nbr,
+                      double *kappa, uint8_t *flags);
+void orc_curvature_cells_ex(const float *phi, int64_t X, int64_t Y, int64_t Z, int kind, int nbr,
+                            const int64_t *cells, int64_t ncells, double *kappa, double *info3);
+int orc_curv_cell_fd_grad_k(const double phi[27], const unsigned char mask[27], int kind, double h,
+                            double grad[27]);
+int64_t orc_curvature_grad_ex(const float *phi, int64_t X, int64_t Y, int64_t Z, int kind,
+                              const float *grad_kappa, double h, double *grad_phi,
+                              uint8_t *bad_cells);
+
 #ifdef __cplusplus
 }
 #endif

@@ -54,6 +54,10 @@ extern "C" {
 #define PLIC_MIXED 1      /* FP32 bulk; FP64 for the cubic-case root and the curvature fit solve   */
 #define PLIC_FP64 2       /* all FP64                                                              */
 
+/* interface normal of the curvature step (App. B.1) */
+#define PLIC_NORMAL_PY 0  /* Parker-Youngs: fill-level gradient with weights 4 / 2 / 1              */
+#define PLIC_NORMAL_CM 1  /* centre of mass: equal weights                                         */
+
 /*
  * plic_offset_f32 / plic_offset_f64 — the PLIC problem (Sec. 2): n, V0 -> d0.
  *   nx, ny, nz, V0 : inputs, `count` elements each.
@@ -158,6 +162,36 @@ int plic_curvature_backward_f32(const float *phi, int64_t X, int64_t Y, int64_t 
                                 const float *grad_kappa, float *grad_phi, int solver,
                                 int precision, void *workspace, size_t workspace_bytes,
                                 void *stream);
+
+/*
+ * plic_curvature_ex_f32 — plic_curvature_f32 with the options of the paper's
+ * curvature section:
+ *   normal            : PLIC_NORMAL_PY (as plic_curvature_f32) or PLIC_NORMAL_CM
+ *                       (App. B.1; about 4 degrees of normal error against 1).
+ *   neighbour_normals : 0 = every neighbour's PLIC plane uses the centre
+ *                       normal (Sec. 5.2, as plic_curvature_f32); 1 = each
+ *                       interface neighbour's plane uses that neighbour's own
+ *                       normal from its 3x3x3 fill levels (the variant of
+ *                       Sec. 5.2 and Sec. 5.3), its point being the foot of
+ *                       its plane, e + d0(phi_q, n_q) n_q - d0(phi_0, n) n, in
+ *                       the centre frame.  A neighbour on the outer lattice
+ *                       layer, or with a vanishing gradient, keeps the centre
+ *                       normal.  Reads a 5x5x5 neighbourhood per cell.
+ * Other arguments, workspace and results as plic_curvature_f32.
+ */
+int plic_curvature_ex_f32(const float *phi, int64_t X, int64_t Y, int64_t Z, float *kappa,
+                          int solver, int precision, int normal, int neighbour_normals,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * plic_curvature_backward_ex_f32 — plic_curvature_backward_f32 with the normal
+ * of plic_curvature_ex_f32 (the weights enter the normal's adjoint).  The
+ * neighbour-normal variant has no backward.
+ */
+int plic_curvature_backward_ex_f32(const float *phi, int64_t X, int64_t Y, int64_t Z,
+                                   const float *grad_kappa, float *grad_phi, int solver,
+                                   int precision, int normal, void *workspace,
+                                   size_t workspace_bytes, void *stream);
 
 /* human-readable status; never NULL */
 const char *plic_status_string(int status);

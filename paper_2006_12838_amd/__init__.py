@@ -18,9 +18,13 @@ import torch
 
 from ._lib import (  # noqa: F401  (re-exported: the C ABI by name)
     EXPORTED,
+    NORMALS,
     PRECISIONS,
     SOLVERS,
+    plic_bench_isolated_f32,
+    plic_curvature_backward_ex_f32,
     plic_curvature_backward_f32,
+    plic_curvature_ex_f32,
     plic_curvature_f32,
     plic_curvature_workspace_bytes,
     plic_last_hip_error,
@@ -34,7 +38,7 @@ from ._lib import (  # noqa: F401  (re-exported: the C ABI by name)
     plic_volume_f64,
 )
 
-__all__ = ["offset", "volume", "curvature", "PlicOffset", "PlicCurvature", "SOLVERS", "PRECISIONS",
+__all__ = ["offset", "volume", "curvature", "PlicOffset", "PlicCurvature", "SOLVERS", "PRECISIONS", "NORMALS",
            "plic_version"]
 
 
@@ -104,23 +108,29 @@ class PlicCurvature(torch.autograd.Function):
     """kappa(phi) on a (Z, Y, X) lattice with the recomputing backward."""
 
     @staticmethod
-    def forward(ctx, phi, solver="analytic", precision="mixed"):
+    def forward(ctx, phi, solver="analytic", precision="mixed", normal="py", neighbour_normals=False):
         phi = phi.contiguous()
         kappa = torch.empty_like(phi)
-        plic_curvature_f32(phi, kappa, solver, precision)
+        plic_curvature_ex_f32(phi, kappa, solver, precision, normal, neighbour_normals)
         ctx.save_for_backward(phi)
-        ctx.solver, ctx.precision = solver, precision
+        ctx.opts = (solver, precision, normal, neighbour_normals)
         return kappa
 
     @staticmethod
     def backward(ctx, grad_kappa):
         (phi,) = ctx.saved_tensors
+        solver, precision, normal, neighbour_normals = ctx.opts
+        if neighbour_normals:
+            raise NotImplementedError("the neighbour-normal curvature variant has no backward")
         grad_phi = torch.empty_like(phi)
-        plic_curvature_backward_f32(phi, grad_kappa.contiguous(), grad_phi, ctx.solver, ctx.precision)
-        return grad_phi, None, None
+        plic_curvature_backward_ex_f32(phi, grad_kappa.contiguous(), grad_phi, solver, precision, normal)
+        return grad_phi, None, None, None, None
 
 
-def curvature(phi, solver: str = "analytic", precision: str = "mixed"):
+def curvature(phi, solver: str = "analytic", precision: str = "mixed", normal: str = "py",
+              neighbour_normals: bool = False):
     """Mean curvature kappa of the VoF lattice ``phi`` (float32, shape (Z, Y, X)):
-    0 off the interface, +1/R for a fluid sphere of radius R."""
-    return PlicCurvature.apply(phi, solver, precision)
+    0 off the interface, +1/R for a fluid sphere of radius R.  normal: "py"
+    (Parker-Youngs) or "cm" (centre of mass); neighbour_normals: each interface
+    neighbour's PLIC plane from its own normal (forward only)."""
+    return PlicCurvature.apply(phi, solver, precision, normal, neighbour_normals)

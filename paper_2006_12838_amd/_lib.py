@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_PKG, "libplic.so")
 PLIC_OK, PLIC_EINVAL, PLIC_EHIP = 0, -1, -2
 SOLVERS = {"analytic": 0, "sz": 1, "newton": 2, "nested": 3}
 PRECISIONS = {"fp32": 0, "mixed": 1, "fp64": 2}
+NORMALS = {"py": 0, "cm": 1}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -45,6 +46,11 @@ _c = {
                                         [_vp, _i64, _i64, _i64, _vp, _vp, _int, _int, _vp,
                                          ctypes.c_size_t, _vp]),
     "plic_bench_isolated_f32": _sig("plic_bench_isolated_f32", [_vp, _vp, _vp, _i64, _int, _int, _int, _vp, _vp]),
+    "plic_curvature_ex_f32": _sig("plic_curvature_ex_f32",
+                                  [_vp, _i64, _i64, _i64, _vp, _int, _int, _int, _int, _vp, ctypes.c_size_t, _vp]),
+    "plic_curvature_backward_ex_f32": _sig("plic_curvature_backward_ex_f32",
+                                           [_vp, _i64, _i64, _i64, _vp, _vp, _int, _int, _int, _vp,
+                                            ctypes.c_size_t, _vp]),
 }
 _lib.plic_curvature_workspace_bytes.restype = ctypes.c_size_t
 _lib.plic_curvature_workspace_bytes.argtypes = [_i64, _i64, _i64]
@@ -198,10 +204,27 @@ def _workspace(phi, workspace, X, Y, Z):
     return workspace
 
 
-def plic_curvature_f32(phi, kappa, solver="analytic", precision="mixed", workspace=None):
+def plic_curvature_ex_f32(phi, kappa, solver="analytic", precision="mixed", normal="py",
+                          neighbour_normals=False, workspace=None):
     """workspace: optional uint8 device tensor, at least the fixed part and
     best plic_curvature_workspace_bytes bytes (allocated through torch's
-    caching allocator when omitted)."""
+    caching allocator when omitted).  normal: "py" or "cm"; neighbour_normals:
+    each interface neighbour's plane from its own normal."""
+    X, Y, Z = _lattice_dims(phi)
+    n = X * Y * Z
+    _same_device(phi, kappa)
+    ws = _workspace(phi, workspace, X, Y, Z)
+    _check(_c["plic_curvature_ex_f32"](_ptr(phi, torch.float32, n, "phi"), X, Y, Z,
+                                       _ptr(kappa, torch.float32, n, "kappa"),
+                                       _enum(SOLVERS, solver, "solver"),
+                                       _enum(PRECISIONS, precision, "precision"),
+                                       _enum(NORMALS, normal, "normal"), int(bool(neighbour_normals)),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
+           "plic_curvature_ex_f32")
+    return kappa
+
+
+def plic_curvature_f32(phi, kappa, solver="analytic", precision="mixed", workspace=None):
     X, Y, Z = _lattice_dims(phi)
     n = X * Y * Z
     _same_device(phi, kappa)
@@ -213,6 +236,23 @@ def plic_curvature_f32(phi, kappa, solver="analytic", precision="mixed", workspa
                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
            "plic_curvature_f32")
     return kappa
+
+
+def plic_curvature_backward_ex_f32(phi, grad_kappa, grad_phi, solver="analytic", precision="mixed", normal="py",
+                                   workspace=None):
+    X, Y, Z = _lattice_dims(phi)
+    n = X * Y * Z
+    _same_device(phi, grad_kappa, grad_phi)
+    ws = _workspace(phi, workspace, X, Y, Z)
+    _check(_c["plic_curvature_backward_ex_f32"](_ptr(phi, torch.float32, n, "phi"), X, Y, Z,
+                                                _ptr(grad_kappa, torch.float32, n, "grad_kappa"),
+                                                _ptr(grad_phi, torch.float32, n, "grad_phi"),
+                                                _enum(SOLVERS, solver, "solver"),
+                                                _enum(PRECISIONS, precision, "precision"),
+                                                _enum(NORMALS, normal, "normal"),
+                                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
+           "plic_curvature_backward_ex_f32")
+    return grad_phi
 
 
 def plic_curvature_backward_f32(phi, grad_kappa, grad_phi, solver="analytic", precision="mixed",

@@ -39,6 +39,8 @@ constexpr int kPersistentBlocks = 2048;
 constexpr double kR0 = 0.56270900, kR1 = 0.32704452, kR2 = 0.75921047;
 
 // neighbour q = (dz+1)*9 + (dy+1)*3 + (dx+1); centre q = 13
+enum Normal : int { kNormalPY = PLIC_NORMAL_PY, kNormalCM = PLIC_NORMAL_CM };
+
 __host__ __device__ constexpr int q_dx(int q) { return q % 3 - 1; }
 __host__ __device__ constexpr int q_dy(int q) { return (q / 3) % 3 - 1; }
 __host__ __device__ constexpr int q_dz(int q) { return q / 9 - 1; }
@@ -149,22 +151,39 @@ __host__ __device__ constexpr int tri(int i, int k) { return i * (i + 1) / 2 + k
 // from the lane that owns q, with the interface mask, the PLIC cases and the
 // active fit parameters held fixed.
 // ---------------------------------------------------------------------------
-template <int SOLVER, class T, class U, class F, bool ADJ>
-__device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, int sy, int sz, int j,
-                                            float gk, float* __restrict__ out, GroupLds<F>& L) {
-    using mt = M<T>;
-    // Parker-Youngs gradient (App. B.1), weights 4 / 2 / 1 for |e|^2 = 1 / 2 / 3;
-    // every lane forms the same sum from the staged fill levels
-    T gx = T(0), gy = T(0), gz = T(0);
+// weight of neighbour offset e in the fill-level gradient (App. B.1):
+// Parker-Youngs 4 / 2 / 1 for |e|^2 = 1 / 2 / 3, centre of mass 1
+template <int NRM>
+__host__ __device__ constexpr int nrm_weight(int e2) {
+    return NRM == kNormalCM ? 1 : (e2 == 1 ? 4 : (e2 == 2 ? 2 : 1));
+}
+
+// fill-level gradient of the 3^3 neighbourhood centred at LDS index c
+template <int NRM, class T>
+__device__ __forceinline__ void gradient27(const float* __restrict__ s, int c, int sy, int sz, T& gx, T& gy, T& gz) {
+    gx = T(0); gy = T(0); gz = T(0);
 #pragma unroll
     for (int q = 0; q < 27; ++q) {
         if (q == 13) continue;
         const int e2 = q_dx(q) * q_dx(q) + q_dy(q) * q_dy(q) + q_dz(q) * q_dz(q);
-        const T w = T(e2 == 1 ? 4 : (e2 == 2 ? 2 : 1)) * T(s[c + q_dz(q) * sz + q_dy(q) * sy + q_dx(q)]);
+        const T w = T(nrm_weight<NRM>(e2)) * T(s[c + q_dz(q) * sz + q_dy(q) * sy + q_dx(q)]);
         gx += T(q_dx(q)) * w;
         gy += T(q_dy(q)) * w;
         gz += T(q_dz(q)) * w;
     }
+}
+
+template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
+__device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, int sy, int sz, int j,
+                                            float gk, float* __restrict__ out, GroupLds<F>& L,
+                                            int gx0 = 0, int gy0 = 0, int gz0 = 0, int X = 0, int Y = 0,
+                                            int Z = 0) {
+    static_assert(!(ADJ && NBR), "the neighbour-normal variant has no backward");
+    using mt = M<T>;
+    // fill-level gradient of the centre (App. B.1); every lane forms the same
+    // sum from the staged fill levels
+    T gx, gy, gz;
+    gradient27<NRM, T>(s, c, sy, sz, gx, gy, gz);
     const bool nbr = j < 26;                      // lane owns neighbour q
     const bool centre = j == 26;                  // lane owns the centre
     const int q = nbr ? (j < 13 ? j : j + 1) : 13;
@@ -172,7 +191,7 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
     const float p = (nbr || centre) ? s[c + dz * sz + dy * sy + dx] : 0.0f;
     const T ex = T(dx), ey = T(dy), ez = T(dz);
     const int e2 = dx * dx + dy * dy + dz * dz;
-    const T w = nbr ? T(e2 == 1 ? 4 : (e2 == 2 ? 2 : 1)) : T(0);
+    const T w = nbr ? T(nrm_weight<NRM>(e2)) : T(0);
     const bool iface = nbr && is_iface(p);
     const unsigned long long bal = __ballot(iface);
     const int npts = __popcll(bal & (0xffffffffull << (threadIdx.x & 32)));
@@ -198,10 +217,27 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
     const T iun = mt::rcp(mt::sqrt(un2));
     const T by0 = u0 * iun, by1 = u1 * iun, by2 = u2 * iun;
     const T bx0 = by1 * n2 - by2 * n1, bx1 = by2 * n0 - by0 * n2, bx2 = by0 * n1 - by1 * n0;
-    // PLIC offsets: neighbour lanes and the centre lane in parallel, all with
-    // the centre normal (Sec. 5.2)
+    // PLIC offsets: neighbour lanes and the centre lane in parallel, with the
+    // centre normal (Sec. 5.2) or, in the neighbour-normal variant, each
+    // neighbour with its own normal (centre normal on the outer lattice layer
+    // or for a vanishing gradient)
+    T m0 = n0, m1 = n1, m2 = n2;
+    if constexpr (NBR) {
+        // the neighbour's own 3^3 neighbourhood lies in the lattice
+        const int ax = gx0 + dx, ay = gy0 + dy, az = gz0 + dz;
+        const bool inside = ax >= 1 && ay >= 1 && az >= 1 && ax <= X - 2 && ay <= Y - 2 && az <= Z - 2;
+        if (iface && inside) {
+            T hx, hy, hz;
+            gradient27<NRM, T>(s, c + dz * sz + dy * sy + dx, sy, sz, hx, hy, hz);
+            const T h2 = hx * hx + hy * hy + hz * hz;
+            if (h2 >= T(1e-24)) {
+                const T ih = mt::rcp(mt::sqrt(h2));
+                m0 = -hx * ih; m1 = -hy * ih; m2 = -hz * ih;
+            }
+        }
+    }
     T D = T(0);
-    if (iface || centre) D = offset<SOLVER, T, U>(n0, n1, n2, T(p));
+    if (iface || centre) D = offset<SOLVER, T, U>(m0, m1, m2, T(p));
     if (centre) L.res[24] = F(D);
     __syncwarp();
     const T D0 = T(L.res[24]);
@@ -209,9 +245,17 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
     // the normal equations: Q Q^T (lower triangle) and z Q
     F x = F(0), y = F(0), z = F(0);
     if (iface) {
-        x = F(ex * bx0 + ey * bx1 + ez * bx2);
-        y = F(ex * by0 + ey * by1 + ez * by2);
-        z = F(ex * n0 + ey * n1 + ez * n2 + (D - D0));
+        if constexpr (NBR) {
+            // foot of the neighbour's own plane, e + D n_q - D0 n, in the frame
+            const T P0 = ex + D * m0 - D0 * n0, P1 = ey + D * m1 - D0 * n1, P2 = ez + D * m2 - D0 * n2;
+            x = F(P0 * bx0 + P1 * bx1 + P2 * bx2);
+            y = F(P0 * by0 + P1 * by1 + P2 * by2);
+            z = F(P0 * n0 + P1 * n1 + P2 * n2);
+        } else {
+            x = F(ex * bx0 + ey * bx1 + ez * bx2);
+            y = F(ex * by0 + ey * by1 + ez * by2);
+            z = F(ex * n0 + ey * n1 + ez * n2 + (D - D0));
+        }
     }
     const F Q[5] = {x * x, y * y, x * y, x, y};
     F row[20], sum[20];
@@ -517,12 +561,14 @@ __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx,
 // ---------------------------------------------------------------------------
 constexpr int F_RX = TX + 2, F_RY = TY + 2, F_RZ = TZ + 2, F_REGION = F_RX * F_RY * F_RZ;
 
-template <int SOLVER, class T, class U, class F, bool ADJ>
+// NBR: the neighbour-normal variant needs each neighbour's 3^3, a halo of 2
+template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
 __global__ __launch_bounds__(kThreads) void k_curv_items(const float* __restrict__ phi,
                                                           const float* __restrict__ gkap,
                                                           float* __restrict__ kappa, Workspace ws, int X, int Y,
                                                           int Z, int ntx, int nty) {
-    __shared__ float s[F_REGION];
+    constexpr int H = NBR ? 2 : 1, RX = TX + 2 * H, RY = TY + 2 * H, RZ = TZ + 2 * H;
+    __shared__ float s[RX * RY * RZ];
     __shared__ unsigned short list[kTile];
     __shared__ int wcount[kThreads / 64];
     __shared__ GroupLds<F> glds[kGroups];
@@ -537,28 +583,29 @@ __global__ __launch_bounds__(kThreads) void k_curv_items(const float* __restrict
             if (row0 >= ws.rows) continue;                       // uniform; the gather recomputes
         }
         const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
-        load_region<F_RX, F_RY, F_RZ>(s, phi, x0 - 1, y0 - 1, z0 - 1, X, Y, Z);
+        load_region<RX, RY, RZ>(s, phi, x0 - H, y0 - H, z0 - H, X, Y, Z);
         __syncthreads();
         const int n = ordered_compact(kTile, [&](int cl) {
             const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
             const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
             return gx >= 1 && gy >= 1 && gz >= 1 && gx <= X - 2 && gy <= Y - 2 && gz <= Z - 2 &&
-                   is_iface(s[((cz + 1) * F_RY + (cy + 1)) * F_RX + (cx + 1)]);
+                   is_iface(s[((cz + H) * RY + (cy + H)) * RX + (cx + H)]);
         }, list, wcount);
         const int i = part * kPartCells + grp;
         if (i < n) {
             const int cl = list[i];
             const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-            const int64_t g = (static_cast<int64_t>(z0 + cz) * Y + (y0 + cy)) * X + (x0 + cx);
-            const int c = ((cz + 1) * F_RY + (cy + 1)) * F_RX + (cx + 1);
+            const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
+            const int64_t g = (static_cast<int64_t>(gz) * Y + gy) * X + gx;
+            const int c = ((cz + H) * RY + (cy + H)) * RX + (cx + H);
             if constexpr (ADJ) {
                 const unsigned r = row0 + static_cast<unsigned>(grp);
                 if (r < ws.rows)                                 // uniform per group
-                    group_cell<SOLVER, T, U, F, true>(s, c, F_RX, F_RX * F_RY, j, gkap[g],
-                                                      ws.contrib + static_cast<size_t>(r) * 27, glds[grp]);
+                    group_cell<SOLVER, T, U, F, true, NRM, false>(s, c, RX, RX * RY, j, gkap[g],
+                                                                  ws.contrib + static_cast<size_t>(r) * 27, glds[grp]);
             } else {
-                const float kv = group_cell<SOLVER, T, U, F, false>(s, c, F_RX, F_RX * F_RY, j, 0.0f, nullptr,
-                                                                     glds[grp]);
+                const float kv = group_cell<SOLVER, T, U, F, false, NRM, NBR>(s, c, RX, RX * RY, j, 0.0f, nullptr,
+                                                                             glds[grp], gx, gy, gz, X, Y, Z);
                 if (j == 0) kappa[g] = kv;
             }
         }
@@ -593,7 +640,7 @@ __device__ __forceinline__ unsigned contrib_row(const Workspace& ws, int gx, int
 // did not fit is passed on to the overflow list untouched.  FALLBACK = true:
 // the overflow list, candidates without a row recomputed here.  Splitting keeps
 // the register-heavy recomputation out of the common kernel.
-template <int SOLVER, class T, class U, class F, bool FALLBACK>
+template <int SOLVER, class T, class U, class F, int NRM, bool FALLBACK>
 __global__ __launch_bounds__(kThreads) void k_curv_gather(const float* __restrict__ phi,
                                                            const float* __restrict__ gkap,
                                                            float* __restrict__ gphi, Workspace ws, int X, int Y,
@@ -673,8 +720,8 @@ __global__ __launch_bounds__(kThreads) void k_curv_gather(const float* __restric
                     const int lx = ci % C_RX, ly = (ci / C_RX) % C_RY, lz = ci / (C_RX * C_RY);
                     const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
                     const float gk = gkap[(static_cast<int64_t>(gz) * Y + gy) * X + gx];
-                    group_cell<SOLVER, T, U, F, true>(s, ((lz + 1) * RY + (ly + 1)) * RX + (lx + 1), RX,
-                                                      RX * RY, j, gk, contrib[i], glds[grp]);
+                    group_cell<SOLVER, T, U, F, true, NRM, false>(s, ((lz + 1) * RY + (ly + 1)) * RX + (lx + 1),
+                                                                  RX, RX * RY, j, gk, contrib[i], glds[grp]);
                 }
             }
             __syncthreads();
@@ -769,42 +816,63 @@ unsigned persistent_grid(int64_t items_max) {
     return static_cast<unsigned>(items_max < kPersistentBlocks ? items_max : kPersistentBlocks);
 }
 
-template <int SOLVER, class T, class U, class F>
-void launch_items(bool adj, const float* phi, const float* gk, float* kappa, Workspace ws, int X, int Y,
-                  int Z, const Grid& g, hipStream_t st) {
+template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
+void launch_items(const float* phi, const float* gk, float* kappa, Workspace ws, int X, int Y, int Z,
+                  const Grid& g, hipStream_t st) {
     const dim3 grid(persistent_grid(static_cast<int64_t>(g.ntiles) * kMaxParts)), block(kThreads);
-    if (adj)
-        hipLaunchKernelGGL((k_curv_items<SOLVER, T, U, F, true>), grid, block, 0, st, phi, gk, kappa, ws, X, Y, Z, g.ntx, g.nty);
-    else
-        hipLaunchKernelGGL((k_curv_items<SOLVER, T, U, F, false>), grid, block, 0, st, phi, gk, kappa, ws, X, Y, Z, g.ntx, g.nty);
+    hipLaunchKernelGGL((k_curv_items<SOLVER, T, U, F, ADJ, NRM, NBR>), grid, block, 0, st, phi, gk, kappa, ws, X, Y, Z,
+                       g.ntx, g.nty);
+}
+
+// forward: precision picks the types, then the normal and the variant
+template <int SOLVER, class T, class U, class F>
+void launch_fwd_t(int normal, bool nbr, const float* phi, float* kappa, Workspace ws, int X, int Y, int Z,
+                  const Grid& g, hipStream_t st) {
+    if (normal == kNormalCM) {
+        if (nbr) launch_items<SOLVER, T, U, F, false, kNormalCM, true>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
+        else launch_items<SOLVER, T, U, F, false, kNormalCM, false>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
+    } else {
+        if (nbr) launch_items<SOLVER, T, U, F, false, kNormalPY, true>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
+        else launch_items<SOLVER, T, U, F, false, kNormalPY, false>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
+    }
 }
 
 template <int SOLVER>
-void launch_fwd(int precision, const float* phi, float* kappa, Workspace ws, int X, int Y, int Z,
-                const Grid& g, hipStream_t st) {
-    if (precision == PLIC_FP32) launch_items<SOLVER, float, float, float>(false, phi, nullptr, kappa, ws, X, Y, Z, g, st);
-    else if (precision == PLIC_MIXED) launch_items<SOLVER, float, double, double>(false, phi, nullptr, kappa, ws, X, Y, Z, g, st);
-    else launch_items<SOLVER, double, double, double>(false, phi, nullptr, kappa, ws, X, Y, Z, g, st);
+void launch_fwd(int precision, int normal, bool nbr, const float* phi, float* kappa, Workspace ws, int X, int Y,
+                int Z, const Grid& g, hipStream_t st) {
+    if (precision == PLIC_FP32) launch_fwd_t<SOLVER, float, float, float>(normal, nbr, phi, kappa, ws, X, Y, Z, g, st);
+    else if (precision == PLIC_MIXED) launch_fwd_t<SOLVER, float, double, double>(normal, nbr, phi, kappa, ws, X, Y, Z, g, st);
+    else launch_fwd_t<SOLVER, double, double, double>(normal, nbr, phi, kappa, ws, X, Y, Z, g, st);
 }
 
-template <int SOLVER, class T, class U, class F>
+// backward: adjoint work items (rows that fit), gather list, lean gather of
+// the stored rows (independent of solver and precision), then the fallback
+// gather that recomputes the rows that did not fit
+template <int SOLVER, class T, class U, class F, int NRM>
 void launch_bwd_t(const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y, int Z,
                   const Grid& g, hipStream_t st) {
-    if (ws.rows > 0) launch_items<SOLVER, T, U, F>(true, phi, gk, nullptr, ws, X, Y, Z, g, st);
+    if (ws.rows > 0) launch_items<SOLVER, T, U, F, true, NRM, false>(phi, gk, nullptr, ws, X, Y, Z, g, st);
     hipLaunchKernelGGL(k_curv_dilate, dim3((g.ntiles + kThreads - 1) / kThreads), dim3(kThreads), 0, st, ws,
                        g.ntx, g.nty, g.ntz, g.ntiles);
-    hipLaunchKernelGGL((k_curv_gather<SOLVER, T, U, F, false>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0,
-                       st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
-    hipLaunchKernelGGL((k_curv_gather<SOLVER, T, U, F, true>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0,
+    hipLaunchKernelGGL((k_curv_gather<kAnalytic, float, float, float, kNormalPY, false>), dim3(persistent_grid(g.ntiles)),
+                       dim3(kThreads), 0, st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
+    hipLaunchKernelGGL((k_curv_gather<SOLVER, T, U, F, NRM, true>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0,
                        st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
 }
 
+template <int SOLVER, class T, class U, class F>
+void launch_bwd_n(int normal, const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y, int Z,
+                  const Grid& g, hipStream_t st) {
+    if (normal == kNormalCM) launch_bwd_t<SOLVER, T, U, F, kNormalCM>(phi, gk, gp, ws, X, Y, Z, g, st);
+    else launch_bwd_t<SOLVER, T, U, F, kNormalPY>(phi, gk, gp, ws, X, Y, Z, g, st);
+}
+
 template <int SOLVER>
-void launch_bwd(int precision, const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y,
+void launch_bwd(int precision, int normal, const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y,
                 int Z, const Grid& g, hipStream_t st) {
-    if (precision == PLIC_FP32) launch_bwd_t<SOLVER, float, float, float>(phi, gk, gp, ws, X, Y, Z, g, st);
-    else if (precision == PLIC_MIXED) launch_bwd_t<SOLVER, float, double, double>(phi, gk, gp, ws, X, Y, Z, g, st);
-    else launch_bwd_t<SOLVER, double, double, double>(phi, gk, gp, ws, X, Y, Z, g, st);
+    if (precision == PLIC_FP32) launch_bwd_n<SOLVER, float, float, float>(normal, phi, gk, gp, ws, X, Y, Z, g, st);
+    else if (precision == PLIC_MIXED) launch_bwd_n<SOLVER, float, double, double>(normal, phi, gk, gp, ws, X, Y, Z, g, st);
+    else launch_bwd_n<SOLVER, double, double, double>(normal, phi, gk, gp, ws, X, Y, Z, g, st);
 }
 
 // shared argument checks of the two entry points
@@ -835,13 +903,15 @@ size_t plic_curvature_workspace_bytes(int64_t X, int64_t Y, int64_t Z) {
     return fixed_bytes(g) + static_cast<size_t>(g.ntiles) * kDefaultRowsPerTile * kRowBytes;
 }
 
-int plic_curvature_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float* kappa, int solver,
-                       int precision, void* workspace, size_t workspace_bytes, void* stream) {
+int plic_curvature_ex_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float* kappa, int solver,
+                          int precision, int normal, int neighbour_normals, void* workspace, size_t workspace_bytes,
+                          void* stream) {
     bool empty;
     Grid g{};
     int64_t n = 0;
     if (check_common(phi, X, Y, Z, solver, precision, workspace, workspace_bytes, &empty, &g, &n) != PLIC_OK)
         return PLIC_EINVAL;
+    if (!valid_normal(normal) || (neighbour_normals != 0 && neighbour_normals != 1)) return PLIC_EINVAL;
     if (!valid_array(kappa, n)) return PLIC_EINVAL;
     const size_t nb = static_cast<size_t>(n) * sizeof(float);
     if (overlap(phi, nb, kappa, nb)) return PLIC_EINVAL;
@@ -850,24 +920,32 @@ int plic_curvature_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float*
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Workspace ws = carve(workspace, workspace_bytes, g);
     const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
+    const bool nbr = neighbour_normals != 0;
     launch_scan<true>(phi, kappa, ws, x, y, z, g, st);
     switch (solver) {
-        case kSZ: launch_fwd<kSZ>(precision, phi, kappa, ws, x, y, z, g, st); break;
-        case kNewton: launch_fwd<kNewton>(precision, phi, kappa, ws, x, y, z, g, st); break;
-        case kNested: launch_fwd<kNested>(precision, phi, kappa, ws, x, y, z, g, st); break;
-        default: launch_fwd<kAnalytic>(precision, phi, kappa, ws, x, y, z, g, st); break;
+        case kSZ: launch_fwd<kSZ>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
+        case kNewton: launch_fwd<kNewton>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
+        case kNested: launch_fwd<kNested>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
+        default: launch_fwd<kAnalytic>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
     }
     return launch_status();
 }
 
-int plic_curvature_backward_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, const float* grad_kappa,
-                                float* grad_phi, int solver, int precision, void* workspace,
-                                size_t workspace_bytes, void* stream) {
+int plic_curvature_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float* kappa, int solver,
+                       int precision, void* workspace, size_t workspace_bytes, void* stream) {
+    return plic_curvature_ex_f32(phi, X, Y, Z, kappa, solver, precision, PLIC_NORMAL_PY, 0, workspace,
+                                 workspace_bytes, stream);
+}
+
+int plic_curvature_backward_ex_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, const float* grad_kappa,
+                                   float* grad_phi, int solver, int precision, int normal, void* workspace,
+                                   size_t workspace_bytes, void* stream) {
     bool empty;
     Grid g{};
     int64_t n = 0;
     if (check_common(phi, X, Y, Z, solver, precision, workspace, workspace_bytes, &empty, &g, &n) != PLIC_OK)
         return PLIC_EINVAL;
+    if (!valid_normal(normal)) return PLIC_EINVAL;
     if (!valid_array(grad_kappa, n) || !valid_array(grad_phi, n)) return PLIC_EINVAL;
     const size_t nb = static_cast<size_t>(n) * sizeof(float);
     if (overlap(grad_phi, nb, phi, nb) || overlap(grad_phi, nb, grad_kappa, nb)) return PLIC_EINVAL;
@@ -880,12 +958,19 @@ int plic_curvature_backward_f32(const float* phi, int64_t X, int64_t Y, int64_t 
     const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
     launch_scan<false>(phi, grad_phi, ws, x, y, z, g, st);
     switch (solver) {
-        case kSZ: launch_bwd<kSZ>(precision, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
-        case kNewton: launch_bwd<kNewton>(precision, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
-        case kNested: launch_bwd<kNested>(precision, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
-        default: launch_bwd<kAnalytic>(precision, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
+        case kSZ: launch_bwd<kSZ>(precision, normal, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
+        case kNewton: launch_bwd<kNewton>(precision, normal, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
+        case kNested: launch_bwd<kNested>(precision, normal, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
+        default: launch_bwd<kAnalytic>(precision, normal, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
     }
     return launch_status();
+}
+
+int plic_curvature_backward_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, const float* grad_kappa,
+                                float* grad_phi, int solver, int precision, void* workspace,
+                                size_t workspace_bytes, void* stream) {
+    return plic_curvature_backward_ex_f32(phi, X, Y, Z, grad_kappa, grad_phi, solver, precision, PLIC_NORMAL_PY,
+                                          workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"

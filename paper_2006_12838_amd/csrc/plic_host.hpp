@@ -28,6 +28,7 @@ inline bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 
 inline bool valid_solver(int s) { return s >= PLIC_ANALYTIC && s <= PLIC_NESTED; }
 inline bool valid_precision(int p) { return p >= PLIC_FP32 && p <= PLIC_FP64; }
+inline bool valid_normal(int n) { return n == PLIC_NORMAL_PY || n == PLIC_NORMAL_CM; }
 
 // check the launch that was just enqueued
 inline int launch_status() {

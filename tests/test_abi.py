@@ -131,6 +131,21 @@ def test_curvature_validation(lib):
     assert g(A, 3, 3, 3, B, C, 0, 1, C, ws, None) == -1               # workspace overlaps grad_phi
 
 
+def test_curvature_options_validation(lib):
+    W = 0xA0000
+    ws = lib.plic_curvature_workspace_bytes(4, 4, 4)
+    f = lib.raw("plic_curvature_ex_f32")
+    assert f(A, 0, 5, 5, B, 0, 1, 0, 0, None, 0, None) == 0             # empty lattice
+    assert f(A, 4, 4, 4, B, 0, 1, 2, 0, W, ws, None) == -1              # bad normal
+    assert f(A, 4, 4, 4, B, 0, 1, -1, 0, W, ws, None) == -1
+    assert f(A, 4, 4, 4, B, 0, 1, 1, 2, W, ws, None) == -1              # bad neighbour flag
+    assert f(A, 4, 4, 4, A + 64, 0, 1, 1, 1, W, ws, None) == -1         # kappa overlaps phi
+    g = lib.raw("plic_curvature_backward_ex_f32")
+    assert g(A, 3, 3, 0, B, C, 0, 1, 1, None, 0, None) == 0
+    assert g(A, 3, 3, 3, B, C, 0, 1, 5, W, ws, None) == -1              # bad normal
+    assert g(A, 3, 3, 3, B, A, 0, 1, 1, W, ws, None) == -1              # grad_phi overlaps phi
+
+
 def test_bench_validation(lib):
     f = lib.raw("plic_bench_isolated_f32")
     assert f(A, B, C, 0, 256, 0, 0, D, None) == 0                     # empty

@@ -35,11 +35,11 @@ def gpu_kappa(P, phi, solver="analytic", precision="mixed"):
     return host(k)
 
 
-def cell_reference(orc, phi):
+def cell_reference(orc, phi, normal="py", neighbour_normals=False):
     """Oracle kappa on the interface cells and their conditioning info."""
-    kref, flags = orc.curvature(phi, flags=True)
+    kref, flags = orc.curvature(phi, flags=True, normal=normal, neighbour_normals=neighbour_normals)
     cells = np.flatnonzero(flags & 1)
-    _, info = orc.curvature_cells(phi, cells)
+    _, info = orc.curvature_cells(phi, cells, normal=normal, neighbour_normals=neighbour_normals)
     return cells, kref.ravel()[cells], info
 
 

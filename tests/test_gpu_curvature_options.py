@@ -1,0 +1,116 @@
+"""GPU parity of the curvature options against the FP64 oracle: the
+centre-of-mass normal (forward and backward) and the neighbour-normal
+variant (forward), with the per-cell bar of the curvature tests."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from tests.gpu_util import PRECISIONS, SOLVERS, dev, host
+from tests.test_gpu_curvature import cell_reference, check_against
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2006_12838_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def sphere():
+    return workloads.sphere_lattice(N=48, R=14.0, seed=0)[0]
+
+
+def gpu_kappa(P, phi, solver, precision, normal, nbr):
+    t = dev(phi)
+    k = torch.empty_like(t)
+    P.plic_curvature_ex_f32(t, k, solver, precision, normal, nbr)
+    return host(k)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_cm_normal_parity(P, orc, sphere, solver, precision):
+    ref = cell_reference(orc, sphere, normal="cm")
+    check_against(ref, sphere, gpu_kappa(P, sphere, solver, precision, "cm", False), precision,
+                  f"cm {solver}/{precision}")
+
+
+@pytest.mark.parametrize("normal", ["py", "cm"])
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("solver", ["analytic", "sz", "newton"])
+def test_neighbour_normals_parity(P, orc, sphere, solver, precision, normal):
+    ref = cell_reference(orc, sphere, normal=normal, neighbour_normals=True)
+    check_against(ref, sphere, gpu_kappa(P, sphere, solver, precision, normal, True), precision,
+                  f"nbr {normal} {solver}/{precision}")
+
+
+@pytest.mark.parametrize("shape", [(37, 35, 67), (9, 70, 13)])
+def test_neighbour_normals_ragged(P, orc, shape):
+    """Lattices that are not a multiple of the 64x4x4 tile, the interface
+    crossing tile boundaries and reaching the outer layers."""
+    Z, Y, X = shape
+    N = max(shape)
+    full, _, _ = workloads.perturbed_sphere_lattice(N=N, R=0.42 * min(shape), seed=4, ss=4)
+    z0, y0, x0 = (N - Z) // 2, (N - Y) // 2, (N - X) // 2
+    phi = np.ascontiguousarray(full[z0:z0 + Z, y0:y0 + Y, x0:x0 + X])
+    assert ((phi > 0) & (phi < 1)).sum() > 50
+    for normal in ("py", "cm"):
+        ref = cell_reference(orc, phi, normal=normal, neighbour_normals=True)
+        check_against(ref, phi, gpu_kappa(P, phi, "analytic", "mixed", normal, True), "mixed",
+                      f"ragged {shape} {normal}")
+
+
+@pytest.mark.parametrize("normal", ["py", "cm"])
+def test_neighbour_normals_planes(P, orc, normal):
+    N = 12
+    for nrm, off in (((0.0, 0.0, 1.0), 0.3), ((1 / np.sqrt(2), 1 / np.sqrt(2), 0.0), 0.17)):
+        n = np.array(nrm)
+        r = np.arange(N) - N / 2
+        z, y, x = np.meshgrid(r, r, r, indexing="ij")
+        d0 = off - (n[0] * x + n[1] * y + n[2] * z)
+        phi = orc.volume(np.full(d0.size, n[0]), np.full(d0.size, n[1]), np.full(d0.size, n[2]),
+                         d0.ravel()).reshape(d0.shape).astype(np.float32)
+        for precision in PRECISIONS:
+            k = gpu_kappa(P, phi, "analytic", precision, normal, True)
+            assert np.abs(k).max() <= 2e-6, (nrm, precision)
+
+
+@pytest.fixture(scope="module")
+def cm_case(orc):
+    phi, _, _ = workloads.perturbed_sphere_lattice(N=36, R=11.0, seed=2, ss=4)
+    kref, flags = orc.curvature(phi, flags=True, normal="cm")
+    cells = np.flatnonzero(flags & 1)
+    _, info = orc.curvature_cells(phi, cells, normal="cm")
+    ok = (info[:, 0] >= 5) & (info[:, 2] <= 1e4)
+    _, bad = orc.curvature_grad(phi, np.ones_like(phi), h=1e-6, normal="cm")
+    sel = cells[ok & ~bad.ravel()[cells]]
+    gk = np.zeros(phi.size, np.float32)
+    gk[sel] = np.random.default_rng(3).standard_normal(sel.size).astype(np.float32)
+    gk = gk.reshape(phi.shape)
+    gref, _ = orc.curvature_grad(phi, gk, h=1e-6, normal="cm")
+    return phi, gk, gref
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_cm_backward_matches_oracle(P, cm_case, precision):
+    phi, gk, gref = cm_case
+    tp, tg = dev(phi, gk)
+    out = torch.empty_like(tp)
+    P.plic_curvature_backward_ex_f32(tp, tg, out, "analytic", precision, "cm")
+    err = np.abs(host(out).astype(np.float64) - gref).max() / np.abs(gref).max()
+    print(f"cm backward {precision}: {err:.3e}")
+    assert err <= {"fp32": 2e-3, "mixed": 2e-3, "fp64": 1e-6}[precision]
+
+
+def test_autograd_options(P, cm_case):
+    phi, gk, gref = cm_case
+    t = dev(phi).requires_grad_(True)
+    (P.curvature(t, "analytic", "mixed", normal="cm") * dev(gk)).sum().backward()
+    assert np.abs(host(t.grad).astype(np.float64) - gref).max() / np.abs(gref).max() <= 2e-3
+    t2 = dev(phi).requires_grad_(True)
+    k = P.curvature(t2, "analytic", "mixed", neighbour_normals=True)
+    with pytest.raises(NotImplementedError):
+        k.sum().backward()

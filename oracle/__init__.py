@@ -73,6 +73,12 @@ def _load():
     lib.orc_curv_cell_fd_grad.argtypes = [_D, _U8, c_d, _D]
     lib.orc_curvature_grad.restype = c_i64
     lib.orc_curvature_grad.argtypes = [_F, c_i64, c_i64, c_i64, _F, c_d, _D, _U8]
+    lib.orc_sphere_volume1.restype = c_d
+    lib.orc_sphere_volume1.argtypes = [c_d]
+    lib.orc_sphere_offset1.restype = c_d
+    lib.orc_sphere_offset1.argtypes = [c_d]
+    lib.orc_sphere_volume.argtypes = [_D, _D, c_i64]
+    lib.orc_sphere_offset.argtypes = [_D, _D, c_i64]
     lib.orc_curv_cell_k.restype = c_d
     lib.orc_curv_cell_k.argtypes = [_D, _U8, ctypes.c_int, _D, _D]
     lib.orc_curv_cell_nbr.restype = c_d
@@ -192,6 +198,26 @@ def fit_paraboloid(px, py, pz):
 def paraboloid_kappa(coef):
     c = _d(coef)
     return _load().orc_paraboloid_kappa(_p(c))
+
+
+def sphere_volume(d0):
+    """volume of the unit-volume sphere below the plane at distance d0 (Sec. 4)"""
+    d = _d(d0)
+    out = np.empty_like(d)
+    _load().orc_sphere_volume(_p(d), _p(out), d.size)
+    return out
+
+
+def sphere_offset(V0):
+    """inverse of sphere_volume by bisection (the plane-sphere PLIC problem)"""
+    v = _d(V0)
+    out = np.empty_like(v)
+    _load().orc_sphere_offset(_p(v), _p(out), v.size)
+    return out
+
+
+def sphere_radius() -> float:
+    return float(np.cbrt(3.0 / (4.0 * np.pi)))
 
 
 NORMALS = {"py": 0, "cm": 1}

@@ -20,6 +20,8 @@
  *  - gradient of d0: implicit differentiation of V0(n, d0) = volume below the
  *    plane; dV0/dd0 = A/|n| and dV0/dn = -(A/|n|) * centroid, with A and the
  *    centroid of the plane-cube intersection polygon built explicitly;
+ *  - plane-sphere intersection (Sec. 4): the spherical-cap volume of the
+ *    unit-volume sphere and its inverse by bisection;
  *  - curvature: Sec. 5.2 (PLIC point neighbourhood, coordinate transform with
  *    the fixed vector r), App. B.1 (Parker-Youngs normal, or the centre-of-mass
  *    normal as an option), B.2 (paraboloid mean curvature at the origin), B.3
@@ -282,6 +284,56 @@ void orc_offset_grad(const double *nx, const double *ny, const double *nz, const
         orc_offset_grad1(nx[i], ny[i], nz[i], V0[i], &d0[i], &dd_dV0[i], g, NULL);
         dd_dnx[i] = g[0]; dd_dny[i] = g[1]; dd_dnz[i] = g[2];
     }
+}
+
+/* ------------------------------------------------------------------------- */
+/* plane-sphere intersection (Sec. 4)                                         */
+/* ------------------------------------------------------------------------- */
+
+/* radius of the unit-volume sphere */
+static double sphere_radius(void) { return cbrt(3.0 / (4.0 * 3.14159265358979323846)); }
+
+/* volume of the unit-volume sphere below the plane at signed distance d0 from
+ * its centre: the spherical cap (pi/3) (r + d0)^2 (2r - d0), 0 / 1 outside [-r, r] */
+double orc_sphere_volume1(double d0)
+{
+    double r = sphere_radius(), h;
+    if (isnan(d0)) return NAN;
+    if (d0 <= -r) return 0.0;
+    if (d0 >= r) return 1.0;
+    h = r + d0;
+    return 3.14159265358979323846 / 3.0 * h * h * (2.0 * r - d0);
+}
+
+/* the inverse: d0 in [-r, r] with volume V0 (clamped to [0, 1]), by bisection
+ * of the monotone cap volume down to adjacent doubles */
+double orc_sphere_offset1(double V0)
+{
+    double r = sphere_radius(), lo = -r, hi = r;
+    int it;
+    if (isnan(V0)) return NAN;
+    if (V0 <= 0.0) return -r;
+    if (V0 >= 1.0) return r;
+    for (it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (orc_sphere_volume1(mid) < V0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+void orc_sphere_volume(const double *d0, double *V0, int64_t count)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < count; ++i) V0[i] = orc_sphere_volume1(d0[i]);
+}
+
+void orc_sphere_offset(const double *V0, double *d0, int64_t count)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < count; ++i) d0[i] = orc_sphere_offset1(V0[i]);
 }
 
 /* ------------------------------------------------------------------------- */

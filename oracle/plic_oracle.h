@@ -45,6 +45,14 @@ void orc_offset_grad(const double *nx, const double *ny, const double *nz, const
                      double *d0, double *dd_dV0, double *dd_dnx, double *dd_dny,
                      double *dd_dnz, int64_t count);
 
+/* ---- plane-sphere intersection (Sec. 4): sphere of unit volume, radius
+ * r = (3 / (4 pi))^(1/3); d0 = signed distance of the plane from the centre,
+ * V0 = volume on the side n.x <= d0 (any unit normal: the sphere is isotropic) */
+double orc_sphere_volume1(double d0);
+double orc_sphere_offset1(double V0);
+void orc_sphere_volume(const double *d0, double *V0, int64_t count);
+void orc_sphere_offset(const double *V0, double *d0, int64_t count);
+
 /* ---- curvature (Sec. 5 and Appendix B) ----
  * Neighbourhood index q = (dz+1)*9 + (dy+1)*3 + (dx+1), centre q = 13.
  * mask[q] != 0 marks interface neighbours (0 < phi < 1) used as fit points.

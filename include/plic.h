@@ -164,6 +164,25 @@ int plic_curvature_backward_f32(const float *phi, int64_t X, int64_t Y, int64_t 
                                 void *stream);
 
 /*
+ * plic_sphere_offset_f32 / _f64 — the PLIC problem for a spherical cell of
+ * unit volume (Sec. 4): V0 -> d0, the signed distance of the plane from the
+ * sphere's centre with volume V0 on the side n.x <= d0 (any normal: the
+ * sphere is isotropic), d0 in [-r, r], r = (3 / (4 pi))^(1/3).  The paper's
+ * closed form d0 = (6/pi)^(1/3) sin(pi/6 - atan2(2 sqrt(V0 - V0^2), 2 V0 - 1)/3).
+ * V0 is clamped to [0, 1]; NaN stays NaN.
+ * plic_sphere_volume_f32 / _f64 — the inverse: the spherical cap
+ * (pi/3) (r + d0)^2 (2r - d0), 0 below -r and 1 above r.
+ *   in, out : count elements each (V0 -> d0, or d0 -> V0); out may be the
+ *             same array as in, otherwise they must not overlap.
+ * Status codes and stream as for plic_offset_f32; the f32 entries compute in
+ * FP32.
+ */
+int plic_sphere_offset_f32(const float *V0, float *d0, int64_t count, void *stream);
+int plic_sphere_offset_f64(const double *V0, double *d0, int64_t count, void *stream);
+int plic_sphere_volume_f32(const float *d0, float *V0, int64_t count, void *stream);
+int plic_sphere_volume_f64(const double *d0, double *V0, int64_t count, void *stream);
+
+/*
  * plic_curvature_ex_f32 — plic_curvature_f32 with the options of the paper's
  * curvature section:
  *   normal            : PLIC_NORMAL_PY (as plic_curvature_f32) or PLIC_NORMAL_CM

@@ -32,6 +32,10 @@ from ._lib import (  # noqa: F401  (re-exported: the C ABI by name)
     plic_offset_backward_f64,
     plic_offset_f32,
     plic_offset_f64,
+    plic_sphere_offset_f32,
+    plic_sphere_offset_f64,
+    plic_sphere_volume_f32,
+    plic_sphere_volume_f64,
     plic_status_string,
     plic_version,
     plic_volume_f32,

@@ -46,6 +46,10 @@ _c = {
                                         [_vp, _i64, _i64, _i64, _vp, _vp, _int, _int, _vp,
                                          ctypes.c_size_t, _vp]),
     "plic_bench_isolated_f32": _sig("plic_bench_isolated_f32", [_vp, _vp, _vp, _i64, _int, _int, _int, _vp, _vp]),
+    "plic_sphere_offset_f32": _sig("plic_sphere_offset_f32", [_vp, _vp, _i64, _vp]),
+    "plic_sphere_offset_f64": _sig("plic_sphere_offset_f64", [_vp, _vp, _i64, _vp]),
+    "plic_sphere_volume_f32": _sig("plic_sphere_volume_f32", [_vp, _vp, _i64, _vp]),
+    "plic_sphere_volume_f64": _sig("plic_sphere_volume_f64", [_vp, _vp, _i64, _vp]),
     "plic_curvature_ex_f32": _sig("plic_curvature_ex_f32",
                                   [_vp, _i64, _i64, _i64, _vp, _int, _int, _int, _int, _vp, ctypes.c_size_t, _vp]),
     "plic_curvature_backward_ex_f32": _sig("plic_curvature_backward_ex_f32",
@@ -269,6 +273,33 @@ def plic_curvature_backward_f32(phi, grad_kappa, grad_phi, solver="analytic", pr
                                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
            "plic_curvature_backward_f32")
     return grad_phi
+
+
+def _sphere(name, src, dst, dtype):
+    n = src.numel()
+    if dst.numel() != n:
+        raise ValueError(f"{name}: input and output sizes differ")
+    _same_device(src, dst)
+    _check(_c[name](_ptr(src, dtype, n, "in"), _ptr(dst, dtype, n, "out"), n, _stream(src)), name)
+    return dst
+
+
+def plic_sphere_offset_f32(V0, d0):
+    """plane-sphere PLIC (Sec. 4): V0 -> d0 for the unit-volume sphere"""
+    return _sphere("plic_sphere_offset_f32", V0, d0, torch.float32)
+
+
+def plic_sphere_offset_f64(V0, d0):
+    return _sphere("plic_sphere_offset_f64", V0, d0, torch.float64)
+
+
+def plic_sphere_volume_f32(d0, V0):
+    """spherical-cap volume below the plane at distance d0 from the centre"""
+    return _sphere("plic_sphere_volume_f32", d0, V0, torch.float32)
+
+
+def plic_sphere_volume_f64(d0, V0):
+    return _sphere("plic_sphere_volume_f64", d0, V0, torch.float64)
 
 
 def plic_bench_isolated_f32(nx, ny, nz, err, L=256, solver="sz", blank=False):

@@ -583,4 +583,43 @@ __device__ __forceinline__ T offset_grad_from_d0(T nx, T ny, T nz, T V0, T d0, T
     return Fu > T(0) ? m::rcp(Fu) : T(__builtin_inf());
 }
 
+// ---------------------------------------------------------------------------
+// Plane-sphere intersection (Sec. 4): a sphere of unit volume, radius
+// r = (3 / (4 pi))^(1/3); d0 is the signed distance of the plane from the
+// centre and V0 the volume on the side n.x <= d0 (the normal does not matter).
+// Forward: the spherical cap (pi/3) (r + d0)^2 (2r - d0), 0 / 1 beyond +-r.
+// Inverse, as printed: d0 = (6/pi)^(1/3) sin(pi/6 - atan2(2 sqrt(V0 - V0^2),
+// 2 V0 - 1) / 3); with x = 2 V0 - 1 < 0 the angle is pi - atan(y / |x|), so the
+// sine's argument stays in [-pi/6, pi/6].  V0 is clamped to [0, 1]; NaN stays NaN.
+// ---------------------------------------------------------------------------
+template <class T> struct SphereConst;
+template <> struct SphereConst<float> {
+    static constexpr float r = 0.62035049089940001667f, two_r = 1.2407009817988000333f, pi3 = 1.0471975511965977462f;
+};
+template <> struct SphereConst<double> {
+    static constexpr double r = 0.62035049089940001667, two_r = 1.2407009817988000333, pi3 = 1.0471975511965977462;
+};
+
+template <class T>
+__device__ __forceinline__ T sphere_offset(T V0) {
+    using m = M<T>;
+    const T v = m::fmin(m::fmax(V0, T(0)), T(1));
+    const T y = T(2) * m::sqrt(v * (T(1) - v));
+    const T x = T(2) * v - T(1);
+    const T theta = x >= T(0) ? m::atan2_pos(y, x) : T(3.14159265358979323846) - m::atan2_pos(y, -x);
+    T d0 = SphereConst<T>::two_r * m::sin_small(T(0.52359877559829887308) - theta * (T(1) / T(3)));
+    if (__builtin_isnan(V0)) d0 = V0;
+    return d0;
+}
+
+template <class T>
+__device__ __forceinline__ T sphere_volume(T d0) {
+    const T r = SphereConst<T>::r;
+    const T h = r + d0;
+    T V = SphereConst<T>::pi3 * h * h * (T(2) * r - d0);
+    V = d0 <= -r ? T(0) : (d0 >= r ? T(1) : V);
+    if (__builtin_isnan(d0)) V = d0;
+    return V;
+}
+
 }  // namespace plic

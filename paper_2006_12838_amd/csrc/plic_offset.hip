@@ -172,6 +172,23 @@ __global__ __launch_bounds__(kBlock) void k_volume(const S* __restrict__ nx, con
     }
 }
 
+// plane-sphere intersection (Sec. 4): one input and one output array;
+// OP 0 inverts (V0 -> d0), OP 1 evaluates the cap volume (d0 -> V0)
+template <int OP, class S, class T, int VEC>
+__global__ __launch_bounds__(kBlock) void k_sphere(const S* in, S* out, int64_t count) {
+    const int64_t i = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) * VEC;
+    if (i + VEC <= count) {
+        S a[VEC], r[VEC];
+        load<S, VEC>(in, i, a);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) r[k] = S(OP == 0 ? sphere_offset<T>(T(a[k])) : sphere_volume<T>(T(a[k])));
+        store<S, VEC>(out, i, r);
+    } else {
+        for (int64_t j = i; j < count; ++j)
+            out[j] = S(OP == 0 ? sphere_offset<T>(T(in[j])) : sphere_volume<T>(T(in[j])));
+    }
+}
+
 // vector-Jacobian product of one problem given its offset d0
 template <class T>
 __device__ __forceinline__ void backward1(T nx, T ny, T nz, T V0, T d0, T gd, T& gx, T& gy, T& gz, T& gv) {
@@ -232,6 +249,20 @@ void launch_volume_v(const S* nx, const S* ny, const S* nz, const S* d0, S* V0, 
 
 // ---- dispatch ------------------------------------------------------------------
 // whole blocks unchecked, then the remainder in one checked block
+template <int OP, class S>
+void launch_sphere(const S* in, S* out, int64_t count, hipStream_t st) {
+    const bool vec = aligned(in, 16) && aligned(out, 16);
+    for (int64_t base = 0; base < count; base += kChunkProblems) {
+        const int64_t n = count - base < kChunkProblems ? count - base : kChunkProblems;
+        if (vec)
+            hipLaunchKernelGGL((k_sphere<OP, S, S, kVec<S>>), dim3(grid_for(n, kVec<S>)), dim3(kBlock), 0, st,
+                               in + base, out + base, n);
+        else
+            hipLaunchKernelGGL((k_sphere<OP, S, S, 1>), dim3(grid_for(n, 1)), dim3(kBlock), 0, st, in + base,
+                               out + base, n);
+    }
+}
+
 template <int SOLVER, class S, class T, class U, int VEC>
 void launch_offset_v(const S* nx, const S* ny, const S* nz, const S* V0, S* d0, int64_t count, hipStream_t st) {
     const int64_t per = static_cast<int64_t>(kBlock) * VEC, full = count / per * per, rem = count - full;
@@ -302,6 +333,18 @@ bool all_aligned16(std::initializer_list<const void*> ps) {
     for (const void* p : ps)
         if (!aligned(p, 16)) return false;
     return true;
+}
+
+// plane-sphere entry points: in and out may be the same array (each element
+// is read and written by the same thread); otherwise they must not overlap
+template <int OP, class S>
+int sphere_entry(const S* in, S* out, int64_t count, void* stream) {
+    if (count < 0 || !valid_array(in, count) || !valid_array(out, count)) return PLIC_EINVAL;
+    const size_t nb = static_cast<size_t>(count) * sizeof(S);
+    if (static_cast<const void*>(in) != static_cast<const void*>(out) && overlap(in, nb, out, nb)) return PLIC_EINVAL;
+    if (count == 0) return PLIC_OK;
+    launch_sphere<OP, S>(in, out, count, static_cast<hipStream_t>(stream));
+    return launch_status();
 }
 
 }  // namespace
@@ -430,6 +473,20 @@ int plic_offset_backward_f64(const double* nx, const double* ny, const double* n
     const bool vec = all_aligned16<double>({nx, ny, nz, V0, grad_d0, grad_nx, grad_ny, grad_nz, grad_V0});
     launch_bwd_s<double, double, double>(solver, nx, ny, nz, V0, grad_d0, grad_nx, grad_ny, grad_nz, grad_V0, count, vec, st);
     return launch_status();
+}
+
+
+int plic_sphere_offset_f32(const float* V0, float* d0, int64_t count, void* stream) {
+    return sphere_entry<0, float>(V0, d0, count, stream);
+}
+int plic_sphere_offset_f64(const double* V0, double* d0, int64_t count, void* stream) {
+    return sphere_entry<0, double>(V0, d0, count, stream);
+}
+int plic_sphere_volume_f32(const float* d0, float* V0, int64_t count, void* stream) {
+    return sphere_entry<1, float>(d0, V0, count, stream);
+}
+int plic_sphere_volume_f64(const double* d0, double* V0, int64_t count, void* stream) {
+    return sphere_entry<1, double>(d0, V0, count, stream);
 }
 
 }  // extern "C"

@@ -146,6 +146,19 @@ def test_curvature_options_validation(lib):
     assert g(A, 3, 3, 3, B, A, 0, 1, 1, W, ws, None) == -1              # grad_phi overlaps phi
 
 
+def test_sphere_validation(lib):
+    for name in ("plic_sphere_offset_f32", "plic_sphere_volume_f32", "plic_sphere_offset_f64",
+                 "plic_sphere_volume_f64"):
+        f = lib.raw(name)
+        assert f(A, B, 0, None) == 0                                     # empty
+        assert f(None, None, 0, None) == 0
+        assert f(A, B, -1, None) == -1
+        assert f(None, B, 8, None) == -1
+        assert f(A, A + 8, 8, None) == -1                                # partial overlap
+    assert lib.raw("plic_sphere_offset_f32")(A + 2, B, 8, None) == -1    # misaligned
+    assert lib.raw("plic_sphere_offset_f64")(A + 4, B, 8, None) == -1
+
+
 def test_bench_validation(lib):
     f = lib.raw("plic_bench_isolated_f32")
     assert f(A, B, C, 0, 256, 0, 0, D, None) == 0                     # empty

@@ -270,6 +270,26 @@ def paper_isolated(P, torch, dev, log2n, L=256, reps=5):
     return out
 
 
+def sphere_rate(P, torch, V0, reps=10):
+    """Plane-sphere inversion (Sec. 4) on the same fill levels: HBM-streamed
+    V0 -> d0 (8 bytes per problem), outside the step (not a plane-cube solve)."""
+    d = torch.empty_like(V0)
+    stream = torch.cuda.current_stream(V0.device)
+    P.plic_sphere_offset_f32(V0, d)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        P.plic_sphere_offset_f32(V0, d)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    n = V0.numel()
+    gbs = 8 * n / (ms * 1e-3) / 1e9
+    return {"ms": round(ms, 4), "rate": n / (ms * 1e-3), "unit": "solves/s", "GBps": gbs,
+            "hbm_frac": gbs / HBM_PEAK_GBS}
+
+
 def cpu_baseline(nx, ny, nz, V0, seconds):
     """The oracle (bisection on the FP64 forward volume), timed on the host
     cores on chunks of the same workload until `seconds` have passed."""
@@ -426,6 +446,8 @@ def main():
                                                      "hbm_frac": rates[fast[0]]["hbm_frac"]},
         "roofline": roofline,
     }
+    if not args.only:
+        out["sphere_offset"] = sphere_rate(P, torch, tn[3])
     if not args.no_paper_isolated and not args.only:
         out["paper_isolated"] = paper_isolated(P, torch, dev, args.log2n)
     if not args.no_cpu_baseline:

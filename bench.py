@@ -90,15 +90,16 @@ def measured_traffic(kernel):
 
 # bench kernel -> dispatch names (demangled prefixes) that make up one launch
 PMC_DISPATCHES = {
-    "offset_analytic": ("k_offset<0, float, float, float, 4>",),
-    "offset_sz": ("k_offset<1, float, float, float, 4>",),
-    "offset_newton": ("k_offset<2, float, float, float, 4>",),
-    "offset_nested": ("k_offset<3, float, float, float, 4>",),
+    "offset_analytic": ("k_offset<0, float, float, float, 4,",),
+    "offset_sz": ("k_offset<1, float, float, float, 4,",),
+    "offset_newton": ("k_offset<2, float, float, float, 4,",),
+    "offset_nested": ("k_offset<3, float, float, float, 4,",),
     "volume": ("k_volume<float, float, 4>",),
-    "offset_backward_sz": ("k_offset_bwd<1, float, float, float, 4>",),
-    "curvature_fwd": ("k_curv_scan<true, true>", "k_curv_items<0, float, double, double, false>"),
-    "curvature_bwd": ("k_curv_scan<true, false>", "k_curv_items<0, float, double, double, true>", "k_curv_dilate",
-                      "k_curv_gather<0, float, double, double, false>", "k_curv_gather<0, float, double, double, true>"),
+    "offset_backward_sz": ("k_offset_bwd<1, float, float, float, 4,",),
+    "curvature_fwd": ("k_curv_scan<true, true>", "k_curv_items<0, float, double, double, false, 0, false>"),
+    "curvature_bwd": ("k_curv_scan<true, false>", "k_curv_items<0, float, double, double, true, 0, false>",
+                      "k_curv_dilate", "k_curv_gather<0, float, float, float, 0, false>",
+                      "k_curv_gather<0, float, double, double, 0, true>"),
     "copy": ("__amd_rocclr_copyBuffer",),
 }
 ALGORITHMIC_BYTES = {"offset_analytic": 20, "offset_sz": 20, "offset_newton": 20, "offset_nested": 20,

@@ -112,8 +112,11 @@ int plic_offset_backward_f64(const double *nx, const double *ny, const double *n
  * about 0.8 byte per cell) and, for the backward pass, a store of 108 bytes
  * (27 floats) per interface cell.  The recommended size budgets 16 interface
  * cells per tile (41 MB at 256^3); any size of at least the fixed part is
- * valid: interface cells beyond the store's capacity are recomputed by the
- * backward pass (slower, same result).  The forward pass uses only the fixed
+ * valid: rows go to the interface cells in tile order, and cells beyond the
+ * store's capacity are recomputed by the backward pass (slower; the same bits
+ * unless the 3x3x3-grown neighbourhood of a 64x4x4 tile holds more than 128
+ * interface cells, where the summation order differs in the last bits).
+ * Results are deterministic for a given size.  The forward pass uses only the fixed
  * part.  0 for an empty or invalid lattice (2^24 tiles or more, i.e. about
  * 1.7e10 cells, is invalid).
  * The workspace is caller-owned device memory; its contents need no

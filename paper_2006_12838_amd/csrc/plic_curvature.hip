@@ -3,22 +3,31 @@
 //
 // Layout: phi, kappa, grad_kappa, grad_phi are X*Y*Z floats, x fastest.  The
 // lattice is cut into 64x4x4 tiles.  A call runs:
-//  1. a one-thread kernel that zeroes the work-list counter in the workspace
+//  1. a one-thread kernel that zeroes the work-list counters in the workspace
 //     (a kernel, not a memset, so the call can be captured in a graph);
-//  2. a streaming scan over the whole lattice (float4 loads and stores, no
-//     LDS, low register use, full occupancy) that writes the zero result
-//     everywhere and records the interface cells (0 < phi < 1, away from the
-//     outer layer): forward, one work item per 8 interface cells of a tile;
-//     backward, one flag per tile, then a small kernel lists every tile whose
-//     3x3x3 tile neighbourhood is flagged;
+//  2. a streaming scan over the whole lattice (float4 loads and stores) that
+//     writes the zero result everywhere and lists one work item per 8
+//     interface cells (0 < phi < 1, away from the outer layer) of each tile;
+//     the backward also records each tile's interface bitmask and count;
 //  3. a persistent kernel over the work list that stages the fill levels of a
 //     tile plus a halo in LDS and computes each interface cell with a group of
 //     32 lanes: lane j takes neighbour j of the 3x3x3 neighbourhood (its PLIC
 //     offset, its row of the normal equations), lane 26 the centre.  Sums over
 //     the neighbours go through a small LDS tile and are added in a fixed
 //     order, so results are bitwise reproducible.
+// The backward stores each interface cell's 27 contributions in a row of the
+// workspace (rows assigned by a prefix over the tiles' counts, in tile order)
+// and gathers them per target cell in a fixed order; rows beyond the
+// workspace are recomputed by a fallback gather.
 // The interface is one cell thick (about 0.2 % of a 256^3 sphere lattice), so
 // the scan carries the HBM traffic and the list kernels the arithmetic.
+//
+// Floating-point contraction is limited to single expressions in this file,
+// so the per-cell arithmetic gives the same bits in every kernel that inlines
+// it (a contribution stored by the work items and one recomputed by the
+// fallback gather are identical).
+#pragma clang fp contract(on)
+
 #include <hip/hip_runtime.h>
 
 #include "plic_host.hpp"
@@ -410,13 +419,15 @@ __device__ __forceinline__ int ordered_compact(int n, Pred pred, unsigned short*
 // ---------------------------------------------------------------------------
 // Workspace (caller device memory, 4-byte aligned):
 //   [0, 256)  counters: [0] work items, [1] gather tiles, [2] overflow tiles
-//   flags     ntiles      tile holds an interface cell (backward)
+//   flags     ntiles      interface cells in the tile (backward)
 //   cbase     ntiles      first contribution row of the tile's interface cells
+//                         (prefix of flags in tile order)
 //   mask      32 ntiles   interface bit of each of the tile's 1024 cells
 //   prefix    32 ntiles   set bits of mask before word w
 //   items     128 ntiles  work items (tile << 7 | part), 8 interface cells each
 //   tiles     ntiles      backward gather tiles
-//   over      ntiles      gather tiles holding a cell without a stored row
+//   over      ntiles      row-prefix block totals, then the gather tiles with a
+//                         source cell without a stored row
 //   contrib   the rest:   27 floats per row (backward contributions)
 // The fixed part (everything but contrib) is 784 bytes per tile.  The
 // backward stores the 27 contributions of an interface cell in row
@@ -513,8 +524,7 @@ __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict_
             for (unsigned p = 0; p < parts; ++p) ws.items[base + p] = (static_cast<unsigned>(tile) << 7) | p;
         }
         if constexpr (!FWD) {
-            ws.flags[tile] = total ? 1u : 0u;
-            ws.cbase[tile] = base < kRowCap / kPartCells ? base * kPartCells : kRowCap;
+            ws.flags[tile] = static_cast<unsigned>(total);          // rows are assigned from these counts
             unsigned acc = 0u;
             for (int w = 0; w < kWords; ++w) {
                 ws.prefix[tile * kWords + w] = acc;
@@ -524,6 +534,72 @@ __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict_
     }
     if constexpr (!FWD) {
         if (t < kWords) ws.mask[tile * kWords + t] = smask[t];
+    }
+}
+
+// Contribution rows in tile order: cbase[tile] = number of interface cells in
+// the tiles before it (exclusive prefix of flags), saturated at kRowCap, so
+// the cells that get a row for a given workspace size do not depend on the
+// order in which the scan's blocks ran.  Two passes: per 2048 tiles, then each
+// block adds the totals of the blocks before it.  The block totals live in the
+// overflow list until the gather uses it.
+constexpr int kPrefixPer = 8;                                 // tiles per thread
+constexpr int kPrefixBlock = kThreads * kPrefixPer;           // 2048 tiles per block
+
+__global__ __launch_bounds__(kThreads) void k_curv_prefix_a(Workspace ws, int ntiles) {
+    __shared__ unsigned wsum[kThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int base = blockIdx.x * kPrefixBlock + t * kPrefixPer;
+    unsigned v[kPrefixPer], sum = 0u;
+#pragma unroll
+    for (int u = 0; u < kPrefixPer; ++u) {
+        v[u] = base + u < ntiles ? ws.flags[base + u] : 0u;
+        sum += v[u];
+    }
+    unsigned incl = sum;                                      // inclusive scan over the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    unsigned woff = 0u, total = 0u;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        woff += w < wave ? wsum[w] : 0u;
+        total += wsum[w];
+    }
+    unsigned excl = woff + incl - sum;
+#pragma unroll
+    for (int u = 0; u < kPrefixPer; ++u) {
+        if (base + u < ntiles) ws.cbase[base + u] = excl;
+        excl += v[u];
+    }
+    if (t == 0) ws.over[blockIdx.x] = total;                  // at most 2048 * 1024 = 2^21
+}
+
+// block b of 2048 tiles: its offset is the sum of the totals of blocks 0..b-1
+// (64-bit, fixed order), added to the local prefixes with saturation
+__global__ __launch_bounds__(kThreads) void k_curv_prefix_b(Workspace ws, int ntiles) {
+    __shared__ unsigned long long part[kThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    unsigned long long acc = 0ull;
+    for (int i = t; i < static_cast<int>(blockIdx.x); i += kThreads) acc += ws.over[i];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    if (lane == 0) part[wave] = acc;
+    __syncthreads();
+    unsigned long long off = 0ull;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) off += part[w];
+    const int base = blockIdx.x * kPrefixBlock + t * kPrefixPer;
+#pragma unroll
+    for (int u = 0; u < kPrefixPer; ++u) {
+        if (base + u < ntiles) {
+            const unsigned long long r = off + ws.cbase[base + u];
+            ws.cbase[base + u] = static_cast<unsigned>(r < kRowCap ? r : kRowCap);
+        }
     }
 }
 
@@ -636,31 +712,30 @@ __device__ __forceinline__ unsigned contrib_row(const Workspace& ws, int gx, int
     return ws.cbase[ctile] + ws.prefix[ctile * kWords + l / 32] + __popc(w & ((1u << (l % 32)) - 1u));
 }
 
-// FALLBACK = false: tiles of the gather list; a tile with a candidate whose row
-// did not fit is passed on to the overflow list untouched.  FALLBACK = true:
-// the overflow list, candidates without a row recomputed here.  Splitting keeps
-// the register-heavy recomputation out of the common kernel.
-template <int SOLVER, class T, class U, class F, int NRM, bool FALLBACK>
-__global__ __launch_bounds__(kThreads) void k_curv_gather(const float* __restrict__ phi,
-                                                           const float* __restrict__ gkap,
-                                                           float* __restrict__ gphi, Workspace ws, int X, int Y,
-                                                           int Z, int ntx, int nty) {
-    // the lean kernel only tests interface status (halo 1); recomputation needs halo 2
-    constexpr int RX = FALLBACK ? B_RX : F_RX, RY = FALLBACK ? B_RY : F_RY, RZ = FALLBACK ? B_RZ : F_RZ;
-    constexpr int H = FALLBACK ? 2 : 1;
+// Fallback gather over the overflow list: the tiles with a source cell whose
+// row did not fit in the workspace.  Candidates (interface cells of the tile
+// grown by one) are processed in chunks of kChunk in region order: stored rows
+// are copied, missing ones recomputed (halo 2 in LDS); each target then adds
+// its 27 neighbours' entries in q order.  With at most kChunk candidates this
+// is the direct gather's order, so the result is the same bits.
+template <int SOLVER, class T, class U, class F, int NRM>
+__global__ __launch_bounds__(kThreads) void k_curv_gather_fallback(const float* __restrict__ phi,
+                                                                    const float* __restrict__ gkap,
+                                                                    float* __restrict__ gphi, Workspace ws, int X,
+                                                                    int Y, int Z, int ntx, int nty) {
+    constexpr int RX = B_RX, RY = B_RY, RZ = B_RZ, H = 2;
     __shared__ float s[RX * RY * RZ];
     __shared__ unsigned short cand[C_REGION];
     __shared__ unsigned short slot[C_REGION];
     __shared__ float contrib[kChunk][27];
     __shared__ unsigned crow[kChunk];
     __shared__ int wcount[kThreads / 64];
-    __shared__ GroupLds<F> glds[FALLBACK ? kGroups : 1];
+    __shared__ GroupLds<F> glds[kGroups];
     const int tid = threadIdx.x, grp = tid / kGroup, j = tid % kGroup;
     for (int i = tid; i < C_REGION; i += kThreads) slot[i] = kNoSlot;
-    const unsigned ntl = *static_cast<volatile unsigned*>(ws.counter + (FALLBACK ? 2 : 1));
-    const unsigned* tiles = FALLBACK ? ws.over : ws.tiles;
+    const unsigned ntl = *static_cast<volatile unsigned*>(ws.counter + 2);
     for (unsigned it = blockIdx.x; it < ntl; it += gridDim.x) {
-        const int tile = static_cast<int>(tiles[it]);
+        const int tile = static_cast<int>(ws.over[it]);
         const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
         load_region<RX, RY, RZ>(s, phi, x0 - H, y0 - H, z0 - H, X, Y, Z);
         __syncthreads();
@@ -670,18 +745,6 @@ __global__ __launch_bounds__(kThreads) void k_curv_gather(const float* __restric
             return gx >= 1 && gy >= 1 && gz >= 1 && gx <= X - 2 && gy <= Y - 2 && gz <= Z - 2 &&
                    is_iface(s[((lz + H - 1) * RY + (ly + H - 1)) * RX + (lx + H - 1)]);
         }, cand, wcount);
-        if constexpr (!FALLBACK) {
-            int miss = 0;
-            for (int i = tid; i < ncand; i += kThreads) {
-                const int ci = cand[i];
-                const int lx = ci % C_RX, ly = (ci / C_RX) % C_RY, lz = ci / (C_RX * C_RY);
-                miss |= contrib_row(ws, x0 - 1 + lx, y0 - 1 + ly, z0 - 1 + lz, ntx, nty) >= ws.rows;
-            }
-            if (__syncthreads_or(miss)) {                            // uniform per workgroup
-                if (tid == 0) ws.over[atomicAdd(ws.counter + 2, 1u)] = static_cast<unsigned>(tile);
-                continue;
-            }
-        }
         float acc[kCellsPerThread];
 #pragma unroll
         for (int k = 0; k < kCellsPerThread; ++k) acc[k] = 0.0f;
@@ -712,7 +775,7 @@ __global__ __launch_bounds__(kThreads) void k_curv_gather(const float* __restric
                 for (int u = 0; u < kCopyBatch; ++u)
                     if (at[u] != 0xFFFFFFFFu) contrib[at[u] / 27][at[u] % 27] = v[u];
             }
-            if constexpr (FALLBACK) {
+            {
                 // rows that did not fit: recomputed, one group of lanes per cell
                 for (int i = grp; i < nc; i += kGroups) {
                     if (crow[i] < ws.rows) continue;                     // uniform per group
@@ -752,6 +815,74 @@ __global__ __launch_bounds__(kThreads) void k_curv_gather(const float* __restric
             if (gx < X && gy < Y && gz < Z) gphi[(static_cast<int64_t>(gz) * Y + gy) * X + gx] = acc[k];
         }
         __syncthreads();                                             // LDS reused by the next tile
+    }
+}
+
+// Direct backward gather for the tiles whose sources all have a stored row:
+// the interface bitmasks, prefix counts and first rows of the 3x3x3 tiles
+// around the tile are staged in LDS; each target cell then adds, for q = 0..26
+// in order, entry q of the row of its source cell target - e_q when that cell
+// is an interface cell.  Two dependent global loads per tile, no fill levels.
+// A tile with a source beyond the store goes to the overflow list unwritten.
+__global__ __launch_bounds__(kThreads) void k_curv_gather_direct(float* __restrict__ gphi, Workspace ws, int X,
+                                                                  int Y, int Z, int ntx, int nty, int ntz) {
+    __shared__ unsigned smask[27][kWords];
+    __shared__ unsigned spref[27][kWords];
+    __shared__ unsigned sbase[27];
+    const int tid = threadIdx.x;
+    const unsigned ntl = *static_cast<volatile unsigned*>(ws.counter + 1);
+    for (unsigned it = blockIdx.x; it < ntl; it += gridDim.x) {
+        const int tile = static_cast<int>(ws.tiles[it]);
+        const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+        for (int i = tid; i < 27 * (2 * kWords + 1); i += kThreads) {
+            const int t = i / (2 * kWords + 1), w = i % (2 * kWords + 1);
+            const int ax = tx + q_dx(t), ay = ty + q_dy(t), az = tz + q_dz(t);
+            const bool in = ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz;
+            const int nt = (az * nty + ay) * ntx + ax;
+            if (w < kWords) smask[t][w] = in ? ws.mask[nt * kWords + w] : 0u;
+            else if (w < 2 * kWords) spref[t][w - kWords] = in ? ws.prefix[nt * kWords + (w - kWords)] : 0u;
+            else sbase[t] = in ? ws.cbase[nt] : 0u;
+        }
+        __syncthreads();
+        float acc[kCellsPerThread];
+        int miss = 0;
+#pragma unroll 1
+        for (int k = 0; k < kCellsPerThread; ++k) {
+            const int cl = tid + k * kThreads;
+            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
+            float a = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 27; ++q) {
+                // source cell target - e_q in tile-local coordinates, possibly
+                // one tile over in each direction
+                const int sx = cx - q_dx(q), sy = cy - q_dy(q), sz = cz - q_dz(q);
+                const int rx = sx < 0 ? -1 : (sx >= TX ? 1 : 0);
+                const int ry = sy < 0 ? -1 : (sy >= TY ? 1 : 0);
+                const int rz = sz < 0 ? -1 : (sz >= TZ ? 1 : 0);
+                const int tq = (rz + 1) * 9 + (ry + 1) * 3 + (rx + 1);
+                const int l = ((sz - rz * TZ) * TY + (sy - ry * TY)) * TX + (sx - rx * TX);
+                const unsigned word = smask[tq][l >> 5];
+                const unsigned bit = 1u << (l & 31);
+                if (word & bit) {
+                    const unsigned r = sbase[tq] + spref[tq][l >> 5] + __popc(word & (bit - 1u));
+                    if (r < ws.rows) a += ws.contrib[static_cast<size_t>(r) * 27 + q];
+                    else miss = 1;
+                }
+            }
+            acc[k] = a;
+        }
+        if (__syncthreads_or(miss)) {                                // uniform per workgroup
+            if (tid == 0) ws.over[atomicAdd(ws.counter + 2, 1u)] = static_cast<unsigned>(tile);
+            continue;
+        }
+#pragma unroll
+        for (int k = 0; k < kCellsPerThread; ++k) {
+            const int cl = tid + k * kThreads;
+            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
+            const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
+            if (gx < X && gy < Y && gz < Z) gphi[(static_cast<int64_t>(gz) * Y + gy) * X + gx] = acc[k];
+        }
     }
 }
 
@@ -851,13 +982,16 @@ void launch_fwd(int precision, int normal, bool nbr, const float* phi, float* ka
 template <int SOLVER, class T, class U, class F, int NRM>
 void launch_bwd_t(const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y, int Z,
                   const Grid& g, hipStream_t st) {
+    const int nb = (g.ntiles + kPrefixBlock - 1) / kPrefixBlock;
+    hipLaunchKernelGGL(k_curv_prefix_a, dim3(nb), dim3(kThreads), 0, st, ws, g.ntiles);
+    hipLaunchKernelGGL(k_curv_prefix_b, dim3(nb), dim3(kThreads), 0, st, ws, g.ntiles);
     if (ws.rows > 0) launch_items<SOLVER, T, U, F, true, NRM, false>(phi, gk, nullptr, ws, X, Y, Z, g, st);
     hipLaunchKernelGGL(k_curv_dilate, dim3((g.ntiles + kThreads - 1) / kThreads), dim3(kThreads), 0, st, ws,
                        g.ntx, g.nty, g.ntz, g.ntiles);
-    hipLaunchKernelGGL((k_curv_gather<kAnalytic, float, float, float, kNormalPY, false>), dim3(persistent_grid(g.ntiles)),
-                       dim3(kThreads), 0, st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
-    hipLaunchKernelGGL((k_curv_gather<SOLVER, T, U, F, NRM, true>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0,
-                       st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
+    hipLaunchKernelGGL(k_curv_gather_direct, dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0, st, gp, ws, X, Y, Z,
+                       g.ntx, g.nty, g.ntz);
+    hipLaunchKernelGGL((k_curv_gather_fallback<SOLVER, T, U, F, NRM>), dim3(persistent_grid(g.ntiles)), dim3(kThreads),
+                       0, st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
 }
 
 template <int SOLVER, class T, class U, class F>

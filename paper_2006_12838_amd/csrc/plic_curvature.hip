@@ -441,9 +441,12 @@ constexpr int kWords = kTile / 32;            // mask words per tile
 constexpr size_t kFixedPerTile = sizeof(unsigned) * (1 + 1 + kWords + kWords + kMaxParts + 1 + 1);
 constexpr size_t kRowBytes = 27 * sizeof(float);
 constexpr size_t kDefaultRowsPerTile = 16;    // contribution rows budgeted per tile by default
-// rows are 32-bit indices: capacity and first rows saturate here, so that a
-// first row plus a rank (< kTile) never wraps and a saturated tile recomputes
+// rows are 32-bit indices: first rows saturate at kRowCap, so that a first
+// row plus a rank (< kTile) never wraps and a saturated tile recomputes; the
+// capacity is at most kRowLimit rows, so an entry's index row * 27 + q stays
+// below 2^30 (a 32-bit byte offset from the store's base)
 constexpr unsigned kRowCap = 0xF0000000u;
+constexpr unsigned kRowLimit = (1u << 30) / 27u;
 
 struct Workspace {
     unsigned* counter;  // [0] items, [1] gather tiles, [2] overflow tiles
@@ -480,7 +483,7 @@ __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict_
     const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
     const int t = threadIdx.x;
     const int x = x0 + (t % 16) * 4, y = y0 + (t / 16) % TY, z = z0 + t / (16 * TY);
-    if (!FWD && t < kWords) smask[t] = 0u;
+    if (t < kWords) smask[t] = 0u;
     unsigned nib = 0u;
     if (y < Y && z < Z) {
         const bool yz_in = y >= 1 && y <= Y - 2 && z >= 1 && z <= Z - 2;
@@ -508,33 +511,26 @@ __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict_
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
     if ((t & 63) == 0) wsum[t >> 6] = cnt;
-    if constexpr (!FWD) {
-        __syncthreads();                                  // smask cleared
-        if (nib) atomicOr(&smask[t / 8], nib << ((t % 8) * 4));
-    }
+    __syncthreads();                                      // smask cleared
+    if (nib) atomicOr(&smask[t / 8], nib << ((t % 8) * 4));
     __syncthreads();
     int total = 0;
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) total += wsum[w];
     const unsigned parts = (total + kPartCells - 1) / kPartCells;
     if (t == 0) {
-        unsigned base = 0u;
         if (parts) {
-            base = atomicAdd(ws.counter, parts);
+            const unsigned base = atomicAdd(ws.counter, parts);
             for (unsigned p = 0; p < parts; ++p) ws.items[base + p] = (static_cast<unsigned>(tile) << 7) | p;
         }
-        if constexpr (!FWD) {
-            ws.flags[tile] = static_cast<unsigned>(total);          // rows are assigned from these counts
-            unsigned acc = 0u;
-            for (int w = 0; w < kWords; ++w) {
-                ws.prefix[tile * kWords + w] = acc;
-                acc += __popc(smask[w]);
-            }
+        if constexpr (!FWD) ws.flags[tile] = static_cast<unsigned>(total);  // rows are assigned from these counts
+        unsigned acc = 0u;
+        for (int w = 0; w < kWords; ++w) {
+            ws.prefix[tile * kWords + w] = acc;
+            acc += __popc(smask[w]);
         }
     }
-    if constexpr (!FWD) {
-        if (t < kWords) ws.mask[tile * kWords + t] = smask[t];
-    }
+    if (t < kWords) ws.mask[tile * kWords + t] = smask[t];
 }
 
 // Contribution rows in tile order: cbase[tile] = number of interface cells in
@@ -604,7 +600,8 @@ __global__ __launch_bounds__(kThreads) void k_curv_prefix_b(Workspace ws, int nt
 }
 
 // backward gather list: every tile whose 3x3x3 tile neighbourhood holds an
-// interface cell (its targets can receive a contribution)
+// interface cell (its cells can receive a contribution); one tile per thread,
+// the list's order does not affect any result
 __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx, int nty, int ntz, int ntiles) {
     const int tile = blockIdx.x * kThreads + threadIdx.x;
     bool act = false;
@@ -619,12 +616,12 @@ __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx,
     }
     const unsigned long long bal = __ballot(act);
     const int lane = threadIdx.x & 63;
-    unsigned base = 0;
-    if (lane == 0 && bal) base = atomicAdd(ws.counter + 1, static_cast<unsigned>(__popcll(bal)));
-    base = __shfl(base, 0, 64);
+    unsigned first = 0;
+    if (lane == 0 && bal) first = atomicAdd(ws.counter + 1, static_cast<unsigned>(__popcll(bal)));
+    first = __shfl(first, 0, 64);
     if (act) {
         const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
-        ws.tiles[base + __popcll(below)] = static_cast<unsigned>(tile);
+        ws.tiles[first + __popcll(below)] = static_cast<unsigned>(tile);
     }
 }
 
@@ -635,57 +632,64 @@ __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx,
 // well defined.  Forward: kappa.  Backward: the cell's 27 contributions
 // gk * d kappa / d phi_q into its contribution row (when it fits).
 // ---------------------------------------------------------------------------
-constexpr int F_RX = TX + 2, F_RY = TY + 2, F_RZ = TZ + 2, F_REGION = F_RX * F_RY * F_RZ;
 
-// NBR: the neighbour-normal variant needs each neighbour's 3^3, a halo of 2
+// One work item = up to kPartCells interface cells of a tile, one 32-lane
+// group per cell.  The group finds its cell, the i-th interface cell of the
+// tile in cell order, from the tile's bitmask and prefix counts (two ballots),
+// stages the fill levels of its 3x3x3 neighbourhood (5x5x5 for the
+// neighbour-normal variant, which needs each neighbour's own 3x3x3) in LDS,
+// and runs the cell.  Groups never wait for each other: no block barrier.
 template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
 __global__ __launch_bounds__(kThreads) void k_curv_items(const float* __restrict__ phi,
                                                           const float* __restrict__ gkap,
                                                           float* __restrict__ kappa, Workspace ws, int X, int Y,
                                                           int Z, int ntx, int nty) {
-    constexpr int H = NBR ? 2 : 1, RX = TX + 2 * H, RY = TY + 2 * H, RZ = TZ + 2 * H;
-    __shared__ float s[RX * RY * RZ];
-    __shared__ unsigned short list[kTile];
-    __shared__ int wcount[kThreads / 64];
+    constexpr int H = NBR ? 2 : 1, W = 2 * H + 1, NB = W * W * W, C = (H * W + H) * W + H;
+    __shared__ float nbh[kGroups][NB];
     __shared__ GroupLds<F> glds[kGroups];
     const int tid = threadIdx.x, grp = tid / kGroup, j = tid % kGroup;
+    const int half = tid & 32;                               // this group's lanes in the wave
     const unsigned nitems = *static_cast<volatile unsigned*>(ws.counter);
     for (unsigned item = blockIdx.x; item < nitems; item += gridDim.x) {
         const unsigned e = ws.items[item];
         const int tile = static_cast<int>(e >> 7), part = static_cast<int>(e & 127u);
-        unsigned row0 = 0u;
+        const int i = part * kPartCells + grp;               // rank of this group's cell
+        unsigned row = 0u;
         if constexpr (ADJ) {
-            row0 = ws.cbase[tile] + static_cast<unsigned>(part * kPartCells);
-            if (row0 >= ws.rows) continue;                       // uniform; the gather recomputes
+            row = ws.cbase[tile] + static_cast<unsigned>(i);
+            if (row >= ws.rows) continue;                    // uniform per group; the gather recomputes
         }
+        // lane j holds mask word j and the count of set bits before it
+        const unsigned mw = ws.mask[tile * kWords + j], pw = ws.prefix[tile * kWords + j];
+        const int n = static_cast<int>(__shfl(pw + __popc(mw), kWords - 1, kGroup));
+        if (i >= n) continue;                                // uniform per group
+        const unsigned ui = static_cast<unsigned>(i);
+        const unsigned in_word = static_cast<unsigned>(__ballot(pw <= ui && ui < pw + __popc(mw)) >> half);
+        const int w = __ffs(static_cast<int>(in_word)) - 1;
+        const unsigned word = __shfl(mw, w, kGroup);
+        const unsigned k = ui - __shfl(pw, w, kGroup);
+        const bool hit = ((word >> j) & 1u) && static_cast<unsigned>(__popc(word & ((1u << j) - 1u))) == k;
+        const int b = __ffs(static_cast<int>(static_cast<unsigned>(__ballot(hit) >> half))) - 1;
+        const int cl = w * 32 + b;
         const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
-        load_region<RX, RY, RZ>(s, phi, x0 - H, y0 - H, z0 - H, X, Y, Z);
-        __syncthreads();
-        const int n = ordered_compact(kTile, [&](int cl) {
-            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-            const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
-            return gx >= 1 && gy >= 1 && gz >= 1 && gx <= X - 2 && gy <= Y - 2 && gz <= Z - 2 &&
-                   is_iface(s[((cz + H) * RY + (cy + H)) * RX + (cx + H)]);
-        }, list, wcount);
-        const int i = part * kPartCells + grp;
-        if (i < n) {
-            const int cl = list[i];
-            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-            const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
-            const int64_t g = (static_cast<int64_t>(gz) * Y + gy) * X + gx;
-            const int c = ((cz + H) * RY + (cy + H)) * RX + (cx + H);
-            if constexpr (ADJ) {
-                const unsigned r = row0 + static_cast<unsigned>(grp);
-                if (r < ws.rows)                                 // uniform per group
-                    group_cell<SOLVER, T, U, F, true, NRM, false>(s, c, RX, RX * RY, j, gkap[g],
-                                                                  ws.contrib + static_cast<size_t>(r) * 27, glds[grp]);
-            } else {
-                const float kv = group_cell<SOLVER, T, U, F, false, NRM, NBR>(s, c, RX, RX * RY, j, 0.0f, nullptr,
-                                                                             glds[grp], gx, gy, gz, X, Y, Z);
-                if (j == 0) kappa[g] = kv;
-            }
+        const int gx = x0 + cl % TX, gy = y0 + (cl / TX) % TY, gz = z0 + cl / (TX * TY);
+        // the neighbourhood's fill levels (outside the lattice: 0)
+        for (int t = j; t < NB; t += kGroup) {
+            const int ax = gx + t % W - H, ay = gy + (t / W) % W - H, az = gz + t / (W * W) - H;
+            nbh[grp][t] = (ax >= 0 && ax < X && ay >= 0 && ay < Y && az >= 0 && az < Z)
+                              ? phi[(static_cast<int64_t>(az) * Y + ay) * X + ax] : 0.0f;
         }
-        __syncthreads();                                         // LDS reused by the next item
+        __syncwarp();
+        const int64_t g = (static_cast<int64_t>(gz) * Y + gy) * X + gx;
+        if constexpr (ADJ) {
+            group_cell<SOLVER, T, U, F, true, NRM, false>(nbh[grp], C, W, W * W, j, gkap[g],
+                                                          ws.contrib + static_cast<size_t>(row) * 27, glds[grp]);
+        } else {
+            const float kv = group_cell<SOLVER, T, U, F, false, NRM, NBR>(nbh[grp], C, W, W * W, j, 0.0f, nullptr,
+                                                                         glds[grp], gx, gy, gz, X, Y, Z);
+            if (j == 0) kappa[g] = kv;
+        }
+        __syncwarp();                                        // nbh and glds reused by the next cell
     }
 }
 
@@ -818,56 +822,145 @@ __global__ __launch_bounds__(kThreads) void k_curv_gather_fallback(const float* 
     }
 }
 
-// Direct backward gather for the tiles whose sources all have a stored row:
-// the interface bitmasks, prefix counts and first rows of the 3x3x3 tiles
-// around the tile are staged in LDS; each target cell then adds, for q = 0..26
-// in order, entry q of the row of its source cell target - e_q when that cell
-// is an interface cell.  Two dependent global loads per tile, no fill levels.
-// A tile with a source beyond the store goes to the overflow list unwritten.
+// Direct backward gather for the tiles whose sources all have a stored row.
+// The interface bitmasks, prefix counts and first rows of the 3x3x3 tiles
+// around the tile are staged in LDS.  Each of the tile's cells tests its 27
+// sources (target - e_q) there; the cells with a source (the band along the
+// interface; the rest keep the scan's zero) are listed in cell order, and each
+// adds entry q of its sources' rows for q = 0..26 in order, all loads issued
+// before the first add.  A tile with a source beyond the store goes to the
+// overflow list unwritten.
+struct SourceMap {
+    unsigned smask[27][kWords];
+    unsigned spref[27][kWords];
+    unsigned sbase[27];
+};
+
+// row of source q of the cell (cx, cy, cz) of the centre tile; sets src when
+// that source is an interface cell
+__device__ __forceinline__ unsigned source_row(const SourceMap& m, int cx, int cy, int cz, int q, bool& src) {
+    const int sx = cx - q_dx(q), sy = cy - q_dy(q), sz = cz - q_dz(q);
+    const int rx = sx < 0 ? -1 : (sx >= TX ? 1 : 0);
+    const int ry = sy < 0 ? -1 : (sy >= TY ? 1 : 0);
+    const int rz = sz < 0 ? -1 : (sz >= TZ ? 1 : 0);
+    const int tq = (rz + 1) * 9 + (ry + 1) * 3 + (rx + 1);
+    const int l = ((sz - rz * TZ) * TY + (sy - ry * TY)) * TX + (sx - rx * TX);
+    const unsigned word = m.smask[tq][l >> 5];
+    const unsigned bit = 1u << (l & 31);
+    src = (word & bit) != 0u;
+    return m.sbase[tq] + m.spref[tq][l >> 5] + __popc(word & (bit - 1u));
+}
+
 __global__ __launch_bounds__(kThreads) void k_curv_gather_direct(float* __restrict__ gphi, Workspace ws, int X,
                                                                   int Y, int Z, int ntx, int nty, int ntz) {
-    __shared__ unsigned smask[27][kWords];
-    __shared__ unsigned spref[27][kWords];
-    __shared__ unsigned sbase[27];
+    constexpr int kStage = 27 * (2 * kWords + 1), kStageIt = (kStage + kThreads - 1) / kThreads;
+    __shared__ SourceMap m;
+    __shared__ unsigned short band[kTile];
+    __shared__ unsigned long long brow[TY * TZ];
+    __shared__ int bcount[TY * TZ];
     const int tid = threadIdx.x;
     const unsigned ntl = *static_cast<volatile unsigned*>(ws.counter + 1);
     for (unsigned it = blockIdx.x; it < ntl; it += gridDim.x) {
         const int tile = static_cast<int>(ws.tiles[it]);
+        if (ws.rows == 0u) {                                         // nothing stored: all recomputed
+            if (tid == 0) ws.over[atomicAdd(ws.counter + 2, 1u)] = static_cast<unsigned>(tile);
+            continue;
+        }
         const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
-        for (int i = tid; i < 27 * (2 * kWords + 1); i += kThreads) {
+        unsigned sv[kStageIt];
+#pragma unroll
+        for (int u = 0; u < kStageIt; ++u) {                          // every load before the first store
+            const int i = tid + u * kThreads;
             const int t = i / (2 * kWords + 1), w = i % (2 * kWords + 1);
             const int ax = tx + q_dx(t), ay = ty + q_dy(t), az = tz + q_dz(t);
-            const bool in = ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz;
+            const bool in = i < kStage && ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz;
             const int nt = (az * nty + ay) * ntx + ax;
-            if (w < kWords) smask[t][w] = in ? ws.mask[nt * kWords + w] : 0u;
-            else if (w < 2 * kWords) spref[t][w - kWords] = in ? ws.prefix[nt * kWords + (w - kWords)] : 0u;
-            else sbase[t] = in ? ws.cbase[nt] : 0u;
+            sv[u] = !in ? 0u : (w < kWords ? ws.mask[nt * kWords + w]
+                                           : (w < 2 * kWords ? ws.prefix[nt * kWords + (w - kWords)] : ws.cbase[nt]));
+        }
+#pragma unroll
+        for (int u = 0; u < kStageIt; ++u) {
+            const int i = tid + u * kThreads;
+            if (i < kStage) {
+                const int t = i / (2 * kWords + 1), w = i % (2 * kWords + 1);
+                if (w < kWords) m.smask[t][w] = sv[u];
+                else if (w < 2 * kWords) m.spref[t][w - kWords] = sv[u];
+                else m.sbase[t] = sv[u];
+            }
         }
         __syncthreads();
+        // the band: cells with an interface source within one cell.  Row
+        // (y, z) of a tile is one 64-bit word of its mask (bit = x); a target
+        // row's band is the OR over the 9 neighbouring rows of the source row
+        // dilated by one cell in x (bits carried in from the x-neighbour tiles)
+        if (tid < TY * TZ) {
+            const int cy = tid % TY, cz = tid / TY;
+            unsigned long long d = 0ull;
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const int sy = cy + dy, sz = cz + dz;
+                    const int ry = sy < 0 ? -1 : (sy >= TY ? 1 : 0), rz = sz < 0 ? -1 : (sz >= TZ ? 1 : 0);
+                    const int w = ((sz - rz * TZ) * TY + (sy - ry * TY)) * 2;
+                    const int tc = (rz + 1) * 9 + (ry + 1) * 3;                 // + (rx + 1)
+                    const unsigned long long lft = m.smask[tc][w] | (static_cast<unsigned long long>(m.smask[tc][w + 1]) << 32);
+                    const unsigned long long mid = m.smask[tc + 1][w] | (static_cast<unsigned long long>(m.smask[tc + 1][w + 1]) << 32);
+                    const unsigned long long rgt = m.smask[tc + 2][w] | (static_cast<unsigned long long>(m.smask[tc + 2][w + 1]) << 32);
+                    d |= mid | (mid << 1) | (mid >> 1) | (lft >> 63) | ((rgt & 1ull) << 63);
+                }
+            }
+            // cells past the lattice edge are not targets
+            const int gy = y0 + cy, gz = z0 + cz, nx = X - x0;
+            if (gy >= Y || gz >= Z) d = 0ull;
+            else if (nx < TX) d &= (1ull << nx) - 1ull;
+            brow[tid] = d;
+            bcount[tid] = __popcll(d);
+        }
+        __syncthreads();
+        // band cells listed in cell order (rows in order, x ascending)
+        if (tid < TY * TZ) {
+            int e = 0;
+            for (int r = 0; r < tid; ++r) e += bcount[r];
+            unsigned long long d = brow[tid];
+            while (d) {
+                const int x = __ffsll(static_cast<long long>(d)) - 1;
+                band[e++] = static_cast<unsigned short>(tid * TX + x);
+                d &= d - 1ull;
+            }
+        }
+        int nband = 0;
+#pragma unroll
+        for (int r = 0; r < TY * TZ; ++r) nband += bcount[r];
+        __syncthreads();
+        // band cells: rows of their sources, all loads of a group of 9 issued
+        // before its adds; sums kept until the tile is known to be complete
         float acc[kCellsPerThread];
         int miss = 0;
-#pragma unroll 1
-        for (int k = 0; k < kCellsPerThread; ++k) {
-            const int cl = tid + k * kThreads;
-            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-            float a = 0.0f;
 #pragma unroll
-            for (int q = 0; q < 27; ++q) {
-                // source cell target - e_q in tile-local coordinates, possibly
-                // one tile over in each direction
-                const int sx = cx - q_dx(q), sy = cy - q_dy(q), sz = cz - q_dz(q);
-                const int rx = sx < 0 ? -1 : (sx >= TX ? 1 : 0);
-                const int ry = sy < 0 ? -1 : (sy >= TY ? 1 : 0);
-                const int rz = sz < 0 ? -1 : (sz >= TZ ? 1 : 0);
-                const int tq = (rz + 1) * 9 + (ry + 1) * 3 + (rx + 1);
-                const int l = ((sz - rz * TZ) * TY + (sy - ry * TY)) * TX + (sx - rx * TX);
-                const unsigned word = smask[tq][l >> 5];
-                const unsigned bit = 1u << (l & 31);
-                if (word & bit) {
-                    const unsigned r = sbase[tq] + spref[tq][l >> 5] + __popc(word & (bit - 1u));
-                    if (r < ws.rows) a += ws.contrib[static_cast<size_t>(r) * 27 + q];
-                    else miss = 1;
+        for (int k = 0; k < kCellsPerThread; ++k) {
+            const int e = k * kThreads + tid;
+            float a = 0.0f;                                          // +0 + 0 stays +0: same bits as skipping
+            if (e < nband) {
+                const int cl = band[e];
+                const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
+#pragma unroll 1
+                for (int q0 = 0; q0 < 27; q0 += 9) {
+                    float v[9];
+                    unsigned has = 0u;
+#pragma unroll
+                    for (int qq = 0; qq < 9; ++qq) {
+                        bool src;
+                        const unsigned r = source_row(m, cx, cy, cz, q0 + qq, src);
+                        const bool stored = src && r < ws.rows;
+                        miss |= src && !stored;
+                        has |= stored ? (1u << qq) : 0u;
+                        // a non-source reads entry q of row 0 (rows >= 1 here) and is masked out
+                        v[qq] = ws.contrib[(stored ? r : 0u) * 27u + static_cast<unsigned>(q0 + qq)];
+                    }
+#pragma unroll
+                    for (int qq = 0; qq < 9; ++qq) a += (has >> qq) & 1u ? v[qq] : 0.0f;
                 }
             }
             acc[k] = a;
@@ -878,11 +971,14 @@ __global__ __launch_bounds__(kThreads) void k_curv_gather_direct(float* __restri
         }
 #pragma unroll
         for (int k = 0; k < kCellsPerThread; ++k) {
-            const int cl = tid + k * kThreads;
-            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-            const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
-            if (gx < X && gy < Y && gz < Z) gphi[(static_cast<int64_t>(gz) * Y + gy) * X + gx] = acc[k];
+            const int e = k * kThreads + tid;
+            if (e < nband) {
+                const int cl = band[e];
+                const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
+                gphi[(static_cast<int64_t>(z0 + cz) * Y + (y0 + cy)) * X + (x0 + cx)] = acc[k];
+            }
         }
+        __syncthreads();                                             // LDS reused by the next tile
     }
 }
 
@@ -928,7 +1024,7 @@ Workspace carve(void* base, size_t bytes, const Grid& g) {
     w.over = w.tiles + nt;
     w.contrib = reinterpret_cast<float*>(w.over + nt);
     const size_t rows = (bytes - fixed_bytes(g)) / kRowBytes;
-    w.rows = static_cast<unsigned>(rows < kRowCap ? rows : kRowCap);
+    w.rows = static_cast<unsigned>(rows < kRowLimit ? rows : kRowLimit);
     return w;
 }
 
@@ -985,13 +1081,14 @@ void launch_bwd_t(const float* phi, const float* gk, float* gp, Workspace ws, in
     const int nb = (g.ntiles + kPrefixBlock - 1) / kPrefixBlock;
     hipLaunchKernelGGL(k_curv_prefix_a, dim3(nb), dim3(kThreads), 0, st, ws, g.ntiles);
     hipLaunchKernelGGL(k_curv_prefix_b, dim3(nb), dim3(kThreads), 0, st, ws, g.ntiles);
+    hipLaunchKernelGGL(k_curv_dilate, dim3((g.ntiles + kThreads - 1) / kThreads), dim3(kThreads), 0, st, ws, g.ntx,
+                       g.nty, g.ntz, g.ntiles);
     if (ws.rows > 0) launch_items<SOLVER, T, U, F, true, NRM, false>(phi, gk, nullptr, ws, X, Y, Z, g, st);
-    hipLaunchKernelGGL(k_curv_dilate, dim3((g.ntiles + kThreads - 1) / kThreads), dim3(kThreads), 0, st, ws,
-                       g.ntx, g.nty, g.ntz, g.ntiles);
     hipLaunchKernelGGL(k_curv_gather_direct, dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0, st, gp, ws, X, Y, Z,
                        g.ntx, g.nty, g.ntz);
-    hipLaunchKernelGGL((k_curv_gather_fallback<SOLVER, T, U, F, NRM>), dim3(persistent_grid(g.ntiles)), dim3(kThreads),
-                       0, st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
+    // usually empty: a small grid keeps the launch cheap when nothing overflowed
+    hipLaunchKernelGGL((k_curv_gather_fallback<SOLVER, T, U, F, NRM>), dim3(g.ntiles < 512 ? g.ntiles : 512),
+                       dim3(kThreads), 0, st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
 }
 
 template <int SOLVER, class T, class U, class F>

@@ -235,7 +235,7 @@ PAPER_TABLE3 = {"sz": (12.8, 6.58e-8), "analytic": (19.0, 5.73e-8), "newton": (1
 
 
 def paper_isolated(P, torch, dev, log2n, L=256, reps=5):
-    """The paper's GPU benchmark method (Sec. 3.5): 2^log2n normals of its mix
+    """The paper's GPU benchmark method (Sec. 2.6.2): 2^log2n normals of its mix
     (one axis, one face diagonal, 1/8 random 2D, the rest random 3D), each
     thread sweeping L equally spaced V0 in series with a round trip through the
     forward volume; the blank run (d0 = V0 - 1/2) is subtracted and the time
@@ -272,7 +272,7 @@ def paper_isolated(P, torch, dev, log2n, L=256, reps=5):
 
 
 def sphere_rate(P, torch, V0, reps=10):
-    """Plane-sphere inversion (Sec. 4) on the same fill levels: HBM-streamed
+    """Plane-sphere inversion (Sec. 3) on the same fill levels: HBM-streamed
     V0 -> d0 (8 bytes per problem), outside the step (not a plane-cube solve)."""
     d = torch.empty_like(V0)
     stream = torch.cuda.current_stream(V0.device)

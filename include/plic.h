@@ -43,11 +43,11 @@ extern "C" {
 #define PLIC_EINVAL (-1)  /* null / misaligned / overlapping pointer, negative size, bad enum */
 #define PLIC_EHIP (-2)    /* the HIP runtime refused the launch (see plic_last_hip_error) */
 
-/* PLIC solvers: the four inversion methods compared in Sec. 3 of the paper */
+/* PLIC solvers: the four inversion methods of Sec. 2.3-2.5, compared in Sec. 2.6 */
 #define PLIC_ANALYTIC 0   /* the paper's analytic solution (Sec. 2.3, trigonometric root via atan) */
-#define PLIC_SZ 1         /* optimized Scardovelli-Zaleski solution (Sec. 3.1, root via asin)      */
-#define PLIC_NEWTON 2     /* Newton-Raphson on the cubic cases (Sec. 3.2), |step| <= 1e-6 (f32)    */
-#define PLIC_NESTED 3     /* nested intervals (bisection) on the cubic cases (Sec. 3.2)            */
+#define PLIC_SZ 1         /* optimized Scardovelli-Zaleski solution (Sec. 2.4, root via asin)      */
+#define PLIC_NEWTON 2     /* Newton-Raphson on the cubic cases (Sec. 2.5), |step| <= 1e-6 (f32)    */
+#define PLIC_NESTED 3     /* nested intervals (bisection) on the cubic cases (Sec. 2.5)            */
 
 /* arithmetic precision of the computation (independent of the storage type) */
 #define PLIC_FP32 0       /* all FP32                                                              */
@@ -126,7 +126,7 @@ int plic_offset_backward_f64(const double *nx, const double *ny, const double *n
 size_t plic_curvature_workspace_bytes(int64_t X, int64_t Y, int64_t Z);
 
 /*
- * plic_curvature_f32 — PLIC curvature of a VoF fill-level lattice (Sec. 5.1-5.2,
+ * plic_curvature_f32 — PLIC curvature of a VoF fill-level lattice (Sec. 4.1-5.2,
  * Appendix B): for every interface cell (0 < phi < 1) away from the outer
  * one-cell layer: Parker-Youngs normal from the 3x3x3 fill levels, local frame
  * from the fixed vector r, PLIC points of the interface neighbours (centre
@@ -168,7 +168,7 @@ int plic_curvature_backward_f32(const float *phi, int64_t X, int64_t Y, int64_t 
 
 /*
  * plic_sphere_offset_f32 / _f64 — the PLIC problem for a spherical cell of
- * unit volume (Sec. 4): V0 -> d0, the signed distance of the plane from the
+ * unit volume (Sec. 3): V0 -> d0, the signed distance of the plane from the
  * sphere's centre with volume V0 on the side n.x <= d0 (any normal: the
  * sphere is isotropic), d0 in [-r, r], r = (3 / (4 pi))^(1/3).  The paper's
  * closed form d0 = (6/pi)^(1/3) sin(pi/6 - atan2(2 sqrt(V0 - V0^2), 2 V0 - 1)/3).
@@ -191,10 +191,10 @@ int plic_sphere_volume_f64(const double *d0, double *V0, int64_t count, void *st
  *   normal            : PLIC_NORMAL_PY (as plic_curvature_f32) or PLIC_NORMAL_CM
  *                       (App. B.1; about 4 degrees of normal error against 1).
  *   neighbour_normals : 0 = every neighbour's PLIC plane uses the centre
- *                       normal (Sec. 5.2, as plic_curvature_f32); 1 = each
+ *                       normal (Sec. 4.2, as plic_curvature_f32); 1 = each
  *                       interface neighbour's plane uses that neighbour's own
  *                       normal from its 3x3x3 fill levels (the variant of
- *                       Sec. 5.2 and Sec. 5.3), its point being the foot of
+ *                       Sec. 4.2 and Sec. 4.3), its point being the foot of
  *                       its plane, e + d0(phi_q, n_q) n_q - d0(phi_0, n) n, in
  *                       the centre frame.  A neighbour on the outer lattice
  *                       layer, or with a vanishing gradient, keeps the centre

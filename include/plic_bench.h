@@ -1,6 +1,6 @@
 /*
  * plic_bench.h — compute-isolated timing of the PLIC inversion in the manner
- * of the paper's GPU benchmark (Lehmann & Gekle, arXiv 2006.12838, Sec. 3.5
+ * of the paper's GPU benchmark (Lehmann & Gekle, arXiv 2006.12838, Sec. 2.6.2
  * and Table 3): every thread keeps one normal and sweeps L equally spaced
  * fill levels V0 = j / (L - 1), j = 0 .. L-1 (edge cases included) in series,
  * inverting each and measuring the round trip E = |V(n, d0(n, V0)) - V0|

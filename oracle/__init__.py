@@ -201,7 +201,7 @@ def paraboloid_kappa(coef):
 
 
 def sphere_volume(d0):
-    """volume of the unit-volume sphere below the plane at distance d0 (Sec. 4)"""
+    """volume of the unit-volume sphere below the plane at distance d0 (Sec. 3)"""
     d = _d(d0)
     out = np.empty_like(d)
     _load().orc_sphere_volume(_p(d), _p(out), d.size)

@@ -20,13 +20,13 @@
  *  - gradient of d0: implicit differentiation of V0(n, d0) = volume below the
  *    plane; dV0/dd0 = A/|n| and dV0/dn = -(A/|n|) * centroid, with A and the
  *    centroid of the plane-cube intersection polygon built explicitly;
- *  - plane-sphere intersection (Sec. 4): the spherical-cap volume of the
+ *  - plane-sphere intersection (Sec. 3): the spherical-cap volume of the
  *    unit-volume sphere and its inverse by bisection;
- *  - curvature: Sec. 5.2 (PLIC point neighbourhood, coordinate transform with
+ *  - curvature: Sec. 4.2 (PLIC point neighbourhood, coordinate transform with
  *    the fixed vector r), App. B.1 (Parker-Youngs normal, or the centre-of-mass
  *    normal as an option), B.2 (paraboloid mean curvature at the origin), B.3
  *    (least-squares normal equations, reduced dimension when fewer than 5
- *    points); as an option, the variant of Sec. 5.2 and Sec. 5.3 in which each
+ *    points); as an option, the variant of Sec. 4.2 and Sec. 4.3 in which each
  *    interface neighbour's PLIC plane uses that neighbour's own normal.
  *
  * Readings where the paper is silent or ambiguous (each also used by the GPU
@@ -287,7 +287,7 @@ void orc_offset_grad(const double *nx, const double *ny, const double *nz, const
 }
 
 /* ------------------------------------------------------------------------- */
-/* plane-sphere intersection (Sec. 4)                                         */
+/* plane-sphere intersection (Sec. 3)                                         */
 /* ------------------------------------------------------------------------- */
 
 /* radius of the unit-volume sphere */
@@ -340,7 +340,7 @@ void orc_sphere_offset(const double *V0, double *d0, int64_t count)
 /* curvature                                                                  */
 /* ------------------------------------------------------------------------- */
 
-/* the fixed auxiliary vector r of Sec. 5.2 */
+/* the fixed auxiliary vector r of Sec. 4.2 */
 static const double R_AUX[3] = {0.56270900, 0.32704452, 0.75921047};
 
 /* mean curvature of z = A x^2 + B y^2 + C x y + H x + I y at x = y = 0
@@ -429,7 +429,7 @@ static double normal_of(const double p27[27], int kind, double n[3])
     return gn;
 }
 
-/* One interface cell (Sec. 5.2 and App. B).  nbrn == NULL: every neighbour's
+/* One interface cell (Sec. 4.2 and App. B).  nbrn == NULL: every neighbour's
  * PLIC plane uses the centre normal n, the point of neighbour i is
  * (e_i.b_x, e_i.b_y, e_i.n + d0(phi_i, n) - d0(phi_0, n)).  Otherwise nbrn[q]
  * is neighbour q's own normal n_q and its point is the foot of its own plane,
@@ -450,7 +450,7 @@ static double cell_core(const double phi[27], const unsigned char mask[27], cons
     gn = normal_of(phi, kind, n);
     if (!(gn >= 1e-12)) { if (normal) normal[0] = normal[1] = normal[2] = 0; return 0.0; }
     if (normal) { normal[0] = n[0]; normal[1] = n[1]; normal[2] = n[2]; }
-    /* local frame (Sec. 5.2): b_z = n, b_y = n x r / |n x r|, b_x = b_y x b_z */
+    /* local frame (Sec. 4.2): b_z = n, b_y = n x r / |n x r|, b_x = b_y x b_z */
     r[0] = raux[0]; r[1] = raux[1]; r[2] = raux[2];
     cross3(n, r, u);
     un = sqrt(dot3(u, u));

@@ -45,7 +45,7 @@ void orc_offset_grad(const double *nx, const double *ny, const double *nz, const
                      double *d0, double *dd_dV0, double *dd_dnx, double *dd_dny,
                      double *dd_dnz, int64_t count);
 
-/* ---- plane-sphere intersection (Sec. 4): sphere of unit volume, radius
+/* ---- plane-sphere intersection (Sec. 3): sphere of unit volume, radius
  * r = (3 / (4 pi))^(1/3); d0 = signed distance of the plane from the centre,
  * V0 = volume on the side n.x <= d0 (any unit normal: the sphere is isotropic) */
 double orc_sphere_volume1(double d0);
@@ -53,7 +53,7 @@ double orc_sphere_offset1(double V0);
 void orc_sphere_volume(const double *d0, double *V0, int64_t count);
 void orc_sphere_offset(const double *V0, double *d0, int64_t count);
 
-/* ---- curvature (Sec. 5 and Appendix B) ----
+/* ---- curvature (Sec. 4 and Appendix B) ----
  * Neighbourhood index q = (dz+1)*9 + (dy+1)*3 + (dx+1), centre q = 13.
  * mask[q] != 0 marks interface neighbours (0 < phi < 1) used as fit points.
  * info (may be NULL) receives: info[0] = number of fit points,
@@ -95,7 +95,7 @@ int64_t orc_curvature_grad(const float *phi, int64_t X, int64_t Y, int64_t Z,
 /* ---- curvature options ----
  * kind: 0 = Parker-Youngs normal (weights 4/2/1), 1 = centre-of-mass normal
  * (equal weights), App. B.1.  nbr: 0 = every neighbour's PLIC plane uses the
- * centre normal (Sec. 5.2), 1 = each interface neighbour uses its own normal
+ * centre normal (Sec. 4.2), 1 = each interface neighbour uses its own normal
  * (needs the 5^3 neighbourhood; neighbours on the outer lattice layer keep the
  * centre normal). */
 double orc_curv_cell_k(const double phi[27], const unsigned char mask[27], int kind, double info[3],

@@ -285,7 +285,7 @@ def _sphere(name, src, dst, dtype):
 
 
 def plic_sphere_offset_f32(V0, d0):
-    """plane-sphere PLIC (Sec. 4): V0 -> d0 for the unit-volume sphere"""
+    """plane-sphere PLIC (Sec. 3): V0 -> d0 for the unit-volume sphere"""
     return _sphere("plic_sphere_offset_f32", V0, d0, torch.float32)
 
 

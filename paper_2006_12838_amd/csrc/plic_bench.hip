@@ -1,4 +1,4 @@
-// Compute-isolated PLIC timing after the paper's GPU benchmark (Sec. 3.5,
+// Compute-isolated PLIC timing after the paper's GPU benchmark (Sec. 2.6.2,
 // Table 3): one normal per thread, L fill levels in series, round trip
 // through the forward volume; the blank run swaps the inversion for
 // d0 = V0 - 1/2.  One problem per thread, as in the paper's kernels.

@@ -1,4 +1,4 @@
-// PLIC curvature of a VoF fill-level lattice on gfx950 (Sec. 5.1-5.2 and
+// PLIC curvature of a VoF fill-level lattice on gfx950 (Sec. 4.1-5.2 and
 // Appendix B of Lehmann & Gekle, arXiv 2006.12838), forward and backward.
 //
 // Layout: phi, kappa, grad_kappa, grad_phi are X*Y*Z floats, x fastest.  The
@@ -44,7 +44,7 @@ constexpr int kGroup = 32;                    // lanes per interface cell
 constexpr int kGroups = kThreads / kGroup;    // 8 cells in flight per workgroup
 constexpr int kPersistentBlocks = 2048;
 
-// fixed auxiliary vector r of Sec. 5.2 (non-collinear with the normal)
+// fixed auxiliary vector r of Sec. 4.2 (non-collinear with the normal)
 constexpr double kR0 = 0.56270900, kR1 = 0.32704452, kR2 = 0.75921047;
 
 // neighbour q = (dz+1)*9 + (dy+1)*3 + (dx+1); centre q = 13
@@ -214,7 +214,7 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
     }
     const T ign = mt::rcp(mt::sqrt(gn2));
     const T n0 = -gx * ign, n1 = -gy * ign, n2 = -gz * ign;
-    // local frame (Sec. 5.2): b_z = n, b_y = n x r / |n x r|, b_x = b_y x b_z
+    // local frame (Sec. 4.2): b_z = n, b_y = n x r / |n x r|, b_x = b_y x b_z
     T r0 = T(kR0), r1 = T(kR1), r2 = T(kR2);
     T u0 = n1 * r2 - n2 * r1, u1 = n2 * r0 - n0 * r2, u2 = n0 * r1 - n1 * r0;
     T un2 = u0 * u0 + u1 * u1 + u2 * u2;
@@ -227,7 +227,7 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
     const T by0 = u0 * iun, by1 = u1 * iun, by2 = u2 * iun;
     const T bx0 = by1 * n2 - by2 * n1, bx1 = by2 * n0 - by0 * n2, bx2 = by0 * n1 - by1 * n0;
     // PLIC offsets: neighbour lanes and the centre lane in parallel, with the
-    // centre normal (Sec. 5.2) or, in the neighbour-normal variant, each
+    // centre normal (Sec. 4.2) or, in the neighbour-normal variant, each
     // neighbour with its own normal (centre normal on the outer lattice layer
     // or for a vanishing gradient)
     T m0 = n0, m1 = n1, m2 = n2;
@@ -250,7 +250,7 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
     if (centre) L.res[24] = F(D);
     __syncwarp();
     const T D0 = T(L.res[24]);
-    // this lane's point (coordinate transformation of Sec. 5.2) and its row of
+    // this lane's point (coordinate transformation of Sec. 4.2) and its row of
     // the normal equations: Q Q^T (lower triangle) and z Q
     F x = F(0), y = F(0), z = F(0);
     if (iface) {

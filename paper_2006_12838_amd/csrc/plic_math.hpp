@@ -253,7 +253,7 @@ __device__ __forceinline__ T cubic_analytic(const Open<T>& o) {
 }
 
 // ---------------------------------------------------------------------------
-// Optimized Scardovelli-Zaleski solution (Sec. 3.1), on the L1-normalized
+// Optimized Scardovelli-Zaleski solution (Sec. 2.4), on the L1-normalized
 // normal (n1 + n2 + n3 = 1, so d in [0, 1/2]).  Cases (5), (2), (1) first;
 // the boundary between (3) and (4) is decided a priori through the volume v3
 // at d = n3; one root d = c - 2 t sin(asin(arg)/3) serves both.  The printed
@@ -350,7 +350,7 @@ __device__ __forceinline__ Cubic<U> cubic_setup(const Open<T>& o) {
 }
 
 // ---------------------------------------------------------------------------
-// Newton-Raphson (Sec. 3.2).  Cases (5) and (2) in closed form; case (1) and
+// Newton-Raphson (Sec. 2.5).  Cases (5) and (2) in closed form; case (1) and
 // the cubic cases by Newton on the shifted cubic above, starting at the middle
 // of the case's bracket (n1/2 for case (1), as printed).  The printed fixed
 // step counts (7/4/4) do not converge for small V, so each iterate is
@@ -398,7 +398,7 @@ __device__ __forceinline__ T cubic_newton(const Open<T>& o) {
 }
 
 // ---------------------------------------------------------------------------
-// Nested intervals (Sec. 3.2).  Cases (5), (2) closed form, case (1) by cube
+// Nested intervals (Sec. 2.5).  Cases (5), (2) closed form, case (1) by cube
 // root, as printed.  Cases (3) and (4) by bisection of the shifted cubic on
 // the case's own bracket ([n2, min(n3, n1 + n2)] or [n3, S/2] in d; the case
 // is decided by one evaluation at d = n3, where the printed version bisects
@@ -584,7 +584,7 @@ __device__ __forceinline__ T offset_grad_from_d0(T nx, T ny, T nz, T V0, T d0, T
 }
 
 // ---------------------------------------------------------------------------
-// Plane-sphere intersection (Sec. 4): a sphere of unit volume, radius
+// Plane-sphere intersection (Sec. 3): a sphere of unit volume, radius
 // r = (3 / (4 pi))^(1/3); d0 is the signed distance of the plane from the
 // centre and V0 the volume on the side n.x <= d0 (the normal does not matter).
 // Forward: the spherical cap (pi/3) (r + d0)^2 (2r - d0), 0 / 1 beyond +-r.

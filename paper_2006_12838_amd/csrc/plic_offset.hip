@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_volume(const S* __restrict__ nx, con
     }
 }
 
-// plane-sphere intersection (Sec. 4): one input and one output array;
+// plane-sphere intersection (Sec. 3): one input and one output array;
 // OP 0 inverts (V0 -> d0), OP 1 evaluates the cap volume (d0 -> V0)
 template <int OP, class S, class T, int VEC>
 __global__ __launch_bounds__(kBlock) void k_sphere(const S* in, S* out, int64_t count) {

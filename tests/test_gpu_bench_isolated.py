@@ -1,5 +1,5 @@
 """The compute-isolated benchmark kernel (the paper's GPU test method,
-Sec. 3.5): its round-trip errors are at FP32 rounding level, bounded like the
+Sec. 2.6.2): its round-trip errors are at FP32 rounding level, bounded like the
 batched round trip, and average to what the library's batched inversion and
 forward volume give on the same problems.  (Inlined in one kernel the
 compiler may contract the arithmetic differently, so single errors, each

@@ -125,7 +125,7 @@ def test_round_trip_complement_determinism(P, small, solver):
     P.plic_offset_f32(tx, ty, tz, tv, d1, solver, "fp32")
     assert torch.equal(d0, d1)                               # bitwise deterministic
     Vb = torch.empty_like(tv)
-    P.plic_volume_f32(tx, ty, tz, d0, Vb, "fp64")            # E_i of Sec. 3.5
+    P.plic_volume_f32(tx, ty, tz, d0, Vb, "fp64")            # E_i of Sec. 2.6.2
     E = (Vb.double() - tv.double()).abs()
     print(f"{solver}: round trip E_avg {E.mean().item():.3e} E_max {E.max().item():.3e}")
     assert E.max().item() <= 2e-6

@@ -1,4 +1,4 @@
-"""GPU parity of the plane-sphere intersection (Sec. 4) against the FP64
+"""GPU parity of the plane-sphere intersection (Sec. 3) against the FP64
 oracle: the closed-form inverse and the cap volume, FP32 and FP64, with edge
 values, NaN, in-place calls and unaligned, ragged sizes."""
 import numpy as np

@@ -1,9 +1,9 @@
-"""Pins for the oracle's PLIC curvature (Sec. 5.2 and Appendix B).
+"""Pins for the oracle's PLIC curvature (Sec. 4.2 and Appendix B).
 
 Checked against: exact recovery of synthetic paraboloids by the least-squares
 fit (B.3), the textbook mean curvature of a Monge patch from its fundamental
 forms (B.2), planes (zero curvature), the sphere (1/R) and the cylinder (1/(2R))
-of the paper's validation (Sec. 5.3), rotation invariance of the fit in the
+of the paper's validation (Sec. 4.3), rotation invariance of the fit in the
 tangent plane (independence of the auxiliary vector r), lattice symmetries, the
 fluid/gas complement, and the Parker-Youngs normal error (B.1).
 """
@@ -114,7 +114,7 @@ def test_sphere_mean_curvature(orc, sphere20):
     ratio = k[sel].mean() * 20.0
     assert 0.97 < ratio < 1.03          # kappa -> 1/R, positive for a drop
     E = np.abs(k[sel] - 1 / 20.0).sum() / (sel.sum() / 20.0)
-    assert E < 0.3                      # L1 error E(kappa) of Sec. 5.3 (no relaxation)
+    assert E < 0.3                      # L1 error E(kappa) of Sec. 4.3 (no relaxation)
 
 
 def test_sphere_normal_is_radial_within_a_degree(orc, sphere20):

@@ -1,5 +1,5 @@
 """Oracle pins for the curvature options: the centre-of-mass normal (App. B.1)
-and the neighbour-normal variant (Sec. 5.2, Sec. 5.3).
+and the neighbour-normal variant (Sec. 4.2, Sec. 4.3).
 
 * Both normal estimators are exact for a linear fill-level field: the
   weighted sum of e_i (g . e_i) is a multiple of g by the lattice symmetry.

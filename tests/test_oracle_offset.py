@@ -4,7 +4,7 @@ Checked against the paper's closed forms evaluated at 50 digits
 (tests/golden/plic_closed_forms.txt, written by make_plic_closed_forms.py from
 Sec. 2.1 and 2.3), the 1D/2D/diagonal special cases, exact rational
 bisection, the round trip V0(n, d0(n, V0)) = V0 (the paper's error E_i of
-Sec. 3.5), the complement symmetry and the range endpoints.
+Sec. 2.6.2), the complement symmetry and the range endpoints.
 """
 from fractions import Fraction
 import math
@@ -133,5 +133,5 @@ def test_offset_matches_exact_rational_bisection(orc):
 @pytest.mark.parametrize("V0", [0.0, 1.0])
 def test_offset_kawano_edge_is_finite(orc, V0):
     """The SZ translation of the paper returns NaN for n = (1,0,0), V0 in {0,1}
-    (Sec. 3.5); the definition gives -+1/2."""
+    (Sec. 2.6.2); the definition gives -+1/2."""
     assert orc.offset1(1.0, 0.0, 0.0, V0) == (V0 - 0.5)

@@ -1,4 +1,4 @@
-"""Oracle pins for the plane-sphere intersection (Sec. 4): the cap volume of
+"""Oracle pins for the plane-sphere intersection (Sec. 3): the cap volume of
 the unit-volume sphere against quadrature of its cross-sections and a voxel
 count, and the bisection inverse against the volume, its symmetries and its
 end points."""

@@ -57,6 +57,7 @@ def _load():
     lib.orc_volume.argtypes = [_D] * 5 + [c_i64]
     lib.orc_offset.argtypes = [_D] * 5 + [c_i64]
     lib.orc_offset_grad.argtypes = [_D] * 9 + [c_i64]
+    lib.orc_offset_kawano.argtypes = [_D] * 5 + [ctypes.POINTER(ctypes.c_int32), _D, c_i64]
     lib.orc_curv_cell.restype = c_d
     lib.orc_curv_cell.argtypes = [_D, _U8, _D]
     lib.orc_curv_cell_full.restype = c_d
@@ -120,6 +121,19 @@ def offset(nx, ny, nz, V0):
     out = np.empty_like(nx)
     lib.orc_offset(_p(nx), _p(ny), _p(nz), _p(V0), _p(out), nx.size)
     return out
+
+
+def offset_kawano(nx, ny, nz, V0):
+    """(d0, case, acos argument) of the SZ solution as implemented by Kawano
+    (Sec. 2.4), elementwise in float64: NaN for an axis normal at V0 in {0, 1}
+    (Sec. 2.6); case 1..5; the argument of acos in the cubic cases, else NaN."""
+    lib = _load()
+    nx, ny, nz, V0 = (_d(a).ravel() for a in np.broadcast_arrays(nx, ny, nz, V0))
+    out, arg = np.empty_like(nx), np.empty_like(nx)
+    kase = np.empty(nx.size, dtype=np.int32)
+    lib.orc_offset_kawano(_p(nx), _p(ny), _p(nz), _p(V0), _p(out), kase.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                          _p(arg), nx.size)
+    return out, kase, arg
 
 
 def offset_grad(nx, ny, nz, V0):

@@ -20,6 +20,9 @@
  *  - gradient of d0: implicit differentiation of V0(n, d0) = volume below the
  *    plane; dV0/dd0 = A/|n| and dV0/dn = -(A/|n|) * centroid, with A and the
  *    centroid of the plane-cube intersection polygon built explicitly;
+ *  - the SZ solution in the form of Kawano's implementation (Sec. 2.4), the
+ *    unoptimized variant of the paper's comparison, with its own case order
+ *    and its NaN in the axis edge case (Sec. 2.6);
  *  - plane-sphere intersection (Sec. 3): the spherical-cap volume of the
  *    unit-volume sphere and its inverse by bisection;
  *  - curvature: Sec. 4.2 (PLIC point neighbourhood, coordinate transform with
@@ -271,6 +274,108 @@ void orc_offset(const double *nx, const double *ny, const double *nz, const doub
     int64_t i;
 #pragma omp parallel for schedule(static)
     for (i = 0; i < count; ++i) d0[i] = orc_offset1(nx[i], ny[i], nz[i], V0[i]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Scardovelli-Zaleski solution as implemented by Kawano (Sec. 2.4)           */
+/* ------------------------------------------------------------------------- */
+
+/* The SZ solution in the form the paper reproduces from Kawano's Fortran code,
+ * kept with that code's characteristic choices, in FP64:
+ *  - the normal is L1-normalized, m_k = |n_k| / l with l = |nx| + |ny| + |nz|,
+ *    and the plane offset is alpha in [0, 1] from the cube corner, so the
+ *    cube-centred offset is l (1/2 - alpha) with the sign of V0 - 1/2;
+ *  - the reduced volume is the printed w = 1/2 - |V0 - 1/2|;
+ *  - m1 = min m_k, m3 = max m_k and the middle one is taken as 1 - m1 - m3
+ *    (not below 0);
+ *  - the thresholds are the volumes at alpha = m1 (V1, with a tiny 1e-25 added
+ *    to its denominator), the case-(2) end V1 + (m2 - m1) / (2 m3), and V3, the
+ *    volume at alpha = m3 when m3 < m1 + m2 (where case (4) exists), else at
+ *    alpha = m1 + m2 (the start of case (5));
+ *  - the cases are tested in the order (1), (2), then (5), (3), (4).  Case (5)
+ *    records its alpha, and alpha == 0 means "not settled yet": a case-(5)
+ *    root of exactly 0 (an axis normal at V0 in {0, 1}) falls through to the
+ *    cubic of case (4), whose trigonometric root then takes the square root of
+ *    a negative number.  This is the NaN the paper reports for this variant
+ *    (Sec. 2.6.1 and 2.6.2, the edge case n = (1, 0, 0), V0 in {0, 1});
+ *  - cases (3) and (4) solve the monic cubic alpha^3 + a2 alpha^2 + a1 alpha
+ *    + a0 = 0 of the case's volume (inclusion-exclusion of the cut corners:
+ *    (3) removes the corners at m1 and m2, (4) all three, where m1 + m2 + m3
+ *    = 1 simplifies the coefficients), by the trigonometric (Viete) form of
+ *    its third real root: with p = a1 - a2^2 / 3 and sp = sqrt(-p / 3),
+ *    alpha = 2 sp cos(4 pi / 3 + acos(q0 / sp^3) / 3) - a2 / 3,
+ *    q0 = (a1 a2 - 3 a0) / 6 - a2^3 / 27.
+ * V0 is clamped to [0, 1] first (as for every solver here); NaN inputs and
+ * n = 0 give NaN.  *kase receives the case taken (1..5, 0 for NaN inputs) and
+ * *acos_arg the argument q0 / sp^3 of the cubic cases (NaN otherwise). */
+double orc_offset_kawano1(double nx, double ny, double nz, double V0, int *kase, double *acos_arg)
+{
+    double l, m[3], m1, m2, m3, m12, w, V1, w6, V3, alpha = 0.0;
+    int k = 0;
+    *kase = 0;
+    *acos_arg = NAN;
+    if (isnan(nx) || isnan(ny) || isnan(nz) || isnan(V0)) return NAN;
+    if (V0 < 0.0) V0 = 0.0;
+    if (V0 > 1.0) V0 = 1.0;
+    l = fabs(nx) + fabs(ny) + fabs(nz);
+    if (!(l > 0.0)) return NAN;
+    m[0] = fabs(nx) / l; m[1] = fabs(ny) / l; m[2] = fabs(nz) / l;
+    w = 0.5 - fabs(V0 - 0.5);
+    m1 = fmin(fmin(m[0], m[1]), m[2]);
+    m3 = fmax(fmax(m[0], m[1]), m[2]);
+    m2 = fmax(1.0 - (m1 + m3), 0.0);
+    m12 = m1 + m2;
+    V1 = m1 * m1 / (6.0 * m2 * m3 + 1e-25);
+    w6 = 6.0 * m1 * m2 * m3 * w;
+    if (w < V1) {
+        k = 1;
+        alpha = cbrt(w6);
+    } else if (w < V1 + 0.5 * (m2 - m1) / m3) {
+        k = 2;
+        alpha = 0.5 * (m1 + sqrt(m1 * m1 + 8.0 * m2 * m3 * (w - V1)));
+    } else {
+        if (m3 < m12) {
+            /* volume at alpha = m3: [m3^3 - (m3 - m1)^3 - (m3 - m2)^3] / (6 m1 m2 m3), expanded */
+            V3 = (m3 * m3 * (3.0 * m12 - m3) + m1 * m1 * (m1 - 3.0 * m3) + m2 * m2 * (m2 - 3.0 * m3))
+                 / (6.0 * m1 * m2 * m3);
+        } else {
+            V3 = 0.5 * m12 / m3;
+            if (V3 <= w) { k = 5; alpha = m3 * w + 0.5 * m12; }
+        }
+        if (alpha == 0.0) {
+            double a2, a1, a0, q0, sp, arg;
+            if (w < V3) {
+                k = 3;
+                a2 = -3.0 * m12;
+                a1 = 3.0 * (m1 * m1 + m2 * m2);
+                a0 = w6 - m1 * m1 * m1 - m2 * m2 * m2;
+            } else {
+                k = 4;
+                a2 = -1.5;
+                a1 = 1.5 * (m1 * m1 + m2 * m2 + m3 * m3);
+                a0 = 0.5 * (w6 - m1 * m1 * m1 - m2 * m2 * m2 - m3 * m3 * m3);
+            }
+            q0 = (a1 * a2 - 3.0 * a0) / 6.0 - a2 * a2 * a2 / 27.0;
+            sp = sqrt(a2 * a2 / 9.0 - a1 / 3.0);
+            arg = q0 / (sp * sp * sp);
+            *acos_arg = arg;
+            alpha = 2.0 * sp * cos(4.0 * 3.14159265358979323846 / 3.0 + acos(arg) / 3.0) - a2 / 3.0;
+        }
+    }
+    *kase = k;
+    return l * copysign(0.5 - alpha, V0 - 0.5);
+}
+
+void orc_offset_kawano(const double *nx, const double *ny, const double *nz, const double *V0,
+                       double *d0, int32_t *kase, double *acos_arg, int64_t count)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < count; ++i) {
+        int k;
+        d0[i] = orc_offset_kawano1(nx[i], ny[i], nz[i], V0[i], &k, &acos_arg[i]);
+        kase[i] = k;
+    }
 }
 
 void orc_offset_grad(const double *nx, const double *ny, const double *nz, const double *V0,

@@ -45,6 +45,15 @@ void orc_offset_grad(const double *nx, const double *ny, const double *nz, const
                      double *d0, double *dd_dV0, double *dd_dnx, double *dd_dny,
                      double *dd_dnz, int64_t count);
 
+/* Scardovelli-Zaleski solution in the form of Kawano's implementation (Sec.
+ * 2.4), with that code's case order, reduced volume and "alpha == 0 means
+ * unsettled" rule (NaN for an axis normal at V0 in {0, 1}, Sec. 2.6).  kase:
+ * 1..5 (0 for NaN inputs); acos_arg: the trigonometric root's argument in the
+ * cubic cases (3), (4), NaN otherwise. */
+double orc_offset_kawano1(double nx, double ny, double nz, double V0, int *kase, double *acos_arg);
+void orc_offset_kawano(const double *nx, const double *ny, const double *nz, const double *V0,
+                       double *d0, int32_t *kase, double *acos_arg, int64_t count);
+
 /* ---- plane-sphere intersection (Sec. 3): sphere of unit volume, radius
  * r = (3 / (4 pi))^(1/3); d0 = signed distance of the plane from the centre,
  * V0 = volume on the side n.x <= d0 (any unit normal: the sphere is isotropic) */

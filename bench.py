@@ -230,8 +230,10 @@ def write_issue_profile(sq_csv, log2n, lattice, out=ISSUE_PROFILE):
 
 
 # Table 3 of the paper (Nvidia Titan Xp, OpenCL, FP32): ps per isolated PLIC and E_avg
+# Table 3 (Titan Xp): ps per PLIC and E_avg; None where the paper prints NaN
 PAPER_TABLE3 = {"sz": (12.8, 6.58e-8), "analytic": (19.0, 5.73e-8), "newton": (19.2, 5.47e-8),
-                "nested": (106.4, 2.86e-8)}
+                "nested": (106.4, 2.86e-8), "sz_kawano": (16.0, None)}
+ISOLATED_SOLVERS = SOLVERS + ("sz_kawano",)
 
 
 def paper_isolated(P, torch, dev, log2n, L=256, reps=5):
@@ -261,14 +263,41 @@ def paper_isolated(P, torch, dev, log2n, L=256, reps=5):
 
     blank_ms = timed(lambda: P.plic_bench_isolated_f32(*t, err, L, "sz", True))
     out = {"normals": n, "L": L, "reps": reps, "blank_ms": round(blank_ms, 4), "solvers": {}}
-    for s in SOLVERS:
+    for s in ISOLATED_SOLVERS:
         ms = timed(lambda: P.plic_bench_isolated_f32(*t, err, L, s, False))
-        e_avg = err.double().sum().item() / (n * L)
+        e = err.double()
+        fin = torch.isfinite(e)
+        nan_normals = int((~fin).sum().item())
+        e_fin = e[fin].sum().item() / (int(fin.sum().item()) * L)
         ps = (ms - blank_ms) * 1e9 / (n * L)
-        out["solvers"][s] = {"ms": round(ms, 4), "ps_per_plic": round(ps, 3), "E_avg": e_avg,
+        # E_avg over every evaluation is NaN when any is (JSON null), as the paper prints for Kawano's form
+        out["solvers"][s] = {"ms": round(ms, 4), "ps_per_plic": round(ps, 3),
+                             "E_avg": e_fin if nan_normals == 0 else None, "nan_normals": nan_normals,
+                             "E_avg_finite_normals": e_fin,
                              "paper_titan_xp_ps": PAPER_TABLE3[s][0], "paper_E_avg": PAPER_TABLE3[s][1]}
         print(f"bench: isolated {s}: {ps:.2f} ps/PLIC", file=sys.stderr, flush=True)
     return out
+
+
+def kawano_rate(P, torch, tn, reps=10):
+    """Kawano's form of the SZ solution (Sec. 2.4), FP32, on the step's 2^26
+    problems: HBM-streamed like the four solvers (20 bytes per problem), timed
+    outside the step (a comparison variant, not one of the paper's solvers)."""
+    d = torch.empty_like(tn[3])
+    stream = torch.cuda.current_stream(d.device)
+    P.plic_offset_f32(*tn[:4], d, "sz_kawano", "fp32")
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        P.plic_offset_f32(*tn[:4], d, "sz_kawano", "fp32")
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    n = d.numel()
+    gbs = 20 * n / (ms * 1e-3) / 1e9
+    return {"ms": round(ms, 4), "rate": n / (ms * 1e-3), "unit": "solves/s", "GBps": gbs,
+            "hbm_frac": gbs / HBM_PEAK_GBS}
 
 
 def sphere_rate(P, torch, V0, reps=10):
@@ -449,6 +478,7 @@ def main():
     }
     if not args.only:
         out["sphere_offset"] = sphere_rate(P, torch, tn[3])
+        out["offset_sz_kawano"] = kawano_rate(P, torch, tn)
     if not args.no_paper_isolated and not args.only:
         out["paper_isolated"] = paper_isolated(P, torch, dev, args.log2n)
     if not args.no_cpu_baseline:

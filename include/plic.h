@@ -48,6 +48,16 @@ extern "C" {
 #define PLIC_SZ 1         /* optimized Scardovelli-Zaleski solution (Sec. 2.4, root via asin)      */
 #define PLIC_NEWTON 2     /* Newton-Raphson on the cubic cases (Sec. 2.5), |step| <= 1e-6 (f32)    */
 #define PLIC_NESTED 3     /* nested intervals (bisection) on the cubic cases (Sec. 2.5)            */
+/* The SZ solution as implemented by Kawano (Sec. 2.4): the unoptimized variant
+ * of the comparison, root via acos / cos, with that code's case order and
+ * reduced volume.  It returns NaN for an axis normal at V0 in {0, 1}, as the
+ * paper reports (Sec. 2.6), and is not held to the accuracy bound of the
+ * offset entry points: its cubic coefficients cancel for a small m1, so in
+ * FP32 it loses up to about 5e-5 on random unit normals and far more (and
+ * gives NaN) near the axes and face diagonals; in FP64 it stays within
+ * 1e-13 of the exact root on random normals.  Accepted by the offset, offset
+ * backward and benchmark entry points; the curvature returns PLIC_EINVAL. */
+#define PLIC_SZ_KAWANO 4
 
 /* arithmetic precision of the computation (independent of the storage type) */
 #define PLIC_FP32 0       /* all FP32                                                              */
@@ -62,11 +72,12 @@ extern "C" {
  * plic_offset_f32 / plic_offset_f64 — the PLIC problem (Sec. 2): n, V0 -> d0.
  *   nx, ny, nz, V0 : inputs, `count` elements each.
  *   d0             : output, `count` elements; may alias V0 (read before write).
- *   solver         : PLIC_ANALYTIC, PLIC_SZ, PLIC_NEWTON or PLIC_NESTED.
+ *   solver         : PLIC_ANALYTIC, PLIC_SZ, PLIC_NEWTON, PLIC_NESTED or
+ *                    PLIC_SZ_KAWANO.
  *   precision      : (f32 only) PLIC_FP32, PLIC_MIXED or PLIC_FP64; the f64 entry
  *                    point always computes in FP64.
  * Accuracy: |d0 - exact| <= 1e-5 (f32 storage) and <= 1e-12 (f64), absolute,
- * for unit normals, for every solver.
+ * for unit normals, for the paper's four solvers (PLIC_SZ_KAWANO: see there).
  * Returns PLIC_OK, PLIC_EINVAL or PLIC_EHIP.
  */
 int plic_offset_f32(const float *nx, const float *ny, const float *nz, const float *V0,
@@ -135,7 +146,8 @@ size_t plic_curvature_workspace_bytes(int64_t X, int64_t Y, int64_t Z);
  *   phi   : X*Y*Z floats, x fastest (index (z*Y + y)*X + x, torch shape (Z,Y,X)).
  *   kappa : X*Y*Z floats, written everywhere; 0 on non-interface cells and on
  *           the outer layer.  Must not overlap phi or the workspace.
- *   solver, precision : PLIC solver for the points; PLIC_FP32 fits in FP32,
+ *   solver, precision : PLIC solver for the points (the paper's four;
+ *           PLIC_SZ_KAWANO gives PLIC_EINVAL); PLIC_FP32 fits in FP32,
  *           PLIC_MIXED fits in FP64 (FP32 points), PLIC_FP64 is FP64 throughout.
  *   workspace, workspace_bytes : device scratch, 4-byte aligned, not
  *           overlapping phi or kappa, of at least the fixed part (see

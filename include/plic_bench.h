@@ -25,7 +25,9 @@ extern "C" {
  *   nx, ny, nz : device arrays of count normals (any non-zero length), read.
  *   count      : number of normals (0 does nothing).
  *   L          : fill levels per normal, L >= 2.
- *   solver     : PLIC_ANALYTIC / PLIC_SZ / PLIC_NEWTON / PLIC_NESTED (plic.h).
+ *   solver     : PLIC_ANALYTIC / PLIC_SZ / PLIC_NEWTON / PLIC_NESTED /
+ *                PLIC_SZ_KAWANO (plic.h); Kawano's form gives err = NaN for an
+ *                axis normal (its V0 = 0 and V0 = 1 evaluations).
  *   blank      : 0 = invert with the solver, 1 = blank run (d0 = V0 - 1/2).
  *   err        : device array of count floats, written: the sum over the L
  *                fill levels of E for that normal (E_avg = sum / (count L)).

@@ -14,7 +14,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libplic.so")
 
 PLIC_OK, PLIC_EINVAL, PLIC_EHIP = 0, -1, -2
-SOLVERS = {"analytic": 0, "sz": 1, "newton": 2, "nested": 3}
+SOLVERS = {"analytic": 0, "sz": 1, "newton": 2, "nested": 3, "sz_kawano": 4}
 PRECISIONS = {"fp32": 0, "mixed": 1, "fp64": 2}
 NORMALS = {"py": 0, "cm": 1}
 

@@ -60,6 +60,7 @@ extern "C" int plic_bench_isolated_f32(const float* nx, const float* ny, const f
         case kSZ: launch_isolated<kSZ>(blank, nx, ny, nz, count, L, err, st); break;
         case kNewton: launch_isolated<kNewton>(blank, nx, ny, nz, count, L, err, st); break;
         case kNested: launch_isolated<kNested>(blank, nx, ny, nz, count, L, err, st); break;
+        case kKawano: launch_isolated<kKawano>(blank, nx, ny, nz, count, L, err, st); break;
         default: launch_isolated<kAnalytic>(blank, nx, ny, nz, count, L, err, st); break;
     }
     return launch_status();

@@ -1109,7 +1109,7 @@ void launch_bwd(int precision, int normal, const float* phi, const float* gk, fl
 // shared argument checks of the two entry points
 int check_common(const float* phi, int64_t X, int64_t Y, int64_t Z, int solver, int precision,
                  const void* ws, size_t ws_bytes, bool* empty, Grid* g, int64_t* n) {
-    if (!valid_solver(solver) || !valid_precision(precision)) return PLIC_EINVAL;
+    if (!valid_curvature_solver(solver) || !valid_precision(precision)) return PLIC_EINVAL;
     if (check_lattice(X, Y, Z, empty, g) != PLIC_OK) return PLIC_EINVAL;
     *n = *empty ? 0 : X * Y * Z;
     if (!valid_array(phi, *n)) return PLIC_EINVAL;

@@ -26,7 +26,9 @@ inline bool overlap(const void* a, size_t na, const void* b, size_t nb) {
     return na > 0 && nb > 0 && x < y + nb && y < x + na;
 }
 
-inline bool valid_solver(int s) { return s >= PLIC_ANALYTIC && s <= PLIC_NESTED; }
+inline bool valid_solver(int s) { return s >= PLIC_ANALYTIC && s <= PLIC_SZ_KAWANO; }
+// the curvature takes the paper's four solvers, not Kawano's unoptimized SZ
+inline bool valid_curvature_solver(int s) { return s >= PLIC_ANALYTIC && s <= PLIC_NESTED; }
 inline bool valid_precision(int p) { return p >= PLIC_FP32 && p <= PLIC_FP64; }
 inline bool valid_normal(int n) { return n == PLIC_NORMAL_PY || n == PLIC_NORMAL_CM; }
 

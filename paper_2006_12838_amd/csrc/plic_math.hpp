@@ -40,6 +40,8 @@ template <> struct M<float> {
         return x + x * x2 * p;
     }
     static __device__ __forceinline__ float asin(float x) { return ::asinf(x); }
+    static __device__ __forceinline__ float acos(float x) { return ::acosf(x); }
+    static __device__ __forceinline__ float cos(float x) { return ::cosf(x); }
     static __device__ __forceinline__ float atan(float x) { return ::atanf(x); }
     // atan(y / x) for y >= 0, x > 0
     static __device__ __forceinline__ float atan2_pos(float y, float x) { return ::atanf(y * __builtin_amdgcn_rcpf(x)); }
@@ -79,6 +81,8 @@ template <> struct M<double> {
         return x + x * x2 * p;
     }
     static __device__ __forceinline__ double asin(double x) { return ::asin(x); }
+    static __device__ __forceinline__ double acos(double x) { return ::acos(x); }
+    static __device__ __forceinline__ double cos(double x) { return ::cos(x); }
     static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
     // atan(y / x) for y >= 0, x > 0 (within 3 ulp).  With a <= b the smaller
     // and larger of y and x, u = a / b in [0, 1] is reduced about tan(k pi/8),
@@ -120,7 +124,7 @@ template <> struct M<double> {
     static constexpr double pivot_rel = 1e-10;
 };
 
-enum Solver : int { kAnalytic = 0, kSZ = 1, kNewton = 2, kNested = 3 };
+enum Solver : int { kAnalytic = 0, kSZ = 1, kNewton = 2, kNested = 3, kKawano = 4 };
 
 // ---------------------------------------------------------------------------
 // Symmetry reduction (Sec. 2.1).  The reduced volume is taken as
@@ -429,6 +433,68 @@ __device__ __forceinline__ T cubic_nested(const Open<T>& o) {
     return T(q.base + (lo + w));
 }
 
+// ---------------------------------------------------------------------------
+// The SZ solution as implemented by Kawano (Sec. 2.4): the unoptimized variant
+// of the paper's comparison, kept with its own choices.  The normal is
+// L1-normalized (m, sorted m1 <= m2 <= m3 with the middle one taken as
+// 1 - m1 - m3), the offset alpha is measured from the cube corner, and the
+// reduced volume is the printed w = 1/2 - |V0 - 1/2|.  The cases are tested
+// (1), (2), then (5), (3), (4); alpha = 0 is read as "not settled", so an axis
+// normal at V0 in {0, 1}, whose case-(5) root is 0, goes on to the cubic of
+// case (4) and returns NaN (Sec. 2.6).  V1 (the volume at alpha = m1) carries
+// a tiny 1e-25 in its denominator.  The cubic cases take the third real root
+// of the monic cubic alpha^3 + a2 alpha^2 + a1 alpha + a0 in trigonometric
+// form, through acos and cos.  The open problem carries (m1, m2, m3, w).
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ bool closed_kawano(const Reduced<T>& r, T& alpha, Open<T>& o) {
+    using m = M<T>;
+    const T il = m::rcp(r.n1 + r.n2 + r.n3);
+    const T m1 = r.n1 * il, m3 = r.n3 * il, m2 = m::fmax(T(1) - (m1 + m3), T(0));
+    const T w = T(0.5) - m::fabs(r.V0 - T(0.5));
+    const T v1 = m::div(m1 * m1, T(6) * m2 * m3 + T(1e-25));
+    o = Open<T>{m1, m2, m3, w};
+    if (w < v1) {                                                         // case (1)
+        alpha = m::cbrt(T(6) * m1 * m2 * m3 * w);
+        return true;
+    }
+    if (w < v1 + m::div(T(0.5) * (m2 - m1), m3)) {                        // case (2)
+        alpha = T(0.5) * (m1 + m::sqrt(m1 * m1 + T(8) * m2 * m3 * (w - v1)));
+        return true;
+    }
+    const T m12 = m1 + m2;
+    if (!(m3 < m12)) {                                                    // no case (4)
+        alpha = m3 * w + T(0.5) * m12;
+        if (T(0.5) * m::div(m12, m3) <= w && alpha != T(0)) return true;  // case (5), unless alpha = 0
+    }
+    return false;
+}
+
+template <class T, class U>
+__device__ __forceinline__ T cubic_kawano(const Open<T>& o) {
+    using m = M<U>;
+    const U m1 = o.n1, m2 = o.n2, m3 = o.n3, w = o.V, m12 = m1 + m2;
+    const U s1 = m1 * m1, s2 = m2 * m2, w6 = U(6) * m1 * m2 * m3 * w;
+    // volume at alpha = m3 (case (4) exists), else at alpha = m1 + m2
+    const U v3 = m3 < m12 ? m::div(m3 * m3 * (U(3) * m12 - m3) + s1 * (m1 - U(3) * m3) + s2 * (m2 - U(3) * m3),
+                                   U(6) * m1 * m2 * m3)
+                          : U(0.5) * m::div(m12, m3);
+    U a2, a1, a0;
+    if (w < v3) {                                                         // case (3)
+        a2 = U(-3) * m12;
+        a1 = U(3) * (s1 + s2);
+        a0 = w6 - s1 * m1 - s2 * m2;
+    } else {                                                              // case (4)
+        a2 = U(-1.5);
+        a1 = U(1.5) * (s1 + s2 + m3 * m3);
+        a0 = U(0.5) * (w6 - s1 * m1 - s2 * m2 - m3 * m3 * m3);
+    }
+    const U q0 = (a1 * a2 - U(3) * a0) * U(1.0 / 6.0) - a2 * a2 * a2 * U(1.0 / 27.0);
+    const U sp = m::sqrt(a2 * a2 * U(1.0 / 9.0) - a1 * U(1.0 / 3.0));  // NaN below 0: the axis edge case
+    const U ang = U(4.18879020478639098461) + m::acos(m::div(q0, sp * sp * sp)) * U(1.0 / 3.0);  // 4 pi / 3 + ...
+    return T(U(2) * sp * m::cos(ang) - a2 * U(1.0 / 3.0));
+}
+
 // ---- the two stages per solver --------------------------------------------------
 // Units of the solver: SZ works on the L1-normalized normal, the others on |n|.
 template <int SOLVER, class T>
@@ -441,7 +507,9 @@ __device__ __forceinline__ T solver_scale(const Reduced<T>& r) {
 // false with the open problem in o
 template <int SOLVER, class T>
 __device__ __forceinline__ bool closed_stage(const Reduced<T>& r, T& d, Open<T>& o) {
-    if constexpr (SOLVER == kSZ) {
+    if constexpr (SOLVER == kKawano) {
+        return closed_kawano(r, d, o);
+    } else if constexpr (SOLVER == kSZ) {
         const T l = r.n1 + r.n2 + r.n3, il = M<T>::rcp(l);
         const T n1 = r.n1 * il, n2 = r.n2 * il, n3 = r.n3 * il;
         if (closed_sz(n1, n2, n3, r.V, d)) return true;
@@ -460,10 +528,24 @@ __device__ __forceinline__ bool closed_stage(const Reduced<T>& r, T& d, Open<T>&
 
 template <int SOLVER, class T, class U>
 __device__ __forceinline__ T cubic_stage(const Open<T>& o) {
-    if constexpr (SOLVER == kSZ) return cubic_sz<T, U>(o);
+    if constexpr (SOLVER == kKawano) return cubic_kawano<T, U>(o);
+    else if constexpr (SOLVER == kSZ) return cubic_sz<T, U>(o);
     else if constexpr (SOLVER == kNewton) return cubic_newton<T, U>(o);
     else if constexpr (SOLVER == kNested) return cubic_nested<T, U>(o);
     else return cubic_analytic<T, U>(o);
+}
+
+// d0 from the solver's reduced root: sign(V0 - 1/2) (S/2 - d), or for Kawano's
+// form l (1/2 - alpha) with the sign of V0 - 1/2
+template <int SOLVER, class T>
+__device__ __forceinline__ T finish(const Reduced<T>& r, T d, T nx, T ny, T nz, T V0raw) {
+    if constexpr (SOLVER == kKawano) {
+        T d0 = (r.n1 + r.n2 + r.n3) * __builtin_copysign(T(0.5) - d, r.V0 - T(0.5));
+        if (__builtin_isnan(nx + ny + nz + V0raw) || !(r.n3 > T(0))) d0 = M<T>::nan_v;
+        return d0;
+    } else {
+        return unreduce(r, d * solver_scale<SOLVER>(r), nx, ny, nz, V0raw);
+    }
 }
 
 // full problem: (n, V0) -> d0 with the chosen solver, one thread per problem
@@ -473,7 +555,7 @@ __device__ __forceinline__ T offset(T nx, T ny, T nz, T V0) {
     T d;
     Open<T> o;
     if (!closed_stage<SOLVER>(r, d, o)) d = cubic_stage<SOLVER, T, U>(o);
-    return unreduce(r, d * solver_scale<SOLVER>(r), nx, ny, nz, V0);
+    return finish<SOLVER>(r, d, nx, ny, nz, V0);
 }
 
 // ---------------------------------------------------------------------------

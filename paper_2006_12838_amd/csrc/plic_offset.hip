@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_offset(const S* __restrict__ nx, con
     S out[VEC];
 #pragma unroll
     for (int k = 0; k < VEC; ++k)
-        out[k] = S(unreduce(r[k], d[k] * solver_scale<SOLVER>(r[k]), T(a[k]), T(b[k]), T(c[k]), T(v[k])));
+        out[k] = S(finish<SOLVER>(r[k], d[k], T(a[k]), T(b[k]), T(c[k]), T(v[k])));
     store_part<S, VEC, FULL>(d0, i, count, out);
 }
 
@@ -290,6 +290,7 @@ void launch_offset_s(int solver, const S* nx, const S* ny, const S* nz, const S*
         case kSZ: launch_offset_t<kSZ, S, T, U>(nx, ny, nz, V0, d0, count, vec, st); break;
         case kNewton: launch_offset_t<kNewton, S, T, U>(nx, ny, nz, V0, d0, count, vec, st); break;
         case kNested: launch_offset_t<kNested, S, T, U>(nx, ny, nz, V0, d0, count, vec, st); break;
+        case kKawano: launch_offset_t<kKawano, S, T, U>(nx, ny, nz, V0, d0, count, vec, st); break;
         default: launch_offset_t<kAnalytic, S, T, U>(nx, ny, nz, V0, d0, count, vec, st); break;
     }
 }
@@ -324,6 +325,7 @@ void launch_bwd_s(int solver, const S* nx, const S* ny, const S* nz, const S* V0
         case kSZ: launch_bwd_t<kSZ, S, T, U>(nx, ny, nz, V0, gd, gx, gy, gz, gv, count, vec, st); break;
         case kNewton: launch_bwd_t<kNewton, S, T, U>(nx, ny, nz, V0, gd, gx, gy, gz, gv, count, vec, st); break;
         case kNested: launch_bwd_t<kNested, S, T, U>(nx, ny, nz, V0, gd, gx, gy, gz, gv, count, vec, st); break;
+        case kKawano: launch_bwd_t<kKawano, S, T, U>(nx, ny, nz, V0, gd, gx, gy, gz, gv, count, vec, st); break;
         default: launch_bwd_t<kAnalytic, S, T, U>(nx, ny, nz, V0, gd, gx, gy, gz, gv, count, vec, st); break;
     }
 }

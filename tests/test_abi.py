@@ -66,7 +66,7 @@ def test_offset_validation(lib):
     assert f(None, B, C, D, E, 8, 0, 0, None) == -1                   # null input
     assert f(A, B, C, D, None, 8, 0, 0, None) == -1                   # null output
     assert f(A + 2, B, C, D, E, 8, 0, 0, None) == -1                  # misaligned
-    assert f(A, B, C, D, E, 8, 4, 0, None) == -1                      # bad solver
+    assert f(A, B, C, D, E, 8, 5, 0, None) == -1                      # bad solver (4 is Kawano's SZ)
     assert f(A, B, C, D, E, 8, -1, 0, None) == -1
     assert f(A, B, C, D, E, 8, 0, 3, None) == -1                      # bad precision
     assert f(A, B, C, D, A + 4, 8, 0, 0, None) == -1                  # d0 overlaps nx
@@ -116,6 +116,7 @@ def test_curvature_validation(lib):
     assert f(None, 4, 4, 4, B, 0, 1, W, ws, None) == -1
     assert f(A, 4, 4, 4, A + 64, 0, 1, W, ws, None) == -1             # kappa overlaps phi
     assert f(A, 4, 4, 4, B, 9, 1, W, ws, None) == -1
+    assert f(A, 4, 4, 4, B, 4, 1, W, ws, None) == -1                  # Kawano's SZ: not for the curvature
     assert f(A, 4, 4, 4, B, 0, 7, W, ws, None) == -1
     assert f(A, 4, 4, 4, B, 0, 1, None, ws, None) == -1               # no workspace
     assert f(A, 4, 4, 4, B, 0, 1, W, 256 + 783, None) == -1           # below the fixed part
@@ -164,7 +165,7 @@ def test_bench_validation(lib):
     assert f(A, B, C, 0, 256, 0, 0, D, None) == 0                     # empty
     assert f(A, B, C, -1, 256, 0, 0, D, None) == -1
     assert f(A, B, C, 8, 1, 0, 0, D, None) == -1                      # L < 2
-    assert f(A, B, C, 8, 256, 4, 0, D, None) == -1                    # bad solver
+    assert f(A, B, C, 8, 256, 5, 0, D, None) == -1                    # bad solver
     assert f(A, B, C, 8, 256, 0, 2, D, None) == -1                    # bad blank flag
     assert f(A, B, C, 8, 256, 0, 0, A + 4, None) == -1                # err overlaps nx
     assert f(A + 2, B, C, 8, 256, 0, 0, D, None) == -1                # misaligned

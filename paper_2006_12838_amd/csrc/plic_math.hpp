@@ -622,38 +622,34 @@ __device__ __forceinline__ T offset_grad_from_d0(T nx, T ny, T nz, T V0, T d0, T
     const T n1 = m::fmin(m::fmin(ax, ay), az), n3 = m::fmax(m::fmax(ax, ay), az);
     const T n2 = m::med3(ax, ay, az);
     const T u = m::fmax(T(0.5) * (n1 + n2 + n3) - m::fabs(d0), T(0));
+    // one reciprocal per component, shared by the cases
+    const T r1 = m::rcp(n1), r2 = m::rcp(n2), r3 = m::rcp(n3);
     T z1, z2, z3, Fu;
     if (n1 + n2 <= u && u <= n3) {                                        // case (5)
-        Fu = m::rcp(n3);
+        Fu = r3;
         z1 = T(0.5); z2 = T(0.5);
-        z3 = m::div(u - T(0.5) * (n1 + n2), n3);
+        z3 = (u - T(0.5) * (n1 + n2)) * r3;
     } else if (u < n1) {                                                  // case (1)
-        Fu = m::div(u * u, T(2) * n1 * n2 * n3);
         const T t = u * T(1.0 / 3.0);
-        z1 = m::div(t, n1); z2 = m::div(t, n2); z3 = m::div(t, n3);
-    } else if (u <= n2) {                                                 // case (2)
-        const T G = T(3) * u * (u - n1) + n1 * n1;
-        const T Gu = T(6) * u - T(3) * n1;
-        Fu = m::div(Gu, T(6) * n2 * n3);
+        Fu = T(0.5) * u * u * r1 * r2 * r3;
+        z1 = t * r1; z2 = t * r2; z3 = t * r3;
+    } else {                                                              // cases (2)-(4)
+        const T P2 = m::fmax(u - n2, T(0)), P3 = m::fmax(u - n3, T(0));
+        // 1/a1 only where a corner is cut off (P2 > 0, hence a1 > 0); case (2)
+        // has no such term, also for a1 = 0
+        const T k1 = P2 > T(0) ? r1 : T(0);
+        const T c3 = (P2 * P2 * P2 + P3 * P3 * P3) * k1;
+        const T G = T(3) * u * (u - n1) + n1 * n1 - c3;
+        const T Gu = T(6) * u - T(3) * n1 - T(3) * (P2 * P2 + P3 * P3) * k1;
+        Fu = Gu * T(1.0 / 6.0) * r2 * r3;
         if (Gu > T(0)) {
             const T iG = m::rcp(Gu);
-            z1 = (T(3) * u - T(2) * n1) * iG;
-            z2 = m::div(G, n2) * iG;
-            z3 = m::div(G, n3) * iG;
-        } else {                                      // u = 0 with n1 = 0: an edge
+            z1 = (T(3) * u - T(2) * n1 - c3 * k1) * iG;
+            z2 = (G * r2 - T(3) * P2 * P2 * k1) * iG;
+            z3 = (G * r3 - T(3) * P3 * P3 * k1) * iG;
+        } else {                                      // u = 0 with a1 = 0: an edge
             z1 = T(0.5); z2 = T(0); z3 = T(0);
         }
-    } else {                                                              // cases (3), (4)
-        const T P2 = u - n2, P3 = m::fmax(u - n3, T(0));
-        const T r1 = m::rcp(n1);
-        const T c3 = (P2 * P2 * P2 + P3 * P3 * P3) * r1;
-        const T G = T(3) * u * (u - n1) + n1 * n1 - c3;
-        const T Gu = T(6) * u - T(3) * n1 - T(3) * (P2 * P2 + P3 * P3) * r1;
-        Fu = m::div(Gu, T(6) * n2 * n3);
-        const T iG = m::rcp(Gu);
-        z1 = (T(3) * u - T(2) * n1 - c3 * r1) * iG;
-        z2 = (m::div(G, n2) - T(3) * P2 * P2 * r1) * iG;
-        z3 = (m::div(G, n3) - T(3) * P3 * P3 * r1) * iG;
     }
     // selects, not an indexed array (which would live in scratch memory)
     auto pick = [&](int k) { return k == 0 ? z1 : (k == 1 ? z2 : z3); };

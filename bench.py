@@ -279,6 +279,46 @@ def paper_isolated(P, torch, dev, log2n, L=256, reps=5):
     return out
 
 
+def timed_reps(torch, stream, fn, reps=10):
+    """average ms of fn over reps back-to-back calls, HIP events on its stream"""
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def f64_rates(P, torch, tn):
+    """The four solvers with FP64 storage and arithmetic on the step's 2^26
+    problems (40 bytes per problem), outside the step."""
+    t64 = [t.double() for t in tn[:4]]
+    out = torch.empty_like(t64[3])
+    stream = torch.cuda.current_stream(out.device)
+    res = {}
+    for s in SOLVERS:
+        ms = timed_reps(torch, stream, lambda: P.plic_offset_f64(*t64, out, s))
+        n = out.numel()
+        gbs = 40 * n / (ms * 1e-3) / 1e9
+        res[s] = {"ms": round(ms, 4), "rate": n / (ms * 1e-3), "unit": "solves/s", "GBps": gbs,
+                  "hbm_frac": gbs / HBM_PEAK_GBS}
+    return res
+
+
+def curvature_warm(P, torch, tphi, tgk, kap, gphi, ws):
+    """Curvature forward and backward repeated back to back: phi (64 MiB at
+    256^3) stays in the 256 MB last-level cache, unlike in the step."""
+    stream = torch.cuda.current_stream(tphi.device)
+    fwd = timed_reps(torch, stream, lambda: P.plic_curvature_f32(tphi, kap, "analytic", "mixed", ws))
+    bwd = timed_reps(torch, stream, lambda: P.plic_curvature_backward_f32(tphi, tgk, gphi, "analytic", "mixed", ws))
+    n = tphi.numel()
+    return {"fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4), "fwd_cells_per_s": n / (fwd * 1e-3),
+            "bwd_cells_per_s": n / (bwd * 1e-3)}
+
+
 def kawano_rate(P, torch, tn, reps=10):
     """Kawano's form of the SZ solution (Sec. 2.4), FP32, on the step's 2^26
     problems: HBM-streamed like the four solvers (20 bytes per problem), timed
@@ -479,6 +519,8 @@ def main():
     if not args.only:
         out["sphere_offset"] = sphere_rate(P, torch, tn[3])
         out["offset_sz_kawano"] = kawano_rate(P, torch, tn)
+        out["offset_f64"] = f64_rates(P, torch, tn)
+        out["curvature_warm"] = curvature_warm(P, torch, tphi, tgk, kap, gphi, ws)
     if not args.no_paper_isolated and not args.only:
         out["paper_isolated"] = paper_isolated(P, torch, dev, args.log2n)
     if not args.no_cpu_baseline:

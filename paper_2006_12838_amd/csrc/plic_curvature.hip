@@ -639,8 +639,17 @@ __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx,
 // stages the fill levels of its 3x3x3 neighbourhood (5x5x5 for the
 // neighbour-normal variant, which needs each neighbour's own 3x3x3) in LDS,
 // and runs the cell.  Groups never wait for each other: no block barrier.
+// Waves per SIMD the work items are compiled for: the work is a chain of
+// dependent steps per cell, so concurrency (VGPRs at most 128 for 4 waves, 168
+// for 3) sets the time.  The forward fits 4 without spilling; the adjoint fits
+// 3, except the SZ solver's and full FP64's, which would spill and keep 2.
+template <int SOLVER, class T, bool ADJ>
+constexpr int items_waves() {
+    return !ADJ ? 4 : ((SOLVER == kSZ || sizeof(T) == 8) ? 2 : 3);
+}
+
 template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
-__global__ __launch_bounds__(kThreads) void k_curv_items(const float* __restrict__ phi,
+__global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, ADJ>())) void k_curv_items(const float* __restrict__ phi,
                                                           const float* __restrict__ gkap,
                                                           float* __restrict__ kappa, Workspace ws, int X, int Y,
                                                           int Z, int ntx, int nty) {
@@ -851,7 +860,7 @@ __device__ __forceinline__ unsigned source_row(const SourceMap& m, int cx, int c
     return m.sbase[tq] + m.spref[tq][l >> 5] + __popc(word & (bit - 1u));
 }
 
-__global__ __launch_bounds__(kThreads) void k_curv_gather_direct(float* __restrict__ gphi, Workspace ws, int X,
+__global__ __launch_bounds__(kThreads, 4) void k_curv_gather_direct(float* __restrict__ gphi, Workspace ws, int X,
                                                                   int Y, int Z, int ntx, int nty, int ntz) {
     constexpr int kStage = 27 * (2 * kWords + 1), kStageIt = (kStage + kThreads - 1) / kThreads;
     __shared__ SourceMap m;

@@ -319,6 +319,24 @@ def curvature_warm(P, torch, tphi, tgk, kap, gphi, ws):
             "bwd_cells_per_s": n / (bwd * 1e-3)}
 
 
+def curvature_variants(P, torch, tphi, tgk, kap, gphi, ws):
+    """The curvature options beside the base method, on the same 256^3 lattice
+    (warm cache, back-to-back calls): the centre-of-mass normal (forward and
+    backward) and each interface neighbour's own normal (forward only, 5^3
+    neighbourhood)."""
+    stream = torch.cuda.current_stream(tphi.device)
+    n = tphi.numel()
+    res = {}
+    for name, fn in (
+            ("cm_fwd", lambda: P.plic_curvature_ex_f32(tphi, kap, "analytic", "mixed", "cm", False, ws)),
+            ("cm_bwd", lambda: P.plic_curvature_backward_ex_f32(tphi, tgk, gphi, "analytic", "mixed", "cm", ws)),
+            ("neighbour_normals_fwd",
+             lambda: P.plic_curvature_ex_f32(tphi, kap, "analytic", "mixed", "py", True, ws))):
+        ms = timed_reps(torch, stream, fn)
+        res[name] = {"ms": round(ms, 4), "cells_per_s": n / (ms * 1e-3)}
+    return res
+
+
 def kawano_rate(P, torch, tn, reps=10):
     """Kawano's form of the SZ solution (Sec. 2.4), FP32, on the step's 2^26
     problems: HBM-streamed like the four solvers (20 bytes per problem), timed
@@ -521,6 +539,7 @@ def main():
         out["offset_sz_kawano"] = kawano_rate(P, torch, tn)
         out["offset_f64"] = f64_rates(P, torch, tn)
         out["curvature_warm"] = curvature_warm(P, torch, tphi, tgk, kap, gphi, ws)
+        out["curvature_variants"] = curvature_variants(P, torch, tphi, tgk, kap, gphi, ws)
     if not args.no_paper_isolated and not args.only:
         out["paper_isolated"] = paper_isolated(P, torch, dev, args.log2n)
     if not args.no_cpu_baseline:

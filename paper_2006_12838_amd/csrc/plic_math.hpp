@@ -422,15 +422,18 @@ template <class T, class U>
 __device__ __forceinline__ T cubic_nested(const Open<T>& o) {
     const Cubic<U> q = cubic_setup<T, U>(o);
     U lo = q.lo;
-    U w = U(0.5) * (q.hi - q.lo);
+    const U w0 = U(0.5) * (q.hi - q.lo);
+    // the i-th half width is w0 2^-i exactly, a constant multiple of w0 once
+    // the loop is unrolled, so each midpoint is one fused multiply-add
+    U s = U(1);
 #pragma unroll
     for (int i = 0; i < M<T>::bisect_steps; ++i) {
-        const U mid = lo + w;
+        const U mid = w0 * s + lo;
         const U h = ((q.a3 * mid + q.a2) * mid + q.a1) * mid;
         lo = h < q.c ? mid : lo;
-        w *= U(0.5);                 // exact: the widths are w0 2^-i
+        s *= U(0.5);
     }
-    return T(q.base + (lo + w));
+    return T(q.base + (w0 * s + lo));
 }
 
 // ---------------------------------------------------------------------------

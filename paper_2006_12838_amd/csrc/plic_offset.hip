@@ -19,6 +19,11 @@ namespace plic {
 namespace {
 
 constexpr int kBlock = 256;
+// The backward streams 5 input and 4 output arrays; workgroups of 512 keep
+// twice the consecutive bytes of each array in flight per workgroup, which
+// the memory system serves faster for this many streams (measured: a plain
+// 5-read / 4-write copy and this kernel both about 6 % faster than with 256).
+constexpr int kBwdBlock = 512;
 
 template <class S, int VEC> struct Vec;
 template <> struct Vec<float, 4> { using type = float4; };
@@ -205,12 +210,12 @@ __device__ __forceinline__ void backward1(T nx, T ny, T nz, T V0, T d0, T gd, T&
 // is as long as the solve, and the packing's LDS and barriers cost more
 // occupancy than they save there.  grad_d0 is loaded with the other inputs.
 template <int SOLVER, class S, class T, class U, int VEC, bool FULL>
-__global__ __launch_bounds__(kBlock) void k_offset_bwd(const S* __restrict__ nx, const S* __restrict__ ny,
+__global__ __launch_bounds__(kBwdBlock) void k_offset_bwd(const S* __restrict__ nx, const S* __restrict__ ny,
                                                        const S* __restrict__ nz, const S* __restrict__ V0,
                                                        const S* __restrict__ gd, S* __restrict__ gnx,
                                                        S* __restrict__ gny, S* __restrict__ gnz,
                                                        S* __restrict__ gV0, int64_t count) {
-    const int64_t i = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) * VEC;
+    const int64_t i = (static_cast<int64_t>(blockIdx.x) * kBwdBlock + threadIdx.x) * VEC;
     S a[VEC], b[VEC], c[VEC], v[VEC], g[VEC];
     load_part<S, VEC, FULL>(nx, i, count, a); load_part<S, VEC, FULL>(ny, i, count, b);
     load_part<S, VEC, FULL>(nz, i, count, c); load_part<S, VEC, FULL>(V0, i, count, v);
@@ -227,8 +232,8 @@ __global__ __launch_bounds__(kBlock) void k_offset_bwd(const S* __restrict__ nx,
     store_part<S, VEC, FULL>(gnz, i, count, oz); store_part<S, VEC, FULL>(gV0, i, count, ov);
 }
 
-inline unsigned grid_for(int64_t count, int vec) {
-    const int64_t per = static_cast<int64_t>(kBlock) * vec;
+inline unsigned grid_for(int64_t count, int vec, int block = kBlock) {
+    const int64_t per = static_cast<int64_t>(block) * vec;
     return static_cast<unsigned>((count + per - 1) / per);
 }
 
@@ -298,15 +303,15 @@ void launch_offset_s(int solver, const S* nx, const S* ny, const S* nz, const S*
 template <int SOLVER, class S, class T, class U, int VEC>
 void launch_bwd_v(const S* nx, const S* ny, const S* nz, const S* V0, const S* gd, S* gx, S* gy, S* gz, S* gv,
                   int64_t count, hipStream_t st) {
-    const int64_t per = static_cast<int64_t>(kBlock) * VEC, full = count / per * per, rem = count - full;
+    const int64_t per = static_cast<int64_t>(kBwdBlock) * VEC, full = count / per * per, rem = count - full;
     for (int64_t base = 0; base < full; base += kChunkProblems) {
         const int64_t n = full - base < kChunkProblems ? full - base : kChunkProblems;
-        hipLaunchKernelGGL((k_offset_bwd<SOLVER, S, T, U, VEC, true>), dim3(grid_for(n, VEC)), dim3(kBlock), 0,
+        hipLaunchKernelGGL((k_offset_bwd<SOLVER, S, T, U, VEC, true>), dim3(grid_for(n, VEC, kBwdBlock)), dim3(kBwdBlock), 0,
                            st, nx + base, ny + base, nz + base, V0 + base, gd + base, gx + base, gy + base, gz + base,
                            gv + base, n);
     }
     if (rem)
-        hipLaunchKernelGGL((k_offset_bwd<SOLVER, S, T, U, VEC, false>), dim3(1), dim3(kBlock), 0, st,
+        hipLaunchKernelGGL((k_offset_bwd<SOLVER, S, T, U, VEC, false>), dim3(1), dim3(kBwdBlock), 0, st,
                            nx + full, ny + full, nz + full, V0 + full, gd + full, gx + full, gy + full, gz + full,
                            gv + full, rem);
 }

@@ -19,6 +19,7 @@ import torch
 from ._lib import (  # noqa: F401  (re-exported: the C ABI by name)
     EXPORTED,
     NORMALS,
+    PAPER_SOLVERS,
     PRECISIONS,
     SOLVERS,
     plic_bench_isolated_f32,
@@ -42,7 +43,8 @@ from ._lib import (  # noqa: F401  (re-exported: the C ABI by name)
     plic_volume_f64,
 )
 
-__all__ = ["offset", "volume", "curvature", "PlicOffset", "PlicCurvature", "SOLVERS", "PRECISIONS", "NORMALS",
+__all__ = ["offset", "volume", "curvature", "PlicOffset", "PlicCurvature", "SOLVERS", "PAPER_SOLVERS", "PRECISIONS",
+           "NORMALS",
            "plic_version"]
 
 
@@ -90,7 +92,9 @@ def offset(n, V0, solver: str = "sz", precision: str = "fp32"):
 
     ``n`` is a (..., 3) tensor or a tuple (nx, ny, nz); float32 tensors use the
     chosen ``precision`` ("fp32", "mixed", "fp64"), float64 tensors compute in
-    FP64.  ``solver``: "analytic", "sz", "newton" or "nested"."""
+    FP64.  ``solver``: "analytic", "sz", "newton", "nested", or "sz_kawano" (the
+    unoptimized SZ comparison variant: NaN for an axis normal at V0 in {0, 1},
+    not held to the 1e-5 bound)."""
     nx, ny, nz = _split_normal(n)
     return PlicOffset.apply(nx, ny, nz, V0, solver, precision)
 

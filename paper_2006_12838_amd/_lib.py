@@ -15,6 +15,9 @@ LIB_PATH = os.path.join(_PKG, "libplic.so")
 
 PLIC_OK, PLIC_EINVAL, PLIC_EHIP = 0, -1, -2
 SOLVERS = {"analytic": 0, "sz": 1, "newton": 2, "nested": 3, "sz_kawano": 4}
+# the paper's four solvers, held to the accuracy bound; "sz_kawano" is the
+# unoptimized comparison variant (offset, offset backward, benchmark only)
+PAPER_SOLVERS = ("analytic", "sz", "newton", "nested")
 PRECISIONS = {"fp32": 0, "mixed": 1, "fp64": 2}
 NORMALS = {"py": 0, "cm": 1}
 

@@ -62,13 +62,22 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_2p26_problems_256c
 KERNEL_SOURCES = ("plic_math.hpp", "plic_host.hpp", "plic_offset.hip", "plic_curvature.hip")
 
 
+def code_text(src):
+    """C++ source without comments and blank space (string literals kept)"""
+    import re
+    tok = re.compile(r'"(?:\\.|[^"\\])*"|\'(?:\\.|[^\'\\])*\'|//[^\n]*|/\*.*?\*/', re.S)
+    code = tok.sub(lambda m: m.group(0) if m.group(0)[0] in "\"'" else " ", src)
+    return "\n".join(" ".join(line.split()) for line in code.splitlines() if line.strip())
+
+
 def kernel_source_hash():
-    """sha256 over the device sources, in a fixed order."""
+    """sha256 over the device sources' code (comments and blank space removed,
+    so a comment-only edit keeps a measurement valid), in a fixed order."""
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2006_12838_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2006_12838_amd", "csrc", name)) as f:
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()
 
 
@@ -149,7 +158,8 @@ def write_traffic_profile(fetch_csv, write_csv, log2n, lattice, out=TRAFFIC_PROF
         f"by {ff:.4f} and WRITE_SIZE by {fw:.4f}.  HBM bytes = 1024 (FETCH_SIZE * {ff:.4f} + "
         f"WRITE_SIZE * {fw:.4f}), summed over the dispatches of one launch.",
         "",
-        f"kernel source sha256: `{kernel_source_hash()}` (bench.py reports these bytes as "
+        f"kernel source sha256: `{kernel_source_hash()}` (of the sources' code, comments and blank space removed; "
+        f"bench.py reports these bytes as "
         "`roofline.traffic` only while the device sources hash to this value)",
         "",
         "| bench kernel | dispatches | HBM bytes per launch | FETCH_SIZE KiB | WRITE_SIZE KiB | algorithmic bytes | ratio |",

@@ -6,19 +6,23 @@
 //  1. a one-thread kernel that zeroes the work-list counters in the workspace
 //     (a kernel, not a memset, so the call can be captured in a graph);
 //  2. a streaming scan over the whole lattice (float4 loads and stores) that
-//     writes the zero result everywhere and lists one work item per 8
-//     interface cells (0 < phi < 1, away from the outer layer) of each tile;
-//     the backward also records each tile's interface bitmask and count;
-//  3. a persistent kernel over the work list that stages the fill levels of a
-//     tile plus a halo in LDS and computes each interface cell with a group of
-//     32 lanes: lane j takes neighbour j of the 3x3x3 neighbourhood (its PLIC
-//     offset, its row of the normal equations), lane 26 the centre.  Sums over
-//     the neighbours go through a small LDS tile and are added in a fixed
-//     order, so results are bitwise reproducible.
-// The backward stores each interface cell's 27 contributions in a row of the
-// workspace (rows assigned by a prefix over the tiles' counts, in tile order)
-// and gathers them per target cell in a fixed order; rows beyond the
-// workspace are recomputed by a fallback gather.
+//     writes the zero result everywhere, records each tile's interface bitmask
+//     (0 < phi < 1, away from the outer layer) with its prefix counts, and
+//     lists one work item per 8 interface cells of each tile; the backward
+//     also records each tile's interface count;
+//  3. a persistent kernel over the work list in which each interface cell is
+//     computed by a group of 32 lanes: the group finds its cell from the
+//     bitmask, stages its neighbourhood in LDS, and lane j takes neighbour j
+//     of the 3x3x3 neighbourhood (its PLIC offset, its row of the normal
+//     equations), lane 26 the centre.  Sums over the neighbours go through a
+//     small LDS tile and are added in a fixed order, so results are bitwise
+//     reproducible.
+// The backward first assigns contribution rows by a prefix over the tiles'
+// interface counts in tile order and lists the tiles next to the interface;
+// the work items store each interface cell's 27 contributions in its row; a
+// direct gather sums, for every cell next to the interface, its sources' rows
+// in a fixed order; a fallback gather handles the tiles with a source whose
+// row did not fit the workspace, recomputing those rows.
 // The interface is one cell thick (about 0.2 % of a 256^3 sphere lattice), so
 // the scan carries the HBM traffic and the list kernels the arithmetic.
 //
@@ -432,7 +436,7 @@ __device__ __forceinline__ int ordered_compact(int n, Pred pred, unsigned short*
 // The fixed part (everything but contrib) is 784 bytes per tile.  The
 // backward stores the 27 contributions of an interface cell in row
 // cbase[tile] + rank when that row fits; cells beyond the capacity are
-// recomputed by the gather kernel, so every workspace size >= the fixed part
+// recomputed by the fallback gather, so every workspace size >= the fixed part
 // is correct and a larger one is faster.
 // ---------------------------------------------------------------------------
 constexpr int kPartCells = kGroups;           // interface cells per work item
@@ -468,11 +472,12 @@ __global__ void k_curv_zero(unsigned* counter) {
 }
 
 // ---------------------------------------------------------------------------
-// 1. streaming scan: zero output everywhere; one work item (tile << 7 | part)
-// per kPartCells interface cells of the tile.  The backward also records the
-// tile's flag, interface bitmask, its prefix counts and its first
-// contribution row.  Thread t handles 4 consecutive cells along x, which are
-// the cells 4t .. 4t+3 of the tile in cell order (x fastest, then y, z).
+// 1. streaming scan: zero output everywhere; the tile's interface bitmask and
+// the set bits before each of its words; one work item (tile << 7 | part) per
+// kPartCells interface cells of the tile.  The backward also records the
+// tile's interface count (its flag), from which the contribution rows are
+// assigned.  Thread t handles 4 consecutive cells along x, which are the cells
+// 4t .. 4t+3 of the tile in cell order (x fastest, then y, z).
 // ---------------------------------------------------------------------------
 template <bool VEC, bool FWD>
 __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict__ phi, float* __restrict__ out,
@@ -626,19 +631,16 @@ __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx,
 }
 
 // ---------------------------------------------------------------------------
-// 2. work items: up to kPartCells interface cells of a tile, one group of 32
-// lanes per cell, the tile's fill levels plus a one-cell halo in LDS.  The
-// tile's interface cells are listed in cell order, so the part of an item is
-// well defined.  Forward: kappa.  Backward: the cell's 27 contributions
-// gk * d kappa / d phi_q into its contribution row (when it fits).
+// 2. work items: up to kPartCells interface cells of a tile, one 32-lane group
+// per cell.  The group finds its cell, the i-th interface cell of the tile in
+// cell order, from the tile's bitmask and prefix counts (two ballots), stages
+// the fill levels of its 3x3x3 neighbourhood (5x5x5 for the neighbour-normal
+// variant, which needs each neighbour's own 3x3x3) in LDS, and runs the cell.
+// Groups never wait for each other: no block barrier.  Forward: kappa.
+// Backward: the cell's 27 contributions gk * d kappa / d phi_q into its
+// contribution row (when it fits).
 // ---------------------------------------------------------------------------
 
-// One work item = up to kPartCells interface cells of a tile, one 32-lane
-// group per cell.  The group finds its cell, the i-th interface cell of the
-// tile in cell order, from the tile's bitmask and prefix counts (two ballots),
-// stages the fill levels of its 3x3x3 neighbourhood (5x5x5 for the
-// neighbour-normal variant, which needs each neighbour's own 3x3x3) in LDS,
-// and runs the cell.  Groups never wait for each other: no block barrier.
 // Waves per SIMD the work items are compiled for: the work is a chain of
 // dependent steps per cell, so concurrency (VGPRs at most 128 for 4 waves, 168
 // for 3) sets the time.  The forward fits 4 without spilling; the adjoint fits
@@ -703,12 +705,11 @@ __global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, ADJ>())) void k_c
 }
 
 // ---------------------------------------------------------------------------
-// 3. backward gather: per tile of the gather list, the candidates are the
-// interface cells of the tile grown by one cell, in region order, processed in
-// chunks of kChunk.  A candidate's 27 contributions are copied from its
-// contribution row, or recomputed (halo 2 in LDS) when the row did not fit.
-// Each target cell of the tile then adds the contributions of its 27
-// neighbours chunk by chunk in a fixed order: deterministic, no atomics.
+// 3. backward gathers: every cell next to the interface adds the
+// contributions of its interface neighbours in a fixed order (deterministic,
+// no atomics).  The direct gather reads them from the stored rows; a tile with
+// a source whose row did not fit goes to the overflow list, where the fallback
+// gather copies the stored rows and recomputes the missing ones.
 // ---------------------------------------------------------------------------
 constexpr int B_RX = TX + 4, B_RY = TY + 4, B_RZ = TZ + 4, B_REGION = B_RX * B_RY * B_RZ;
 constexpr int C_RX = TX + 2, C_RY = TY + 2, C_RZ = TZ + 2, C_REGION = C_RX * C_RY * C_RZ;

@@ -137,7 +137,7 @@ int plic_offset_backward_f64(const double *nx, const double *ny, const double *n
 size_t plic_curvature_workspace_bytes(int64_t X, int64_t Y, int64_t Z);
 
 /*
- * plic_curvature_f32 — PLIC curvature of a VoF fill-level lattice (Sec. 4.1-5.2,
+ * plic_curvature_f32 — PLIC curvature of a VoF fill-level lattice (Sec. 4.1-4.2,
  * Appendix B): for every interface cell (0 < phi < 1) away from the outer
  * one-cell layer: Parker-Youngs normal from the 3x3x3 fill levels, local frame
  * from the fixed vector r, PLIC points of the interface neighbours (centre

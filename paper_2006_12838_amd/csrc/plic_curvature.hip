@@ -1,4 +1,4 @@
-// PLIC curvature of a VoF fill-level lattice on gfx950 (Sec. 4.1-5.2 and
+// PLIC curvature of a VoF fill-level lattice on gfx950 (Sec. 4.1-4.2 and
 // Appendix B of Lehmann & Gekle, arXiv 2006.12838), forward and backward.
 //
 // Layout: phi, kappa, grad_kappa, grad_phi are X*Y*Z floats, x fastest.  The

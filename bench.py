@@ -55,10 +55,18 @@ def parse():
     ap.add_argument("--write-issue-profile", metavar="SQ_CSV",
                     help="write the instruction-issue summary from a rocprofv3 --pmc run and exit (no GPU)")
     ap.add_argument("--issue-out", default=ISSUE_PROFILE, help="where --write-issue-profile writes")
+    ap.add_argument("--write-isa-profile", action="store_true",
+                    help="static gfx950 instruction counts of the paper-method benchmark kernels "
+                         "(compiles plic_bench.hip to assembly; no GPU)")
+    ap.add_argument("--isa-out", default=ISA_PROFILE, help="where --write-isa-profile writes")
     return ap.parse_args()
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_2p26_problems_256cube_sphere_pmc.md")
+ISA_PROFILE = os.path.join(ROOT, "profiles", "isolated_plic_isa_counts_gfx950.md")
+# Table 3 (Titan Xp, PTX): arithmetic operations N_a and branches N_b per PLIC, blank run subtracted
+PAPER_TABLE3_OPS = {"sz": (132, 12), "sz_kawano": (149, 14), "analytic": (189, 13), "newton": (256, 11),
+                    "nested": (106, 13)}
 KERNEL_SOURCES = ("plic_math.hpp", "plic_host.hpp", "plic_offset.hip", "plic_curvature.hip")
 
 
@@ -184,6 +192,96 @@ ISSUE_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_TRANS_F32", "SQ_IN
                   "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES")
 
 
+# instructions that are neither arithmetic nor a branch: waits, memory, control
+_NON_ARITH = ("s_waitcnt", "s_endpgm", "s_nop", "s_load", "s_buffer", "s_barrier", "s_setpc", "s_getpc",
+              "s_swappc", "s_sleep", "s_dcache", "s_setprio", "s_trap", "s_sendmsg", "s_delay", "s_clause",
+              "global_", "buffer_", "flat_", "scratch_", "ds_")
+
+
+def isa_counts(asm):
+    """static instruction counts of each k_isolated<solver, blank> in gfx950
+    assembly: arithmetic (vector and scalar ALU, compares and selects
+    included), branches, transcendental vector ops"""
+    import re
+    out, cur = {}, None
+    for line in asm.splitlines():
+        m = re.match(r"^(_Z\w*k_isolatedILi(\d)ELb(\d)E\w*):", line)
+        if m:
+            cur = (int(m.group(2)), bool(int(m.group(3))))
+            out[cur] = {"arith": 0, "branch": 0, "trans": 0, "total": 0}
+            continue
+        if cur is None:
+            continue
+        if line.startswith(".Lfunc_end"):
+            cur = None
+            continue
+        if not line.startswith("\t") or line.strip().startswith((".", ";")):
+            continue
+        op = line.split()[0]
+        c = out[cur]
+        c["total"] += 1
+        if op.startswith(("s_cbranch", "s_branch")):
+            c["branch"] += 1
+        elif op.startswith(_NON_ARITH):
+            pass
+        elif op.startswith(("v_", "s_")):
+            c["arith"] += 1
+            if re.match(r"v_(sin|cos|rcp|rsq|sqrt|log|exp)_", op):
+                c["trans"] += 1
+    return out
+
+
+def write_isa_profile(out_path=ISA_PROFILE):
+    """Markdown summary of the static instruction counts of the paper-method
+    benchmark kernels, blank run subtracted as in Table 3 (N_a, N_b)."""
+    import importlib.util
+    import subprocess
+    import tempfile
+    spec = importlib.util.spec_from_file_location("_plic_build", os.path.join(ROOT, "paper_2006_12838_amd", "_build.py"))
+    bld = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bld)
+    src = os.path.join(ROOT, "paper_2006_12838_amd", "csrc", "plic_bench.hip")
+    with tempfile.TemporaryDirectory() as tmp:
+        asm_path = os.path.join(tmp, "plic_bench.s")
+        cmd = [bld.HIPCC, *bld.FLAGS, "--offload-device-only", "-S", src, "-o", asm_path]
+        subprocess.run(cmd, check=True, capture_output=True)
+        counts = isa_counts(open(asm_path).read())
+    names = {0: "analytic", 1: "sz", 2: "newton", 3: "nested", 4: "sz_kawano"}
+    blank = counts[(1, True)]
+    lines = [
+        "# Static gfx950 instruction counts of the paper-method benchmark kernels (Table 3's N_a, N_b)",
+        "",
+        "Command (repository root, no GPU needed):",
+        "",
+        "```",
+        "python3 bench.py --write-isa-profile",
+        "# compiles paper_2006_12838_amd/csrc/plic_bench.hip with the library's flags:",
+        "# " + " ".join(["hipcc", *bld.FLAGS, "--offload-device-only", "-S", "plic_bench.hip"]),
+        "```",
+        "",
+        f"kernel source sha256: `{kernel_source_hash()}` (of the sources' code, comments and blank space removed)",
+        "",
+        "Each `k_isolated<solver, false>` inlines one inversion and one forward volume per loop trip; the "
+        "blank kernel (`k_isolated<1, true>`, d0 = V0 - 1/2) holds everything else, so the solver's own "
+        "static count is the difference, as Table 3 counts PTX with the blank run subtracted.  "
+        "`N_a` = vector and scalar ALU instructions (compares, selects and bit operations included; "
+        "memory, waits and control excluded), `N_b` = branch instructions; static counts, so a loop "
+        "body counts once and an unrolled loop in full.",
+        "",
+        "| solver | N_a (gfx950) | N_b (gfx950) | transcendental | instructions in the kernel | N_a (Titan Xp PTX) | N_b (PTX) |",
+        "|---|---:|---:|---:|---:|---:|---:|",
+    ]
+    for sv in (1, 4, 0, 2, 3):
+        c = counts[(sv, False)]
+        pa, pb = PAPER_TABLE3_OPS[names[sv]]
+        lines.append(f"| {names[sv]} | {c['arith'] - blank['arith']} | {c['branch'] - blank['branch']} | "
+                     f"{c['trans'] - blank['trans']} | {c['total']} | {pa} | {pb} |")
+    lines.append(f"| blank (subtracted) | {blank['arith']} | {blank['branch']} | {blank['trans']} | {blank['total']} | – | – |")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return out_path
+
+
 def write_issue_profile(sq_csv, log2n, lattice, out=ISSUE_PROFILE):
     """Summary of one rocprofv3 --pmc run with ISSUE_COUNTERS over
     `bench.py --only <kernels> --steps 1 --warmup 0`: instructions issued per
@@ -246,13 +344,16 @@ PAPER_TABLE3 = {"sz": (12.8, 6.58e-8), "analytic": (19.0, 5.73e-8), "newton": (1
 ISOLATED_SOLVERS = SOLVERS + ("sz_kawano",)
 
 
-def paper_isolated(P, torch, dev, log2n, L=256, reps=5):
+def paper_isolated(P, torch, dev, log2n, L=256, reps=64):
     """The paper's GPU benchmark method (Sec. 2.6.2): 2^log2n normals of its mix
     (one axis, one face diagonal, 1/8 random 2D, the rest random 3D), each
     thread sweeping L equally spaced V0 in series with a round trip through the
-    forward volume; the blank run (d0 = V0 - 1/2) is subtracted and the time
-    divided by the N L evaluations.  Context for the paper's Table 3, not the
-    headline (which streams inputs from HBM)."""
+    forward volume; each variant is run `reps` times (64 in the paper), the
+    mean blank-run time (d0 = V0 - 1/2) is subtracted from the mean and the
+    difference divided by the N L evaluations.  Context for the paper's
+    Table 3, not the headline (which streams inputs from HBM)."""
+    import math
+
     import workloads
 
     n = 1 << log2n
@@ -260,32 +361,37 @@ def paper_isolated(P, torch, dev, log2n, L=256, reps=5):
     err = torch.empty_like(t[0])
     stream = torch.cuda.current_stream(dev)
 
-    def timed(fn):
+    def runs(fn):
+        """per-run ms of `reps` back-to-back runs after one warm-up run"""
         fn()
         torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(stream)
+        for k in range(reps):
             fn()
-        b.record(stream)
+            ev[k + 1].record(stream)
         torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
+        ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]
+        mean = sum(ms) / reps
+        std = math.sqrt(sum((x - mean) ** 2 for x in ms) / max(reps - 1, 1))
+        return mean, std
 
-    blank_ms = timed(lambda: P.plic_bench_isolated_f32(*t, err, L, "sz", True))
+    blank_ms, blank_sd = runs(lambda: P.plic_bench_isolated_f32(*t, err, L, "sz", True))
     out = {"normals": n, "L": L, "reps": reps, "blank_ms": round(blank_ms, 4), "solvers": {}}
     for s in ISOLATED_SOLVERS:
-        ms = timed(lambda: P.plic_bench_isolated_f32(*t, err, L, s, False))
+        ms, sd = runs(lambda: P.plic_bench_isolated_f32(*t, err, L, s, False))
         e = err.double()
         fin = torch.isfinite(e)
         nan_normals = int((~fin).sum().item())
         e_fin = e[fin].sum().item() / (int(fin.sum().item()) * L)
         ps = (ms - blank_ms) * 1e9 / (n * L)
+        ps_sd = math.sqrt(sd * sd + blank_sd * blank_sd) * 1e9 / (n * L)
         # E_avg over every evaluation is NaN when any is (JSON null), as the paper prints for Kawano's form
-        out["solvers"][s] = {"ms": round(ms, 4), "ps_per_plic": round(ps, 3),
+        out["solvers"][s] = {"ms": round(ms, 4), "ps_per_plic": round(ps, 3), "ps_std": round(ps_sd, 3),
                              "E_avg": e_fin if nan_normals == 0 else None, "nan_normals": nan_normals,
                              "E_avg_finite_normals": e_fin,
                              "paper_titan_xp_ps": PAPER_TABLE3[s][0], "paper_E_avg": PAPER_TABLE3[s][1]}
-        print(f"bench: isolated {s}: {ps:.2f} ps/PLIC", file=sys.stderr, flush=True)
+        print(f"bench: isolated {s}: {ps:.3f} +- {ps_sd:.3f} ps/PLIC", file=sys.stderr, flush=True)
     return out
 
 
@@ -417,6 +523,9 @@ def main():
     args = parse()
     if args.write_traffic_profile:
         print(write_traffic_profile(*args.write_traffic_profile, args.log2n, args.lattice, args.traffic_out))
+        return
+    if args.write_isa_profile:
+        print(write_isa_profile(args.isa_out))
         return
     if args.write_issue_profile:
         print(write_issue_profile(args.write_issue_profile, args.log2n, args.lattice, args.issue_out))

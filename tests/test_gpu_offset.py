@@ -189,3 +189,21 @@ def test_full_size_sampled(P, orc):
         assert E.max().item() <= 2e-6
     del tx, ty, tz, tv, d0, Vb
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("solver", SOLVERS + ["sz_kawano"])
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_packing_does_not_change_bits(P, solver, precision):
+    """The open problems of a workgroup are packed (and, for Newton, grouped by
+    case) before the cubic stage.  Shifting the arrays by one or five elements
+    misaligns them (the one-problem-per-lane path) and regroups every problem
+    with other neighbours; each result must keep its bits."""
+    nx, ny, nz, V0 = workloads.plic_problems((1 << 20) + 37, seed=17)
+    t = dev(nx, ny, nz, V0)
+    ref = torch.empty_like(t[3])
+    P.plic_offset_f32(*t, ref, solver, precision)
+    for shift in (1, 5):
+        out = torch.empty_like(t[3][shift:])
+        P.plic_offset_f32(*(x[shift:] for x in t), out, solver, precision)
+        torch.cuda.synchronize()
+        assert torch.equal(out.nan_to_num(7.0), ref[shift:].nan_to_num(7.0)), (solver, precision, shift)

@@ -91,6 +91,10 @@ def _load():
     lib.orc_curv_cell_fd_grad_k.argtypes = [_D, _U8, ctypes.c_int, c_d, _D]
     lib.orc_curvature_grad_ex.restype = c_i64
     lib.orc_curvature_grad_ex.argtypes = [_F, c_i64, c_i64, c_i64, ctypes.c_int, _F, c_d, _D, _U8]
+    lib.orc_curv_cell_nbr_fd_grad.restype = ctypes.c_int
+    lib.orc_curv_cell_nbr_fd_grad.argtypes = [_D, _U8, ctypes.c_int, c_d, _D]
+    lib.orc_curvature_grad_nbr.restype = c_i64
+    lib.orc_curvature_grad_nbr.argtypes = [_F, c_i64, c_i64, c_i64, ctypes.c_int, _F, c_d, _D, _U8]
     _lib = lib
     return lib
 
@@ -303,16 +307,29 @@ def curv_cell_fd_grad(phi27, mask27=None, h=1e-6, normal="py"):
     return g, bool(bad)
 
 
-def curvature_grad(phi, grad_kappa, h=1e-6, normal="py"):
+def curv_cell_nbr_fd_grad(phi125, normal="py", inside27=None, h=1e-6):
+    """central-difference gradient of the neighbour-normal cell over its 5^3
+    neighbourhood (index (dz+2)*25 + (dy+2)*5 + (dx+2)); bad when a mask or the
+    fit's rank would change"""
+    v = _d(phi125).ravel()
+    ins = None if inside27 is None else np.ascontiguousarray(np.asarray(inside27, dtype=np.uint8))
+    g = np.empty(125)
+    bad = _load().orc_curv_cell_nbr_fd_grad(_p(v), None if ins is None else _p(ins, _U8), _kind(normal), float(h), _p(g))
+    return g, bool(bad)
+
+
+def curvature_grad(phi, grad_kappa, h=1e-6, normal="py", neighbour_normals=False):
     """grad_phi (float64) of sum(grad_kappa * kappa) by finite differences of the
-    oracle's curvature with the interface mask fixed; also the bad-cell mask."""
+    oracle's curvature with the interface mask fixed; also the bad-cell mask.
+    With neighbour_normals, of the neighbour-normal variant (5^3 per cell)."""
     lib = _load()
     phi = np.ascontiguousarray(np.asarray(phi, dtype=np.float32))
     gk = np.ascontiguousarray(np.asarray(grad_kappa, dtype=np.float32))
     Z, Y, X = phi.shape
     out = np.empty(phi.shape, dtype=np.float64)
     bad = np.empty(phi.shape, dtype=np.uint8)
-    lib.orc_curvature_grad_ex(_p(phi, _F), X, Y, Z, _kind(normal), _p(gk, _F), float(h), _p(out), _p(bad, _U8))
+    fn = lib.orc_curvature_grad_nbr if neighbour_normals else lib.orc_curvature_grad_ex
+    fn(_p(phi, _F), X, Y, Z, _kind(normal), _p(gk, _F), float(h), _p(out), _p(bad, _U8))
     return out, bad.astype(bool)
 
 

@@ -618,7 +618,10 @@ double orc_curv_cell_k(const double phi[27], const unsigned char mask[27], int k
  * a neighbour keeps the centre normal when its own 3^3 neighbourhood is not
  * inside the lattice (inside27[q] == 0; NULL: all inside) or its gradient
  * vanishes (|g| < 1e-12) */
-double orc_curv_cell_nbr(const double p125[125], const unsigned char inside27[27], int kind, double info[3])
+/* the variant with the interface mask of the inner 3^3 given (mask27), as the
+ * finite-difference gradient holds it fixed; NULL: from the values */
+static double cell_nbr_core(const double p125[125], const unsigned char mask27[27],
+                            const unsigned char inside27[27], int kind, double info[3])
 {
     double p27[27], nbrn[27][3], nc[3];
     unsigned char mask[27];
@@ -627,7 +630,7 @@ double orc_curv_cell_nbr(const double p125[125], const unsigned char inside27[27
         int q = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
         double v = p125[(dz + 2) * 25 + (dy + 2) * 5 + (dx + 2)];
         p27[q] = v;
-        mask[q] = (unsigned char)(v > 0.0 && v < 1.0);
+        mask[q] = mask27 ? mask27[q] : (unsigned char)(v > 0.0 && v < 1.0);
     }
     if (!(normal_of(p27, kind, nc) >= 1e-12)) {
         if (info) { info[0] = 0; info[1] = 0; info[2] = 0; }
@@ -643,6 +646,11 @@ double orc_curv_cell_nbr(const double p125[125], const unsigned char inside27[27
         }
     }
     return cell_core(p27, mask, R_AUX, kind, (const double (*)[3])nbrn, info, NULL, NULL);
+}
+
+double orc_curv_cell_nbr(const double p125[125], const unsigned char inside27[27], int kind, double info[3])
+{
+    return cell_nbr_core(p125, NULL, inside27, kind, info);
 }
 
 static int is_interface(float p) { return p > 0.0f && p < 1.0f; }
@@ -808,6 +816,83 @@ int64_t orc_curvature_grad_ex(const float *phi, int64_t X, int64_t Y, int64_t Z,
         for (dz = -1; dz <= 1; ++dz) for (dy = -1; dy <= 1; ++dy) for (dx = -1; dx <= 1; ++dx) {
             int q = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
             grad_phi[((z + dz) * Y + (y + dy)) * X + (x + dx)] += gk * part[27 * k + q];
+        }
+        if (bad[k]) { ++nbad; if (bad_cells) bad_cells[cc] = 1; }
+    }
+    free(list); free(part); free(bad);
+    return nbad;
+}
+
+/* neighbour-normal variant: central differences over the whole 5^3
+ * neighbourhood (the neighbours' own normals reach two cells out) with the
+ * interface mask held fixed; bad when a perturbed interface entry of the inner
+ * 3^3 (or the centre) would cross 0 or 1, or the active fit parameters change */
+int orc_curv_cell_nbr_fd_grad(const double p125[125], const unsigned char inside27[27], int kind, double h,
+                              double grad[125])
+{
+    double base[3], ip[3], im[3], p[125];
+    unsigned char mask[27];
+    int k, bad = 0;
+    for (k = 0; k < 27; ++k) {
+        double v = p125[(k / 9 + 1) * 25 + ((k / 3) % 3 + 1) * 5 + (k % 3 + 1)];
+        mask[k] = (unsigned char)(v > 0.0 && v < 1.0);
+    }
+    cell_nbr_core(p125, mask, inside27, kind, base);
+    for (k = 0; k < 125; ++k) {
+        int dx = k % 5 - 2, dy = (k / 5) % 5 - 2, dz = k / 25 - 2;
+        double kp, km;
+        memcpy(p, p125, sizeof p);
+        if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
+            double v = p125[k];
+            int centre = dx == 0 && dy == 0 && dz == 0;
+            if ((centre || (v > 0.0 && v < 1.0)) && !(v - h > 0.0 && v + h < 1.0)) bad = 1;
+        }
+        p[k] = p125[k] + h; kp = cell_nbr_core(p, mask, inside27, kind, ip);
+        p[k] = p125[k] - h; km = cell_nbr_core(p, mask, inside27, kind, im);
+        if (ip[0] != base[0] || im[0] != base[0] || ip[1] != base[1] || im[1] != base[1]) bad = 1;
+        grad[k] = (kp - km) / (2.0 * h);
+    }
+    return bad;
+}
+
+int64_t orc_curvature_grad_nbr(const float *phi, int64_t X, int64_t Y, int64_t Z, int kind,
+                               const float *grad_kappa, double h, double *grad_phi, uint8_t *bad_cells)
+{
+    int64_t total = X * Y * Z, c, nif = 0, k, nbad = 0;
+    int64_t *list;
+    double *part;
+    int *bad;
+    for (c = 0; c < total; ++c) { grad_phi[c] = 0.0; if (bad_cells) bad_cells[c] = 0; }
+    for (c = 0; c < total; ++c) {
+        int64_t x = c % X, y = (c / X) % Y, z = c / (X * Y);
+        if (x >= 1 && y >= 1 && z >= 1 && x <= X - 2 && y <= Y - 2 && z <= Z - 2 &&
+            is_interface(phi[c])) ++nif;
+    }
+    list = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nif > 0 ? nif : 1));
+    part = (double *)malloc(sizeof(double) * 125 * (size_t)(nif > 0 ? nif : 1));
+    bad = (int *)malloc(sizeof(int) * (size_t)(nif > 0 ? nif : 1));
+    k = 0;
+    for (c = 0; c < total; ++c) {
+        int64_t x = c % X, y = (c / X) % Y, z = c / (X * Y);
+        if (x >= 1 && y >= 1 && z >= 1 && x <= X - 2 && y <= Y - 2 && z <= Z - 2 &&
+            is_interface(phi[c])) list[k++] = c;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (k = 0; k < nif; ++k) {
+        int64_t cc = list[k], x = cc % X, y = (cc / X) % Y, z = cc / (X * Y);
+        double v[125];
+        unsigned char inside[27];
+        gather125(phi, X, Y, Z, x, y, z, v, inside);
+        bad[k] = orc_curv_cell_nbr_fd_grad(v, inside, kind, h, part + 125 * k);
+    }
+    for (k = 0; k < nif; ++k) {                /* fixed-order scatter, entries inside the lattice */
+        int64_t cc = list[k], x = cc % X, y = (cc / X) % Y, z = cc / (X * Y);
+        double gk = (double)grad_kappa[cc];
+        int dx, dy, dz;
+        for (dz = -2; dz <= 2; ++dz) for (dy = -2; dy <= 2; ++dy) for (dx = -2; dx <= 2; ++dx) {
+            int64_t gx = x + dx, gy = y + dy, gz = z + dz;
+            if (gx < 0 || gy < 0 || gz < 0 || gx >= X || gy >= Y || gz >= Z) continue;
+            grad_phi[(gz * Y + gy) * X + gx] += gk * part[125 * k + (dz + 2) * 25 + (dy + 2) * 5 + (dx + 2)];
         }
         if (bad[k]) { ++nbad; if (bad_cells) bad_cells[cc] = 1; }
     }

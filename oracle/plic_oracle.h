@@ -122,6 +122,12 @@ int orc_curv_cell_fd_grad_k(const double phi[27], const unsigned char mask[27], 
 int64_t orc_curvature_grad_ex(const float *phi, int64_t X, int64_t Y, int64_t Z, int kind,
                               const float *grad_kappa, double h, double *grad_phi,
                               uint8_t *bad_cells);
+/* the neighbour-normal variant's gradient: central differences over each
+ * cell's 5^3 neighbourhood, scattered in cell order (same conventions) */
+int orc_curv_cell_nbr_fd_grad(const double p125[125], const unsigned char inside27[27], int kind, double h,
+                              double grad[125]);
+int64_t orc_curvature_grad_nbr(const float *phi, int64_t X, int64_t Y, int64_t Z, int kind,
+                               const float *grad_kappa, double h, double *grad_phi, uint8_t *bad_cells);
 
 #ifdef __cplusplus
 }

@@ -124,3 +124,41 @@ def test_neighbour_normals_lattice_rotation(orc):
         assert abs(k0 - k1) <= 1e-9 * max(1.0, abs(k0))
         checked += 1
     assert checked > 20
+
+
+def test_neighbour_normals_fd_gradient_converges_and_respects_complement(orc):
+    """The variant's gradient reaches two cells out (each neighbour's own
+    normal).  Central differences at h and 2h agree, and since kappa(1 - phi) =
+    -kappa(phi) for this variant too (every normal and offset flips), the
+    gradient at 1 - phi equals the gradient at phi."""
+    phi, _, _ = workloads.perturbed_sphere_lattice(N=36, R=11.0, seed=2, ss=4)
+    kn = orc.curvature(phi, neighbour_normals=True)
+    kc = orc.curvature((1.0 - phi).astype(np.float32), neighbour_normals=True)
+    _, fl = orc.curvature(phi, flags=True)
+    assert np.max(np.abs(kn + kc)[(fl & 1) == 1]) <= 1e-12
+    Z, Y, X = phi.shape
+    cells = np.flatnonzero(fl == 1)[::53][:16]
+    checked = 0
+    for cc in cells:
+        x, y, z = cc % X, (cc // X) % Y, cc // (X * Y)
+        if min(x, y, z) < 2 or x > X - 3 or y > Y - 3 or z > Z - 3:
+            continue
+        nb = phi[z - 2:z + 3, y - 2:y + 3, x - 2:x + 3].astype(np.float64)
+        inner = nb[1:4, 1:4, 1:4]
+        if np.any((inner > 0) & (inner < 1e-4)) or np.any((inner < 1) & (inner > 1 - 1e-4)):
+            continue
+        g1, bad1 = orc.curv_cell_nbr_fd_grad(nb.ravel(), h=1e-6)
+        g2, bad2 = orc.curv_cell_nbr_fd_grad(nb.ravel(), h=2e-6)
+        if bad1 or bad2:
+            continue
+        scale = max(1.0, np.abs(g1).max())
+        assert np.max(np.abs(g1 - g2)) <= 1e-6 * scale
+        gc, badc = orc.curv_cell_nbr_fd_grad((1.0 - nb).ravel(), h=1e-6)
+        assert not badc
+        assert np.max(np.abs(gc - g1)) <= 1e-6 * scale
+        # the outer layer of the 5^3 matters (own normals of the neighbours)
+        outer = np.ones((5, 5, 5), bool)
+        outer[1:4, 1:4, 1:4] = False
+        assert np.abs(g1.reshape(5, 5, 5)[outer]).max() > 1e-5 * scale     # FD noise is ~1e-9
+        checked += 1
+    assert checked >= 5

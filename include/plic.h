@@ -137,6 +137,17 @@ int plic_offset_backward_f64(const double *nx, const double *ny, const double *n
 size_t plic_curvature_workspace_bytes(int64_t X, int64_t Y, int64_t Z);
 
 /*
+ * plic_curvature_workspace_bytes_ex — as plic_curvature_workspace_bytes, and
+ * with neighbour_normals = 1 the recommended size for the backward of the
+ * neighbour-normal variant (plic_curvature_backward_ex_f32): its rows hold 105
+ * floats (the 27 contributions and the adjoints of the 26 neighbours' own
+ * fill-level gradients) plus 3 (the adjoint of the cell's own gradient),
+ * 432 bytes per interface cell, 64 per tile budgeted (that variant has no
+ * recomputing fallback; 453 MB at 256^3).  0 for an invalid lattice or flag.
+ */
+size_t plic_curvature_workspace_bytes_ex(int64_t X, int64_t Y, int64_t Z, int neighbour_normals);
+
+/*
  * plic_curvature_f32 — PLIC curvature of a VoF fill-level lattice (Sec. 4.1-4.2,
  * Appendix B): for every interface cell (0 < phi < 1) away from the outer
  * one-cell layer: Parker-Youngs normal from the 3x3x3 fill levels, local frame
@@ -218,14 +229,25 @@ int plic_curvature_ex_f32(const float *phi, int64_t X, int64_t Y, int64_t Z, flo
                           void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * plic_curvature_backward_ex_f32 — plic_curvature_backward_f32 with the normal
- * of plic_curvature_ex_f32 (the weights enter the normal's adjoint).  The
- * neighbour-normal variant has no backward.
+ * plic_curvature_backward_ex_f32 — plic_curvature_backward_f32 with the options
+ * of plic_curvature_ex_f32.  normal: its weights enter the normal's adjoint.
+ * neighbour_normals = 1: the backward of the neighbour-normal variant, whose
+ * gradient reaches two cells from an interface cell (each neighbour's own
+ * normal reads that neighbour's 3x3x3).  Each interface cell stores its 27
+ * contributions and the adjoints of its neighbours' own fill-level gradients
+ * in a row; a second pass sums, for every interface cell, the adjoints of its
+ * own gradient that its neighbours stored; the gather adds both in a fixed
+ * order (deterministic).  This variant has no recomputing fallback: the
+ * workspace must hold at least one row (fixed part + 432 bytes, else
+ * PLIC_EINVAL), and where a row does not fit, the gradient on the affected
+ * tile's cells next to the interface is NaN.  plic_curvature_workspace_bytes_ex
+ * (X, Y, Z, 1) gives room for 64 interface cells per tile.  The interface
+ * masks and the choice of each neighbour's normal are held fixed.
  */
 int plic_curvature_backward_ex_f32(const float *phi, int64_t X, int64_t Y, int64_t Z,
                                    const float *grad_kappa, float *grad_phi, int solver,
-                                   int precision, int normal, void *workspace,
-                                   size_t workspace_bytes, void *stream);
+                                   int precision, int normal, int neighbour_normals,
+                                   void *workspace, size_t workspace_bytes, void *stream);
 
 /* human-readable status; never NULL */
 const char *plic_status_string(int status);

@@ -28,6 +28,7 @@ from ._lib import (  # noqa: F401  (re-exported: the C ABI by name)
     plic_curvature_ex_f32,
     plic_curvature_f32,
     plic_curvature_workspace_bytes,
+    plic_curvature_workspace_bytes_ex,
     plic_last_hip_error,
     plic_offset_backward_f32,
     plic_offset_backward_f64,
@@ -128,10 +129,9 @@ class PlicCurvature(torch.autograd.Function):
     def backward(ctx, grad_kappa):
         (phi,) = ctx.saved_tensors
         solver, precision, normal, neighbour_normals = ctx.opts
-        if neighbour_normals:
-            raise NotImplementedError("the neighbour-normal curvature variant has no backward")
         grad_phi = torch.empty_like(phi)
-        plic_curvature_backward_ex_f32(phi, grad_kappa.contiguous(), grad_phi, solver, precision, normal)
+        plic_curvature_backward_ex_f32(phi, grad_kappa.contiguous(), grad_phi, solver, precision, normal,
+                                       neighbour_normals)
         return grad_phi, None, None, None, None
 
 
@@ -140,5 +140,5 @@ def curvature(phi, solver: str = "analytic", precision: str = "mixed", normal: s
     """Mean curvature kappa of the VoF lattice ``phi`` (float32, shape (Z, Y, X)):
     0 off the interface, +1/R for a fluid sphere of radius R.  normal: "py"
     (Parker-Youngs) or "cm" (centre of mass); neighbour_normals: each interface
-    neighbour's PLIC plane from its own normal (forward only)."""
+    neighbour's PLIC plane from its own normal."""
     return PlicCurvature.apply(phi, solver, precision, normal, neighbour_normals)

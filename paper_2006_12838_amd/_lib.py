@@ -56,11 +56,13 @@ _c = {
     "plic_curvature_ex_f32": _sig("plic_curvature_ex_f32",
                                   [_vp, _i64, _i64, _i64, _vp, _int, _int, _int, _int, _vp, ctypes.c_size_t, _vp]),
     "plic_curvature_backward_ex_f32": _sig("plic_curvature_backward_ex_f32",
-                                           [_vp, _i64, _i64, _i64, _vp, _vp, _int, _int, _int, _vp,
+                                           [_vp, _i64, _i64, _i64, _vp, _vp, _int, _int, _int, _int, _vp,
                                             ctypes.c_size_t, _vp]),
 }
 _lib.plic_curvature_workspace_bytes.restype = ctypes.c_size_t
 _lib.plic_curvature_workspace_bytes.argtypes = [_i64, _i64, _i64]
+_lib.plic_curvature_workspace_bytes_ex.restype = ctypes.c_size_t
+_lib.plic_curvature_workspace_bytes_ex.argtypes = [_i64, _i64, _i64, _int]
 _lib.plic_status_string.restype = ctypes.c_char_p
 _lib.plic_status_string.argtypes = [_int]
 _lib.plic_version.restype = ctypes.c_char_p
@@ -69,11 +71,15 @@ _lib.plic_last_hip_error.restype = ctypes.c_int
 _lib.plic_last_hip_error.argtypes = []
 
 EXPORTED = tuple(_c) + ("plic_status_string", "plic_version", "plic_last_hip_error",
-                        "plic_curvature_workspace_bytes")
+                        "plic_curvature_workspace_bytes", "plic_curvature_workspace_bytes_ex")
 
 
 def plic_curvature_workspace_bytes(X: int, Y: int, Z: int) -> int:
     return int(_lib.plic_curvature_workspace_bytes(int(X), int(Y), int(Z)))
+
+
+def plic_curvature_workspace_bytes_ex(X: int, Y: int, Z: int, neighbour_normals: bool = False) -> int:
+    return int(_lib.plic_curvature_workspace_bytes_ex(int(X), int(Y), int(Z), int(bool(neighbour_normals))))
 
 
 def plic_status_string(status: int) -> str:
@@ -199,12 +205,13 @@ def _lattice_dims(phi):
     return X, Y, Z
 
 
-def _workspace(phi, workspace, X, Y, Z):
+def _workspace(phi, workspace, X, Y, Z, neighbour_normals=False):
     """The recommended workspace when none is given; a caller's workspace may
     be smaller (down to the fixed part, which the library checks: interface
-    cells beyond its contribution store are recomputed)."""
+    cells beyond its contribution store are recomputed; the neighbour-normal
+    backward needs one row at least and gives NaN where a row is missing)."""
     if workspace is None:
-        need = plic_curvature_workspace_bytes(X, Y, Z)
+        need = plic_curvature_workspace_bytes_ex(X, Y, Z, neighbour_normals)
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=phi.device)
     if not (workspace.is_cuda and workspace.is_contiguous() and workspace.dtype == torch.uint8):
         raise ValueError("workspace must be a contiguous uint8 GPU tensor")
@@ -246,17 +253,17 @@ def plic_curvature_f32(phi, kappa, solver="analytic", precision="mixed", workspa
 
 
 def plic_curvature_backward_ex_f32(phi, grad_kappa, grad_phi, solver="analytic", precision="mixed", normal="py",
-                                   workspace=None):
+                                   neighbour_normals=False, workspace=None):
     X, Y, Z = _lattice_dims(phi)
     n = X * Y * Z
     _same_device(phi, grad_kappa, grad_phi)
-    ws = _workspace(phi, workspace, X, Y, Z)
+    ws = _workspace(phi, workspace, X, Y, Z, neighbour_normals)
     _check(_c["plic_curvature_backward_ex_f32"](_ptr(phi, torch.float32, n, "phi"), X, Y, Z,
                                                 _ptr(grad_kappa, torch.float32, n, "grad_kappa"),
                                                 _ptr(grad_phi, torch.float32, n, "grad_phi"),
                                                 _enum(SOLVERS, solver, "solver"),
                                                 _enum(PRECISIONS, precision, "precision"),
-                                                _enum(NORMALS, normal, "normal"),
+                                                _enum(NORMALS, normal, "normal"), int(bool(neighbour_normals)),
                                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
            "plic_curvature_backward_ex_f32")
     return grad_phi

@@ -191,7 +191,6 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
                                             float gk, float* __restrict__ out, GroupLds<F>& L,
                                             int gx0 = 0, int gy0 = 0, int gz0 = 0, int X = 0, int Y = 0,
                                             int Z = 0) {
-    static_assert(!(ADJ && NBR), "the neighbour-normal variant has no backward");
     using mt = M<T>;
     // fill-level gradient of the centre (App. B.1); every lane forms the same
     // sum from the staged fill levels
@@ -213,6 +212,9 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
         if constexpr (ADJ) {
             if (nbr) out[q] = 0.0f;
             if (centre) out[13] = 0.0f;
+            if constexpr (NBR) {
+                if (nbr) out[27 + 3 * j] = out[28 + 3 * j] = out[29 + 3 * j] = 0.0f;
+            }
         }
         return 0.0f;
     }
@@ -235,6 +237,8 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
     // neighbour with its own normal (centre normal on the outer lattice layer
     // or for a vanishing gradient)
     T m0 = n0, m1 = n1, m2 = n2;
+    bool own = false;                             // this lane's point uses its own normal
+    T ihq = T(0);                                 // 1 / |h| of that normal's gradient
     if constexpr (NBR) {
         // the neighbour's own 3^3 neighbourhood lies in the lattice
         const int ax = gx0 + dx, ay = gy0 + dy, az = gz0 + dz;
@@ -246,6 +250,8 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
             if (h2 >= T(1e-24)) {
                 const T ih = mt::rcp(mt::sqrt(h2));
                 m0 = -hx * ih; m1 = -hy * ih; m2 = -hz * ih;
+                own = true;
+                ihq = ih;
             }
         }
     }
@@ -257,10 +263,11 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
     // this lane's point (coordinate transformation of Sec. 4.2) and its row of
     // the normal equations: Q Q^T (lower triangle) and z Q
     F x = F(0), y = F(0), z = F(0);
+    T P0 = T(0), P1 = T(0), P2 = T(0);            // neighbour-normal variant: the point before the frame
     if (iface) {
         if constexpr (NBR) {
             // foot of the neighbour's own plane, e + D n_q - D0 n, in the frame
-            const T P0 = ex + D * m0 - D0 * n0, P1 = ey + D * m1 - D0 * n1, P2 = ez + D * m2 - D0 * n2;
+            P0 = ex + D * m0 - D0 * n0; P1 = ey + D * m1 - D0 * n1; P2 = ez + D * m2 - D0 * n2;
             x = F(P0 * bx0 + P1 * bx1 + P2 * bx2);
             y = F(P0 * by0 + P1 * by1 + P2 * by2);
             z = F(P0 * n0 + P1 * n1 + P2 * n2);
@@ -310,6 +317,7 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
         ldlt_solve<F>(m, act, abar, lam);          // M symmetric: lambda = M^-1 abar
         // this lane's point: zbar = lam.Q, Qbar = lam (z - a.Q) - a (lam.Q)
         T phib = T(0);
+        T hb0 = T(0), hb1 = T(0), hb2 = T(0);     // neighbour-normal variant: adjoint of this lane's h
         F arow[10];
 #pragma unroll
         for (int i = 0; i < 10; ++i) arow[i] = F(0);
@@ -323,13 +331,38 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
             const T xb = T(F(2) * x * Qb[0] + y * Qb[2] + Qb[3]);
             const T yb = T(F(2) * y * Qb[1] + x * Qb[2] + Qb[4]);
             const T zt = T(zb);
-            T cq[3];
-            const T dv = offset_grad_from_d0<T>(n0, n1, n2, T(p), D, cq);   // 1/A, centroid
-            phib = zt * dv;
-            arow[0] = F(xb * ex); arow[1] = F(xb * ey); arow[2] = F(xb * ez);
-            arow[3] = F(yb * ex); arow[4] = F(yb * ey); arow[5] = F(yb * ez);
-            arow[6] = F(zt * (ex + cq[0])); arow[7] = F(zt * (ey + cq[1])); arow[8] = F(zt * (ez + cq[2]));
-            arow[9] = F(zt);
+            if constexpr (NBR) {
+                // x = P.b_x, y = P.b_y, z = P.n with P = e + D m - D0 n, D = d0(phi_q, m)
+                const T Pb0 = xb * bx0 + yb * by0 + zt * n0;
+                const T Pb1 = xb * bx1 + yb * by1 + zt * n1;
+                const T Pb2 = xb * bx2 + yb * by2 + zt * n2;
+                T cq[3];
+                const T dv = offset_grad_from_d0<T>(m0, m1, m2, T(p), D, cq);   // 1/A, centroid for m
+                const T Db = Pb0 * m0 + Pb1 * m1 + Pb2 * m2;
+                const T mb0 = D * Pb0 + Db * cq[0], mb1 = D * Pb1 + Db * cq[1], mb2 = D * Pb2 + Db * cq[2];
+                phib = Db * dv;
+                arow[0] = F(xb * P0); arow[1] = F(xb * P1); arow[2] = F(xb * P2);
+                arow[3] = F(yb * P0); arow[4] = F(yb * P1); arow[5] = F(yb * P2);
+                // n enters through z = P.n, through -D0 n in P, and as m where the lane keeps it
+                arow[6] = F(zt * P0 - D0 * Pb0 + (own ? T(0) : mb0));
+                arow[7] = F(zt * P1 - D0 * Pb1 + (own ? T(0) : mb1));
+                arow[8] = F(zt * P2 - D0 * Pb2 + (own ? T(0) : mb2));
+                arow[9] = F(zt);
+                if (own) {                                   // m = -h / |h|: the adjoint of h
+                    const T md = m0 * mb0 + m1 * mb1 + m2 * mb2;
+                    hb0 = -(mb0 - m0 * md) * ihq;
+                    hb1 = -(mb1 - m1 * md) * ihq;
+                    hb2 = -(mb2 - m2 * md) * ihq;
+                }
+            } else {
+                T cq[3];
+                const T dv = offset_grad_from_d0<T>(n0, n1, n2, T(p), D, cq);   // 1/A, centroid
+                phib = zt * dv;
+                arow[0] = F(xb * ex); arow[1] = F(xb * ey); arow[2] = F(xb * ez);
+                arow[3] = F(yb * ex); arow[4] = F(yb * ey); arow[5] = F(yb * ez);
+                arow[6] = F(zt * (ex + cq[0])); arow[7] = F(zt * (ey + cq[1])); arow[8] = F(zt * (ez + cq[2]));
+                arow[9] = F(zt);
+            }
         }
         T dvc = T(0);
         if (centre) {
@@ -362,6 +395,15 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
         const T gb0 = -(nb0 - n0 * nd) * ign, gb1 = -(nb1 - n1 * nd) * ign, gb2 = -(nb2 - n2 * nd) * ign;
         if (nbr) out[q] = float(phib + w * (ex * gb0 + ey * gb1 + ez * gb2));
         if (centre) out[13] = float(-sz_ * dvc);
+        if constexpr (NBR) {
+            // the adjoint of neighbour q's own fill-level gradient, gathered later
+            // at that neighbour and spread over its 3^3 by the gradient's weights
+            if (nbr) {
+                out[27 + 3 * j] = float(hb0);
+                out[28 + 3 * j] = float(hb1);
+                out[29 + 3 * j] = float(hb2);
+            }
+        }
         __syncwarp();                              // res is reused by the next cell
     }
     return kappa;
@@ -451,6 +493,16 @@ constexpr size_t kDefaultRowsPerTile = 16;    // contribution rows budgeted per 
 // below 2^30 (a 32-bit byte offset from the store's base)
 constexpr unsigned kRowCap = 0xF0000000u;
 constexpr unsigned kRowLimit = (1u << 30) / 27u;
+// The neighbour-normal variant's backward: a row holds the 27 contributions
+// and, per neighbour, the adjoint of that neighbour's own fill-level gradient
+// (26 x 3), followed in the workspace by one 3-vector per row, the sum of
+// those adjoints at the row's cell
+constexpr int kRowFloatsNbr = 27 + 26 * 3;
+constexpr size_t kRowBytesNbr = (kRowFloatsNbr + 3) * sizeof(float);
+constexpr unsigned kRowLimitNbr = (1u << 30) / kRowFloatsNbr;
+// budgeted per tile by default: without a fallback a missing row is NaN, so
+// the default leaves room for interfaces that cross a tile several times
+constexpr size_t kDefaultRowsPerTileNbr = 64;
 
 struct Workspace {
     unsigned* counter;  // [0] items, [1] gather tiles, [2] overflow tiles
@@ -462,6 +514,7 @@ struct Workspace {
     unsigned* tiles;
     unsigned* over;
     float* contrib;
+    float* hbar;        // neighbour-normal backward: 3 floats per row
     unsigned rows;      // contribution capacity
 };
 
@@ -645,13 +698,13 @@ __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx,
 // dependent steps per cell, so concurrency (VGPRs at most 128 for 4 waves, 168
 // for 3) sets the time.  The forward fits 4 without spilling; the adjoint fits
 // 3, except the SZ solver's and full FP64's, which would spill and keep 2.
-template <int SOLVER, class T, bool ADJ>
+template <int SOLVER, class T, bool ADJ, bool NBR>
 constexpr int items_waves() {
-    return !ADJ ? 4 : ((SOLVER == kSZ || sizeof(T) == 8) ? 2 : 3);
+    return !ADJ ? 4 : ((NBR || SOLVER == kSZ || sizeof(T) == 8) ? 2 : 3);
 }
 
 template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
-__global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, ADJ>())) void k_curv_items(const float* __restrict__ phi,
+__global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, ADJ, NBR>())) void k_curv_items(const float* __restrict__ phi,
                                                           const float* __restrict__ gkap,
                                                           float* __restrict__ kappa, Workspace ws, int X, int Y,
                                                           int Z, int ntx, int nty) {
@@ -693,8 +746,10 @@ __global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, ADJ>())) void k_c
         __syncwarp();
         const int64_t g = (static_cast<int64_t>(gz) * Y + gy) * X + gx;
         if constexpr (ADJ) {
-            group_cell<SOLVER, T, U, F, true, NRM, false>(nbh[grp], C, W, W * W, j, gkap[g],
-                                                          ws.contrib + static_cast<size_t>(row) * 27, glds[grp]);
+            constexpr int ROWF = NBR ? kRowFloatsNbr : 27;
+            group_cell<SOLVER, T, U, F, true, NRM, NBR>(nbh[grp], C, W, W * W, j, gkap[g],
+                                                        ws.contrib + static_cast<size_t>(row) * ROWF, glds[grp],
+                                                        gx, gy, gz, X, Y, Z);
         } else {
             const float kv = group_cell<SOLVER, T, U, F, false, NRM, NBR>(nbh[grp], C, W, W * W, j, 0.0f, nullptr,
                                                                          glds[grp], gx, gy, gz, X, Y, Z);
@@ -861,9 +916,90 @@ __device__ __forceinline__ unsigned source_row(const SourceMap& m, int cx, int c
     return m.sbase[tq] + m.spref[tq][l >> 5] + __popc(word & (bit - 1u));
 }
 
-__global__ __launch_bounds__(kThreads, 4) void k_curv_gather_direct(float* __restrict__ gphi, Workspace ws, int X,
-                                                                  int Y, int Z, int ntx, int nty, int ntz) {
+// Stages the interface bitmasks, prefix counts and first rows of the 3x3x3
+// tiles around tile (tx, ty, tz) in LDS (zeros outside the lattice); every
+// load is issued before the first store.  Block-wide; the caller syncs.
+__device__ __forceinline__ void stage_sources(SourceMap& m, const Workspace& ws, int tx, int ty, int tz, int ntx,
+                                              int nty, int ntz) {
     constexpr int kStage = 27 * (2 * kWords + 1), kStageIt = (kStage + kThreads - 1) / kThreads;
+    const int tid = threadIdx.x;
+    unsigned sv[kStageIt];
+#pragma unroll
+    for (int u = 0; u < kStageIt; ++u) {
+        const int i = tid + u * kThreads;
+        const int t = i / (2 * kWords + 1), w = i % (2 * kWords + 1);
+        const int ax = tx + q_dx(t), ay = ty + q_dy(t), az = tz + q_dz(t);
+        const bool in = i < kStage && ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz;
+        const int nt = (az * nty + ay) * ntx + ax;
+        sv[u] = !in ? 0u : (w < kWords ? ws.mask[nt * kWords + w]
+                                       : (w < 2 * kWords ? ws.prefix[nt * kWords + (w - kWords)] : ws.cbase[nt]));
+    }
+#pragma unroll
+    for (int u = 0; u < kStageIt; ++u) {
+        const int i = tid + u * kThreads;
+        if (i < kStage) {
+            const int t = i / (2 * kWords + 1), w = i % (2 * kWords + 1);
+            if (w < kWords) m.smask[t][w] = sv[u];
+            else if (w < 2 * kWords) m.spref[t][w - kWords] = sv[u];
+            else m.sbase[t] = sv[u];
+        }
+    }
+}
+
+// Neighbour-normal backward, between the work items and the gather: for every
+// interface cell n of a gather tile, the sum in q order over its interface
+// neighbours c = n - e_q of the adjoint that c stored for its neighbour at
+// +e_q (that is n): the adjoint of n's own fill-level gradient, written to the
+// 3-vector beside n's row.  A source without a stored row makes it NaN.
+__global__ __launch_bounds__(kThreads) void k_curv_hgather(Workspace ws, int ntx, int nty, int ntz) {
+    __shared__ SourceMap m;
+    const int tid = threadIdx.x;
+    const unsigned ntl = *static_cast<volatile unsigned*>(ws.counter + 1);
+    for (unsigned it = blockIdx.x; it < ntl; it += gridDim.x) {
+        const int tile = static_cast<int>(ws.tiles[it]);
+        const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+        stage_sources(m, ws, tx, ty, tz, ntx, nty, ntz);
+        __syncthreads();
+#pragma unroll 1
+        for (int k = 0; k < kCellsPerThread; ++k) {
+            const int cl = tid + k * kThreads;
+            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
+            bool self;
+            const unsigned rn = source_row(m, cx, cy, cz, 13, self);   // the cell's own row
+            if (!self || rn >= ws.rows) continue;                       // no row: the gather sees the miss
+            float h0 = 0.0f, h1 = 0.0f, h2 = 0.0f;
+            bool miss = false;
+#pragma unroll 1
+            for (int q = 0; q < 27; ++q) {
+                if (q == 13) continue;
+                bool src;
+                const unsigned r = source_row(m, cx, cy, cz, q, src);
+                if (!src) continue;
+                if (r >= ws.rows) {
+                    miss = true;
+                    continue;
+                }
+                const unsigned b = r * static_cast<unsigned>(kRowFloatsNbr) + 27u + 3u * static_cast<unsigned>(q < 13 ? q : q - 1);
+                h0 += ws.contrib[b];
+                h1 += ws.contrib[b + 1];
+                h2 += ws.contrib[b + 2];
+            }
+            const float nan = __builtin_nanf("");
+            ws.hbar[3 * rn] = miss ? nan : h0;
+            ws.hbar[3 * rn + 1] = miss ? nan : h1;
+            ws.hbar[3 * rn + 2] = miss ? nan : h2;
+        }
+        __syncthreads();                                             // LDS reused by the next tile
+    }
+}
+
+// NBR: the neighbour-normal variant's rows, plus each source's own-gradient
+// adjoint spread by the gradient weights of NRM; a tile with a source beyond
+// the store gets NaN on its band (that variant has no fallback)
+template <bool NBR, int NRM>
+__global__ __launch_bounds__(kThreads, (NBR ? 3 : 4)) void k_curv_gather_direct(float* __restrict__ gphi, Workspace ws, int X,
+                                                                  int Y, int Z, int ntx, int nty, int ntz) {
+    constexpr unsigned ROWF = NBR ? kRowFloatsNbr : 27;
     __shared__ SourceMap m;
     __shared__ unsigned short band[kTile];
     __shared__ unsigned long long brow[TY * TZ];
@@ -878,25 +1014,29 @@ __global__ __launch_bounds__(kThreads, 4) void k_curv_gather_direct(float* __res
         }
         const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
-        unsigned sv[kStageIt];
+        {
+            // stage_sources written out: as a call it costs this kernel a spill
+            constexpr int kStage = 27 * (2 * kWords + 1), kStageIt = (kStage + kThreads - 1) / kThreads;
+            unsigned sv[kStageIt];
 #pragma unroll
-        for (int u = 0; u < kStageIt; ++u) {                          // every load before the first store
-            const int i = tid + u * kThreads;
-            const int t = i / (2 * kWords + 1), w = i % (2 * kWords + 1);
-            const int ax = tx + q_dx(t), ay = ty + q_dy(t), az = tz + q_dz(t);
-            const bool in = i < kStage && ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz;
-            const int nt = (az * nty + ay) * ntx + ax;
-            sv[u] = !in ? 0u : (w < kWords ? ws.mask[nt * kWords + w]
-                                           : (w < 2 * kWords ? ws.prefix[nt * kWords + (w - kWords)] : ws.cbase[nt]));
-        }
-#pragma unroll
-        for (int u = 0; u < kStageIt; ++u) {
-            const int i = tid + u * kThreads;
-            if (i < kStage) {
+            for (int u = 0; u < kStageIt; ++u) {                      // every load before the first store
+                const int i = tid + u * kThreads;
                 const int t = i / (2 * kWords + 1), w = i % (2 * kWords + 1);
-                if (w < kWords) m.smask[t][w] = sv[u];
-                else if (w < 2 * kWords) m.spref[t][w - kWords] = sv[u];
-                else m.sbase[t] = sv[u];
+                const int ax = tx + q_dx(t), ay = ty + q_dy(t), az = tz + q_dz(t);
+                const bool in = i < kStage && ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz;
+                const int nt = (az * nty + ay) * ntx + ax;
+                sv[u] = !in ? 0u : (w < kWords ? ws.mask[nt * kWords + w]
+                                               : (w < 2 * kWords ? ws.prefix[nt * kWords + (w - kWords)] : ws.cbase[nt]));
+            }
+#pragma unroll
+            for (int u = 0; u < kStageIt; ++u) {
+                const int i = tid + u * kThreads;
+                if (i < kStage) {
+                    const int t = i / (2 * kWords + 1), w = i % (2 * kWords + 1);
+                    if (w < kWords) m.smask[t][w] = sv[u];
+                    else if (w < 2 * kWords) m.spref[t][w - kWords] = sv[u];
+                    else m.sbase[t] = sv[u];
+                }
             }
         }
         __syncthreads();
@@ -955,29 +1095,66 @@ __global__ __launch_bounds__(kThreads, 4) void k_curv_gather_direct(float* __res
             if (e < nband) {
                 const int cl = band[e];
                 const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
+                if constexpr (NBR) {
 #pragma unroll 1
-                for (int q0 = 0; q0 < 27; q0 += 9) {
-                    float v[9];
-                    unsigned has = 0u;
+                    for (int q0 = 0; q0 < 27; q0 += 9) {
+                        float v[9], hv[9][3];
+                        unsigned has = 0u;
 #pragma unroll
-                    for (int qq = 0; qq < 9; ++qq) {
-                        bool src;
-                        const unsigned r = source_row(m, cx, cy, cz, q0 + qq, src);
-                        const bool stored = src && r < ws.rows;
-                        miss |= src && !stored;
-                        has |= stored ? (1u << qq) : 0u;
-                        // a non-source reads entry q of row 0 (rows >= 1 here) and is masked out
-                        v[qq] = ws.contrib[(stored ? r : 0u) * 27u + static_cast<unsigned>(q0 + qq)];
+                        for (int qq = 0; qq < 9; ++qq) {
+                            bool src;
+                            const unsigned r = source_row(m, cx, cy, cz, q0 + qq, src);
+                            const bool stored = src && r < ws.rows;
+                            miss |= src && !stored;
+                            has |= stored ? (1u << qq) : 0u;
+                            const unsigned rr = stored ? r : 0u;  // rows >= 1: row 0 read and masked out
+                            v[qq] = ws.contrib[rr * ROWF + static_cast<unsigned>(q0 + qq)];
+                            hv[qq][0] = ws.hbar[3u * rr];
+                            hv[qq][1] = ws.hbar[3u * rr + 1u];
+                            hv[qq][2] = ws.hbar[3u * rr + 2u];
+                        }
+#pragma unroll
+                        for (int qq = 0; qq < 9; ++qq) {
+                            // the source's own gradient h = sum_q w_q e_q phi_(source + e_q)
+                            const int q = q0 + qq;
+                            const int e2 = q_dx(q) * q_dx(q) + q_dy(q) * q_dy(q) + q_dz(q) * q_dz(q);
+                            const float wq = static_cast<float>(q == 13 ? 0 : nrm_weight<NRM>(e2));
+                            const float t = v[qq] + wq * (static_cast<float>(q_dx(q)) * hv[qq][0] +
+                                                          static_cast<float>(q_dy(q)) * hv[qq][1] +
+                                                          static_cast<float>(q_dz(q)) * hv[qq][2]);
+                            a += (has >> qq) & 1u ? t : 0.0f;
+                        }
                     }
+                } else {
+#pragma unroll 1
+                    for (int q0 = 0; q0 < 27; q0 += 9) {
+                        float v[9];
+                        unsigned has = 0u;
 #pragma unroll
-                    for (int qq = 0; qq < 9; ++qq) a += (has >> qq) & 1u ? v[qq] : 0.0f;
+                        for (int qq = 0; qq < 9; ++qq) {
+                            bool src;
+                            const unsigned r = source_row(m, cx, cy, cz, q0 + qq, src);
+                            const bool stored = src && r < ws.rows;
+                            miss |= src && !stored;
+                            has |= stored ? (1u << qq) : 0u;
+                            // a non-source reads entry q of row 0 (rows >= 1 here) and is masked out
+                            v[qq] = ws.contrib[(stored ? r : 0u) * 27u + static_cast<unsigned>(q0 + qq)];
+                        }
+#pragma unroll
+                        for (int qq = 0; qq < 9; ++qq) a += (has >> qq) & 1u ? v[qq] : 0.0f;
+                    }
                 }
             }
             acc[k] = a;
         }
         if (__syncthreads_or(miss)) {                                // uniform per workgroup
-            if (tid == 0) ws.over[atomicAdd(ws.counter + 2, 1u)] = static_cast<unsigned>(tile);
-            continue;
+            if constexpr (NBR) {
+#pragma unroll
+                for (int k = 0; k < kCellsPerThread; ++k) acc[k] = __builtin_nanf("");
+            } else {
+                if (tid == 0) ws.over[atomicAdd(ws.counter + 2, 1u)] = static_cast<unsigned>(tile);
+                continue;
+            }
         }
 #pragma unroll
         for (int k = 0; k < kCellsPerThread; ++k) {
@@ -1020,7 +1197,8 @@ int check_lattice(int64_t X, int64_t Y, int64_t Z, bool* empty, Grid* g) {
 
 size_t fixed_bytes(const Grid& g) { return 256 + static_cast<size_t>(g.ntiles) * kFixedPerTile; }
 
-Workspace carve(void* base, size_t bytes, const Grid& g) {
+// nbr: the neighbour-normal backward's rows (and their gradient adjoints)
+Workspace carve(void* base, size_t bytes, const Grid& g, bool nbr = false) {
     char* p = static_cast<char*>(base);
     const size_t nt = static_cast<size_t>(g.ntiles);
     Workspace w;
@@ -1033,8 +1211,10 @@ Workspace carve(void* base, size_t bytes, const Grid& g) {
     w.tiles = w.items + nt * kMaxParts;
     w.over = w.tiles + nt;
     w.contrib = reinterpret_cast<float*>(w.over + nt);
-    const size_t rows = (bytes - fixed_bytes(g)) / kRowBytes;
-    w.rows = static_cast<unsigned>(rows < kRowLimit ? rows : kRowLimit);
+    const size_t rows = (bytes - fixed_bytes(g)) / (nbr ? kRowBytesNbr : kRowBytes);
+    const unsigned limit = nbr ? kRowLimitNbr : kRowLimit;
+    w.rows = static_cast<unsigned>(rows < limit ? rows : limit);
+    w.hbar = nbr ? w.contrib + static_cast<size_t>(w.rows) * kRowFloatsNbr : nullptr;
     return w;
 }
 
@@ -1094,26 +1274,52 @@ void launch_bwd_t(const float* phi, const float* gk, float* gp, Workspace ws, in
     hipLaunchKernelGGL(k_curv_dilate, dim3((g.ntiles + kThreads - 1) / kThreads), dim3(kThreads), 0, st, ws, g.ntx,
                        g.nty, g.ntz, g.ntiles);
     if (ws.rows > 0) launch_items<SOLVER, T, U, F, true, NRM, false>(phi, gk, nullptr, ws, X, Y, Z, g, st);
-    hipLaunchKernelGGL(k_curv_gather_direct, dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0, st, gp, ws, X, Y, Z,
-                       g.ntx, g.nty, g.ntz);
+    hipLaunchKernelGGL((k_curv_gather_direct<false, 0>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0, st, gp,
+                       ws, X, Y, Z, g.ntx, g.nty, g.ntz);
     // usually empty: a small grid keeps the launch cheap when nothing overflowed
     hipLaunchKernelGGL((k_curv_gather_fallback<SOLVER, T, U, F, NRM>), dim3(g.ntiles < 512 ? g.ntiles : 512),
                        dim3(kThreads), 0, st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
 }
 
+// neighbour-normal backward: the rows (contributions and the neighbours'
+// gradient adjoints), the gradient adjoint per interface cell, then the
+// gather; there is no fallback (the entry point requires one row at least)
+template <int SOLVER, class T, class U, class F, int NRM>
+void launch_bwd_nbr_t(const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y, int Z,
+                      const Grid& g, hipStream_t st) {
+    const int nb = (g.ntiles + kPrefixBlock - 1) / kPrefixBlock;
+    hipLaunchKernelGGL(k_curv_prefix_a, dim3(nb), dim3(kThreads), 0, st, ws, g.ntiles);
+    hipLaunchKernelGGL(k_curv_prefix_b, dim3(nb), dim3(kThreads), 0, st, ws, g.ntiles);
+    hipLaunchKernelGGL(k_curv_dilate, dim3((g.ntiles + kThreads - 1) / kThreads), dim3(kThreads), 0, st, ws, g.ntx,
+                       g.nty, g.ntz, g.ntiles);
+    launch_items<SOLVER, T, U, F, true, NRM, true>(phi, gk, nullptr, ws, X, Y, Z, g, st);
+    hipLaunchKernelGGL(k_curv_hgather, dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0, st, ws, g.ntx, g.nty,
+                       g.ntz);
+    hipLaunchKernelGGL((k_curv_gather_direct<true, NRM>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0, st, gp,
+                       ws, X, Y, Z, g.ntx, g.nty, g.ntz);
+}
+
 template <int SOLVER, class T, class U, class F>
-void launch_bwd_n(int normal, const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y, int Z,
-                  const Grid& g, hipStream_t st) {
-    if (normal == kNormalCM) launch_bwd_t<SOLVER, T, U, F, kNormalCM>(phi, gk, gp, ws, X, Y, Z, g, st);
-    else launch_bwd_t<SOLVER, T, U, F, kNormalPY>(phi, gk, gp, ws, X, Y, Z, g, st);
+void launch_bwd_n(int normal, bool nbr, const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y,
+                  int Z, const Grid& g, hipStream_t st) {
+    if (nbr) {
+        if (normal == kNormalCM) launch_bwd_nbr_t<SOLVER, T, U, F, kNormalCM>(phi, gk, gp, ws, X, Y, Z, g, st);
+        else launch_bwd_nbr_t<SOLVER, T, U, F, kNormalPY>(phi, gk, gp, ws, X, Y, Z, g, st);
+    } else {
+        if (normal == kNormalCM) launch_bwd_t<SOLVER, T, U, F, kNormalCM>(phi, gk, gp, ws, X, Y, Z, g, st);
+        else launch_bwd_t<SOLVER, T, U, F, kNormalPY>(phi, gk, gp, ws, X, Y, Z, g, st);
+    }
 }
 
 template <int SOLVER>
-void launch_bwd(int precision, int normal, const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y,
-                int Z, const Grid& g, hipStream_t st) {
-    if (precision == PLIC_FP32) launch_bwd_n<SOLVER, float, float, float>(normal, phi, gk, gp, ws, X, Y, Z, g, st);
-    else if (precision == PLIC_MIXED) launch_bwd_n<SOLVER, float, double, double>(normal, phi, gk, gp, ws, X, Y, Z, g, st);
-    else launch_bwd_n<SOLVER, double, double, double>(normal, phi, gk, gp, ws, X, Y, Z, g, st);
+void launch_bwd(int precision, int normal, bool nbr, const float* phi, const float* gk, float* gp, Workspace ws,
+                int X, int Y, int Z, const Grid& g, hipStream_t st) {
+    if (precision == PLIC_FP32)
+        launch_bwd_n<SOLVER, float, float, float>(normal, nbr, phi, gk, gp, ws, X, Y, Z, g, st);
+    else if (precision == PLIC_MIXED)
+        launch_bwd_n<SOLVER, float, double, double>(normal, nbr, phi, gk, gp, ws, X, Y, Z, g, st);
+    else
+        launch_bwd_n<SOLVER, double, double, double>(normal, nbr, phi, gk, gp, ws, X, Y, Z, g, st);
 }
 
 // shared argument checks of the two entry points
@@ -1142,6 +1348,15 @@ size_t plic_curvature_workspace_bytes(int64_t X, int64_t Y, int64_t Z) {
     Grid g;
     if (check_lattice(X, Y, Z, &empty, &g) != PLIC_OK || empty) return 0;
     return fixed_bytes(g) + static_cast<size_t>(g.ntiles) * kDefaultRowsPerTile * kRowBytes;
+}
+
+size_t plic_curvature_workspace_bytes_ex(int64_t X, int64_t Y, int64_t Z, int neighbour_normals) {
+    bool empty;
+    Grid g;
+    if (neighbour_normals != 0 && neighbour_normals != 1) return 0;
+    if (check_lattice(X, Y, Z, &empty, &g) != PLIC_OK || empty) return 0;
+    if (!neighbour_normals) return fixed_bytes(g) + static_cast<size_t>(g.ntiles) * kDefaultRowsPerTile * kRowBytes;
+    return fixed_bytes(g) + static_cast<size_t>(g.ntiles) * kDefaultRowsPerTileNbr * kRowBytesNbr;
 }
 
 int plic_curvature_ex_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float* kappa, int solver,
@@ -1179,14 +1394,16 @@ int plic_curvature_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float*
 }
 
 int plic_curvature_backward_ex_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, const float* grad_kappa,
-                                   float* grad_phi, int solver, int precision, int normal, void* workspace,
-                                   size_t workspace_bytes, void* stream) {
+                                   float* grad_phi, int solver, int precision, int normal, int neighbour_normals,
+                                   void* workspace, size_t workspace_bytes, void* stream) {
     bool empty;
     Grid g{};
     int64_t n = 0;
     if (check_common(phi, X, Y, Z, solver, precision, workspace, workspace_bytes, &empty, &g, &n) != PLIC_OK)
         return PLIC_EINVAL;
-    if (!valid_normal(normal)) return PLIC_EINVAL;
+    if (!valid_normal(normal) || (neighbour_normals != 0 && neighbour_normals != 1)) return PLIC_EINVAL;
+    // the neighbour-normal backward has no fallback: it needs one row at least
+    if (!empty && neighbour_normals && workspace_bytes < fixed_bytes(g) + kRowBytesNbr) return PLIC_EINVAL;
     if (!valid_array(grad_kappa, n) || !valid_array(grad_phi, n)) return PLIC_EINVAL;
     const size_t nb = static_cast<size_t>(n) * sizeof(float);
     if (overlap(grad_phi, nb, phi, nb) || overlap(grad_phi, nb, grad_kappa, nb)) return PLIC_EINVAL;
@@ -1195,14 +1412,15 @@ int plic_curvature_backward_ex_f32(const float* phi, int64_t X, int64_t Y, int64
         return PLIC_EINVAL;
     if (empty) return PLIC_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const Workspace ws = carve(workspace, workspace_bytes, g);
+    const bool nbr = neighbour_normals != 0;
+    const Workspace ws = carve(workspace, workspace_bytes, g, nbr);
     const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
     launch_scan<false>(phi, grad_phi, ws, x, y, z, g, st);
     switch (solver) {
-        case kSZ: launch_bwd<kSZ>(precision, normal, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
-        case kNewton: launch_bwd<kNewton>(precision, normal, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
-        case kNested: launch_bwd<kNested>(precision, normal, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
-        default: launch_bwd<kAnalytic>(precision, normal, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
+        case kSZ: launch_bwd<kSZ>(precision, normal, nbr, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
+        case kNewton: launch_bwd<kNewton>(precision, normal, nbr, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
+        case kNested: launch_bwd<kNested>(precision, normal, nbr, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
+        default: launch_bwd<kAnalytic>(precision, normal, nbr, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
     }
     return launch_status();
 }
@@ -1210,7 +1428,7 @@ int plic_curvature_backward_ex_f32(const float* phi, int64_t X, int64_t Y, int64
 int plic_curvature_backward_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, const float* grad_kappa,
                                 float* grad_phi, int solver, int precision, void* workspace,
                                 size_t workspace_bytes, void* stream) {
-    return plic_curvature_backward_ex_f32(phi, X, Y, Z, grad_kappa, grad_phi, solver, precision, PLIC_NORMAL_PY,
+    return plic_curvature_backward_ex_f32(phi, X, Y, Z, grad_kappa, grad_phi, solver, precision, PLIC_NORMAL_PY, 0,
                                           workspace, workspace_bytes, stream);
 }
 

@@ -142,9 +142,15 @@ def test_curvature_options_validation(lib):
     assert f(A, 4, 4, 4, B, 0, 1, 1, 2, W, ws, None) == -1              # bad neighbour flag
     assert f(A, 4, 4, 4, A + 64, 0, 1, 1, 1, W, ws, None) == -1         # kappa overlaps phi
     g = lib.raw("plic_curvature_backward_ex_f32")
-    assert g(A, 3, 3, 0, B, C, 0, 1, 1, None, 0, None) == 0
-    assert g(A, 3, 3, 3, B, C, 0, 1, 5, W, ws, None) == -1              # bad normal
-    assert g(A, 3, 3, 3, B, A, 0, 1, 1, W, ws, None) == -1              # grad_phi overlaps phi
+    assert g(A, 3, 3, 0, B, C, 0, 1, 1, 1, None, 0, None) == 0           # empty lattice
+    assert g(A, 3, 3, 3, B, C, 0, 1, 5, 0, W, ws, None) == -1           # bad normal
+    assert g(A, 3, 3, 3, B, C, 0, 1, 0, 2, W, ws, None) == -1           # bad neighbour flag
+    assert g(A, 3, 3, 3, B, A, 0, 1, 1, 1, W, ws, None) == -1           # grad_phi overlaps phi
+    fixed = 256 + 784                                                   # one tile
+    assert g(A, 3, 3, 3, B, C, 0, 1, 0, 1, W, fixed + 431, None) == -1  # neighbour normals: no row
+    assert lib.plic_curvature_workspace_bytes_ex(4, 4, 4, 1) == fixed + 64 * 432
+    assert lib.plic_curvature_workspace_bytes_ex(4, 4, 4, 0) == lib.plic_curvature_workspace_bytes(4, 4, 4)
+    assert lib._lib.plic_curvature_workspace_bytes_ex(4, 4, 4, 2) == 0       # bad flag (C entry point)
 
 
 def test_sphere_validation(lib):

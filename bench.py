@@ -437,17 +437,20 @@ def curvature_warm(P, torch, tphi, tgk, kap, gphi, ws):
 
 def curvature_variants(P, torch, tphi, tgk, kap, gphi, ws):
     """The curvature options beside the base method, on the same 256^3 lattice
-    (warm cache, back-to-back calls): the centre-of-mass normal (forward and
-    backward) and each interface neighbour's own normal (forward only, 5^3
-    neighbourhood)."""
+    (warm cache, back-to-back calls): the centre-of-mass normal and each
+    interface neighbour's own normal (5^3 neighbourhood), forward and backward."""
     stream = torch.cuda.current_stream(tphi.device)
     n = tphi.numel()
+    Z, Y, X = tphi.shape
+    ws_nbr = torch.empty(P.plic_curvature_workspace_bytes_ex(X, Y, Z, True), dtype=torch.uint8, device=tphi.device)
     res = {}
     for name, fn in (
             ("cm_fwd", lambda: P.plic_curvature_ex_f32(tphi, kap, "analytic", "mixed", "cm", False, ws)),
-            ("cm_bwd", lambda: P.plic_curvature_backward_ex_f32(tphi, tgk, gphi, "analytic", "mixed", "cm", ws)),
+            ("cm_bwd", lambda: P.plic_curvature_backward_ex_f32(tphi, tgk, gphi, "analytic", "mixed", "cm", False, ws)),
             ("neighbour_normals_fwd",
-             lambda: P.plic_curvature_ex_f32(tphi, kap, "analytic", "mixed", "py", True, ws))):
+             lambda: P.plic_curvature_ex_f32(tphi, kap, "analytic", "mixed", "py", True, ws)),
+            ("neighbour_normals_bwd",
+             lambda: P.plic_curvature_backward_ex_f32(tphi, tgk, gphi, "analytic", "mixed", "py", True, ws_nbr))):
         ms = timed_reps(torch, stream, fn)
         res[name] = {"ms": round(ms, 4), "cells_per_s": n / (ms * 1e-3)}
     return res

@@ -1,6 +1,7 @@
 """GPU parity of the curvature options against the FP64 oracle: the
 centre-of-mass normal (forward and backward) and the neighbour-normal
-variant (forward), with the per-cell bar of the curvature tests."""
+variant (forward; its backward has a file of its own), with the per-cell bar
+of the curvature tests."""
 import numpy as np
 import pytest
 import torch

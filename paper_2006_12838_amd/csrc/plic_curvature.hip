@@ -951,7 +951,7 @@ __device__ __forceinline__ void stage_sources(SourceMap& m, const Workspace& ws,
 // neighbours c = n - e_q of the adjoint that c stored for its neighbour at
 // +e_q (that is n): the adjoint of n's own fill-level gradient, written to the
 // 3-vector beside n's row.  A source without a stored row makes it NaN.
-__global__ __launch_bounds__(kThreads) void k_curv_hgather(Workspace ws, int ntx, int nty, int ntz) {
+__global__ __launch_bounds__(kThreads, 4) void k_curv_hgather(Workspace ws, int ntx, int nty, int ntz) {
     __shared__ SourceMap m;
     const int tid = threadIdx.x;
     const unsigned ntl = *static_cast<volatile unsigned*>(ws.counter + 1);
@@ -969,20 +969,35 @@ __global__ __launch_bounds__(kThreads) void k_curv_hgather(Workspace ws, int ntx
             if (!self || rn >= ws.rows) continue;                       // no row: the gather sees the miss
             float h0 = 0.0f, h1 = 0.0f, h2 = 0.0f;
             bool miss = false;
+            // sources in groups of 9, every load of a group issued before its
+            // adds; a non-source reads row 0 (rows >= 1 here) and is masked out
 #pragma unroll 1
-            for (int q = 0; q < 27; ++q) {
-                if (q == 13) continue;
-                bool src;
-                const unsigned r = source_row(m, cx, cy, cz, q, src);
-                if (!src) continue;
-                if (r >= ws.rows) {
-                    miss = true;
-                    continue;
+            for (int q0 = 0; q0 < 27; q0 += 9) {
+                float hv[9][3];
+                unsigned has = 0u;
+#pragma unroll
+                for (int qq = 0; qq < 9; ++qq) {
+                    const int q = q0 + qq;
+                    bool src;
+                    const unsigned r = source_row(m, cx, cy, cz, q, src);
+                    src = src && q != 13;
+                    const bool stored = src && r < ws.rows;
+                    miss |= src && !stored;
+                    has |= stored ? (1u << qq) : 0u;
+                    const unsigned b = (stored ? r : 0u) * static_cast<unsigned>(kRowFloatsNbr) + 27u +
+                                       3u * static_cast<unsigned>(q < 13 ? q : (q == 13 ? 0 : q - 1));
+                    hv[qq][0] = ws.contrib[b];
+                    hv[qq][1] = ws.contrib[b + 1];
+                    hv[qq][2] = ws.contrib[b + 2];
                 }
-                const unsigned b = r * static_cast<unsigned>(kRowFloatsNbr) + 27u + 3u * static_cast<unsigned>(q < 13 ? q : q - 1);
-                h0 += ws.contrib[b];
-                h1 += ws.contrib[b + 1];
-                h2 += ws.contrib[b + 2];
+#pragma unroll
+                for (int qq = 0; qq < 9; ++qq) {
+                    if ((has >> qq) & 1u) {
+                        h0 += hv[qq][0];
+                        h1 += hv[qq][1];
+                        h2 += hv[qq][2];
+                    }
+                }
             }
             const float nan = __builtin_nanf("");
             ws.hbar[3 * rn] = miss ? nan : h0;

@@ -162,7 +162,12 @@ __host__ __device__ constexpr int tri(int i, int k) { return i * (i + 1) / 2 + k
 // Every lane of the group must call it.  Returns kappa (same bits on every
 // lane).  With ADJ, also writes out[q] = gk * d kappa / d phi_q (q = 0..26)
 // from the lane that owns q, with the interface mask, the PLIC cases and the
-// active fit parameters held fixed.
+// active fit parameters held fixed.  With NBR (neighbour normals: each
+// interface neighbour's point from its own normal m = -h / |h|, h its 3^3
+// fill-level gradient), out[q] holds the derivative with every m held fixed,
+// and lane j also writes out[27 + 3j .. 29 + 3j] = gk * d kappa / d h of its
+// neighbour (zero where the neighbour keeps the centre normal); spreading that
+// over the neighbour's 3^3 is left to the gathers.
 // ---------------------------------------------------------------------------
 // weight of neighbour offset e in the fill-level gradient (App. B.1):
 // Parker-Youngs 4 / 2 / 1 for |e|^2 = 1 / 2 / 3, centre of mass 1

@@ -699,6 +699,29 @@ __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx,
 // contribution row (when it fits).
 // ---------------------------------------------------------------------------
 
+// Lattice position of the interface cell of rank i (in cell order) of a
+// tile, found by the 32 lanes of a group together: lane j reads mask word j
+// and the count of set bits before it.  False, for the whole group, when the
+// tile has no more than i interface cells.
+__device__ __forceinline__ bool tile_cell(const Workspace& ws, int tile, int i, int j, int half, int ntx, int nty,
+                                          int& gx, int& gy, int& gz) {
+    const unsigned mw = ws.mask[tile * kWords + j], pw = ws.prefix[tile * kWords + j];
+    const int n = static_cast<int>(__shfl(pw + __popc(mw), kWords - 1, kGroup));
+    if (i >= n) return false;
+    const unsigned ui = static_cast<unsigned>(i);
+    const unsigned in_word = static_cast<unsigned>(__ballot(pw <= ui && ui < pw + __popc(mw)) >> half);
+    const int w = __ffs(static_cast<int>(in_word)) - 1;
+    const unsigned word = __shfl(mw, w, kGroup);
+    const unsigned k = ui - __shfl(pw, w, kGroup);
+    const bool hit = ((word >> j) & 1u) && static_cast<unsigned>(__popc(word & ((1u << j) - 1u))) == k;
+    const int b = __ffs(static_cast<int>(static_cast<unsigned>(__ballot(hit) >> half))) - 1;
+    const int cl = w * 32 + b;
+    gx = (tile % ntx) * TX + cl % TX;
+    gy = ((tile / ntx) % nty) * TY + (cl / TX) % TY;
+    gz = (tile / (ntx * nty)) * TZ + cl / (TX * TY);
+    return true;
+}
+
 // Waves per SIMD the work items are compiled for: the work is a chain of
 // dependent steps per cell, so concurrency (VGPRs at most 128 for 4 waves, 168
 // for 3) sets the time.  The forward fits 4 without spilling; the adjoint fits
@@ -728,7 +751,8 @@ __global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, ADJ, NBR>())) voi
             row = ws.cbase[tile] + static_cast<unsigned>(i);
             if (row >= ws.rows) continue;                    // uniform per group; the gather recomputes
         }
-        // lane j holds mask word j and the count of set bits before it
+        // tile_cell written out (through the call the mixed-precision adjoint
+        // spills): lane j holds mask word j and the count of set bits before it
         const unsigned mw = ws.mask[tile * kWords + j], pw = ws.prefix[tile * kWords + j];
         const int n = static_cast<int>(__shfl(pw + __popc(mw), kWords - 1, kGroup));
         if (i >= n) continue;                                // uniform per group
@@ -892,6 +916,59 @@ __global__ __launch_bounds__(kThreads) void k_curv_gather_fallback(const float* 
     }
 }
 
+// Neighbour-normal backward, between the work items and the gather: over the
+// work items, one 32-lane group per interface cell n, lane j < 26 taking the
+// neighbour q of the adjoint's lane order.  The source c = n - e_q, when an
+// interface cell, stored in slot j of its row the adjoint for its neighbour at
+// +e_q, which is n: the adjoint of n's own fill-level gradient is the sum of
+// these 26 slots (zero where c is no interface cell), formed by a fixed
+// butterfly and written to the 3-vector beside n's row.  A source without a
+// stored row makes it NaN.
+__global__ __launch_bounds__(kThreads) void k_curv_hgather(Workspace ws, int X, int Y, int Z, int ntx, int nty) {
+    const int tid = threadIdx.x, grp = tid / kGroup, j = tid % kGroup;
+    const int half = tid & 32;
+    const int q = j < 13 ? j : j + 1;
+    const unsigned nitems = *static_cast<volatile unsigned*>(ws.counter);
+    for (unsigned item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const unsigned e = ws.items[item];
+        const int tile = static_cast<int>(e >> 7), part = static_cast<int>(e & 127u);
+        const int i = part * kPartCells + grp;
+        const unsigned row = ws.cbase[tile] + static_cast<unsigned>(i);
+        if (row >= ws.rows) continue;                        // uniform per group; the gather sees the miss
+        int gx, gy, gz;
+        if (!tile_cell(ws, tile, i, j, half, ntx, nty, gx, gy, gz)) continue;
+        const int cx = gx - q_dx(q), cy = gy - q_dy(q), cz = gz - q_dz(q);
+        bool src = j < 26 && cx >= 0 && cx < X && cy >= 0 && cy < Y && cz >= 0 && cz < Z;
+        unsigned r = 0u;
+        if (src) {
+            const int ctile = ((cz / TZ) * nty + cy / TY) * ntx + cx / TX;
+            const int l = ((cz % TZ) * TY + cy % TY) * TX + cx % TX;
+            const unsigned w = ws.mask[ctile * kWords + l / 32], bit = 1u << (l % 32);
+            src = (w & bit) != 0u;
+            r = ws.cbase[ctile] + ws.prefix[ctile * kWords + l / 32] + __popc(w & (bit - 1u));
+        }
+        const bool stored = src && r < ws.rows;
+        const bool miss = ((__ballot(src && !stored) >> half) & 0xffffffffull) != 0ull;
+        float h0 = 0.0f, h1 = 0.0f, h2 = 0.0f;
+        if (stored) {
+            const float* p = ws.contrib + static_cast<size_t>(r) * kRowFloatsNbr + 27 + 3 * j;
+            h0 = p[0];
+            h1 = p[1];
+            h2 = p[2];
+        }
+#pragma unroll
+        for (int o = kGroup / 2; o > 0; o >>= 1) {
+            h0 += __shfl_xor(h0, o, kGroup);
+            h1 += __shfl_xor(h1, o, kGroup);
+            h2 += __shfl_xor(h2, o, kGroup);
+        }
+        if (j < 3) {
+            const float h = j == 0 ? h0 : (j == 1 ? h1 : h2);
+            ws.hbar[3u * row + static_cast<unsigned>(j)] = miss ? __builtin_nanf("") : h;
+        }
+    }
+}
+
 // Direct backward gather for the tiles whose sources all have a stored row.
 // The interface bitmasks, prefix counts and first rows of the 3x3x3 tiles
 // around the tile are staged in LDS.  Each of the tile's cells tests its 27
@@ -921,98 +998,6 @@ __device__ __forceinline__ unsigned source_row(const SourceMap& m, int cx, int c
     return m.sbase[tq] + m.spref[tq][l >> 5] + __popc(word & (bit - 1u));
 }
 
-// Stages the interface bitmasks, prefix counts and first rows of the 3x3x3
-// tiles around tile (tx, ty, tz) in LDS (zeros outside the lattice); every
-// load is issued before the first store.  Block-wide; the caller syncs.
-__device__ __forceinline__ void stage_sources(SourceMap& m, const Workspace& ws, int tx, int ty, int tz, int ntx,
-                                              int nty, int ntz) {
-    constexpr int kStage = 27 * (2 * kWords + 1), kStageIt = (kStage + kThreads - 1) / kThreads;
-    const int tid = threadIdx.x;
-    unsigned sv[kStageIt];
-#pragma unroll
-    for (int u = 0; u < kStageIt; ++u) {
-        const int i = tid + u * kThreads;
-        const int t = i / (2 * kWords + 1), w = i % (2 * kWords + 1);
-        const int ax = tx + q_dx(t), ay = ty + q_dy(t), az = tz + q_dz(t);
-        const bool in = i < kStage && ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz;
-        const int nt = (az * nty + ay) * ntx + ax;
-        sv[u] = !in ? 0u : (w < kWords ? ws.mask[nt * kWords + w]
-                                       : (w < 2 * kWords ? ws.prefix[nt * kWords + (w - kWords)] : ws.cbase[nt]));
-    }
-#pragma unroll
-    for (int u = 0; u < kStageIt; ++u) {
-        const int i = tid + u * kThreads;
-        if (i < kStage) {
-            const int t = i / (2 * kWords + 1), w = i % (2 * kWords + 1);
-            if (w < kWords) m.smask[t][w] = sv[u];
-            else if (w < 2 * kWords) m.spref[t][w - kWords] = sv[u];
-            else m.sbase[t] = sv[u];
-        }
-    }
-}
-
-// Neighbour-normal backward, between the work items and the gather: for every
-// interface cell n of a gather tile, the sum in q order over its interface
-// neighbours c = n - e_q of the adjoint that c stored for its neighbour at
-// +e_q (that is n): the adjoint of n's own fill-level gradient, written to the
-// 3-vector beside n's row.  A source without a stored row makes it NaN.
-__global__ __launch_bounds__(kThreads, 4) void k_curv_hgather(Workspace ws, int ntx, int nty, int ntz) {
-    __shared__ SourceMap m;
-    const int tid = threadIdx.x;
-    const unsigned ntl = *static_cast<volatile unsigned*>(ws.counter + 1);
-    for (unsigned it = blockIdx.x; it < ntl; it += gridDim.x) {
-        const int tile = static_cast<int>(ws.tiles[it]);
-        const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
-        stage_sources(m, ws, tx, ty, tz, ntx, nty, ntz);
-        __syncthreads();
-#pragma unroll 1
-        for (int k = 0; k < kCellsPerThread; ++k) {
-            const int cl = tid + k * kThreads;
-            const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-            bool self;
-            const unsigned rn = source_row(m, cx, cy, cz, 13, self);   // the cell's own row
-            if (!self || rn >= ws.rows) continue;                       // no row: the gather sees the miss
-            float h0 = 0.0f, h1 = 0.0f, h2 = 0.0f;
-            bool miss = false;
-            // sources in groups of 9, every load of a group issued before its
-            // adds; a non-source reads row 0 (rows >= 1 here) and is masked out
-#pragma unroll 1
-            for (int q0 = 0; q0 < 27; q0 += 9) {
-                float hv[9][3];
-                unsigned has = 0u;
-#pragma unroll
-                for (int qq = 0; qq < 9; ++qq) {
-                    const int q = q0 + qq;
-                    bool src;
-                    const unsigned r = source_row(m, cx, cy, cz, q, src);
-                    src = src && q != 13;
-                    const bool stored = src && r < ws.rows;
-                    miss |= src && !stored;
-                    has |= stored ? (1u << qq) : 0u;
-                    const unsigned b = (stored ? r : 0u) * static_cast<unsigned>(kRowFloatsNbr) + 27u +
-                                       3u * static_cast<unsigned>(q < 13 ? q : (q == 13 ? 0 : q - 1));
-                    hv[qq][0] = ws.contrib[b];
-                    hv[qq][1] = ws.contrib[b + 1];
-                    hv[qq][2] = ws.contrib[b + 2];
-                }
-#pragma unroll
-                for (int qq = 0; qq < 9; ++qq) {
-                    if ((has >> qq) & 1u) {
-                        h0 += hv[qq][0];
-                        h1 += hv[qq][1];
-                        h2 += hv[qq][2];
-                    }
-                }
-            }
-            const float nan = __builtin_nanf("");
-            ws.hbar[3 * rn] = miss ? nan : h0;
-            ws.hbar[3 * rn + 1] = miss ? nan : h1;
-            ws.hbar[3 * rn + 2] = miss ? nan : h2;
-        }
-        __syncthreads();                                             // LDS reused by the next tile
-    }
-}
-
 // NBR: the neighbour-normal variant's rows, plus each source's own-gradient
 // adjoint spread by the gradient weights of NRM; a tile with a source beyond
 // the store gets NaN on its band (that variant has no fallback)
@@ -1035,7 +1020,7 @@ __global__ __launch_bounds__(kThreads, (NBR ? 3 : 4)) void k_curv_gather_direct(
         const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
         {
-            // stage_sources written out: as a call it costs this kernel a spill
+            // the 3x3x3 tiles' bitmasks, prefix counts and first rows (zeros outside)
             constexpr int kStage = 27 * (2 * kWords + 1), kStageIt = (kStage + kThreads - 1) / kThreads;
             unsigned sv[kStageIt];
 #pragma unroll
@@ -1313,8 +1298,8 @@ void launch_bwd_nbr_t(const float* phi, const float* gk, float* gp, Workspace ws
     hipLaunchKernelGGL(k_curv_dilate, dim3((g.ntiles + kThreads - 1) / kThreads), dim3(kThreads), 0, st, ws, g.ntx,
                        g.nty, g.ntz, g.ntiles);
     launch_items<SOLVER, T, U, F, true, NRM, true>(phi, gk, nullptr, ws, X, Y, Z, g, st);
-    hipLaunchKernelGGL(k_curv_hgather, dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0, st, ws, g.ntx, g.nty,
-                       g.ntz);
+    hipLaunchKernelGGL(k_curv_hgather, dim3(persistent_grid(static_cast<int64_t>(g.ntiles) * kMaxParts)),
+                       dim3(kThreads), 0, st, ws, X, Y, Z, g.ntx, g.nty);
     hipLaunchKernelGGL((k_curv_gather_direct<true, NRM>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0, st, gp,
                        ws, X, Y, Z, g.ntx, g.nty, g.ntz);
 }

@@ -78,9 +78,11 @@ __device__ __forceinline__ void store_part(S* p, int64_t i, int64_t count, const
 }
 
 // LDS of one workgroup: its open problems packed densely, and their roots
+// Open problems of a workgroup; the cubic stage replaces each problem's n1
+// with its root (the thread that reads an entry writes it), which keeps the
+// FP32 kernels within 20 KiB of LDS: 8 workgroups, 8 waves per SIMD.
 template <class T, int VEC> struct PackLds {
     Open<T> q[kBlock * VEC];
-    T root[kBlock * VEC];
     int count[VEC][kBlock / 64];
 };
 
@@ -123,11 +125,11 @@ __device__ __forceinline__ void solve_packed(const Reduced<T> (&r)[VEC], const b
     }
     __syncthreads();
 #pragma unroll 1
-    for (int e = tid; e < total; e += kBlock) sm.root[e] = cubic_stage<SOLVER, T, U>(sm.q[e]);
+    for (int e = tid; e < total; e += kBlock) sm.q[e].n1 = cubic_stage<SOLVER, T, U>(sm.q[e]);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < VEC; ++k)
-        if (open[k]) d[k] = sm.root[slot[k]];
+        if (open[k]) d[k] = sm.q[slot[k]].n1;
 }
 
 // S: storage type, T: bulk arithmetic, U: cubic-case arithmetic.  d0 may be

@@ -722,27 +722,42 @@ __device__ __forceinline__ bool tile_cell(const Workspace& ws, int tile, int i, 
     return true;
 }
 
+// threadIdx.x through an opaque move: what a loop derives from it is then
+// recomputed in every iteration (a few ALU instructions) instead of being
+// kept in registers across the loop, where it would spill
+__device__ __forceinline__ int thread_index_per_iteration() {
+    int t;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"(static_cast<int>(threadIdx.x)));
+    return t;
+}
+
 // Waves per SIMD the work items are compiled for: the work is a chain of
-// dependent steps per cell, so concurrency (VGPRs at most 128 for 4 waves, 168
-// for 3) sets the time.  The forward fits 4 without spilling; the adjoint fits
-// 3, except the SZ solver's and full FP64's, which would spill and keep 2.
-template <int SOLVER, class T, bool ADJ, bool NBR>
+// dependent steps per cell, so concurrency sets the time; each count is the
+// largest that compiles without spilling (VGPRs at most 102 for 5 waves, 128
+// for 4, 168 for 3).  The adjoint of a trigonometric root (analytic, SZ) needs
+// more registers than that of an iterative one; FP64 and the neighbour-normal
+// variant more again.
+template <int SOLVER, class T, class U, bool ADJ, bool NBR>
 constexpr int items_waves() {
-    return !ADJ ? 4 : ((NBR || SOLVER == kSZ || sizeof(T) == 8) ? 2 : 3);
+    const bool iter = SOLVER == kNewton || SOLVER == kNested;
+    if (!ADJ) return 5;
+    if (sizeof(U) == 4) return 4;                                         // FP32
+    if (sizeof(T) == 4) return NBR ? (iter ? 3 : 2) : (iter ? 4 : 3);     // mixed
+    return iter && !NBR ? 3 : 2;                                          // FP64
 }
 
 template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
-__global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, ADJ, NBR>())) void k_curv_items(const float* __restrict__ phi,
+__global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, U, ADJ, NBR>())) void k_curv_items(const float* __restrict__ phi,
                                                           const float* __restrict__ gkap,
                                                           float* __restrict__ kappa, Workspace ws, int X, int Y,
                                                           int Z, int ntx, int nty) {
     constexpr int H = NBR ? 2 : 1, W = 2 * H + 1, NB = W * W * W, C = (H * W + H) * W + H;
     __shared__ float nbh[kGroups][NB];
     __shared__ GroupLds<F> glds[kGroups];
-    const int tid = threadIdx.x, grp = tid / kGroup, j = tid % kGroup;
-    const int half = tid & 32;                               // this group's lanes in the wave
     const unsigned nitems = *static_cast<volatile unsigned*>(ws.counter);
     for (unsigned item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int tid = thread_index_per_iteration(), grp = tid / kGroup, j = tid % kGroup;
+        const int half = tid & 32;                           // this group's lanes in the wave
         const unsigned e = ws.items[item];
         const int tile = static_cast<int>(e >> 7), part = static_cast<int>(e & 127u);
         const int i = part * kPartCells + grp;               // rank of this group's cell
@@ -976,7 +991,7 @@ __global__ __launch_bounds__(kThreads) void k_curv_hgather(Workspace ws, int X, 
 // interface; the rest keep the scan's zero) are listed in cell order, and each
 // adds entry q of its sources' rows for q = 0..26 in order, all loads issued
 // before the first add.  A tile with a source beyond the store goes to the
-// overflow list unwritten.
+// overflow list; the fallback gather rewrites every cell of it.
 struct SourceMap {
     unsigned smask[27][kWords];
     unsigned spref[27][kWords];
@@ -1002,16 +1017,17 @@ __device__ __forceinline__ unsigned source_row(const SourceMap& m, int cx, int c
 // adjoint spread by the gradient weights of NRM; a tile with a source beyond
 // the store gets NaN on its band (that variant has no fallback)
 template <bool NBR, int NRM>
-__global__ __launch_bounds__(kThreads, (NBR ? 3 : 4)) void k_curv_gather_direct(float* __restrict__ gphi, Workspace ws, int X,
+__global__ __launch_bounds__(kThreads, (NBR ? 5 : 8)) void k_curv_gather_direct(float* __restrict__ gphi, Workspace ws, int X,
                                                                   int Y, int Z, int ntx, int nty, int ntz) {
     constexpr unsigned ROWF = NBR ? kRowFloatsNbr : 27;
     __shared__ SourceMap m;
     __shared__ unsigned short band[kTile];
     __shared__ unsigned long long brow[TY * TZ];
-    __shared__ int bcount[TY * TZ];
-    const int tid = threadIdx.x;
+    __shared__ int bpref[TY * TZ];
+    __shared__ int bcount;
     const unsigned ntl = *static_cast<volatile unsigned*>(ws.counter + 1);
     for (unsigned it = blockIdx.x; it < ntl; it += gridDim.x) {
+        const int tid = thread_index_per_iteration();
         const int tile = static_cast<int>(ws.tiles[it]);
         if (ws.rows == 0u) {                                         // nothing stored: all recomputed
             if (tid == 0) ws.over[atomicAdd(ws.counter + 2, 1u)] = static_cast<unsigned>(tile);
@@ -1020,29 +1036,35 @@ __global__ __launch_bounds__(kThreads, (NBR ? 3 : 4)) void k_curv_gather_direct(
         const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
         {
-            // the 3x3x3 tiles' bitmasks, prefix counts and first rows (zeros outside)
-            constexpr int kStage = 27 * (2 * kWords + 1), kStageIt = (kStage + kThreads - 1) / kThreads;
-            unsigned sv[kStageIt];
+            // the 3x3x3 tiles' bitmasks, prefix counts and first rows (zeros
+            // outside): word tid % 32 of tiles tid / 32 + 8u, and first row
+            // tid for tid < 27; every load before the first store
+            constexpr int kPer = kThreads / kWords, kStageIt = (27 + kPer - 1) / kPer;
+            const int w = tid % kWords;
+            unsigned smv[kStageIt], spv[kStageIt], sb = 0u;
 #pragma unroll
-            for (int u = 0; u < kStageIt; ++u) {                      // every load before the first store
-                const int i = tid + u * kThreads;
-                const int t = i / (2 * kWords + 1), w = i % (2 * kWords + 1);
+            for (int u = 0; u < kStageIt; ++u) {
+                const int t = tid / kWords + kPer * u;
                 const int ax = tx + q_dx(t), ay = ty + q_dy(t), az = tz + q_dz(t);
-                const bool in = i < kStage && ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz;
+                const bool in = t < 27 && ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz;
                 const int nt = (az * nty + ay) * ntx + ax;
-                sv[u] = !in ? 0u : (w < kWords ? ws.mask[nt * kWords + w]
-                                               : (w < 2 * kWords ? ws.prefix[nt * kWords + (w - kWords)] : ws.cbase[nt]));
+                smv[u] = in ? ws.mask[nt * kWords + w] : 0u;
+                spv[u] = in ? ws.prefix[nt * kWords + w] : 0u;
+            }
+            if (tid < 27) {
+                const int ax = tx + q_dx(tid), ay = ty + q_dy(tid), az = tz + q_dz(tid);
+                if (ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz)
+                    sb = ws.cbase[(az * nty + ay) * ntx + ax];
             }
 #pragma unroll
             for (int u = 0; u < kStageIt; ++u) {
-                const int i = tid + u * kThreads;
-                if (i < kStage) {
-                    const int t = i / (2 * kWords + 1), w = i % (2 * kWords + 1);
-                    if (w < kWords) m.smask[t][w] = sv[u];
-                    else if (w < 2 * kWords) m.spref[t][w - kWords] = sv[u];
-                    else m.sbase[t] = sv[u];
+                const int t = tid / kWords + kPer * u;
+                if (t < 27) {
+                    m.smask[t][w] = smv[u];
+                    m.spref[t][w] = spv[u];
                 }
             }
+            if (tid < 27) m.sbase[tid] = sb;
         }
         __syncthreads();
         // the band: cells with an interface source within one cell.  Row
@@ -1071,36 +1093,43 @@ __global__ __launch_bounds__(kThreads, (NBR ? 3 : 4)) void k_curv_gather_direct(
             if (gy >= Y || gz >= Z) d = 0ull;
             else if (nx < TX) d &= (1ull << nx) - 1ull;
             brow[tid] = d;
-            bcount[tid] = __popcll(d);
-        }
-        __syncthreads();
-        // band cells listed in cell order (rows in order, x ascending)
-        if (tid < TY * TZ) {
-            int e = 0;
-            for (int r = 0; r < tid; ++r) e += bcount[r];
-            unsigned long long d = brow[tid];
-            while (d) {
-                const int x = __ffsll(static_cast<long long>(d)) - 1;
-                band[e++] = static_cast<unsigned short>(tid * TX + x);
-                d &= d - 1ull;
-            }
-        }
-        int nband = 0;
+            // exclusive prefix of the rows' band counts (the 16 rows are lanes
+            // 0..15 of the first wave)
+            const int c = __popcll(d);
+            int inc = c;
 #pragma unroll
-        for (int r = 0; r < TY * TZ; ++r) nband += bcount[r];
+            for (int o = 1; o < TY * TZ; o <<= 1) {
+                const int v = __shfl_up(inc, o, TY * TZ);
+                if (tid >= o) inc += v;
+            }
+            bpref[tid] = inc - c;
+            if (tid == TY * TZ - 1) bcount = inc;
+        }
         __syncthreads();
-        // band cells: rows of their sources, all loads of a group of 9 issued
-        // before its adds; sums kept until the tile is known to be complete
-        float acc[kCellsPerThread];
-        int miss = 0;
+        // band cells listed in cell order (rows in order, x ascending): each
+        // band cell's place is its row's prefix plus the band bits before it
 #pragma unroll
         for (int k = 0; k < kCellsPerThread; ++k) {
-            const int e = k * kThreads + tid;
-            float a = 0.0f;                                          // +0 + 0 stays +0: same bits as skipping
-            if (e < nband) {
-                const int cl = band[e];
-                const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-                if constexpr (NBR) {
+            const int cl = k * kThreads + tid, r = cl / TX, x = cl % TX;
+            const unsigned long long d = brow[r];
+            if ((d >> x) & 1ull)
+                band[bpref[r] + __popcll(d & ((1ull << x) - 1ull))] = static_cast<unsigned short>(cl);
+        }
+        const int nband = bcount;
+        __syncthreads();
+        if constexpr (NBR) {
+            // band cells: rows of their sources, all loads of a group of 9
+            // issued before its adds; sums kept until the tile is known to be
+            // complete (a missing row makes the tile's band NaN)
+            float acc[kCellsPerThread];
+            int miss = 0;
+#pragma unroll
+            for (int k = 0; k < kCellsPerThread; ++k) {
+                const int e = k * kThreads + tid;
+                float a = 0.0f;
+                if (e < nband) {
+                    const int cl = band[e];
+                    const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
 #pragma unroll 1
                     for (int q0 = 0; q0 < 27; q0 += 9) {
                         float v[9], hv[9][3];
@@ -1130,45 +1159,54 @@ __global__ __launch_bounds__(kThreads, (NBR ? 3 : 4)) void k_curv_gather_direct(
                             a += (has >> qq) & 1u ? t : 0.0f;
                         }
                     }
-                } else {
-#pragma unroll 1
-                    for (int q0 = 0; q0 < 27; q0 += 9) {
-                        float v[9];
-                        unsigned has = 0u;
-#pragma unroll
-                        for (int qq = 0; qq < 9; ++qq) {
-                            bool src;
-                            const unsigned r = source_row(m, cx, cy, cz, q0 + qq, src);
-                            const bool stored = src && r < ws.rows;
-                            miss |= src && !stored;
-                            has |= stored ? (1u << qq) : 0u;
-                            // a non-source reads entry q of row 0 (rows >= 1 here) and is masked out
-                            v[qq] = ws.contrib[(stored ? r : 0u) * 27u + static_cast<unsigned>(q0 + qq)];
-                        }
-#pragma unroll
-                        for (int qq = 0; qq < 9; ++qq) a += (has >> qq) & 1u ? v[qq] : 0.0f;
-                    }
                 }
+                acc[k] = a;
             }
-            acc[k] = a;
-        }
-        if (__syncthreads_or(miss)) {                                // uniform per workgroup
-            if constexpr (NBR) {
+            if (__syncthreads_or(miss)) {                            // uniform per workgroup
 #pragma unroll
                 for (int k = 0; k < kCellsPerThread; ++k) acc[k] = __builtin_nanf("");
-            } else {
-                if (tid == 0) ws.over[atomicAdd(ws.counter + 2, 1u)] = static_cast<unsigned>(tile);
-                continue;
             }
-        }
 #pragma unroll
-        for (int k = 0; k < kCellsPerThread; ++k) {
-            const int e = k * kThreads + tid;
-            if (e < nband) {
+            for (int k = 0; k < kCellsPerThread; ++k) {
+                const int e = k * kThreads + tid;
+                if (e < nband) {
+                    const int cl = band[e];
+                    const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
+                    gphi[(static_cast<int64_t>(z0 + cz) * Y + (y0 + cy)) * X + (x0 + cx)] = acc[k];
+                }
+            }
+        } else {
+            // band cells: each sums entry q of its sources' rows in q order, the
+            // loads of a group of 9 issued before its adds, and stores the sum
+            // at once.  A tile with a source beyond the store goes to the
+            // overflow list; the fallback gather, a later launch, rewrites all
+            // of its cells.
+            int miss = 0;
+#pragma unroll 1
+            for (int e = tid; e < nband; e += kThreads) {
                 const int cl = band[e];
                 const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
-                gphi[(static_cast<int64_t>(z0 + cz) * Y + (y0 + cy)) * X + (x0 + cx)] = acc[k];
+                float a = 0.0f;                                      // +0 + 0 stays +0: same bits as skipping
+#pragma unroll 1
+                for (int q0 = 0; q0 < 27; q0 += 9) {
+                    float v[9];
+                    unsigned has = 0u;
+#pragma unroll
+                    for (int qq = 0; qq < 9; ++qq) {
+                        bool src;
+                        const unsigned r = source_row(m, cx, cy, cz, q0 + qq, src);
+                        const bool stored = src && r < ws.rows;
+                        miss |= src && !stored;
+                        has |= stored ? (1u << qq) : 0u;
+                        // a non-source reads entry q of row 0 (rows >= 1 here) and is masked out
+                        v[qq] = ws.contrib[(stored ? r : 0u) * 27u + static_cast<unsigned>(q0 + qq)];
+                    }
+#pragma unroll
+                    for (int qq = 0; qq < 9; ++qq) a += (has >> qq) & 1u ? v[qq] : 0.0f;
+                }
+                gphi[(static_cast<int64_t>(z0 + cz) * Y + (y0 + cy)) * X + (x0 + cx)] = a;
             }
+            if (__syncthreads_or(miss) && tid == 0) ws.over[atomicAdd(ws.counter + 2, 1u)] = static_cast<unsigned>(tile);
         }
         __syncthreads();                                             // LDS reused by the next tile
     }

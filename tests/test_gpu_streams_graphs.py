@@ -1,11 +1,11 @@
 """The entry points run asynchronously on the caller's stream and record into
 a HIP graph: a side stream gives the same bits as the default stream, and a
 captured sequence (batched inversion, forward volume, curvature forward and
-backward, all with caller-owned outputs and workspace) replays correctly
-several times with eager work and new inputs between the replays.  The
-curvature clears its counters with a kernel, not a memset, and sizes its
-launches on the host, so nothing in it depends on reading device memory from
-the host."""
+backward, the neighbour-normal backward, all with caller-owned outputs and
+workspaces) replays correctly several times with eager work and new inputs
+between the replays.  The curvature clears its counters with a kernel, not a
+memset, and sizes its launches on the host, so nothing in it depends on
+reading device memory from the host."""
 import numpy as np
 import pytest
 import torch
@@ -57,7 +57,9 @@ def test_graph_replays_match_eager(P):
     gk = torch.empty_like(phi)
     kap = torch.empty_like(phi)
     gphi = torch.empty_like(phi)
+    gnbr = torch.empty_like(phi)
     ws = torch.empty(P.plic_curvature_workspace_bytes(48, 48, 48), dtype=torch.uint8, device="cuda")
+    ws_nbr = torch.empty(P.plic_curvature_workspace_bytes_ex(48, 48, 48, True), dtype=torch.uint8, device="cuda")
 
     def load(k):
         for dst, src in zip(sn, probs[k]):
@@ -70,6 +72,7 @@ def test_graph_replays_match_eager(P):
         P.plic_volume_f32(sn[0], sn[1], sn[2], d0, vb, "fp32")
         P.plic_curvature_f32(phi, kap, "analytic", "mixed", ws)
         P.plic_curvature_backward_f32(phi, gk, gphi, "analytic", "mixed", ws)
+        P.plic_curvature_backward_ex_f32(phi, gk, gnbr, "analytic", "mixed", "py", True, ws_nbr)
 
     load(0)
     side = torch.cuda.Stream()
@@ -87,10 +90,11 @@ def test_graph_replays_match_eager(P):
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        got = [x.clone() for x in (d0, vb, kap, gphi)]
+        got = [x.clone() for x in (d0, vb, kap, gphi, gnbr)]
         # eager work between the replays, on the same buffers
         work()
         torch.cuda.synchronize()
-        for a, b, name in zip(got, (d0, vb, kap, gphi), ("d0", "V0", "kappa", "grad_phi")):
+        for a, b, name in zip(got, (d0, vb, kap, gphi, gnbr), ("d0", "V0", "kappa", "grad_phi", "grad_phi_nbr")):
             assert torch.equal(a.nan_to_num(7.0), b.nan_to_num(7.0)), (rep, name)
         assert int(torch.count_nonzero(kap).item()) > 500
+        assert bool(torch.isfinite(gnbr).all()) and int(torch.count_nonzero(gnbr).item()) > 500

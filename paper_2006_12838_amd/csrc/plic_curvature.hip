@@ -732,17 +732,20 @@ __device__ __forceinline__ int thread_index_per_iteration() {
 }
 
 // Waves per SIMD the work items are compiled for: the work is a chain of
-// dependent steps per cell, so concurrency sets the time; each count is the
+// dependent steps per cell, so concurrency sets the time.  Each count is the
 // largest that compiles without spilling (VGPRs at most 102 for 5 waves, 128
-// for 4, 168 for 3).  The adjoint of a trigonometric root (analytic, SZ) needs
-// more registers than that of an iterative one; FP64 and the neighbour-normal
+// for 4, 168 for 3), except the mixed-precision neighbour-normal adjoint: its
+// 20-28 bytes of spill at 3 waves cost less than the third wave gains (a
+// spill of about 100 bytes, as the mixed base adjoint would take at 4, costs
+// more).  The adjoint of a trigonometric root (analytic, SZ) needs more
+// registers than that of an iterative one; FP64 and the neighbour-normal
 // variant more again.
 template <int SOLVER, class T, class U, bool ADJ, bool NBR>
 constexpr int items_waves() {
     const bool iter = SOLVER == kNewton || SOLVER == kNested;
     if (!ADJ) return 5;
     if (sizeof(U) == 4) return 4;                                         // FP32
-    if (sizeof(T) == 4) return NBR ? (iter ? 3 : 2) : (iter ? 4 : 3);     // mixed
+    if (sizeof(T) == 4) return NBR ? 3 : (iter ? 4 : 3);                  // mixed
     return iter && !NBR ? 3 : 2;                                          // FP64
 }
 

@@ -734,7 +734,8 @@ __device__ __forceinline__ int thread_index_per_iteration() {
 // Waves per SIMD the work items are compiled for: the work is a chain of
 // dependent steps per cell, so concurrency sets the time.  Each count is the
 // largest that compiles without spilling (VGPRs at most 102 for 5 waves, 128
-// for 4, 168 for 3), except the mixed-precision neighbour-normal adjoint: its
+// for 4, 168 for 3) and that the LDS allows (a forward with an FP64 fit holds
+// 36 KiB per workgroup: 4 waves), except the mixed-precision neighbour-normal adjoint: its
 // 20-28 bytes of spill at 3 waves cost less than the third wave gains (a
 // spill of about 100 bytes, as the mixed base adjoint would take at 4, costs
 // more).  The adjoint of a trigonometric root (analytic, SZ) needs more
@@ -743,7 +744,7 @@ __device__ __forceinline__ int thread_index_per_iteration() {
 template <int SOLVER, class T, class U, bool ADJ, bool NBR>
 constexpr int items_waves() {
     const bool iter = SOLVER == kNewton || SOLVER == kNested;
-    if (!ADJ) return 5;
+    if (!ADJ) return sizeof(U) == 4 ? 5 : 4;                              // FP64 fit: LDS allows 4
     if (sizeof(U) == 4) return 4;                                         // FP32
     if (sizeof(T) == 4) return NBR ? 3 : (iter ? 4 : 3);                  // mixed
     return iter && !NBR ? 3 : 2;                                          // FP64
@@ -813,7 +814,7 @@ __global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, U, ADJ, NBR>())) 
 // a source whose row did not fit goes to the overflow list, where the fallback
 // gather copies the stored rows and recomputes the missing ones.
 // ---------------------------------------------------------------------------
-constexpr int B_RX = TX + 4, B_RY = TY + 4, B_RZ = TZ + 4, B_REGION = B_RX * B_RY * B_RZ;
+constexpr int B_RX = TX + 4, B_RY = TY + 4, B_RZ = TZ + 4;
 constexpr int C_RX = TX + 2, C_RY = TY + 2, C_RZ = TZ + 2, C_REGION = C_RX * C_RY * C_RZ;
 constexpr int kChunk = 128;
 constexpr int kCopyBatch = 8;                 // contribution loads in flight per thread

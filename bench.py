@@ -37,8 +37,11 @@ SOLVERS = ("analytic", "sz", "newton", "nested")
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=20,
+                    help="untimed steps first; the GPU's clock reaches its steady value under this load "
+                         "only after about 20 (some 40 ms), and the instruction-bound solvers run up to "
+                         "16%% slower before that")
     ap.add_argument("--log2n", type=int, default=26, help="log2 of the PLIC batch size")
     ap.add_argument("--lattice", type=int, default=256)
     ap.add_argument("--radius", type=float, default=40.0)
@@ -589,31 +592,33 @@ def main():
             kernels.append(("copy", lambda: cdst.copy_(csrc), N, "floats", 8))
 
     stream = torch.cuda.current_stream(dev)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in kernels]
+    # one pair of events per kernel and step: the K steps run back to back,
+    # and the per-kernel times are read after the closing synchronize
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in kernels]
+          for _ in range(args.steps)]
 
-    def step(record):
-        for (name, fn, *_), (a, b) in zip(kernels, ev):
-            if record:
-                a.record(stream)
+    def step(pairs):
+        for (name, fn, *_), pair in zip(kernels, pairs):
+            if pair:
+                pair[0].record(stream)
             fn()
-            if record:
-                b.record(stream)
+            if pair:
+                pair[1].record(stream)
 
     for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    per = {k[0]: 0.0 for k in kernels}
+        step([None] * len(kernels))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(True)
-        torch.cuda.synchronize()   # events of this step are complete
-        for (name, *_), (a, b) in zip(kernels, ev):
-            per[name] += a.elapsed_time(b)
-        print(f"bench: step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
+        step(ev[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = 1e3 * wall / args.steps
+    per = {k[0]: 0.0 for k in kernels}
+    for pairs in ev:
+        for (name, *_), (a, b) in zip(kernels, pairs):
+            per[name] += a.elapsed_time(b)
+    print(f"bench: {args.steps} steps timed", file=sys.stderr, flush=True)
 
     rates = {}
     for name, fn, units, uname, bpu in kernels:

@@ -537,8 +537,7 @@ def main():
         print(write_issue_profile(args.write_issue_profile, args.log2n, args.lattice, args.issue_out))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(the PLIC path has no cross-GPU step; sharding is described in DESIGN.md)",
+        print("bench.py: runs on one GPU only; --gpus must be 1 (the PLIC path has no cross-GPU step)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -1,0 +1,101 @@
+"""Host logic of bench.py (no GPU): the source hash that ties a profiler
+summary to the kernels it measured, the lookup of the measured HBM bytes,
+the conversion of the two counter runs into bytes per launch by a plain
+copy's counters, and the refusal of more than one GPU."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+
+def test_code_text_drops_comments_and_blank_space_only():
+    a = 'int f(int x) {  // twice\n    /* a\n       block */ return 2 * x;\n\n}\nconst char* s = "// kept";\n'
+    b = 'int f(int x) {\n  return 2 * x;   // other words\n}\nconst char* s = "// kept";\n'
+    assert bench.code_text(a) == bench.code_text(b)
+    assert '"// kept"' in bench.code_text(a)
+    assert bench.code_text(a) != bench.code_text(a.replace("2 * x", "3 * x"))
+
+
+def copy_sources(tmp_path):
+    dst = tmp_path / "paper_2006_12838_amd" / "csrc"
+    dst.mkdir(parents=True)
+    for name in bench.KERNEL_SOURCES:
+        shutil.copy(os.path.join(bench.ROOT, "paper_2006_12838_amd", "csrc", name), dst / name)
+    return dst
+
+
+def test_source_hash_follows_code_not_comments(tmp_path, monkeypatch):
+    ref = bench.kernel_source_hash()
+    dst = copy_sources(tmp_path)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.kernel_source_hash() == ref
+    src = dst / "plic_offset.hip"
+    text = src.read_text()
+    src.write_text("// a new leading comment\n" + text.replace("\n", "\n\n", 3))
+    assert bench.kernel_source_hash() == ref
+    src.write_text(text.replace("kBwdBlock = 512", "kBwdBlock = 256", 1))
+    assert bench.kernel_source_hash() != ref
+
+
+def write_profile(path, digest, rows):
+    lines = [f"kernel source sha256: `{digest}` (test)", "",
+             "| bench kernel | dispatches | HBM bytes per launch | FETCH_SIZE KiB | WRITE_SIZE KiB | algorithmic bytes | ratio |",
+             "|---|---|---:|---:|---:|---:|---:|"]
+    lines += [f"| {k} | `k` | {v:,} | 1.0 | 1.0 | 1 | 1.000 |" for k, v in rows.items()]
+    path.write_text("\n".join(lines) + "\n")
+
+
+def test_measured_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
+    prof = tmp_path / "traffic.md"
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
+    assert bench.measured_traffic("offset_backward_sz") is None                 # no summary
+    write_profile(prof, bench.kernel_source_hash(), {"offset_backward_sz": 2415919104, "volume": 7})
+    assert bench.measured_traffic("offset_backward_sz") == 2415919104
+    assert bench.measured_traffic("volume") == 7
+    assert bench.measured_traffic("offset_sz") is None                          # not in the table
+    write_profile(prof, "0" * 64, {"offset_backward_sz": 2415919104})
+    assert bench.measured_traffic("offset_backward_sz") is None                 # sources changed
+
+
+def write_counters(path, values):
+    lines = ["Kernel_Name,Counter_Value"]
+    for name, v in values:
+        lines.append(f'"{name}",{v}')
+    path.write_text("\n".join(lines) + "\n")
+
+
+def test_traffic_profile_scales_by_the_copy(tmp_path):
+    """FETCH_SIZE that reads half the copy's bytes and WRITE_SIZE that reads
+    all of them: each counter is scaled by its own copy factor, dispatches of
+    one launch are summed, and repeated dispatches are averaged."""
+    log2n, n = 10, 1 << 10
+    kib = 4 * n / 1024                                                         # one array of n floats
+    fetch = [("__amd_rocclr_copyBuffer", kib / 2),
+             ("void plic::(anonymous namespace)::k_offset_bwd<1, float, float, float, 4, true>(...)", 5 * kib / 2),
+             ("void plic::(anonymous namespace)::k_offset_bwd<1, float, float, float, 4, true>(...)", 5 * kib / 2)]
+    write = [("__amd_rocclr_copyBuffer", kib),
+             ("void plic::(anonymous namespace)::k_offset_bwd<1, float, float, float, 4, true>(...)", 4 * kib),
+             ("void plic::(anonymous namespace)::k_offset_bwd<1, float, float, float, 4, true>(...)", 4 * kib)]
+    fc, wc = tmp_path / "fetch.csv", tmp_path / "write.csv"
+    write_counters(fc, fetch)
+    write_counters(wc, write)
+    out = tmp_path / "traffic.md"
+    bench.write_traffic_profile(str(fc), str(wc), log2n, 8, str(out))
+    rows = {line.split("|")[1].strip(): line for line in out.read_text().splitlines() if line.startswith("| ")}
+    assert "offset_backward_sz" in rows and "copy" in rows
+    cells = [c.strip() for c in rows["offset_backward_sz"].split("|")]
+    assert int(cells[3].replace(",", "")) == 36 * n                           # 5 reads + 4 writes of 4 B
+    assert cells[7] == "1.000"
+    assert "volume" not in rows                                               # no dispatches, no row
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(bench.ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""

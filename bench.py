@@ -118,7 +118,7 @@ PMC_DISPATCHES = {
     "offset_backward_sz": ("k_offset_bwd<1, float, float, float, 4,",),
     "curvature_fwd": ("k_curv_scan<true, true>", "k_curv_items<0, float, double, double, false, 0, false>"),
     "curvature_bwd": ("k_curv_scan<true, false>", "k_curv_items<0, float, double, double, true, 0, false>",
-                      "k_curv_prefix_a", "k_curv_prefix_b", "k_curv_dilate", "k_curv_gather_direct",
+                      "k_curv_dilate", "k_curv_prefix", "k_curv_gather_direct",
                       "k_curv_gather_fallback<0, float, double, double, 0>"),
     "copy": ("__amd_rocclr_copyBuffer",),
 }

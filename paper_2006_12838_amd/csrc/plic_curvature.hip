@@ -599,29 +599,45 @@ __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict_
 // Contribution rows in tile order: cbase[tile] = number of interface cells in
 // the tiles before it (exclusive prefix of flags), saturated at kRowCap, so
 // the cells that get a row for a given workspace size do not depend on the
-// order in which the scan's blocks ran.  Two passes: per 2048 tiles, then each
-// block adds the totals of the blocks before it.  The block totals live in the
-// overflow list until the gather uses it.
-constexpr int kPrefixPer = 8;                                 // tiles per thread
-constexpr int kPrefixBlock = kThreads * kPrefixPer;           // 2048 tiles per block
+// order in which the scan's blocks ran.  Two passes over workgroups of 256
+// tiles: the first, with the gather list, writes each workgroup's local
+// prefix and its total; the second adds the totals of the workgroups before
+// it.  The totals live in the overflow list until the gather uses it.
 
-__global__ __launch_bounds__(kThreads) void k_curv_prefix_a(Workspace ws, int ntiles) {
+// Gather list and the first prefix pass, one tile per thread.  The list holds
+// every tile whose 3x3x3 tile neighbourhood has an interface cell (its cells
+// can receive a contribution); its order does not affect any result.
+__global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx, int nty, int ntz, int ntiles) {
     __shared__ unsigned wsum[kThreads / 64];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int base = blockIdx.x * kPrefixBlock + t * kPrefixPer;
-    unsigned v[kPrefixPer], sum = 0u;
+    const int tile = blockIdx.x * kThreads + t;
+    bool act = false;
+    unsigned c = 0u;
+    if (tile < ntiles) {
+        c = ws.flags[tile];
+        const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
 #pragma unroll
-    for (int u = 0; u < kPrefixPer; ++u) {
-        v[u] = base + u < ntiles ? ws.flags[base + u] : 0u;
-        sum += v[u];
+        for (int q = 0; q < 27; ++q) {
+            const int ax = tx + q_dx(q), ay = ty + q_dy(q), az = tz + q_dz(q);
+            if (ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz)
+                act |= ws.flags[(az * nty + ay) * ntx + ax] != 0u;
+        }
     }
-    unsigned incl = sum;                                      // inclusive scan over the wave
+    unsigned incl = c;                                        // inclusive scan over the wave
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         const unsigned o = __shfl_up(incl, d, 64);
         if (lane >= d) incl += o;
     }
     if (lane == 63) wsum[wave] = incl;
+    const unsigned long long bal = __ballot(act);
+    unsigned first = 0;
+    if (lane == 0 && bal) first = atomicAdd(ws.counter + 1, static_cast<unsigned>(__popcll(bal)));
+    first = __shfl(first, 0, 64);
+    if (act) {
+        const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
+        ws.tiles[first + __popcll(below)] = static_cast<unsigned>(tile);
+    }
     __syncthreads();
     unsigned woff = 0u, total = 0u;
 #pragma unroll
@@ -629,18 +645,13 @@ __global__ __launch_bounds__(kThreads) void k_curv_prefix_a(Workspace ws, int nt
         woff += w < wave ? wsum[w] : 0u;
         total += wsum[w];
     }
-    unsigned excl = woff + incl - sum;
-#pragma unroll
-    for (int u = 0; u < kPrefixPer; ++u) {
-        if (base + u < ntiles) ws.cbase[base + u] = excl;
-        excl += v[u];
-    }
-    if (t == 0) ws.over[blockIdx.x] = total;                  // at most 2048 * 1024 = 2^21
+    if (tile < ntiles) ws.cbase[tile] = woff + incl - c;
+    if (t == 0) ws.over[blockIdx.x] = total;                  // at most 256 * 1024 = 2^18
 }
 
-// block b of 2048 tiles: its offset is the sum of the totals of blocks 0..b-1
-// (64-bit, fixed order), added to the local prefixes with saturation
-__global__ __launch_bounds__(kThreads) void k_curv_prefix_b(Workspace ws, int ntiles) {
+// second prefix pass: workgroup b's offset is the sum of the totals of
+// workgroups 0..b-1 (64-bit), added to its local prefixes with saturation
+__global__ __launch_bounds__(kThreads) void k_curv_prefix(Workspace ws, int ntiles) {
     __shared__ unsigned long long part[kThreads / 64];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     unsigned long long acc = 0ull;
@@ -652,39 +663,10 @@ __global__ __launch_bounds__(kThreads) void k_curv_prefix_b(Workspace ws, int nt
     unsigned long long off = 0ull;
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) off += part[w];
-    const int base = blockIdx.x * kPrefixBlock + t * kPrefixPer;
-#pragma unroll
-    for (int u = 0; u < kPrefixPer; ++u) {
-        if (base + u < ntiles) {
-            const unsigned long long r = off + ws.cbase[base + u];
-            ws.cbase[base + u] = static_cast<unsigned>(r < kRowCap ? r : kRowCap);
-        }
-    }
-}
-
-// backward gather list: every tile whose 3x3x3 tile neighbourhood holds an
-// interface cell (its cells can receive a contribution); one tile per thread,
-// the list's order does not affect any result
-__global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx, int nty, int ntz, int ntiles) {
-    const int tile = blockIdx.x * kThreads + threadIdx.x;
-    bool act = false;
+    const int tile = blockIdx.x * kThreads + t;
     if (tile < ntiles) {
-        const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
-#pragma unroll
-        for (int q = 0; q < 27; ++q) {
-            const int ax = tx + q_dx(q), ay = ty + q_dy(q), az = tz + q_dz(q);
-            if (ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz)
-                act |= ws.flags[(az * nty + ay) * ntx + ax] != 0u;
-        }
-    }
-    const unsigned long long bal = __ballot(act);
-    const int lane = threadIdx.x & 63;
-    unsigned first = 0;
-    if (lane == 0 && bal) first = atomicAdd(ws.counter + 1, static_cast<unsigned>(__popcll(bal)));
-    first = __shfl(first, 0, 64);
-    if (act) {
-        const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
-        ws.tiles[first + __popcll(below)] = static_cast<unsigned>(tile);
+        const unsigned long long r = off + ws.cbase[tile];
+        ws.cbase[tile] = static_cast<unsigned>(r < kRowCap ? r : kRowCap);
     }
 }
 
@@ -1280,6 +1262,13 @@ unsigned persistent_grid(int64_t items_max) {
     return static_cast<unsigned>(items_max < kPersistentBlocks ? items_max : kPersistentBlocks);
 }
 
+// gather list and contribution rows (two prefix passes)
+void launch_rows(Workspace ws, const Grid& g, hipStream_t st) {
+    const int nb = (g.ntiles + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_curv_dilate, dim3(nb), dim3(kThreads), 0, st, ws, g.ntx, g.nty, g.ntz, g.ntiles);
+    hipLaunchKernelGGL(k_curv_prefix, dim3(nb), dim3(kThreads), 0, st, ws, g.ntiles);
+}
+
 template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
 void launch_items(const float* phi, const float* gk, float* kappa, Workspace ws, int X, int Y, int Z,
                   const Grid& g, hipStream_t st) {
@@ -1315,11 +1304,7 @@ void launch_fwd(int precision, int normal, bool nbr, const float* phi, float* ka
 template <int SOLVER, class T, class U, class F, int NRM>
 void launch_bwd_t(const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y, int Z,
                   const Grid& g, hipStream_t st) {
-    const int nb = (g.ntiles + kPrefixBlock - 1) / kPrefixBlock;
-    hipLaunchKernelGGL(k_curv_prefix_a, dim3(nb), dim3(kThreads), 0, st, ws, g.ntiles);
-    hipLaunchKernelGGL(k_curv_prefix_b, dim3(nb), dim3(kThreads), 0, st, ws, g.ntiles);
-    hipLaunchKernelGGL(k_curv_dilate, dim3((g.ntiles + kThreads - 1) / kThreads), dim3(kThreads), 0, st, ws, g.ntx,
-                       g.nty, g.ntz, g.ntiles);
+    launch_rows(ws, g, st);
     if (ws.rows > 0) launch_items<SOLVER, T, U, F, true, NRM, false>(phi, gk, nullptr, ws, X, Y, Z, g, st);
     hipLaunchKernelGGL((k_curv_gather_direct<false, 0>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0, st, gp,
                        ws, X, Y, Z, g.ntx, g.nty, g.ntz);
@@ -1334,11 +1319,7 @@ void launch_bwd_t(const float* phi, const float* gk, float* gp, Workspace ws, in
 template <int SOLVER, class T, class U, class F, int NRM>
 void launch_bwd_nbr_t(const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y, int Z,
                       const Grid& g, hipStream_t st) {
-    const int nb = (g.ntiles + kPrefixBlock - 1) / kPrefixBlock;
-    hipLaunchKernelGGL(k_curv_prefix_a, dim3(nb), dim3(kThreads), 0, st, ws, g.ntiles);
-    hipLaunchKernelGGL(k_curv_prefix_b, dim3(nb), dim3(kThreads), 0, st, ws, g.ntiles);
-    hipLaunchKernelGGL(k_curv_dilate, dim3((g.ntiles + kThreads - 1) / kThreads), dim3(kThreads), 0, st, ws, g.ntx,
-                       g.nty, g.ntz, g.ntiles);
+    launch_rows(ws, g, st);
     launch_items<SOLVER, T, U, F, true, NRM, true>(phi, gk, nullptr, ws, X, Y, Z, g, st);
     hipLaunchKernelGGL(k_curv_hgather, dim3(persistent_grid(static_cast<int64_t>(g.ntiles) * kMaxParts)),
                        dim3(kThreads), 0, st, ws, X, Y, Z, g.ntx, g.nty);

@@ -717,12 +717,12 @@ __device__ __forceinline__ int thread_index_per_iteration() {
 // dependent steps per cell, so concurrency sets the time.  Each count is the
 // largest that compiles without spilling (VGPRs at most 102 for 5 waves, 128
 // for 4, 168 for 3) and that the LDS allows (a forward with an FP64 fit holds
-// 36 KiB per workgroup: 4 waves), except the mixed-precision neighbour-normal adjoint: its
-// 20-28 bytes of spill at 3 waves cost less than the third wave gains (a
-// spill of about 100 bytes, as the mixed base adjoint would take at 4, costs
-// more).  The adjoint of a trigonometric root (analytic, SZ) needs more
-// registers than that of an iterative one; FP64 and the neighbour-normal
-// variant more again.
+// 36 KiB per workgroup: 4 waves).  The exception is the mixed-precision
+// neighbour-normal adjoint: its 20-28 bytes of spill at 3 waves cost less
+// than the third wave gains (a spill of about 100 bytes, as the mixed base
+// adjoint would take at 4, costs more).  The adjoint of a trigonometric root
+// (analytic, SZ) needs more registers than that of an iterative one; FP64 and
+// the neighbour-normal variant more again.
 template <int SOLVER, class T, class U, bool ADJ, bool NBR>
 constexpr int items_waves() {
     const bool iter = SOLVER == kNewton || SOLVER == kNested;

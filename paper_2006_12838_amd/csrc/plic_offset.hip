@@ -77,10 +77,10 @@ __device__ __forceinline__ void store_part(S* p, int64_t i, int64_t count, const
     }
 }
 
-// LDS of one workgroup: its open problems packed densely, and their roots
-// Open problems of a workgroup; the cubic stage replaces each problem's n1
-// with its root (the thread that reads an entry writes it), which keeps the
-// FP32 kernels within 20 KiB of LDS: 8 workgroups, 8 waves per SIMD.
+// LDS of one workgroup: its open problems packed densely.  The cubic stage
+// replaces each problem's n1 with its root (the thread that reads an entry
+// writes it), which keeps the FP32 kernels within 20 KiB of LDS: 8
+// workgroups, 8 waves per SIMD.
 template <class T, int VEC> struct PackLds {
     Open<T> q[kBlock * VEC];
     int count[VEC][kBlock / 64];

@@ -500,9 +500,11 @@ def sphere_rate(P, torch, V0, reps=10):
             "hbm_frac": gbs / HBM_PEAK_GBS}
 
 
-def cpu_baseline(nx, ny, nz, V0, seconds):
+def cpu_baseline(nx, ny, nz, V0, seconds, gpu_offset=None):
     """The oracle (bisection on the FP64 forward volume), timed on the host
-    cores on chunks of the same workload until `seconds` have passed."""
+    cores on chunks of the same workload until `seconds` have passed.  With
+    gpu_offset (solver -> the GPU's d0 of the whole batch, on the host), the
+    error of each solver against the oracle's d0 of the first chunk."""
     import numpy as np
     import oracle
 
@@ -510,19 +512,32 @@ def cpu_baseline(nx, ny, nz, V0, seconds):
     chunk = 1 << 21
     done, t0 = 0, time.perf_counter()
     i = 0
+    first = None
     while True:
         s = slice(i * chunk, (i + 1) * chunk)
-        oracle.offset(nx[s], ny[s], nz[s], V0[s])
+        d = oracle.offset(nx[s], ny[s], nz[s], V0[s])
+        if first is None:
+            first = np.asarray(d, dtype=np.float64)
         done += len(V0[s])
         i = (i + 1) % max(1, len(V0) // chunk)
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    return {"value": done / el, "unit": "PLIC solves/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{done} problems of the 2^{int(math.log2(len(V0)))} workload "
-                      f"(chunks of 2^21) through the FP64 oracle's bisection inverse, "
-                      f"{el:.1f} s, {oracle.num_threads()} OpenMP threads"}
+    out = {"value": done / el, "unit": "PLIC solves/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": f"{done} problems of the 2^{int(math.log2(len(V0)))} workload "
+                     f"(chunks of 2^21) through the FP64 oracle's bisection inverse, "
+                     f"{el:.1f} s, {oracle.num_threads()} OpenMP threads"}
+    if gpu_offset is not None:
+        n = len(first)
+        err = {}
+        for solver in SOLVERS:
+            diff = np.abs(np.asarray(gpu_offset(solver)[:n], dtype=np.float64) - first)
+            err[solver] = {"max_abs": float(diff.max()), "rms": float(np.sqrt(np.mean(diff * diff)))}
+        out["error_vs_oracle"] = {"quantity": "d0, FP32 storage and arithmetic", "problems": n,
+                                  "sample": f"the first {n} problems of the workload", "tolerance": 1e-5,
+                                  "per_solver": err}
+    return out
 
 
 def main():
@@ -669,7 +684,11 @@ def main():
     if not args.no_paper_isolated and not args.only:
         out["paper_isolated"] = paper_isolated(P, torch, dev, args.log2n)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(nx, ny, nz, V0, args.cpu_seconds)
+        def gpu_offset(solver):
+            P.plic_offset_f32(*tn[:4], d0, solver, "fp32")
+            torch.cuda.synchronize()
+            return d0[: 1 << 21].cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(nx, ny, nz, V0, args.cpu_seconds, gpu_offset)
     print(json.dumps(out), flush=True)
 
 

@@ -1,7 +1,8 @@
 """Host logic of bench.py (no GPU): the source hash that ties a profiler
 summary to the kernels it measured, the lookup of the measured HBM bytes,
 the conversion of the two counter runs into bytes per launch by a plain
-copy's counters, and the refusal of more than one GPU."""
+copy's counters, the refusal of more than one GPU, and the CPU leg's error
+report against the oracle."""
 import os
 import shutil
 import subprocess
@@ -99,3 +100,24 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_cpu_baseline_reports_error_against_the_oracle():
+    """The CPU leg times the oracle and compares each solver's GPU offsets
+    with the oracle's for the first chunk; here a stand-in GPU result is the
+    oracle's own plus a known shift."""
+    import numpy as np
+    import oracle
+    import workloads
+
+    nx, ny, nz, V0 = workloads.plic_problems(4096, seed=3)
+    ref = np.asarray(oracle.offset(nx, ny, nz, V0), dtype=np.float64)
+    shift = {"analytic": 0.0, "sz": 2e-7, "newton": -3e-6, "nested": 1e-5}
+    out = bench.cpu_baseline(nx, ny, nz, V0, 0.01, lambda s: (ref + shift[s]).astype(np.float32))
+    assert out["kind"] == "oracle" and out["value"] > 0 and out["cores"] >= 1
+    err = out["error_vs_oracle"]
+    assert err["problems"] == 4096 and err["tolerance"] == 1e-5
+    for s, d in shift.items():
+        e = err["per_solver"][s]
+        # the stand-in is rounded to FP32 like the GPU's output
+        assert abs(e["max_abs"] - abs(d)) <= 1e-7 and e["rms"] <= e["max_abs"]

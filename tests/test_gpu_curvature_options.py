@@ -1,7 +1,8 @@
 """GPU parity of the curvature options against the FP64 oracle: the
 centre-of-mass normal (forward and backward) and the neighbour-normal
 variant (forward; its backward has a file of its own), with the per-cell bar
-of the curvature tests."""
+of the curvature tests; both at the benchmark's 256^3 sphere too, the
+backward on sampled, isolated cells."""
 import numpy as np
 import pytest
 import torch
@@ -116,3 +117,63 @@ def test_autograd_options(P, cm_case):
     k = P.curvature(t2, "analytic", "mixed", neighbour_normals=True)
     k.sum().backward()
     assert torch.isfinite(t2.grad).all()
+
+
+@pytest.fixture(scope="module")
+def bench_sphere():
+    return workloads.sphere_lattice(N=256, R=40.0, seed=0)[0]
+
+
+@pytest.mark.parametrize("normal, nbr", [("cm", False), ("py", True)])
+def test_full_size_variants(P, orc, bench_sphere, normal, nbr):
+    """The variants the benchmark times, on its 256^3 R = 40 sphere: every
+    interface cell against the oracle."""
+    phi = bench_sphere
+    ref = cell_reference(orc, phi, normal=normal, neighbour_normals=nbr)
+    check_against(ref, phi, gpu_kappa(P, phi, "analytic", "mixed", normal, nbr), "mixed",
+                  f"256^3 {normal} neighbour_normals={nbr}")
+
+
+@pytest.mark.parametrize("normal, nbr", [("cm", False), ("py", True)])
+def test_full_size_variants_backward_sampled(P, orc, bench_sphere, normal, nbr):
+    """The variants' backward on the benchmark's 256^3 sphere with the
+    recommended workspace: isolated upstream cells (their gradients reach
+    one cell, or two with neighbour normals, and do not overlap), each
+    neighbourhood against the oracle's finite differences."""
+    phi = bench_sphere
+    _, flags = orc.curvature(phi, flags=True, normal=normal, neighbour_normals=nbr)
+    cells = np.flatnonzero(flags & 1)
+    _, info = orc.curvature_cells(phi, cells, normal=normal, neighbour_normals=nbr)
+    ok = cells[(info[:, 0] >= 5) & (info[:, 2] <= 1e4)]
+    H = 2 if nbr else 1
+    rng = np.random.default_rng(11)
+    pick = rng.choice(ok, 300, replace=False)
+    Z, Y, X = phi.shape
+    coords = np.stack([pick % X, (pick // X) % Y, pick // (X * Y)], 1)
+    keep = []
+    for i, c in enumerate(coords):
+        if all(np.abs(c - coords[j]).max() > 2 * H for j in keep):
+            keep.append(i)
+    pick = pick[keep][:40]
+    gk = np.zeros(phi.size, np.float32)
+    gk[pick] = 1.0
+    tp, tg = dev(phi, gk.reshape(phi.shape))
+    out = torch.empty_like(tp)
+    P.plic_curvature_backward_ex_f32(tp, tg, out, "analytic", "mixed", normal, nbr)
+    g = host(out).astype(np.float64)
+    worst, checked = 0.0, 0
+    for c in pick:
+        x, y, z = c % X, (c // X) % Y, c // (X * Y)
+        blk = (slice(z - H, z + H + 1), slice(y - H, y + H + 1), slice(x - H, x + H + 1))
+        nb = phi[blk].astype(np.float64).ravel()
+        if nbr:
+            ref, bad = orc.curv_cell_nbr_fd_grad(nb, normal=normal, h=1e-6)
+        else:
+            ref, bad = orc.curv_cell_fd_grad(nb, normal=normal, h=1e-6)
+        if bad:
+            continue
+        checked += 1
+        worst = max(worst, np.abs(g[blk].ravel() - ref).max() / max(1.0, np.abs(ref).max()))
+    print(f"256^3 {normal} neighbour_normals={nbr} sampled backward: {checked} cells, worst {worst:.3e}")
+    assert checked >= 20
+    assert worst <= 2e-3

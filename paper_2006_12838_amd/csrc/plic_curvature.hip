@@ -47,6 +47,7 @@ constexpr int kCellsPerThread = kTile / kThreads;
 constexpr int kGroup = 32;                    // lanes per interface cell
 constexpr int kGroups = kThreads / kGroup;    // 8 cells in flight per workgroup
 constexpr int kPersistentBlocks = 2048;
+constexpr int kFallbackBlocks = 256;            // one per CU of an MI355X
 
 // fixed auxiliary vector r of Sec. 4.2 (non-collinear with the normal)
 constexpr double kR0 = 0.56270900, kR1 = 0.32704452, kR2 = 0.75921047;
@@ -1308,9 +1309,12 @@ void launch_bwd_t(const float* phi, const float* gk, float* gp, Workspace ws, in
     if (ws.rows > 0) launch_items<SOLVER, T, U, F, true, NRM, false>(phi, gk, nullptr, ws, X, Y, Z, g, st);
     hipLaunchKernelGGL((k_curv_gather_direct<false, 0>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0, st, gp,
                        ws, X, Y, Z, g.ntx, g.nty, g.ntz);
-    // usually empty: a small grid keeps the launch cheap when nothing overflowed
-    hipLaunchKernelGGL((k_curv_gather_fallback<SOLVER, T, U, F, NRM>), dim3(g.ntiles < 512 ? g.ntiles : 512),
-                       dim3(kThreads), 0, st, phi, gk, gp, ws, X, Y, Z, g.ntx, g.nty);
+    // usually empty.  Its registers and LDS allow one workgroup per CU, so a
+    // grid of one per CU (256) runs in a single round, cheap when nothing
+    // overflowed and as concurrent as any larger grid when something did
+    hipLaunchKernelGGL((k_curv_gather_fallback<SOLVER, T, U, F, NRM>),
+                       dim3(g.ntiles < kFallbackBlocks ? g.ntiles : kFallbackBlocks), dim3(kThreads), 0, st, phi,
+                       gk, gp, ws, X, Y, Z, g.ntx, g.nty);
 }
 
 // neighbour-normal backward: the rows (contributions and the neighbours'

@@ -4,7 +4,6 @@ are pinned here against what they promise."""
 import math
 
 import numpy as np
-import pytest
 
 import workloads
 

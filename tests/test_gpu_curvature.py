@@ -92,6 +92,16 @@ def test_full_size_sphere(P, orc):
         assert 0.97 < mean_r < 1.03
 
 
+def test_full_size_sphere_other_solvers(P, orc):
+    """The other three solvers' points on the 256^3 R = 40 sphere: every
+    interface cell against the same oracle (its offsets do not depend on the
+    solver)."""
+    phi, _ = workloads.sphere_lattice(N=256, R=40.0, seed=0)
+    ref = cell_reference(orc, phi)
+    for solver in ("sz", "newton", "nested"):
+        check_against(ref, phi, gpu_kappa(P, phi, solver, "mixed"), "mixed", f"256^3 {solver}")
+
+
 @pytest.mark.parametrize("dims", [(67, 45, 37), (64, 4, 4), (65, 5, 5), (130, 9, 17)])
 def test_ragged_lattices(P, orc, dims):
     """Lattice sizes that are not multiples of the 64x4x4 tile."""

@@ -173,17 +173,18 @@ def test_autograd_function(P, case):
     assert np.abs(g - gref).max() / np.abs(gref).max() <= 2e-3
 
 
-def test_full_size_backward_runs(P, orc):
-    """Perturbed sphere R = 50 on 192^3 (the differentiation workload): the
-    backward against the oracle on a sample of interface cells' neighbourhoods."""
+@pytest.fixture(scope="module")
+def full_case(orc):
+    """Perturbed sphere R = 50 on 192^3 (the differentiation workload), 60
+    isolated well-conditioned upstream cells (pairwise more than 2 cells apart,
+    so that each checked neighbourhood sees one source) and the oracle's FD
+    gradient over each cell's 3^3 (None where the masks would change)."""
     phi, _, _ = workloads.perturbed_sphere_lattice(N=192, R=50.0, seed=0)
     kref, flags = orc.curvature(phi, flags=True)
     cells = np.flatnonzero(flags & 1)
     _, info = orc.curvature_cells(phi, cells)
     ok = cells[(info[:, 0] >= 5) & (info[:, 2] <= 1e4)]
     rng = np.random.default_rng(7)
-    # isolated upstream cells (pairwise more than 2 cells apart) so that each
-    # checked neighbourhood sees one source
     pick = rng.choice(ok, 400, replace=False)
     Z, Y, X = phi.shape
     coords = np.stack([pick % X, (pick // X) % Y, pick // (X * Y)], 1)
@@ -192,18 +193,32 @@ def test_full_size_backward_runs(P, orc):
         if all(np.abs(c - coords[j]).max() > 2 for j in keep):
             keep.append(i)
     pick = pick[keep][:60]
-    gk = np.zeros(phi.size, np.float32)
-    gk[pick] = 1.0
-    gk = gk.reshape(phi.shape)
-    g = gpu_grad(P, phi, gk).astype(np.float64)
-    worst = 0.0
+    refs = []
     for c in pick:
         x, y, z = c % X, (c // X) % Y, c // (X * Y)
         nb = phi[z - 1:z + 2, y - 1:y + 2, x - 1:x + 2].astype(np.float64).ravel()
         ref, bad = orc.curv_cell_fd_grad(nb, h=1e-6)
-        if bad:
+        refs.append(None if bad else ref)
+    gk = np.zeros(phi.size, np.float32)
+    gk[pick] = 1.0
+    return phi, gk.reshape(phi.shape), pick, refs
+
+
+@pytest.mark.parametrize("solver", ["analytic", "sz", "newton", "nested"])
+def test_full_size_backward_runs(P, full_case, solver):
+    """The differentiation workload's backward with each solver's points
+    against the oracle on the sampled cells' neighbourhoods."""
+    phi, gk, pick, refs = full_case
+    Z, Y, X = phi.shape
+    g = gpu_grad(P, phi, gk, solver).astype(np.float64)
+    worst, checked = 0.0, 0
+    for c, ref in zip(pick, refs):
+        if ref is None:
             continue
+        x, y, z = c % X, (c // X) % Y, c // (X * Y)
         got = g[z - 1:z + 2, y - 1:y + 2, x - 1:x + 2].ravel()
         worst = max(worst, np.abs(got - ref).max() / max(1.0, np.abs(ref).max()))
-    print(f"192^3 sampled backward: worst {worst:.3e}")
+        checked += 1
+    print(f"192^3 sampled backward ({solver}): {checked} cells, worst {worst:.3e}")
+    assert checked >= 30
     assert worst <= 2e-3

@@ -42,6 +42,7 @@ extern "C" {
 #define PLIC_OK 0
 #define PLIC_EINVAL (-1)  /* null / misaligned / overlapping pointer, negative size, bad enum */
 #define PLIC_EHIP (-2)    /* the HIP runtime refused the launch (see plic_last_hip_error) */
+#define PLIC_EWORKSPACE (-3) /* the workspace is smaller than the call needs (every other argument valid) */
 
 /* PLIC solvers: the four inversion methods of Sec. 2.3-2.5, compared in Sec. 2.6 */
 #define PLIC_ANALYTIC 0   /* the paper's analytic solution (Sec. 2.3, trigonometric root via atan) */
@@ -162,8 +163,10 @@ size_t plic_curvature_workspace_bytes_ex(int64_t X, int64_t Y, int64_t Z, int ne
  *           PLIC_MIXED fits in FP64 (FP32 points), PLIC_FP64 is FP64 throughout.
  *   workspace, workspace_bytes : device scratch, 4-byte aligned, not
  *           overlapping phi or kappa, of at least the fixed part (see
- *           plic_curvature_workspace_bytes).  Calls that overlap in time must
- *           use distinct workspaces.
+ *           plic_curvature_workspace_bytes); a smaller one gives
+ *           PLIC_EWORKSPACE.  Calls that overlap in time must use distinct
+ *           workspaces.  The call leaves its interface-cell count in the
+ *           workspace (plic_curvature_status).
  * Sign: kappa = +1/R for a fluid sphere of radius R (the normal points out of
  * the fluid); the paper's formula is negated for this.  Fits with fewer than 5
  * points use the leading parameters only (App. B.3); a pivot of the LDL^T
@@ -239,15 +242,41 @@ int plic_curvature_ex_f32(const float *phi, int64_t X, int64_t Y, int64_t Z, flo
  * own gradient that its neighbours stored; the gather adds both in a fixed
  * order (deterministic).  This variant has no recomputing fallback: the
  * workspace must hold at least one row (fixed part + 432 bytes, else
- * PLIC_EINVAL), and where a row does not fit, the gradient on the affected
- * tile's cells next to the interface is NaN.  plic_curvature_workspace_bytes_ex
- * (X, Y, Z, 1) gives room for 64 interface cells per tile.  The interface
- * masks and the choice of each neighbour's normal are held fixed.
+ * PLIC_EWORKSPACE), and where a row does not fit, the gradient on the
+ * affected tile's cells next to the interface is NaN.  Such a call still
+ * returns PLIC_OK (the interface count is only known on the device);
+ * plic_curvature_status then returns PLIC_EWORKSPACE with the size that
+ * holds every row.  plic_curvature_workspace_bytes_ex (X, Y, Z, 1) gives room
+ * for 64 interface cells per tile.  The interface masks and the choice of
+ * each neighbour's normal are held fixed.
  */
 int plic_curvature_backward_ex_f32(const float *phi, int64_t X, int64_t Y, int64_t Z,
                                    const float *grad_kappa, float *grad_phi, int solver,
                                    int precision, int normal, int neighbour_normals,
                                    void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * plic_curvature_status — what the last curvature call (forward or backward,
+ * any variant) found on `workspace`, read after it completed: this call
+ * synchronises `stream` (the stream of that call) and copies 24 bytes of the
+ * workspace header to the host.  Not for use under graph capture.
+ *   X, Y, Z, neighbour_normals, workspace_bytes : as in that call.
+ *   interface_cells    : if not NULL, receives its interface-cell count.
+ *   bytes_for_all_rows : if not NULL, receives the workspace size that holds
+ *                        a backward row for every one of those cells (fixed
+ *                        part + 108 bytes per cell, 432 with neighbour normals).
+ * Returns PLIC_EWORKSPACE when neighbour_normals = 1 and the workspace holds
+ * fewer rows than there are interface cells (a backward of the
+ * neighbour-normal variant on it has NaN where rows were missing; give it
+ * bytes_for_all_rows and call it again), else PLIC_OK (the base backward
+ * recomputes missing rows, so its result is complete for any size).
+ * PLIC_EINVAL for an invalid lattice, flag or pointer, PLIC_EHIP when the
+ * stream or the copy fails.  Row indices are 32-bit: the neighbour-normal
+ * variant holds at most 10,226,107 rows, whatever the workspace.
+ */
+int plic_curvature_status(const void *workspace, size_t workspace_bytes, int64_t X, int64_t Y, int64_t Z,
+                          int neighbour_normals, int64_t *interface_cells, size_t *bytes_for_all_rows,
+                          void *stream);
 
 /* human-readable status; never NULL */
 const char *plic_status_string(int status);

@@ -13,7 +13,7 @@ import torch  # loads torch's HIP runtime first; libplic binds to the same one
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libplic.so")
 
-PLIC_OK, PLIC_EINVAL, PLIC_EHIP = 0, -1, -2
+PLIC_OK, PLIC_EINVAL, PLIC_EHIP, PLIC_EWORKSPACE = 0, -1, -2, -3
 SOLVERS = {"analytic": 0, "sz": 1, "newton": 2, "nested": 3, "sz_kawano": 4}
 # the paper's four solvers, held to the accuracy bound; "sz_kawano" is the
 # unoptimized comparison variant (offset, offset backward, benchmark only)
@@ -63,6 +63,9 @@ _lib.plic_curvature_workspace_bytes.restype = ctypes.c_size_t
 _lib.plic_curvature_workspace_bytes.argtypes = [_i64, _i64, _i64]
 _lib.plic_curvature_workspace_bytes_ex.restype = ctypes.c_size_t
 _lib.plic_curvature_workspace_bytes_ex.argtypes = [_i64, _i64, _i64, _int]
+_lib.plic_curvature_status.restype = ctypes.c_int
+_lib.plic_curvature_status.argtypes = [_vp, ctypes.c_size_t, _i64, _i64, _i64, _int,
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t), _vp]
 _lib.plic_status_string.restype = ctypes.c_char_p
 _lib.plic_status_string.argtypes = [_int]
 _lib.plic_version.restype = ctypes.c_char_p
@@ -71,7 +74,8 @@ _lib.plic_last_hip_error.restype = ctypes.c_int
 _lib.plic_last_hip_error.argtypes = []
 
 EXPORTED = tuple(_c) + ("plic_status_string", "plic_version", "plic_last_hip_error",
-                        "plic_curvature_workspace_bytes", "plic_curvature_workspace_bytes_ex")
+                        "plic_curvature_workspace_bytes", "plic_curvature_workspace_bytes_ex",
+                        "plic_curvature_status")
 
 
 def plic_curvature_workspace_bytes(X: int, Y: int, Z: int) -> int:
@@ -80,6 +84,18 @@ def plic_curvature_workspace_bytes(X: int, Y: int, Z: int) -> int:
 
 def plic_curvature_workspace_bytes_ex(X: int, Y: int, Z: int, neighbour_normals: bool = False) -> int:
     return int(_lib.plic_curvature_workspace_bytes_ex(int(X), int(Y), int(Z), int(bool(neighbour_normals))))
+
+
+def plic_curvature_status(workspace, X: int, Y: int, Z: int, neighbour_normals: bool = False, stream=None):
+    """(status, interface_cells, bytes_for_all_rows) of the last curvature call
+    on ``workspace`` (a uint8 device tensor); synchronises ``stream`` (default:
+    the current stream of the workspace's device)."""
+    cells, need = ctypes.c_int64(0), ctypes.c_size_t(0)
+    st = ctypes.c_void_p(stream) if stream is not None else _stream(workspace)
+    rc = _lib.plic_curvature_status(ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), int(X), int(Y),
+                                    int(Z), int(bool(neighbour_normals)), ctypes.byref(cells), ctypes.byref(need),
+                                    st)
+    return int(rc), int(cells.value), int(need.value)
 
 
 def plic_status_string(status: int) -> str:
@@ -253,19 +269,36 @@ def plic_curvature_f32(phi, kappa, solver="analytic", precision="mixed", workspa
 
 
 def plic_curvature_backward_ex_f32(phi, grad_kappa, grad_phi, solver="analytic", precision="mixed", normal="py",
-                                   neighbour_normals=False, workspace=None):
+                                   neighbour_normals=False, workspace=None, check=True):
+    """With neighbour_normals and check (the default), the call is followed by
+    plic_curvature_status (one stream synchronisation): when the workspace held
+    fewer rows than the lattice has interface cells, a workspace that holds
+    them all is allocated and the call repeated if the workspace was the
+    library's own choice, and a RuntimeError is raised for a caller's
+    workspace (its grad_phi holds NaN where rows were missing)."""
     X, Y, Z = _lattice_dims(phi)
     n = X * Y * Z
     _same_device(phi, grad_kappa, grad_phi)
+    own = workspace is None
     ws = _workspace(phi, workspace, X, Y, Z, neighbour_normals)
-    _check(_c["plic_curvature_backward_ex_f32"](_ptr(phi, torch.float32, n, "phi"), X, Y, Z,
-                                                _ptr(grad_kappa, torch.float32, n, "grad_kappa"),
-                                                _ptr(grad_phi, torch.float32, n, "grad_phi"),
-                                                _enum(SOLVERS, solver, "solver"),
-                                                _enum(PRECISIONS, precision, "precision"),
-                                                _enum(NORMALS, normal, "normal"), int(bool(neighbour_normals)),
-                                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
-           "plic_curvature_backward_ex_f32")
+    for attempt in range(2):
+        _check(_c["plic_curvature_backward_ex_f32"](_ptr(phi, torch.float32, n, "phi"), X, Y, Z,
+                                                    _ptr(grad_kappa, torch.float32, n, "grad_kappa"),
+                                                    _ptr(grad_phi, torch.float32, n, "grad_phi"),
+                                                    _enum(SOLVERS, solver, "solver"),
+                                                    _enum(PRECISIONS, precision, "precision"),
+                                                    _enum(NORMALS, normal, "normal"), int(bool(neighbour_normals)),
+                                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
+               "plic_curvature_backward_ex_f32")
+        if not (neighbour_normals and check):
+            break
+        rc, cells, need = plic_curvature_status(ws, X, Y, Z, True, stream=_stream(phi).value)
+        if rc == PLIC_OK:
+            break
+        if rc != PLIC_EWORKSPACE or not own or attempt == 1:
+            raise RuntimeError(f"plic_curvature_backward_ex_f32: {plic_status_string(rc)} "
+                               f"({cells} interface cells need {need} bytes, workspace has {ws.numel()})")
+        ws = torch.empty(need, dtype=torch.uint8, device=phi.device)
     return grad_phi
 
 

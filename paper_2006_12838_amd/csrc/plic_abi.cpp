@@ -15,6 +15,7 @@ const char* plic_status_string(int status) {
         case PLIC_OK: return "PLIC_OK: success";
         case PLIC_EINVAL: return "PLIC_EINVAL: invalid argument (null, misaligned or overlapping pointer, negative size or unknown enum)";
         case PLIC_EHIP: return "PLIC_EHIP: the HIP runtime rejected the launch";
+        case PLIC_EWORKSPACE: return "PLIC_EWORKSPACE: the workspace is too small for this call";
         default: return "unknown PLIC status";
     }
 }

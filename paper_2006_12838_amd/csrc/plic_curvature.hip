@@ -470,7 +470,8 @@ __device__ __forceinline__ int ordered_compact(int n, Pred pred, unsigned short*
 
 // ---------------------------------------------------------------------------
 // Workspace (caller device memory, 4-byte aligned):
-//   [0, 256)  counters: [0] work items, [1] gather tiles, [2] overflow tiles
+//   [0, 256)  header: [0] work items, [1] gather tiles, [2] overflow tiles,
+//             [4..5] the call's interface-cell count (read by the status query)
 //   flags     ntiles      interface cells in the tile (backward)
 //   cbase     ntiles      first contribution row of the tile's interface cells
 //                         (prefix of flags in tile order)
@@ -510,8 +511,13 @@ constexpr unsigned kRowLimitNbr = (1u << 30) / kRowFloatsNbr;
 // the default leaves room for interfaces that cross a tile several times
 constexpr size_t kDefaultRowsPerTileNbr = 64;
 
+// header words: [0] work items, [1] gather tiles, [2] overflow tiles,
+// [3] unused, [4] / [5] low / high word of the call's interface-cell count
+constexpr int kCounters = 6;
+constexpr int kCountLo = 4, kCountHi = 5;
+
 struct Workspace {
-    unsigned* counter;  // [0] items, [1] gather tiles, [2] overflow tiles
+    unsigned* counter;  // header words (kCounters)
     unsigned* flags;
     unsigned* cbase;
     unsigned* mask;
@@ -525,9 +531,8 @@ struct Workspace {
 };
 
 __global__ void k_curv_zero(unsigned* counter) {
-    counter[0] = 0u;
-    counter[1] = 0u;
-    counter[2] = 0u;
+#pragma unroll
+    for (int i = 0; i < kCounters; ++i) counter[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -584,6 +589,10 @@ __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict_
     const unsigned parts = (total + kPartCells - 1) / kPartCells;
     if (t == 0) {
         if (parts) {
+            // the call's interface-cell count, 64-bit from two words: the add
+            // that carries out of the low word bumps the high word
+            const unsigned old = atomicAdd(ws.counter + kCountLo, static_cast<unsigned>(total));
+            if (old + static_cast<unsigned>(total) < old) atomicAdd(ws.counter + kCountHi, 1u);
             const unsigned base = atomicAdd(ws.counter, parts);
             for (unsigned p = 0; p < parts; ++p) ws.items[base + p] = (static_cast<unsigned>(tile) << 7) | p;
         }
@@ -1354,7 +1363,9 @@ void launch_bwd(int precision, int normal, bool nbr, const float* phi, const flo
         launch_bwd_n<SOLVER, double, double, double>(normal, nbr, phi, gk, gp, ws, X, Y, Z, g, st);
 }
 
-// shared argument checks of the two entry points
+// shared argument checks of the two entry points (the workspace's size is
+// checked last, by each entry point: PLIC_EWORKSPACE only when every other
+// argument is valid)
 int check_common(const float* phi, int64_t X, int64_t Y, int64_t Z, int solver, int precision,
                  const void* ws, size_t ws_bytes, bool* empty, Grid* g, int64_t* n) {
     if (!valid_curvature_solver(solver) || !valid_precision(precision)) return PLIC_EINVAL;
@@ -1362,10 +1373,25 @@ int check_common(const float* phi, int64_t X, int64_t Y, int64_t Z, int solver, 
     *n = *empty ? 0 : X * Y * Z;
     if (!valid_array(phi, *n)) return PLIC_EINVAL;
     if (!*empty) {
-        if (ws == nullptr || !aligned(ws, 4) || ws_bytes < fixed_bytes(*g)) return PLIC_EINVAL;
+        if (ws == nullptr || !aligned(ws, 4)) return PLIC_EINVAL;
         if (overlap(ws, ws_bytes, phi, static_cast<size_t>(*n) * sizeof(float))) return PLIC_EINVAL;
     }
     return PLIC_OK;
+}
+
+// the forward launches, after validation
+int curvature_forward(const float* phi, int64_t X, int64_t Y, int64_t Z, float* kappa, int solver, int precision,
+                      int normal, bool nbr, void* workspace, size_t workspace_bytes, const Grid& g, hipStream_t st) {
+    const Workspace ws = carve(workspace, workspace_bytes, g);
+    const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
+    launch_scan<true>(phi, kappa, ws, x, y, z, g, st);
+    switch (solver) {
+        case kSZ: launch_fwd<kSZ>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
+        case kNewton: launch_fwd<kNewton>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
+        case kNested: launch_fwd<kNested>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
+        default: launch_fwd<kAnalytic>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
+    }
+    return launch_status();
 }
 
 }  // namespace
@@ -1405,18 +1431,9 @@ int plic_curvature_ex_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, flo
     if (overlap(phi, nb, kappa, nb)) return PLIC_EINVAL;
     if (!empty && overlap(workspace, workspace_bytes, kappa, nb)) return PLIC_EINVAL;
     if (empty) return PLIC_OK;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const Workspace ws = carve(workspace, workspace_bytes, g);
-    const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
-    const bool nbr = neighbour_normals != 0;
-    launch_scan<true>(phi, kappa, ws, x, y, z, g, st);
-    switch (solver) {
-        case kSZ: launch_fwd<kSZ>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
-        case kNewton: launch_fwd<kNewton>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
-        case kNested: launch_fwd<kNested>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
-        default: launch_fwd<kAnalytic>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
-    }
-    return launch_status();
+    if (workspace_bytes < fixed_bytes(g)) return PLIC_EWORKSPACE;
+    return curvature_forward(phi, X, Y, Z, kappa, solver, precision, normal, neighbour_normals != 0, workspace,
+                             workspace_bytes, g, static_cast<hipStream_t>(stream));
 }
 
 int plic_curvature_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float* kappa, int solver,
@@ -1424,6 +1441,7 @@ int plic_curvature_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float*
     return plic_curvature_ex_f32(phi, X, Y, Z, kappa, solver, precision, PLIC_NORMAL_PY, 0, workspace,
                                  workspace_bytes, stream);
 }
+
 
 int plic_curvature_backward_ex_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, const float* grad_kappa,
                                    float* grad_phi, int solver, int precision, int normal, int neighbour_normals,
@@ -1434,8 +1452,6 @@ int plic_curvature_backward_ex_f32(const float* phi, int64_t X, int64_t Y, int64
     if (check_common(phi, X, Y, Z, solver, precision, workspace, workspace_bytes, &empty, &g, &n) != PLIC_OK)
         return PLIC_EINVAL;
     if (!valid_normal(normal) || (neighbour_normals != 0 && neighbour_normals != 1)) return PLIC_EINVAL;
-    // the neighbour-normal backward has no fallback: it needs one row at least
-    if (!empty && neighbour_normals && workspace_bytes < fixed_bytes(g) + kRowBytesNbr) return PLIC_EINVAL;
     if (!valid_array(grad_kappa, n) || !valid_array(grad_phi, n)) return PLIC_EINVAL;
     const size_t nb = static_cast<size_t>(n) * sizeof(float);
     if (overlap(grad_phi, nb, phi, nb) || overlap(grad_phi, nb, grad_kappa, nb)) return PLIC_EINVAL;
@@ -1443,6 +1459,8 @@ int plic_curvature_backward_ex_f32(const float* phi, int64_t X, int64_t Y, int64
                    overlap(workspace, workspace_bytes, grad_kappa, nb)))
         return PLIC_EINVAL;
     if (empty) return PLIC_OK;
+    // the neighbour-normal backward has no fallback: it needs one row at least
+    if (workspace_bytes < fixed_bytes(g) + (neighbour_normals ? kRowBytesNbr : 0)) return PLIC_EWORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool nbr = neighbour_normals != 0;
     const Workspace ws = carve(workspace, workspace_bytes, g, nbr);
@@ -1462,6 +1480,31 @@ int plic_curvature_backward_f32(const float* phi, int64_t X, int64_t Y, int64_t 
                                 size_t workspace_bytes, void* stream) {
     return plic_curvature_backward_ex_f32(phi, X, Y, Z, grad_kappa, grad_phi, solver, precision, PLIC_NORMAL_PY, 0,
                                           workspace, workspace_bytes, stream);
+}
+
+int plic_curvature_status(const void* workspace, size_t workspace_bytes, int64_t X, int64_t Y, int64_t Z,
+                          int neighbour_normals, int64_t* interface_cells, size_t* bytes_for_all_rows, void* stream) {
+    bool empty;
+    Grid g{};
+    if (check_lattice(X, Y, Z, &empty, &g) != PLIC_OK || empty) return PLIC_EINVAL;
+    if (neighbour_normals != 0 && neighbour_normals != 1) return PLIC_EINVAL;
+    if (workspace == nullptr || !aligned(workspace, 4)) return PLIC_EINVAL;
+    const bool nbr = neighbour_normals != 0;
+    if (workspace_bytes < fixed_bytes(g) + (nbr ? kRowBytesNbr : 0)) return PLIC_EWORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned h[kCounters];
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemcpy(h, workspace, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        set_last_hip_error(static_cast<int>(e));
+        return PLIC_EHIP;
+    }
+    const uint64_t cells = (static_cast<uint64_t>(h[kCountHi]) << 32) | h[kCountLo];
+    const size_t row_bytes = nbr ? kRowBytesNbr : kRowBytes;
+    if (interface_cells) *interface_cells = static_cast<int64_t>(cells);
+    if (bytes_for_all_rows) *bytes_for_all_rows = fixed_bytes(g) + static_cast<size_t>(cells) * row_bytes;
+    const Workspace ws = carve(const_cast<void*>(workspace), workspace_bytes, g, nbr);
+    return nbr && cells > ws.rows ? PLIC_EWORKSPACE : PLIC_OK;
 }
 
 }  // extern "C"

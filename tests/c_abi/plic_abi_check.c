@@ -118,10 +118,19 @@ int main(void) {
                 if (!(fabs(hk[i]) <= kmax)) kmax = fabs(hk[i]);
             printf("curvature %s: max |kappa| = %.2e\n", pass ? "without interface" : "of a plane", kmax);
             CHECK(kmax <= 1e-6, "curvature of a plane / empty lattice not zero");
+            /* the call's interface-cell count: the plane z = 7 away from the
+             * outer layer, 62 x 14 cells */
+            int64_t cells = -1;
+            size_t need = 0;
+            rc = plic_curvature_status(ws, wsb, X, Y, Z, 0, &cells, &need, st);
+            CHECK(rc == PLIC_OK, "plic_curvature_status: %s", plic_status_string(rc));
+            CHECK(cells == (pass ? 0 : 62 * 14), "interface cells %lld", (long long)cells);
+            /* the recommended size holds 16 rows in each of the 16 tiles */
+            CHECK(need + 256 * 108 == wsb + (size_t)cells * 108, "bytes for all rows %zu", need);
         }
         /* rejected calls enqueue nothing and say why */
         int rc = plic_curvature_f32(dp, X, Y, Z, dk, PLIC_ANALYTIC, PLIC_MIXED, ws, 16, st);
-        CHECK(rc == PLIC_EINVAL, "workspace below the fixed part accepted");
+        CHECK(rc == PLIC_EWORKSPACE, "workspace below the fixed part accepted");
         rc = plic_offset_f32(d[0], d[1], d[2], d[3], dd, -1, PLIC_SZ, PLIC_FP32, st);
         CHECK(rc == PLIC_EINVAL, "negative count accepted");
         rc = plic_offset_f32(d[0], d[1], d[2], d[3], dd, N, 17, PLIC_FP32, st);

@@ -47,6 +47,7 @@ def test_status_and_version(lib):
     assert lib.plic_status_string(0).startswith("PLIC_OK")
     assert lib.plic_status_string(-1).startswith("PLIC_EINVAL")
     assert lib.plic_status_string(-2).startswith("PLIC_EHIP")
+    assert lib.plic_status_string(-3).startswith("PLIC_EWORKSPACE")
     assert lib.plic_status_string(12345) == "unknown PLIC status"
     assert lib.plic_last_hip_error() == 0
 
@@ -119,7 +120,8 @@ def test_curvature_validation(lib):
     assert f(A, 4, 4, 4, B, 4, 1, W, ws, None) == -1                  # Kawano's SZ: not for the curvature
     assert f(A, 4, 4, 4, B, 0, 7, W, ws, None) == -1
     assert f(A, 4, 4, 4, B, 0, 1, None, ws, None) == -1               # no workspace
-    assert f(A, 4, 4, 4, B, 0, 1, W, 256 + 783, None) == -1           # below the fixed part
+    assert f(A, 4, 4, 4, B, 0, 1, W, 256 + 783, None) == -3           # below the fixed part
+    assert f(A, 4, 4, 4, None, 0, 1, W, 256 + 783, None) == -1        # an invalid argument comes first
     assert f(A, 4, 4, 4, B, 0, 1, W + 2, 256 + 784, None) == -1       # misaligned
     assert f(A, 4, 4, 4, B, 0, 1, W + 2, ws, None) == -1              # misaligned workspace
     assert f(A, 4, 4, 4, B, 0, 1, B, ws, None) == -1                  # workspace overlaps kappa
@@ -130,6 +132,7 @@ def test_curvature_validation(lib):
     assert g(A, 3, 3, 3, B, B + 4, 0, 1, W, ws, None) == -1           # grad_phi overlaps grad_kappa
     assert g(A, 3, 3, 3, None, C, 0, 1, W, ws, None) == -1
     assert g(A, 3, 3, 3, B, C, 0, 1, C, ws, None) == -1               # workspace overlaps grad_phi
+    assert g(A, 3, 3, 3, B, C, 0, 1, W, 256 + 783, None) == -3        # below the fixed part
 
 
 def test_curvature_options_validation(lib):
@@ -147,10 +150,26 @@ def test_curvature_options_validation(lib):
     assert g(A, 3, 3, 3, B, C, 0, 1, 0, 2, W, ws, None) == -1           # bad neighbour flag
     assert g(A, 3, 3, 3, B, A, 0, 1, 1, 1, W, ws, None) == -1           # grad_phi overlaps phi
     fixed = 256 + 784                                                   # one tile
-    assert g(A, 3, 3, 3, B, C, 0, 1, 0, 1, W, fixed + 431, None) == -1  # neighbour normals: no row
+    assert g(A, 3, 3, 3, B, C, 0, 1, 0, 1, W, fixed + 431, None) == -3  # neighbour normals: no row
     assert lib.plic_curvature_workspace_bytes_ex(4, 4, 4, 1) == fixed + 64 * 432
     assert lib.plic_curvature_workspace_bytes_ex(4, 4, 4, 0) == lib.plic_curvature_workspace_bytes(4, 4, 4)
     assert lib._lib.plic_curvature_workspace_bytes_ex(4, 4, 4, 2) == 0       # bad flag (C entry point)
+
+
+def test_curvature_status_validation(lib):
+    """The status query rejects what it cannot read before any HIP call."""
+    import ctypes
+    f = lib._lib.plic_curvature_status
+    W = 0xA0000
+    cells, need = ctypes.c_int64(-7), ctypes.c_size_t(7)
+    fixed = 256 + 784                                                   # one tile
+    assert f(W, fixed, 0, 4, 4, 0, ctypes.byref(cells), ctypes.byref(need), None) == -1   # empty lattice
+    assert f(W, fixed, 4, 4, 4, 2, None, None, None) == -1             # bad flag
+    assert f(None, fixed, 4, 4, 4, 0, None, None, None) == -1          # no workspace
+    assert f(W + 2, fixed, 4, 4, 4, 0, None, None, None) == -1         # misaligned
+    assert f(W, fixed - 1, 4, 4, 4, 0, None, None, None) == -3         # below the fixed part
+    assert f(W, fixed + 431, 4, 4, 4, 1, None, None, None) == -3       # neighbour normals: no row
+    assert (cells.value, need.value) == (-7, 7)                         # nothing written on rejection
 
 
 def test_sphere_validation(lib):

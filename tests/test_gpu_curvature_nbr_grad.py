@@ -56,10 +56,10 @@ def case(orc):
     return make_case(orc, "py")
 
 
-def gpu_grad(P, phi, gk, solver="analytic", precision="mixed", normal="py", workspace=None):
+def gpu_grad(P, phi, gk, solver="analytic", precision="mixed", normal="py", workspace=None, check=True):
     tp, tg = dev(phi, gk)
     out = torch.empty_like(tp)
-    P.plic_curvature_backward_ex_f32(tp, tg, out, solver, precision, normal, True, workspace)
+    P.plic_curvature_backward_ex_f32(tp, tg, out, solver, precision, normal, True, workspace, check=check)
     return host(out)
 
 
@@ -149,11 +149,48 @@ def test_workspace_rows(P, case):
     g_big = gpu_grad(P, phi, gk, workspace=torch.empty(fixed + 432 * (n_iface + 50), dtype=torch.uint8,
                                                        device="cuda"))
     assert np.array_equal(g_full, g_big)
-    g_few = gpu_grad(P, phi, gk, workspace=torch.empty(fixed + 432 * 100, dtype=torch.uint8, device="cuda"))
+    few = torch.empty(fixed + 432 * 100, dtype=torch.uint8, device="cuda")
+    g_few = gpu_grad(P, phi, gk, workspace=few, check=False)
     nan = np.isnan(g_few)
     assert nan.any() and not nan[~band_of(phi)].any()
     fin = ~nan
     assert np.array_equal(g_few[fin], g_full[fin])
+    # the overflow is reported: the status query names it and the size that
+    # holds every row; the checked call raises for a caller's workspace
+    interior = np.zeros(phi.shape, bool)
+    interior[1:-1, 1:-1, 1:-1] = True
+    n_cells = int((((phi > 0) & (phi < 1)) & interior).sum())
+    rc, cells, need = P.plic_curvature_status(few, X, Y, Z, True)
+    assert (rc, cells, need) == (-3, n_cells, fixed + 432 * n_cells)
+    with pytest.raises(RuntimeError, match="PLIC_EWORKSPACE"):
+        gpu_grad(P, phi, gk, workspace=few)
+    # a workspace with exactly one row per interface cell is complete
+    exact = torch.empty(need, dtype=torch.uint8, device="cuda")
+    assert np.array_equal(gpu_grad(P, phi, gk, workspace=exact), g_full)
+    assert P.plic_curvature_status(exact, X, Y, Z, True)[0] == 0
+
+
+def test_dense_interface_through_autograd(P):
+    """A lattice where every interior cell is an interface cell (noisy fill
+    levels) needs far more rows than the default workspace's 64 per tile:
+    the autograd path detects the overflow, repeats the call with a
+    workspace that holds every row, and returns a finite gradient equal to a
+    call given that size directly."""
+    rng = np.random.default_rng(11)
+    phi = rng.uniform(0.05, 0.95, size=(16, 16, 64)).astype(np.float32)
+    gk = rng.standard_normal(phi.shape).astype(np.float32)
+    Z, Y, X = phi.shape
+    default = P.plic_curvature_workspace_bytes_ex(X, Y, Z, True)
+    ntiles = 16
+    assert default == 256 + 784 * ntiles + 64 * ntiles * 432 and 14 * 14 * 62 > 64 * ntiles
+    tp = dev(phi).requires_grad_(True)
+    k = P.curvature(tp, neighbour_normals=True)
+    (k * dev(gk)).sum().backward()
+    g = host(tp.grad)
+    assert np.isfinite(g).all() and np.abs(g).max() > 0
+    need = 256 + 784 * ntiles + 432 * 14 * 14 * 62
+    ref = gpu_grad(P, phi, gk, workspace=torch.empty(need, dtype=torch.uint8, device="cuda"))
+    assert np.array_equal(g, ref)
 
 
 def test_autograd(P, case):

@@ -339,3 +339,13 @@ def num_threads() -> int:
     if v and v.isdigit():
         return int(v)
     return os.cpu_count() or 1
+
+
+def curvature_grad_richardson(phi, grad_kappa, h=1e-5, normal="py", neighbour_normals=False):
+    """curvature_grad with Richardson extrapolation of the central differences:
+    (4 g(h) - g(2h)) / 3 cancels their O(h^2) term.  Bad cells are those of
+    either step (a perturbation by 2h that would cross 0 or 1, or change the
+    fit's parameter set)."""
+    g1, b1 = curvature_grad(phi, grad_kappa, h=h, normal=normal, neighbour_normals=neighbour_normals)
+    g2, b2 = curvature_grad(phi, grad_kappa, h=2 * h, normal=normal, neighbour_normals=neighbour_normals)
+    return (4.0 * g1 - g2) / 3.0, b1 | b2

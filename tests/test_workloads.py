@@ -122,3 +122,22 @@ def test_perturbed_sphere_lattice_volume():
     vol = ((R * (1 + amp * sq)) ** 3 / 3.0 * np.sin(T)).sum() * (math.pi / 400) * (2 * math.pi / 800)
     assert abs(phi.astype(np.float64).sum() / vol - 1.0) < 5e-3
     assert np.abs(c - (N - 1) / 2.0).max() <= 0.15
+
+
+def test_spherical_harmonic_series_matches_basis():
+    """The perturbed sphere's radius series (Legendre recurrences, one term at
+    a time) equals the basis-matrix form built on scipy's lpmv."""
+    import math
+
+    from scipy.special import lpmv
+
+    x = np.linspace(-1.0, 1.0, 2001)
+    P = workloads._assoc_legendre(6, x)
+    for l in range(7):
+        for m in range(l + 1):
+            assert np.allclose(P[(l, m)], lpmv(m, l, x), rtol=1e-12, atol=1e-12)
+    rng = np.random.default_rng(0)
+    th, ph = rng.uniform(0, math.pi, 5000), rng.uniform(0, 2 * math.pi, 5000)
+    a = rng.standard_normal(48)
+    ref = workloads._real_sph_harm_basis(6, th, ph) @ a
+    assert np.abs(workloads._real_sph_harm_series(6, a, th, ph) - ref).max() <= 1e-12

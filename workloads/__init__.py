@@ -247,6 +247,48 @@ def _real_sph_harm_basis(lmax: int, theta: np.ndarray, phi: np.ndarray) -> np.nd
     return np.stack(cols, -1)
 
 
+def _assoc_legendre(lmax: int, x: np.ndarray) -> dict:
+    """P_l^m(x) for 0 <= m <= l <= lmax, with the Condon-Shortley phase (the
+    convention of scipy.special.lpmv), by the standard recurrences in m and l."""
+    P = {}
+    s = np.sqrt(np.maximum(1.0 - x * x, 0.0))
+    pmm = np.ones_like(x)
+    for m in range(lmax + 1):
+        if m > 0:
+            pmm = -(2 * m - 1) * s * pmm
+        P[(m, m)] = pmm
+        if m + 1 <= lmax:
+            P[(m + 1, m)] = (2 * m + 1) * x * pmm
+        for l in range(m + 2, lmax + 1):
+            P[(l, m)] = ((2 * l - 1) * x * P[(l - 1, m)] - (l + m - 1) * P[(l - 2, m)]) / (l - m)
+    return P
+
+
+def _real_sph_harm_series(lmax: int, a: np.ndarray, theta: np.ndarray, phi: np.ndarray) -> np.ndarray:
+    """sum_{l=1..lmax} sum_{m=-l..l} a_lm Y_lm(theta, phi) with the real
+    orthonormal harmonics of _real_sph_harm_basis (same coefficient order),
+    accumulated term by term from one table of Legendre functions and of
+    cos / sin(m phi)."""
+    P = _assoc_legendre(lmax, np.cos(theta))
+    cos_m = [None] + [np.cos(m * phi) for m in range(1, lmax + 1)]
+    sin_m = [None] + [np.sin(m * phi) for m in range(1, lmax + 1)]
+    out = np.zeros_like(theta, dtype=np.float64)
+    k = 0
+    for l in range(1, lmax + 1):
+        for m in range(-l, l + 1):
+            am = abs(m)
+            norm = math.sqrt((2 * l + 1) / (4 * math.pi)
+                             * math.factorial(l - am) / math.factorial(l + am))
+            if m == 0:
+                out += (a[k] * norm) * P[(l, 0)]
+            elif m > 0:
+                out += (a[k] * math.sqrt(2.0) * norm) * P[(l, am)] * cos_m[am]
+            else:
+                out += (a[k] * math.sqrt(2.0) * norm) * P[(l, am)] * sin_m[am]
+            k += 1
+    return out
+
+
 def perturbed_sphere_lattice(N: int = 192, R: float = 50.0, seed: int = 0, amp: float = 0.05,
                              lmax: int = 6, ss: int = 4, jitter: float = 0.15):
     """Perturbed sphere r(theta, phi) = R (1 + amp * s(theta, phi)) with
@@ -268,7 +310,7 @@ def perturbed_sphere_lattice(N: int = 192, R: float = 50.0, seed: int = 0, amp: 
         th = np.arccos(np.clip(v[..., 2] / np.maximum(r, 1e-300), -1.0, 1.0))
         ph = np.arctan2(v[..., 1], v[..., 0])
         shp = th.shape
-        Y = _real_sph_harm_basis(lmax, th.ravel(), ph.ravel()) @ a
+        Y = _real_sph_harm_series(lmax, a, th.ravel(), ph.ravel())
         return r, (R * (1.0 + amp * Y)).reshape(shp)
 
     def inside(p):

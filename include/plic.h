@@ -62,7 +62,9 @@ extern "C" {
 
 /* arithmetic precision of the computation (independent of the storage type) */
 #define PLIC_FP32 0       /* all FP32                                                              */
-#define PLIC_MIXED 1      /* FP32 bulk; FP64 for the cubic-case root and the curvature fit solve   */
+#define PLIC_MIXED 1      /* FP32 bulk; FP64 for a cubic-case root within 2^-16 S of a case
+                             boundary (one FP64 Newton step on the case's cubic) and for the
+                             curvature's fit solve                                               */
 #define PLIC_FP64 2       /* all FP64                                                              */
 
 /* interface normal of the curvature step (App. B.1) */

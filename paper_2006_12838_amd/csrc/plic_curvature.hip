@@ -558,7 +558,11 @@ __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict_
         const bool yz_in = y >= 1 && y <= Y - 2 && z >= 1 && z <= Z - 2;
         const int64_t row = (static_cast<int64_t>(z) * Y + y) * X;
         if (VEC && x + 4 <= X) {
-            const float4 v = *reinterpret_cast<const float4*>(phi + row + x);
+            // phi is streamed once here: non-temporal load (the work items
+            // re-read the few interface neighbourhoods later)
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            const f4 l4 = __builtin_nontemporal_load(reinterpret_cast<const f4*>(phi + row + x));
+            const float4 v = make_float4(l4[0], l4[1], l4[2], l4[3]);
             *reinterpret_cast<float4*>(out + row + x) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -727,18 +731,17 @@ __device__ __forceinline__ int thread_index_per_iteration() {
 // dependent steps per cell, so concurrency sets the time.  Each count is the
 // largest that compiles without spilling (VGPRs at most 102 for 5 waves, 128
 // for 4, 168 for 3) and that the LDS allows (a forward with an FP64 fit holds
-// 36 KiB per workgroup: 4 waves).  The exception is the mixed-precision
-// neighbour-normal adjoint: its 20-28 bytes of spill at 3 waves cost less
-// than the third wave gains (a spill of about 100 bytes, as the mixed base
-// adjoint would take at 4, costs more).  The adjoint of a trigonometric root
-// (analytic, SZ) needs more registers than that of an iterative one; FP64 and
+// 36 KiB per workgroup: 4 waves).  In mixed precision the PLIC points are
+// FP32 with the FP64 island only near case boundaries, so the adjoint fits
+// 4 waves (3 with neighbour normals); in FP64 the adjoint of a trigonometric
+// root (analytic, SZ) needs more registers than that of an iterative one, and
 // the neighbour-normal variant more again.
 template <int SOLVER, class T, class U, bool ADJ, bool NBR>
 constexpr int items_waves() {
     const bool iter = SOLVER == kNewton || SOLVER == kNested;
     if (!ADJ) return sizeof(U) == 4 ? 5 : 4;                              // FP64 fit: LDS allows 4
     if (sizeof(U) == 4) return 4;                                         // FP32
-    if (sizeof(T) == 4) return NBR ? 3 : (iter ? 4 : 3);                  // mixed
+    if (sizeof(T) == 4) return NBR ? 3 : 4;                               // mixed
     return iter && !NBR ? 3 : 2;                                          // FP64
 }
 

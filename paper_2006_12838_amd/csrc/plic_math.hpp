@@ -162,26 +162,35 @@ __device__ __forceinline__ T unreduce(const Reduced<T>& r, T d, T nx, T ny, T nz
 }
 
 // ---------------------------------------------------------------------------
-// Closed-form cases shared by the analytic, Newton and nested-interval solvers
-// (a-priori conditions of Sec. 2.3): returns true and sets d for (5), (2), (1).
-// Case (2) is n1^2 <= 6 V n2 n3 and 3 n2 (2 V n3 + n1 - n2) <= n1^2, the form
-// that follows from n1 <= d2 <= n2.  Normals in a coordinate plane (n1 = 0)
-// and along an axis (n2 = 0) are covered by (2) and (5) (Sec. 2.3).
+// Closed-form cases, shared by every solver except Kawano's form.  Derived from
+// the piecewise volume of the reduced problem (Sec. 2.2), written with
+// k = 6 V n2 n3 (an area, like n1^2):
+//   slab,  n1 + n2 <= d <= n3:  V n3 = d - (n1 + n2)/2
+//          -> case (5) when 2 V n3 >= n1 + n2;
+//   corner tetrahedron, d <= n1:  d^3 = k n1
+//          -> case (1) when k < n1^2 (that is, d < n1);
+//   cut wedge, n1 <= d <= n2:  (d - n1/2)^2 = (4k - n1^2) / 12
+//          -> case (2) when d <= n2, that is k - n1^2 <= 3 n2 (n2 - n1)
+//             (the a-priori condition of Sec. 2.3 with its factor 2 restored).
+// Returns the case (5, 1 or 2) with d set, or 0 for the cubic cases.  A
+// coordinate-plane normal (n1 = 0) lands in (2), an axis normal in (5).  The
+// formulas are homogeneous of degree 1 in n, so they hold in any units (the
+// SZ solver passes the L1-normalized normal).
 // ---------------------------------------------------------------------------
 template <class T, bool WITH_CASE1 = true>
 __device__ __forceinline__ int closed_case(T n1, T n2, T n3, T V, T& d) {
     using m = M<T>;
-    const T n12 = n1 + n2, n3V = n3 * V;
-    if (n12 <= T(2) * n3V) { d = n3V + T(0.5) * n12; return 5; }
-    const T V6n2n3 = T(6) * n2 * n3V, sqn1 = n1 * n1;
-    if (V6n2n3 >= sqn1 && T(3) * n2 * (T(2) * n3V + n1 - n2) <= sqn1) {
-        // d2 = n1/2 + sqrt(2 V n2 n3 - n1^2/12) = n1/2 + sqrt(24 V n2 n3 - n1^2) / sqrt(12)
-        d = T(0.5) * n1 + m::sqrt(m::fmax(T(24) * n2 * n3V - sqn1, T(0))) * T(0.28867513459481288225);
-        return 2;
-    }
-    if (V6n2n3 < sqn1) {
-        if constexpr (WITH_CASE1) d = m::cbrt(V6n2n3 * n1);
+    const T half_base = T(0.5) * (n1 + n2);           // d - V n3 inside the slab
+    const T lift = V * n3;
+    if (lift >= half_base) { d = lift + half_base; return 5; }
+    const T k = T(6) * n2 * lift, a = n1 * n1;
+    if (k < a) {
+        if constexpr (WITH_CASE1) d = m::cbrt(k * n1);
         return 1;
+    }
+    if (k - a <= T(3) * n2 * (n2 - n1)) {
+        d = T(0.5) * n1 + m::sqrt(m::fmax(T(4) * k - a, T(0)) * T(1.0 / 12.0));
+        return 2;
     }
     return 0;
 }
@@ -258,7 +267,8 @@ __device__ __forceinline__ T cubic_analytic(const Open<T>& o) {
 
 // ---------------------------------------------------------------------------
 // Optimized Scardovelli-Zaleski solution (Sec. 2.4), on the L1-normalized
-// normal (n1 + n2 + n3 = 1, so d in [0, 1/2]).  Cases (5), (2), (1) first;
+// normal (n1 + n2 + n3 = 1, so d in [0, 1/2]).  Cases (5), (2), (1) first,
+// by the shared closed forms (closed_case) on the L1-normalized normal;
 // the boundary between (3) and (4) is decided a priori through the volume v3
 // at d = n3; one root d = c - 2 t sin(asin(arg)/3) serves both.  The printed
 // coefficients t = sqrt(c^2 - b) and arg = (c^3 - a/2 - 3bc/2)/t^3 are 0/0 for
@@ -270,20 +280,6 @@ __device__ __forceinline__ T cubic_analytic(const Open<T>& o) {
 // form 3 n3 (n3 - n1) + n1^2 - (n3 - n2)^3 / n1 (over 6 n2), which has no
 // cancellation either.  d is in L1 units.
 // ---------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ bool closed_sz(T n1, T n2, T n3, T V, T& d) {
-    using mt = M<T>;
-    const T n12 = n1 + n2, n3V = n3 * V;
-    if (n12 <= T(2) * n3V) { d = n3V + T(0.5) * n12; return true; }        // case (5)
-    const T sqn1 = n1 * n1, n26 = T(6) * n2, v1 = mt::div(sqn1, n26);     // n2 > 0 here
-    if (v1 <= n3V && n3V < v1 + T(0.5) * (n2 - n1)) {                     // case (2)
-        d = T(0.5) * (n1 + mt::sqrt(sqn1 + T(8) * n2 * (n3V - v1)));
-        return true;
-    }
-    if (n3V < v1) { d = mt::cbrt(n1 * n26 * n3V); return true; }          // case (1)
-    return false;
-}
-
 template <class T, class U>
 __device__ __forceinline__ T cubic_sz(const Open<T>& o) {
     using m = M<U>;
@@ -515,7 +511,7 @@ __device__ __forceinline__ bool closed_stage(const Reduced<T>& r, T& d, Open<T>&
     } else if constexpr (SOLVER == kSZ) {
         const T l = r.n1 + r.n2 + r.n3, il = M<T>::rcp(l);
         const T n1 = r.n1 * il, n2 = r.n2 * il, n3 = r.n3 * il;
-        if (closed_sz(n1, n2, n3, r.V, d)) return true;
+        if (closed_case(n1, n2, n3, r.V, d)) return true;
         o = Open<T>{n1, n2, n3, r.V};
         return false;
     } else if constexpr (SOLVER == kNewton) {
@@ -530,12 +526,61 @@ __device__ __forceinline__ bool closed_stage(const Reduced<T>& r, T& d, Open<T>&
 }
 
 template <int SOLVER, class T, class U>
-__device__ __forceinline__ T cubic_stage(const Open<T>& o) {
+__device__ __forceinline__ T cubic_root(const Open<T>& o) {
     if constexpr (SOLVER == kKawano) return cubic_kawano<T, U>(o);
     else if constexpr (SOLVER == kSZ) return cubic_sz<T, U>(o);
     else if constexpr (SOLVER == kNewton) return cubic_newton<T, U>(o);
     else if constexpr (SOLVER == kNested) return cubic_nested<T, U>(o);
     else return cubic_analytic<T, U>(o);
+}
+
+// ---------------------------------------------------------------------------
+// The FP64 island of the mixed precision mode (FP32 bulk, U = double).  The
+// cubic stage runs in FP32; a root that lands within kIslandWidth * S of a
+// case boundary (d = n1, n2, n3 or n1 + n2 in the solver's units), where the
+// FP32 a-priori tests may have picked the neighbouring case, is re-solved on
+// the cubic of the case that FP64 selects: one Newton step in FP64 from the
+// FP32 root, kept inside that case's bracket.  The FP32 root is within
+// rounding of the answer (both cases' roots meet at the boundary), so one
+// step leaves an error of order (FP32 error)^2; the step's quotient needs no
+// FP64 division (the FP32 reciprocal of the slope errs by 1 ulp, times a step
+// of FP32 size).  Elsewhere the FP32 root stands.  Kawano's form keeps its
+// whole cubic stage in FP64 (its variables do not map onto the shifted cubic).
+// ---------------------------------------------------------------------------
+constexpr float kIslandWidth = 1.0f / 65536.0f;
+
+template <class T>
+__device__ __forceinline__ bool near_case_boundary(const Open<T>& o, T d) {
+    using m = M<T>;
+    const T w = (o.n1 + o.n2 + o.n3) * T(kIslandWidth);
+    const T gap = m::fmin(m::fmin(m::fabs(d - o.n1), m::fabs(d - o.n2)),
+                          m::fmin(m::fabs(d - o.n3), m::fabs(d - (o.n1 + o.n2))));
+    return gap <= w;
+}
+
+template <class T>
+__device__ __forceinline__ T island_refine(const Open<T>& o, T d) {
+    using m = M<double>;
+    const Cubic<double> q = cubic_setup<T, double>(o);
+    const double x = m::fmin(m::fmax(double(d) - q.base, q.lo), q.hi);
+    const double f = ((q.a3 * x + q.a2) * x + q.a1) * x - q.c;
+    const double fp = (3.0 * q.a3 * x + 2.0 * q.a2) * x + q.a1;
+    // a vanishing slope (case (1) at t = 0, or below FP32's normal range)
+    // leaves the iterate where it is
+    const float fpf = float(fp);
+    const double step = fpf >= FLT_MIN ? f * double(__builtin_amdgcn_rcpf(fpf)) : 0.0;
+    return T(q.base + m::fmin(m::fmax(x - step, q.lo), q.hi));
+}
+
+template <int SOLVER, class T, class U>
+__device__ __forceinline__ T cubic_stage(const Open<T>& o) {
+    constexpr bool island = sizeof(T) < sizeof(U) && SOLVER != kKawano;
+    if constexpr (island) {
+        const T d = cubic_root<SOLVER, T, T>(o);
+        return near_case_boundary(o, d) ? island_refine(o, d) : d;
+    } else {
+        return cubic_root<SOLVER, T, U>(o);
+    }
 }
 
 // d0 from the solver's reduced root: sign(V0 - 1/2) (S/2 - d), or for Kawano's

@@ -22,7 +22,9 @@ from ._lib import (  # noqa: F401  (re-exported: the C ABI by name)
     PAPER_SOLVERS,
     PRECISIONS,
     SOLVERS,
+    VALU_OPS,
     plic_bench_isolated_f32,
+    plic_bench_valu,
     plic_curvature_backward_ex_f32,
     plic_curvature_backward_f32,
     plic_curvature_ex_f32,

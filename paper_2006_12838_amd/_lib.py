@@ -48,7 +48,9 @@ _c = {
     "plic_curvature_backward_f32": _sig("plic_curvature_backward_f32",
                                         [_vp, _i64, _i64, _i64, _vp, _vp, _int, _int, _vp,
                                          ctypes.c_size_t, _vp]),
-    "plic_bench_isolated_f32": _sig("plic_bench_isolated_f32", [_vp, _vp, _vp, _i64, _int, _int, _int, _vp, _vp]),
+    "plic_bench_isolated_f32": _sig("plic_bench_isolated_f32",
+                                    [_vp, _vp, _vp, _i64, _int, _int, _int, _vp, _vp, _vp]),
+    "plic_bench_valu": _sig("plic_bench_valu", [_int, _i64, _int, ctypes.c_float, _vp, _vp]),
     "plic_sphere_offset_f32": _sig("plic_sphere_offset_f32", [_vp, _vp, _i64, _vp]),
     "plic_sphere_offset_f64": _sig("plic_sphere_offset_f64", [_vp, _vp, _i64, _vp]),
     "plic_sphere_volume_f32": _sig("plic_sphere_volume_f32", [_vp, _vp, _i64, _vp]),
@@ -270,8 +272,9 @@ def plic_curvature_f32(phi, kappa, solver="analytic", precision="mixed", workspa
 
 def plic_curvature_backward_ex_f32(phi, grad_kappa, grad_phi, solver="analytic", precision="mixed", normal="py",
                                    neighbour_normals=False, workspace=None, check=True):
-    """With neighbour_normals and check (the default), the call is followed by
-    plic_curvature_status (one stream synchronisation): when the workspace held
+    """With neighbour_normals and check (the default), and outside graph
+    capture, the call is followed by plic_curvature_status (one stream
+    synchronisation): when the workspace held
     fewer rows than the lattice has interface cells, a workspace that holds
     them all is allocated and the call repeated if the workspace was the
     library's own choice, and a RuntimeError is raised for a caller's
@@ -290,7 +293,10 @@ def plic_curvature_backward_ex_f32(phi, grad_kappa, grad_phi, solver="analytic",
                                                     _enum(NORMALS, normal, "normal"), int(bool(neighbour_normals)),
                                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
                "plic_curvature_backward_ex_f32")
-        if not (neighbour_normals and check):
+        # the status query synchronises the stream, which a stream under graph
+        # capture may not do: there the caller sizes the workspace (and may
+        # query plic_curvature_status after a replay)
+        if not (neighbour_normals and check) or torch.cuda.is_current_stream_capturing():
             break
         rc, cells, need = plic_curvature_status(ws, X, Y, Z, True, stream=_stream(phi).value)
         if rc == PLIC_OK:
@@ -345,14 +351,33 @@ def plic_sphere_volume_f64(d0, V0):
     return _sphere("plic_sphere_volume_f64", d0, V0, torch.float64)
 
 
-def plic_bench_isolated_f32(nx, ny, nz, err, L=256, solver="sz", blank=False):
+VALU_OPS = {name: i for i, name in enumerate(
+    ("fma_f32", "fma_f64", "sqrt_f32", "rsq_f32", "rcp_f32", "sin_f32", "exp_f32", "log_f32", "rcp_f64",
+     "sqrt_f64", "fma_sin_f32"))}
+
+
+def plic_bench_valu(op, sink, iters, seed=0.7):
+    """VALU issue-rate probe (include/plic_bench.h): sink.numel() threads, each
+    issuing 32 * iters instructions of `op` (a name from VALU_OPS)."""
+    n = sink.numel()
+    _check(_c["plic_bench_valu"](_enum(VALU_OPS, op, "op"), n, int(iters), float(seed),
+                                 _ptr(sink, torch.float32, n, "sink"), _stream(sink)), "plic_bench_valu")
+    return sink
+
+
+def plic_bench_isolated_f32(nx, ny, nz, err, L=256, solver="sz", blank=False, d0=None):
     """Compute-isolated timing kernel (include/plic_bench.h): err[i] = sum over
     V0 = j/(L-1), j < L, of |V(n_i, d0(n_i, V0)) - V0|; blank=True swaps the
-    inversion for d0 = V0 - 1/2."""
+    inversion for d0 = V0 - 1/2.  d0, if given (L * count floats), receives
+    every offset, d0[j * count + i]."""
     n = err.numel()
     _same_device(nx, ny, nz, err)
     args = [_ptr(t, torch.float32, n, w) for t, w in zip((nx, ny, nz), ("nx", "ny", "nz"))]
+    dp = None
+    if d0 is not None:
+        _same_device(err, d0)
+        dp = _ptr(d0, torch.float32, n * int(L), "d0")
     _check(_c["plic_bench_isolated_f32"](*args, n, int(L), _enum(SOLVERS, solver, "solver"), int(bool(blank)),
-                                         _ptr(err, torch.float32, n, "err"), _stream(err)),
+                                         _ptr(err, torch.float32, n, "err"), dp, _stream(err)),
            "plic_bench_isolated_f32")
     return err

@@ -185,17 +185,34 @@ def test_sphere_validation(lib):
     assert lib.raw("plic_sphere_offset_f64")(A + 4, B, 8, None) == -1
 
 
+def test_valu_probe_validation(lib):
+    f = lib.raw("plic_bench_valu")
+    assert f(0, 0, 8, 0.5, None, None) == 0                             # empty
+    assert f(-1, 8, 8, 0.5, D, None) == -1                              # bad op
+    assert f(11, 8, 8, 0.5, D, None) == -1
+    assert f(0, -1, 8, 0.5, D, None) == -1
+    assert f(0, 8, -1, 0.5, D, None) == -1
+    assert f(0, 8, 8, 0.5, None, None) == -1                            # null sink
+    assert f(0, 8, 8, 0.5, D + 2, None) == -1                           # misaligned
+    assert f(0, (1 << 31) + 1, 8, 0.5, 1 << 40, None) == -1             # grid limit
+
+
 def test_bench_validation(lib):
     f = lib.raw("plic_bench_isolated_f32")
-    assert f(A, B, C, 0, 256, 0, 0, D, None) == 0                     # empty
-    assert f(A, B, C, -1, 256, 0, 0, D, None) == -1
-    assert f(A, B, C, 8, 1, 0, 0, D, None) == -1                      # L < 2
-    assert f(A, B, C, 8, 256, 5, 0, D, None) == -1                    # bad solver
-    assert f(A, B, C, 8, 256, 0, 2, D, None) == -1                    # bad blank flag
-    assert f(A, B, C, 8, 256, 0, 0, A + 4, None) == -1                # err overlaps nx
-    assert f(A + 2, B, C, 8, 256, 0, 0, D, None) == -1                # misaligned
-    far = [k << 40 for k in (1, 2, 3, 4)]                               # disjoint 8 GiB ranges
-    assert f(*far[:3], (1 << 31) + 1, 256, 0, 0, far[3], None) == -1    # grid limit
+    assert f(A, B, C, 0, 256, 0, 0, D, None, None) == 0               # empty
+    assert f(A, B, C, -1, 256, 0, 0, D, None, None) == -1
+    assert f(A, B, C, 8, 1, 0, 0, D, None, None) == -1                # L < 2
+    assert f(A, B, C, 8, 256, 5, 0, D, None, None) == -1              # bad solver
+    assert f(A, B, C, 8, 256, 0, 2, D, None, None) == -1              # bad blank flag
+    assert f(A, B, C, 8, 256, 0, 0, A + 4, None, None) == -1          # err overlaps nx
+    assert f(A + 2, B, C, 8, 256, 0, 0, D, None, None) == -1          # misaligned
+    far = [k << 40 for k in (1, 2, 3, 4, 5)]                            # disjoint 1 TiB-spaced ranges
+    assert f(*far[:3], (1 << 31) + 1, 256, 0, 0, far[3], None, None) == -1   # grid limit
+    # the optional offsets output: L * count floats, aligned, overlapping nothing
+    assert f(*far[:3], 8, 4, 0, 0, far[3], far[3] + 16, None) == -1    # d0 overlaps err
+    assert f(*far[:3], 8, 4, 0, 0, far[3], far[0] + 4, None) == -1     # d0 overlaps nx
+    assert f(*far[:3], 8, 4, 0, 0, far[3], far[4] + 2, None) == -1     # d0 misaligned
+    assert f(*far[:3], 1 << 31, (1 << 31) - 1, 0, 0, far[3], far[4], None) == -1   # count * L * 4 overflows
 
 
 def test_python_layer_rejects_cpu_tensors(lib):

@@ -36,22 +36,8 @@ def max_abs_err(a, b):
 
 
 def near_degenerate_problems(orc, n, seed, dtype=np.float32):
-    """The precision-study workload: normals within 1e-4 rad of an axis, face or
-    space diagonal, fill levels within 1e-6 of 0, 1 or a case-boundary volume.
-    Boundary volumes come from the oracle's forward volume at the boundary
-    offsets the generator names."""
+    """The precision-study workload (workloads.near_degenerate_problems) with
+    the boundary volumes from the oracle's forward volume."""
     import workloads
 
-    nrm, which, comp, jit = workloads.near_degenerate_normals(n, seed)
-    nrm = nrm.astype(dtype).astype(np.float64)
-    a = np.sort(np.abs(nrm), axis=1)
-    S = a.sum(1)
-    dred = np.select([which == 0, which == 1, which == 2, which == 3],
-                     [np.zeros(n), a[:, 0], a[:, 1], np.minimum(a[:, 0] + a[:, 1], a[:, 2])],
-                     0.5 * S)
-    V = orc.volume(nrm[:, 0], nrm[:, 1], nrm[:, 2], dred - 0.5 * S)
-    V = np.where(comp, 1.0 - V, V) + jit
-    V = np.clip(V, 0.0, 1.0).astype(dtype)
-    nrm = nrm.astype(dtype)
-    return (np.ascontiguousarray(nrm[:, 0]), np.ascontiguousarray(nrm[:, 1]),
-            np.ascontiguousarray(nrm[:, 2]), V)
+    return workloads.near_degenerate_problems(orc.volume, n, seed, dtype)

@@ -2,15 +2,14 @@
 
 Tolerance per interface cell, on cells with a fit of 5 points or more whose
 pivot ratio (largest / smallest LDL^T pivot, the oracle's conditioning proxy)
-is at most 1e6:
-  * FP64 fit (precisions "mixed", "fp64"): |kappa - kappa_ref| <= 1e-5 + 1e-3 |kappa_ref|;
-    FP32 PLIC points carry errors of ~3e-7 in the heights, far below this;
-  * FP32 fit ("fp32"): the normal equations are solved in FP32, with an error
-    of about (pivot ratio) * 2^-23 relative to the coefficients, so the bound
-    is (1e-5 + 1e-3 |kappa_ref|) * max(1, pivot ratio / 25).
-The remaining cells (about 1 in 500 on a sphere) are checked for finiteness
-only: their fit is decided by pivots near the rank threshold.  Non-interface
-and boundary cells are exactly 0.
+is at most 1e6: |kappa - kappa_ref| <= 1e-5 + 1e-3 |kappa_ref| in every
+precision.  FP32 PLIC points carry errors of ~3e-7 in the heights, far below
+this; an FP32 fit ("fp32") adds about (pivot ratio) * 2^-23 relative to the
+coefficients, and the pivot ratios of these lattices stay below 40 (the
+distribution of err/tol is printed: at most 0.009).  The remaining cells
+(about 1 in 500 on a sphere) are checked for finiteness only: their fit is
+decided by pivots near the rank threshold.  Non-interface and boundary cells
+are exactly 0.
 """
 import numpy as np
 import pytest
@@ -48,9 +47,11 @@ def check_against(ref, phi, k, precision, report=""):
     good = (info[:, 0] >= 5) & (info[:, 2] <= 1e6)
     kg = k.ravel()[cells].astype(np.float64)
     tol = 1e-5 + 1e-3 * np.abs(kr)
-    if precision == "fp32":
-        tol *= np.maximum(1.0, info[:, 2] / 25.0)
     err = np.abs(kg - kr) / tol
+    if precision == "fp32" and good.any():
+        q = np.quantile(err[good], [0.5, 0.99, 0.999])
+        print(f"{report}: FP32 fit, err/tol p50 {q[0]:.3g} p99 {q[1]:.3g} p99.9 {q[2]:.3g} "
+              f"max {err[good].max():.3g}; largest pivot ratio {info[good, 2].max():.3g}")
     print(f"{report}: {cells.size} interface cells, {int((~good).sum())} loose; "
           f"max err/tol {err[good].max() if good.any() else 0:.3f}")
     assert np.isfinite(kg).all()

@@ -1,7 +1,16 @@
 """GPU backward of plic_curvature (adjoint per interface cell, stored
 contributions, deterministic gather) against the oracle's FP64
-finite-difference gradient and against central differences of the GPU
-forward."""
+finite-difference gradient (central differences at h and 2h, Richardson
+extrapolated, accurate to about 1e-10 of the largest entry) and against
+central differences of the GPU forward.
+
+Bars, as max |g - g_ref| / max |g_ref| over the whole grad_phi field:
+  * FP32 and mixed precision: 1e-4;
+  * FP64 arithmetic: FP64_BAR.  The boundary stores the 27 contributions of
+    each interface cell and grad_phi in float32, so a gradient entry carries
+    the rounding of up to 27 stored terms and their float32 sum: a few units of
+    2^-24 of the summed magnitudes, not the 1e-9 an FP64 result would allow.
+"""
 import numpy as np
 import pytest
 import torch
@@ -10,6 +19,9 @@ import workloads
 from tests.gpu_util import PRECISIONS, dev, host
 
 pytestmark = pytest.mark.gpu
+
+FP64_BAR = 8 * 2.0 ** -24           # float32 storage of the rows and of grad_phi
+BARS = {"fp32": 1e-4, "mixed": 1e-4, "fp64": FP64_BAR}
 
 
 @pytest.fixture(scope="module")
@@ -28,13 +40,13 @@ def case(orc):
     cells = np.flatnonzero(flags & 1)
     _, info = orc.curvature_cells(phi, cells)
     ok = (info[:, 0] >= 5) & (info[:, 2] <= 1e4)
-    _, bad = orc.curvature_grad(phi, np.ones_like(phi), h=1e-6)
+    _, bad = orc.curvature_grad_richardson(phi, np.ones_like(phi))
     gk = np.zeros(phi.size, np.float32)
     rng = np.random.default_rng(3)
     sel = cells[ok & ~bad.ravel()[cells]]
     gk[sel] = rng.standard_normal(sel.size).astype(np.float32)
     gk = gk.reshape(phi.shape)
-    gref, _ = orc.curvature_grad(phi, gk, h=1e-6)
+    gref, _ = orc.curvature_grad_richardson(phi, gk)
     return phi, gk, gref, sel
 
 
@@ -52,8 +64,7 @@ def test_backward_matches_oracle(P, case, precision):
     scale = np.abs(gref).max()
     err = np.abs(g - gref).max() / scale
     print(f"{precision}: {sel.size} cells, max |g - g_ref| / max|g_ref| = {err:.3e}")
-    tol = {"fp32": 2e-3, "mixed": 2e-3, "fp64": 1e-6}[precision]
-    assert err <= tol
+    assert err <= BARS[precision]
     # away from the interface band the gradient is exactly zero
     band = np.zeros(phi.shape, bool)
     iface = (phi > 0) & (phi < 1)
@@ -68,7 +79,9 @@ def test_backward_matches_oracle(P, case, precision):
 def test_backward_other_solvers(P, case, solver):
     phi, gk, gref, _ = case
     g = gpu_grad(P, phi, gk, solver, "mixed").astype(np.float64)
-    assert np.abs(g - gref).max() / np.abs(gref).max() <= 2e-3
+    err = np.abs(g - gref).max() / np.abs(gref).max()
+    print(f"{solver}/mixed: max |g - g_ref| / max|g_ref| = {err:.3e}")
+    assert err <= BARS["mixed"]
 
 
 def test_backward_against_gpu_finite_differences(P, case):
@@ -153,7 +166,7 @@ def test_workspace_capacity_fallback(P, case):
     # below the fixed part the library refuses before launching anything
     ws = torch.empty(fixed - 4, dtype=torch.uint8, device="cuda")
     out = torch.empty_like(tp)
-    with pytest.raises(RuntimeError, match="EINVAL"):
+    with pytest.raises(RuntimeError, match="PLIC_EWORKSPACE"):
         P.plic_curvature_backward_f32(tp, tg, out, "analytic", "mixed", ws)
     # the forward needs only the fixed part
     ws = torch.empty(fixed, dtype=torch.uint8, device="cuda")
@@ -170,55 +183,35 @@ def test_autograd_function(P, case):
     k = P.curvature(t, "analytic", "mixed")
     (k * dev(gk)).sum().backward()
     g = host(t.grad).astype(np.float64)
-    assert np.abs(g - gref).max() / np.abs(gref).max() <= 2e-3
+    assert np.abs(g - gref).max() / np.abs(gref).max() <= BARS["mixed"]
 
 
 @pytest.fixture(scope="module")
 def full_case(orc):
-    """Perturbed sphere R = 50 on 192^3 (the differentiation workload), 60
-    isolated well-conditioned upstream cells (pairwise more than 2 cells apart,
-    so that each checked neighbourhood sees one source) and the oracle's FD
-    gradient over each cell's 3^3 (None where the masks would change)."""
+    """The differentiation workload: perturbed sphere R = 50 on 192^3, upstream
+    gradient N(0,1) on every interface cell (none of them has inadmissible
+    central differences: no perturbation crosses 0 or 1 or changes the fit's
+    parameter set), and the oracle's gradient over the whole field."""
     phi, _, _ = workloads.perturbed_sphere_lattice(N=192, R=50.0, seed=0)
-    kref, flags = orc.curvature(phi, flags=True)
+    _, flags = orc.curvature(phi, flags=True)
     cells = np.flatnonzero(flags & 1)
-    _, info = orc.curvature_cells(phi, cells)
-    ok = cells[(info[:, 0] >= 5) & (info[:, 2] <= 1e4)]
-    rng = np.random.default_rng(7)
-    pick = rng.choice(ok, 400, replace=False)
-    Z, Y, X = phi.shape
-    coords = np.stack([pick % X, (pick // X) % Y, pick // (X * Y)], 1)
-    keep = []
-    for i, c in enumerate(coords):
-        if all(np.abs(c - coords[j]).max() > 2 for j in keep):
-            keep.append(i)
-    pick = pick[keep][:60]
-    refs = []
-    for c in pick:
-        x, y, z = c % X, (c // X) % Y, c // (X * Y)
-        nb = phi[z - 1:z + 2, y - 1:y + 2, x - 1:x + 2].astype(np.float64).ravel()
-        ref, bad = orc.curv_cell_fd_grad(nb, h=1e-6)
-        refs.append(None if bad else ref)
+    _, bad = orc.curvature_grad_richardson(phi, np.ones_like(phi))
+    assert not bad.ravel()[cells].any()
     gk = np.zeros(phi.size, np.float32)
-    gk[pick] = 1.0
-    return phi, gk.reshape(phi.shape), pick, refs
+    gk[cells] = np.random.default_rng(7).standard_normal(cells.size).astype(np.float32)
+    gk = gk.reshape(phi.shape)
+    gref, _ = orc.curvature_grad_richardson(phi, gk)
+    return phi, gk, gref, cells.size
 
 
 @pytest.mark.parametrize("solver", ["analytic", "sz", "newton", "nested"])
-def test_full_size_backward_runs(P, full_case, solver):
-    """The differentiation workload's backward with each solver's points
-    against the oracle on the sampled cells' neighbourhoods."""
-    phi, gk, pick, refs = full_case
-    Z, Y, X = phi.shape
+def test_full_size_backward_full_field(P, full_case, solver):
+    """The differentiation workload's backward with each solver's points:
+    the whole grad_phi field against the oracle, element by element; every
+    band cell sums the contributions of up to 27 interface cells."""
+    phi, gk, gref, n = full_case
     g = gpu_grad(P, phi, gk, solver).astype(np.float64)
-    worst, checked = 0.0, 0
-    for c, ref in zip(pick, refs):
-        if ref is None:
-            continue
-        x, y, z = c % X, (c // X) % Y, c // (X * Y)
-        got = g[z - 1:z + 2, y - 1:y + 2, x - 1:x + 2].ravel()
-        worst = max(worst, np.abs(got - ref).max() / max(1.0, np.abs(ref).max()))
-        checked += 1
-    print(f"192^3 sampled backward ({solver}): {checked} cells, worst {worst:.3e}")
-    assert checked >= 30
-    assert worst <= 2e-3
+    err = np.abs(g - gref).max() / np.abs(gref).max()
+    print(f"192^3 full field ({solver}, mixed), upstream on all {n} interface cells: "
+          f"max |g - g_ref| / max|g_ref| = {err:.3e}")
+    assert err <= BARS["mixed"]

@@ -1,6 +1,10 @@
 """GPU backward of plic_offset against the oracle's explicit-polygon gradient
 (dd0/dV0 = |n|/A, dd0/dn = centroid) and against central finite differences of
-the GPU forward; the torch.autograd.Function wiring; fwd+bwd at 2^24."""
+the GPU forward; the torch.autograd.Function wiring; fwd+bwd at 2^24.
+
+Bars with FP32 storage, every precision mode: dd0/dV0 relative 1e-5 (measured
+at most 1.1e-6 with V0 in [0.01, 0.99]: the FP32 rounding of the root and of
+1/A), the centroid absolute 2e-5 times the largest upstream gradient."""
 import numpy as np
 import pytest
 import torch
@@ -44,7 +48,8 @@ def test_backward_matches_oracle_f32(P, orc, solver, precision):
     g64 = gd.astype(np.float64)
     rel_v = np.abs(ov - g64 * dv) / np.maximum(np.abs(g64 * dv), 1e-30)
     # dV error is relative (|n|/A can be large for small polygons)
-    assert np.quantile(rel_v, 0.999) <= 1e-4 and rel_v.max() <= 2e-3
+    print(f"{solver}/{precision}: max relative error of dd0/dV0 {rel_v.max():.2e}")
+    assert rel_v.max() <= 1e-5
     for o, r in ((ox, gx), (oy, gy), (oz, gz)):
         assert np.max(np.abs(o - g64 * r)) <= 2e-5 * max(1.0, np.abs(g64).max())
 
@@ -93,7 +98,7 @@ def test_autograd_function(P, orc):
     _, dv, gx, gy, gz = orc.offset_grad(nx, ny, nz, V0)
     wn = host(w).astype(np.float64)
     assert np.max(np.abs(host(tn[0].grad) - wn * gx)) <= 2e-5 * np.abs(wn).max()
-    assert np.quantile(np.abs(host(tn[3].grad) - wn * dv) / np.abs(wn * dv), 0.999) <= 1e-4
+    assert np.max(np.abs(host(tn[3].grad) - wn * dv) / np.abs(wn * dv)) <= 1e-5
     # float64 tensors take the f64 entry points
     t64 = [torch.from_numpy(a.astype(np.float64)).cuda().requires_grad_(True) for a in (nx, ny, nz, V0)]
     P.offset(tuple(t64[:3]), t64[3]).sum().backward()
@@ -126,5 +131,7 @@ def test_fwd_bwd_2p24_sampled(P, orc):
     _, dv, gx, gy, gz = orc.offset_grad(nx[idx], ny[idx], nz[idx], V0[idx])
     ti = torch.from_numpy(idx).cuda()
     g = gd[idx].astype(np.float64)
-    assert np.quantile(np.abs(host(outs[3][ti]) - g * dv) / np.abs(g * dv), 0.999) <= 1e-4
+    rel = np.abs(host(outs[3][ti]) - g * dv) / np.abs(g * dv)
+    print(f"2^24 sampled: max relative error of dd0/dV0 {rel.max():.2e}")
+    assert rel.max() <= 1e-5
     assert np.max(np.abs(host(outs[0][ti]) - g * gx)) <= 2e-5 * np.abs(g).max()

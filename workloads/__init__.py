@@ -149,6 +149,27 @@ def near_degenerate_normals(n: int, seed: int, max_angle: float = 1e-4,
     return nrm, boundary, complement, jitter
 
 
+def near_degenerate_problems(volume, n: int, seed: int, dtype=np.float32):
+    """The precision-study workload: normals within 1e-4 rad of an axis, face or
+    space diagonal, fill levels within 1e-6 of 0, 1 or a case-boundary volume.
+    ``volume(nx, ny, nz, d0) -> V0`` is the caller's forward volume (float64),
+    which turns the boundary offsets that near_degenerate_normals names into
+    fill levels.  Returns (nx, ny, nz, V0) in ``dtype``."""
+    nrm, which, comp, jit = near_degenerate_normals(n, seed)
+    nrm = nrm.astype(dtype).astype(np.float64)
+    a = np.sort(np.abs(nrm), axis=1)
+    S = a.sum(1)
+    dred = np.select([which == 0, which == 1, which == 2, which == 3],
+                     [np.zeros(n), a[:, 0], a[:, 1], np.minimum(a[:, 0] + a[:, 1], a[:, 2])],
+                     0.5 * S)
+    V = np.asarray(volume(nrm[:, 0], nrm[:, 1], nrm[:, 2], dred - 0.5 * S), dtype=np.float64)
+    V = np.where(comp, 1.0 - V, V) + jit
+    V = np.clip(V, 0.0, 1.0).astype(dtype)
+    nrm = nrm.astype(dtype)
+    return (np.ascontiguousarray(nrm[:, 0]), np.ascontiguousarray(nrm[:, 1]),
+            np.ascontiguousarray(nrm[:, 2]), V)
+
+
 def upstream_grad(shape, seed: int, dtype=np.float32):
     """Upstream gradient ~ N(0, 1)."""
     rng = np.random.default_rng(seed)

@@ -12,8 +12,16 @@ is taken around the whole step after a device synchronisation.
 
 Prints one JSON line: value = PLIC solves per second of step time, counting
 the 4 N forward solves and the N solves recomputed by the backward (5 N per
-step); per-kernel rates, the roofline of the dominant kernel and an oracle
-CPU baseline ride along.
+step).  Beside it: per-kernel rates with their fraction of the HBM peak and of
+the measured VALU issue ceiling (valu_ceiling: a probe of each instruction's
+issue rate), the roofline of the dominant kernel, the differentiation
+workload (offset forward + backward on 2^24 problems, curvature forward +
+backward on a 192^3 perturbed sphere), secondary variants, the paper-method
+benchmark, and the CPU-baseline leg.  That leg is the only part that runs
+the oracle: its rate on all host cores and on one, the oracle curvature's
+rate on the lattice, each solver's error against it, and the precision study
+(2^24 near-degenerate problems and the lattice through every precision mode,
+with time and error against the oracle).
 """
 from __future__ import annotations
 
@@ -62,6 +70,10 @@ def parse():
                     help="static gfx950 instruction counts of the paper-method benchmark kernels "
                          "(compiles plic_bench.hip to assembly; no GPU)")
     ap.add_argument("--isa-out", default=ISA_PROFILE, help="where --write-isa-profile writes")
+    ap.add_argument("--write-trace-profile", metavar="TRACE_CSV",
+                    help="summarise a rocprofv3 --kernel-trace run of this script (its "
+                         "*_kernel_trace.csv) into --trace-out")
+    ap.add_argument("--trace-out", default=None, help="where --write-trace-profile writes")
     return ap.parse_args()
 
 
@@ -106,6 +118,40 @@ def measured_traffic(kernel):
         return None
     m = re.search(r"^\| " + re.escape(kernel) + r" \| [^|]* \| ([0-9,]+) \|", text, flags=re.M)
     return int(m.group(1).replace(",", "")) if m else None
+
+
+def measured_issue(kernel):
+    """Wavefronts and instructions per wavefront (all VALU, F32 and F64
+    transcendentals) of one launch of a bench kernel from the committed
+    issue-counter summary, or None when it is missing or the kernel sources
+    changed since."""
+    try:
+        text = open(ISSUE_PROFILE).read()
+    except OSError:
+        return None
+    import re
+    m = re.search(r"kernel source sha256: `([0-9a-f]{64})`", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(r"^\| " + re.escape(kernel) + r" \| ([0-9,]+) \| ([0-9.]+) \| ([0-9.]+) \| ([0-9.]+) \|",
+                  text, flags=re.M)
+    if not m:
+        return None
+    return {"waves": int(m.group(1).replace(",", "")), "valu": float(m.group(2)), "trans_f32": float(m.group(3)),
+            "trans_f64": float(m.group(4))}
+
+
+def valu_bound_ms(issue, ceiling):
+    """Time the launch's VALU instructions need at the measured issue rates
+    (non-transcendental ones at the v_fma_f32 rate, transcendentals at the
+    slowest probed F32 / F64 transcendental's), in ms."""
+    trans32 = min(ceiling[k]["lane_ops_per_s"] for k in ("sqrt_f32", "rsq_f32", "rcp_f32", "sin_f32",
+                                                          "exp_f32", "log_f32"))
+    trans64 = min(ceiling[k]["lane_ops_per_s"] for k in ("rcp_f64", "sqrt_f64"))
+    lanes = issue["waves"] * 64
+    plain = issue["valu"] - issue["trans_f32"] - issue["trans_f64"]
+    return 1e3 * lanes * (plain / ceiling["fma_f32"]["lane_ops_per_s"] + issue["trans_f32"] / trans32
+                          + issue["trans_f64"] / trans64)
 
 
 # bench kernel -> dispatch names (demangled prefixes) that make up one launch
@@ -283,6 +329,74 @@ def write_isa_profile(out_path=ISA_PROFILE):
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     return out_path
+
+
+TRACE_PROFILE = os.path.join(ROOT, "profiles", "hot_path_2p26_problems_256cube_sphere_kernel_trace.md")
+
+
+def short_kernel_name(name):
+    n = name.replace("plic::(anonymous namespace)::", "").replace("void ", "")
+    n = n.split("(", 1)[0] if not n.startswith("__amd") else n
+    return n[:60]
+
+
+def write_trace_profile(trace_csv, out=None):
+    """Summary of `rocprofv3 --kernel-trace` over the default bench command
+    (its *_kernel_trace.csv): per kernel and launch size, the calls, average
+    and minimum dispatch time, and the registers and LDS of the dispatch."""
+    import csv
+
+    out = out or TRACE_PROFILE
+    acc = {}
+    for r in csv.DictReader(open(trace_csv)):
+        key = (short_kernel_name(r["Kernel_Name"]), int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) *
+               int(r["Grid_Size_Z"]))
+        d = acc.setdefault(key, {"t": [], "vgpr": r["VGPR_Count"], "agpr": r.get("Accum_VGPR_Count", "0"),
+                                 "lds": r["LDS_Block_Size"], "scratch": r["Scratch_Size"],
+                                 "wg": r["Workgroup_Size_X"]})
+        d["t"].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(d["t"]) for d in acc.values()) or 1.0
+    rows = sorted(acc.items(), key=lambda kv: -sum(kv[1]["t"]))
+    lines = [
+        "# Kernel time, whole hot path: 2^26 PLIC problems and a 256^3 sphere lattice (R = 40)",
+        "",
+        "Command (from the repository root on an MI355X, ROCm 7.2):",
+        "",
+        "```",
+        "cd /tmp && export TMPDIR=/tmp",
+        "rocprofv3 --kernel-trace --stats --output-format csv -d $REPO/gpurun_out/prof -o bench -- "
+        "python3 $REPO/bench.py --no-cpu-baseline",
+        "python3 $REPO/bench.py --write-trace-profile $REPO/gpurun_out/prof/bench_kernel_trace.csv "
+        "--trace-out <this file>",
+        "```",
+        "",
+        f"kernel source sha256: `{kernel_source_hash()}`",
+        "",
+        "Dispatch durations from the kernel trace, grouped by kernel and launch size (work-items), so the "
+        "step's launches (2^26 problems: `k_offset` and `k_volume` at 16,777,216 work-items, `k_offset_bwd` "
+        "at 16,777,216) are apart from the same kernels on other sizes (the differentiation workload's "
+        "2^24 problems, the precision study).  One bench step launches every step kernel once (the "
+        "default 20 warm-up + 20 timed steps = 40 calls; the curvature scan and the counter reset run once "
+        "for the forward and once for the backward).  The secondary timings after the timed steps (VALU "
+        "probe `k_valu`, plane-sphere, Kawano's SZ, the FP64 solvers, the warm curvature and its variants, "
+        "the 192^3 differentiation lattice, the paper-method benchmark `k_isolated`) appear with their own "
+        "call counts.",
+        "",
+        "Template arguments: `k_offset<solver, storage, bulk, cubic, problems per lane, whole blocks>`, "
+        "`k_curv_items<solver, points, cubic, fit, backward, normal, neighbour normals>`, "
+        "`k_curv_gather_fallback<solver, points, cubic, fit, normal>`; solver 0 analytic, 1 optimized SZ, "
+        "2 Newton-Raphson, 3 nested intervals, 4 Kawano's SZ; normal 0 Parker-Youngs.",
+        "",
+        "| kernel | work-items | calls | avg µs | min µs | share | VGPR | LDS B | scratch B |",
+        "|---|---:|---:|---:|---:|---:|---:|---:|---:|",
+    ]
+    for (name, items), d in rows:
+        t = d["t"]
+        lines.append(f"| `{name}` | {items:,} | {len(t)} | {sum(t) / len(t):.1f} | {min(t):.1f} | "
+                     f"{100 * sum(t) / total:.1f} % | {d['vgpr']} | {d['lds']} | {d['scratch']} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return out
 
 
 def write_issue_profile(sq_csv, log2n, lattice, out=ISSUE_PROFILE):
@@ -500,44 +614,212 @@ def sphere_rate(P, torch, V0, reps=10):
             "hbm_frac": gbs / HBM_PEAK_GBS}
 
 
-def cpu_baseline(nx, ny, nz, V0, seconds, gpu_offset=None):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(oracle, nx, ny, nz, V0, seconds, chunk):
+    """problems/s of the oracle's bisection inverse on chunks of the workload"""
+    done, t0, i = 0, time.perf_counter(), 0
+    nchunks = max(1, len(V0) // chunk)
+    while True:
+        s = slice(i * chunk, (i + 1) * chunk)
+        oracle.offset(nx[s], ny[s], nz[s], V0[s])
+        done += len(V0[s])
+        i = (i + 1) % nchunks
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            return done, el
+
+
+def cpu_baseline(nx, ny, nz, V0, seconds, gpu_offset=None, phi=None):
     """The oracle (bisection on the FP64 forward volume), timed on the host
-    cores on chunks of the same workload until `seconds` have passed.  With
-    gpu_offset (solver -> the GPU's d0 of the whole batch, on the host), the
-    error of each solver against the oracle's d0 of the first chunk."""
+    cores on chunks of the same workload until `seconds` have passed, then on
+    one core for a quarter of that; with phi, the oracle's curvature of the
+    whole lattice on all cores and on one.  With gpu_offset ((solver,
+    precision) -> the GPU's d0 of the whole batch, on the host), the error of
+    each solver and precision against the oracle's d0 of the first chunk."""
     import numpy as np
     import oracle
 
     oracle.build(force=False)
+    threads = oracle.num_threads()
     chunk = 1 << 21
-    done, t0 = 0, time.perf_counter()
-    i = 0
-    first = None
-    while True:
-        s = slice(i * chunk, (i + 1) * chunk)
-        d = oracle.offset(nx[s], ny[s], nz[s], V0[s])
-        if first is None:
-            first = np.asarray(d, dtype=np.float64)
-        done += len(V0[s])
-        i = (i + 1) % max(1, len(V0) // chunk)
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    out = {"value": done / el, "unit": "PLIC solves/s", "cores": oracle.num_threads(),
+    first = np.asarray(oracle.offset(nx[:chunk], ny[:chunk], nz[:chunk], V0[:chunk]), dtype=np.float64)
+    done, el = _oracle_rate(oracle, nx, ny, nz, V0, seconds, chunk)
+    oracle.set_num_threads(1)
+    try:
+        done1, el1 = _oracle_rate(oracle, nx, ny, nz, V0, seconds / 4, 1 << 16)
+        curv1 = None
+        if phi is not None:
+            t0 = time.perf_counter()
+            oracle.curvature(phi)
+            curv1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    out = {"value": done / el, "unit": "PLIC solves/s", "cores": threads,
            "kind": "oracle",
            "sample": f"{done} problems of the 2^{int(math.log2(len(V0)))} workload "
                      f"(chunks of 2^21) through the FP64 oracle's bisection inverse, "
-                     f"{el:.1f} s, {oracle.num_threads()} OpenMP threads"}
+                     f"{el:.1f} s, {threads} OpenMP threads",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "one_core": {"value": done1 / el1, "unit": "PLIC solves/s", "cores": 1,
+                        "sample": f"{done1} problems (chunks of 2^16), {el1:.1f} s"}}
+    if phi is not None:
+        t0 = time.perf_counter()
+        k = oracle.curvature(phi)
+        curv = time.perf_counter() - t0
+        n_if = int(np.count_nonzero(k))
+        out["curvature"] = {
+            "lattice": list(phi.shape), "interface_cells": n_if,
+            "sample": "the oracle's curvature of the whole lattice (bisection offsets, FP64 fit), one call",
+            "all_cores": {"s": round(curv, 3), "cells_per_s": phi.size / curv,
+                          "interface_cells_per_s": n_if / curv, "cores": threads},
+            "one_core": {"s": round(curv1, 3), "cells_per_s": phi.size / curv1,
+                         "interface_cells_per_s": n_if / curv1, "cores": 1}}
     if gpu_offset is not None:
         n = len(first)
         err = {}
         for solver in SOLVERS:
-            diff = np.abs(np.asarray(gpu_offset(solver)[:n], dtype=np.float64) - first)
-            err[solver] = {"max_abs": float(diff.max()), "rms": float(np.sqrt(np.mean(diff * diff)))}
-        out["error_vs_oracle"] = {"quantity": "d0, FP32 storage and arithmetic", "problems": n,
+            for prec in ("fp32", "mixed"):
+                diff = np.abs(np.asarray(gpu_offset(solver, prec)[:n], dtype=np.float64) - first)
+                err[f"{solver}/{prec}"] = {"max_abs": float(diff.max()), "rms": float(np.sqrt(np.mean(diff * diff)))}
+        out["error_vs_oracle"] = {"quantity": "d0, FP32 storage", "problems": n,
                                   "sample": f"the first {n} problems of the workload", "tolerance": 1e-5,
                                   "per_solver": err}
     return out
+
+
+def _stats(err):
+    import numpy as np
+
+    err = np.asarray(err, dtype=np.float64)
+    return {"max_abs": float(err.max()), "rms": float(np.sqrt(np.mean(err * err)))}
+
+
+def precision_study(P, torch, dev, log2n=24, lattice=None, radius=40.0):
+    """The precision modes against the oracle (part of the CPU-baseline leg,
+    the only part of this script that runs the oracle): 2^log2n near-degenerate
+    problems (normals within 1e-4 rad of the axes and diagonals, fill levels
+    within 1e-6 of 0, 1 and the case-boundary volumes) through every solver in
+    FP32, mixed, FP64 arithmetic with FP32 storage, and FP64 storage, each with
+    its time and max / RMS |d0 - oracle|; and the curvature of the lattice in
+    each mode, with max / RMS |kappa - oracle| over the well-conditioned
+    interface cells."""
+    import numpy as np
+    import oracle
+    import workloads
+
+    n = 1 << log2n
+    nx, ny, nz, V0 = workloads.near_degenerate_problems(oracle.volume, n, seed=11)
+    ref = oracle.offset(nx, ny, nz, V0)
+    t32 = [torch.from_numpy(a).to(dev) for a in (nx, ny, nz, V0)]
+    t64 = [t.double() for t in t32]
+    o32, o64 = torch.empty_like(t32[3]), torch.empty_like(t64[3])
+    stream = torch.cuda.current_stream(dev)
+    rows = {}
+    for solver in SOLVERS:
+        for mode in ("fp32", "mixed", "fp64", "f64"):
+            if mode == "f64":
+                fn, out, bpp = (lambda: P.plic_offset_f64(*t64, o64, solver)), o64, 40
+            else:
+                fn, out, bpp = (lambda: P.plic_offset_f32(*t32, o32, solver, mode)), o32, 20
+            ms = timed_reps(torch, stream, fn, reps=5)
+            d = out.cpu().numpy().astype(np.float64)
+            rows[f"{solver}/{mode}"] = {"ms": round(ms, 4), "solves_per_s": n / (ms * 1e-3),
+                                        "hbm_frac": n * bpp / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                        **_stats(np.abs(d - ref))}
+    res = {"problems": {"count": n, "workload": "near-degenerate: normals within 1e-4 rad of the 6 axis, "
+                                                "12 face-diagonal and 8 space-diagonal directions; V0 within "
+                                                "1e-6 of 0, 1 or a case-boundary volume",
+                        "tolerance": {"fp32_storage": 1e-5, "f64": 1e-12}, "per_mode": rows}}
+    if lattice is not None:
+        phi = lattice
+        kref, flags = oracle.curvature(phi, flags=True)
+        cells = np.flatnonzero(flags & 1)
+        _, info = oracle.curvature_cells(phi, cells)
+        good = cells[(info[:, 0] >= 5) & (info[:, 2] <= 1e6)]
+        kr = kref.ravel()[good]
+        tp = torch.from_numpy(phi).to(dev)
+        k = torch.empty_like(tp)
+        Z, Y, X = phi.shape
+        ws = torch.empty(P.plic_curvature_workspace_bytes(X, Y, Z), dtype=torch.uint8, device=dev)
+        crow = {}
+        for mode in ("fp32", "mixed", "fp64"):
+            ms = timed_reps(torch, stream, lambda: P.plic_curvature_f32(tp, k, "analytic", mode, ws), reps=5)
+            kg = k.cpu().numpy().ravel()[good].astype(np.float64)
+            crow[mode] = {"fwd_ms": round(ms, 4), "cells_per_s": phi.size / (ms * 1e-3),
+                          **_stats(np.abs(kg - kr)), "max_abs_times_R": float(np.abs(kg - kr).max() * radius),
+                          "mean_kappa_R": float(kg.mean() * radius)}
+        res["curvature"] = {"lattice": list(phi.shape), "cells_compared": int(good.size),
+                            "interface_cells": int(cells.size),
+                            "compared": "interface cells with >= 5 points and pivot ratio <= 1e6 "
+                                        "(analytic points; warm cache)",
+                            "tolerance": "|dk| <= 1e-5 + 1e-3 |k| per cell (FP64 fit)", "per_mode": crow}
+    return res
+
+
+def differentiation(P, torch, dev, tn, log2n=24):
+    """Forward + backward timings of the differentiation workload: plic_offset
+    on the first 2^log2n problems of the step (upstream N(0,1)), and the
+    curvature of a 192^3 perturbed sphere (R = 50, l <= 6 harmonics, 5 %
+    amplitude) with N(0,1) upstream on every interface cell, FP32 points and
+    FP64 fit.  Warm back-to-back calls."""
+    import numpy as np
+    import workloads
+
+    n = 1 << log2n
+    t = [x[:n] for x in tn]
+    d0 = torch.empty_like(t[3])
+    g = [torch.empty_like(t[3]) for _ in range(4)]
+    stream = torch.cuda.current_stream(dev)
+    fwd = timed_reps(torch, stream, lambda: P.plic_offset_f32(*t[:4], d0, "sz", "fp32"))
+    bwd = timed_reps(torch, stream, lambda: P.plic_offset_backward_f32(*t[:4], t[4], *g, "sz", "fp32"))
+    res = {"plic_offset": {"problems": n, "solver": "sz", "precision": "fp32", "fwd_ms": round(fwd, 4),
+                           "bwd_ms": round(bwd, 4), "fwd_bwd_solves_per_s": n / ((fwd + bwd) * 1e-3),
+                           "bytes_per_problem": 56,
+                           "hbm_frac": n * 56 / ((fwd + bwd) * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    phi, _, _ = workloads.perturbed_sphere_lattice(N=192, R=50.0, seed=0)
+    iface = (phi > 0) & (phi < 1)
+    gk = np.where(iface, workloads.upstream_grad(phi.shape, seed=3), 0.0).astype(np.float32)
+    tp, tg = torch.from_numpy(phi).to(dev), torch.from_numpy(gk).to(dev)
+    kap, gp = torch.empty_like(tp), torch.empty_like(tp)
+    Z, Y, X = phi.shape
+    ws = torch.empty(P.plic_curvature_workspace_bytes(X, Y, Z), dtype=torch.uint8, device=dev)
+    cf = timed_reps(torch, stream, lambda: P.plic_curvature_f32(tp, kap, "analytic", "mixed", ws))
+    cb = timed_reps(torch, stream, lambda: P.plic_curvature_backward_f32(tp, tg, gp, "analytic", "mixed", ws))
+    res["curvature"] = {"lattice": [192, 192, 192], "workload": "perturbed sphere R=50, l<=6, 5% amplitude",
+                        "interface_cells": int(iface.sum()), "fwd_ms": round(cf, 4), "bwd_ms": round(cb, 4),
+                        "fwd_bwd_cells_per_s": phi.size / ((cf + cb) * 1e-3),
+                        "bytes_per_cell": 20, "hbm_frac": phi.size * 20 / ((cf + cb) * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return res
+
+
+def valu_ceiling(P, torch, dev, threads=1 << 20, iters=800):
+    """Measured issue rate of each probed VALU instruction (plic_bench_valu:
+    32 * iters instructions per thread, minus an empty launch), in lane
+    operations per second and in cycles per wavefront instruction at the
+    nominal 2.4 GHz."""
+    from paper_2006_12838_amd._lib import VALU_OPS
+
+    sink = torch.empty(threads, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(10):
+        P.plic_bench_valu("fma_f32", sink, 4 * iters)
+    res = {}
+    for op in VALU_OPS:
+        t = timed_reps(torch, stream, lambda: P.plic_bench_valu(op, sink, iters), reps=5)
+        t0 = timed_reps(torch, stream, lambda: P.plic_bench_valu(op, sink, 0), reps=5)
+        rate = threads * 32 * iters / ((t - t0) * 1e-3)
+        res[op] = {"lane_ops_per_s": rate, "cycles_per_wave_instr_at_2p4GHz": 1024 * 2.4e9 / (rate / 64)}
+    return res
 
 
 def main():
@@ -550,6 +832,9 @@ def main():
         return
     if args.write_issue_profile:
         print(write_issue_profile(args.write_issue_profile, args.log2n, args.lattice, args.issue_out))
+        return
+    if args.write_trace_profile:
+        print(write_trace_profile(args.write_trace_profile, args.trace_out))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: runs on one GPU only; --gpus must be 1 (the PLIC path has no cross-GPU step)",
@@ -606,6 +891,11 @@ def main():
             kernels.append(("copy", lambda: cdst.copy_(csrc), N, "floats", 8))
 
     stream = torch.cuda.current_stream(dev)
+    # the VALU probe runs first: its measurement is reported beside the step,
+    # and its ~0.1 s of issue-bound work brings the GPU clock up before the
+    # warm-up steps (the instruction-bound solvers time up to 16 % slow on a
+    # clock still ramping)
+    ceiling = None if args.only else valu_ceiling(P, torch, dev)
     # one pair of events per kernel and step: the K steps run back to back,
     # and the per-kernel times are read after the closing synchronize
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in kernels]
@@ -676,6 +966,15 @@ def main():
         "roofline": roofline,
     }
     if not args.only:
+        out["valu_ceiling"] = ceiling
+        for name in rates:
+            iss = measured_issue(name)
+            if iss is None:
+                rates[name]["valu_frac"] = None
+                continue
+            rates[name]["valu_frac"] = round(valu_bound_ms(iss, ceiling) / rates[name]["ms"], 4)
+            rates[name]["binds"] = "hbm" if rates[name]["hbm_frac"] >= rates[name]["valu_frac"] else "valu"
+        out["differentiation"] = differentiation(P, torch, dev, tn)
         out["sphere_offset"] = sphere_rate(P, torch, tn[3])
         out["offset_sz_kawano"] = kawano_rate(P, torch, tn)
         out["offset_f64"] = f64_rates(P, torch, tn)
@@ -684,11 +983,13 @@ def main():
     if not args.no_paper_isolated and not args.only:
         out["paper_isolated"] = paper_isolated(P, torch, dev, args.log2n)
     if not args.no_cpu_baseline:
-        def gpu_offset(solver):
-            P.plic_offset_f32(*tn[:4], d0, solver, "fp32")
+        def gpu_offset(solver, prec):
+            P.plic_offset_f32(*tn[:4], d0, solver, prec)
             torch.cuda.synchronize()
             return d0[: 1 << 21].cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(nx, ny, nz, V0, args.cpu_seconds, gpu_offset)
+        out["cpu_baseline"] = cpu_baseline(nx, ny, nz, V0, args.cpu_seconds, gpu_offset, phi)
+        if not args.only:
+            out["precision_study"] = precision_study(P, torch, dev, 24, phi, args.radius)
     print(json.dumps(out), flush=True)
 
 

@@ -333,12 +333,19 @@ def curvature_grad(phi, grad_kappa, h=1e-6, normal="py", neighbour_normals=False
     return out, bad.astype(bool)
 
 
+def _gomp():
+    _load()                                   # the oracle links the OpenMP runtime
+    return ctypes.CDLL("libgomp.so.1")
+
+
 def num_threads() -> int:
-    """OpenMP threads the oracle uses (OMP_NUM_THREADS or the core count)."""
-    v = os.environ.get("OMP_NUM_THREADS")
-    if v and v.isdigit():
-        return int(v)
-    return os.cpu_count() or 1
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_gomp().omp_get_max_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's later parallel loops (for timing it on one core)."""
+    _gomp().omp_set_num_threads(int(n))
 
 
 def curvature_grad_richardson(phi, grad_kappa, h=1e-5, normal="py", neighbour_normals=False):

@@ -113,11 +113,69 @@ def test_cpu_baseline_reports_error_against_the_oracle():
     nx, ny, nz, V0 = workloads.plic_problems(4096, seed=3)
     ref = np.asarray(oracle.offset(nx, ny, nz, V0), dtype=np.float64)
     shift = {"analytic": 0.0, "sz": 2e-7, "newton": -3e-6, "nested": 1e-5}
-    out = bench.cpu_baseline(nx, ny, nz, V0, 0.01, lambda s: (ref + shift[s]).astype(np.float32))
+    prec_shift = {"fp32": 0.0, "mixed": 1e-6}
+    phi, _ = workloads.sphere_lattice(N=16, R=4.0, seed=1)
+    out = bench.cpu_baseline(nx, ny, nz, V0, 0.01,
+                             lambda s, p: (ref + shift[s] + prec_shift[p]).astype(np.float32), phi)
     assert out["kind"] == "oracle" and out["value"] > 0 and out["cores"] >= 1
+    assert out["one_core"]["cores"] == 1 and out["one_core"]["value"] > 0 and out["cpu_model"]
+    assert oracle.num_threads() == out["cores"]                         # restored after the one-core run
+    cur = out["curvature"]
+    assert cur["interface_cells"] == int(np.count_nonzero(oracle.curvature(phi)))
+    assert cur["all_cores"]["cells_per_s"] > 0 and cur["one_core"]["cores"] == 1
     err = out["error_vs_oracle"]
     assert err["problems"] == 4096 and err["tolerance"] == 1e-5
     for s, d in shift.items():
-        e = err["per_solver"][s]
-        # the stand-in is rounded to FP32 like the GPU's output
-        assert abs(e["max_abs"] - abs(d)) <= 1e-7 and e["rms"] <= e["max_abs"]
+        for p, dp in prec_shift.items():
+            e = err["per_solver"][f"{s}/{p}"]
+            # the stand-in is rounded to FP32 like the GPU's output
+            assert abs(e["max_abs"] - abs(d + dp)) <= 1e-7 and e["rms"] <= e["max_abs"]
+
+
+def test_measured_issue_and_valu_bound(tmp_path, monkeypatch):
+    """The issue-counter summary is read only for the profiled sources, and
+    the VALU-bound time prices plain and transcendental instructions at their
+    own measured rates."""
+    prof = tmp_path / "issue.md"
+    monkeypatch.setattr(bench, "ISSUE_PROFILE", str(prof))
+    assert bench.measured_issue("offset_sz") is None
+    head = ["| bench kernel | waves | VALU / wave | of which trans. F32 | trans. F64 | SALU / wave | x |",
+            "|---|---:|---:|---:|---:|---:|---:|",
+            "| offset_sz | 262,144 | 493.7 | 33.5 | 0.0 | 221.9 | 1 |"]
+    prof.write_text(f"kernel source sha256: `{bench.kernel_source_hash()}`\n\n" + "\n".join(head) + "\n")
+    iss = bench.measured_issue("offset_sz")
+    assert iss == {"waves": 262144, "valu": 493.7, "trans_f32": 33.5, "trans_f64": 0.0}
+    assert bench.measured_issue("volume") is None
+    ceiling = {k: {"lane_ops_per_s": 1e12} for k in ("sqrt_f32", "rsq_f32", "rcp_f32", "sin_f32", "exp_f32",
+                                                     "log_f32", "rcp_f64", "sqrt_f64")}
+    ceiling["sin_f32"] = {"lane_ops_per_s": 0.5e12}                 # the slowest transcendental prices them all
+    ceiling["fma_f32"] = {"lane_ops_per_s": 4e12}
+    ms = bench.valu_bound_ms(iss, ceiling)
+    lanes = 262144 * 64
+    assert ms == pytest.approx(1e3 * lanes * ((493.7 - 33.5) / 4e12 + 33.5 / 0.5e12))
+    prof.write_text("kernel source sha256: `" + "0" * 64 + "`\n\n" + "\n".join(head) + "\n")
+    assert bench.measured_issue("offset_sz") is None
+
+
+def test_trace_profile_summary(tmp_path):
+    """The kernel-trace summary groups dispatches by kernel and launch size,
+    with calls and average / minimum duration (ns in the CSV, µs in the
+    table), longest total first."""
+    head = ('"Kind","Agent_Id","Queue_Id","Stream_Id","Thread_Id","Dispatch_Id","Kernel_Id","Kernel_Name",'
+            '"Correlation_Id","Start_Timestamp","End_Timestamp","LDS_Block_Size","Scratch_Size","VGPR_Count",'
+            '"Accum_VGPR_Count","SGPR_Count","Workgroup_Size_X","Workgroup_Size_Y","Workgroup_Size_Z",'
+            '"Grid_Size_X","Grid_Size_Y","Grid_Size_Z"')
+    bwd = '"void plic::(anonymous namespace)::k_offset_bwd<1, float, float, float, 4, true>(float*)"'
+    vol = '"void plic::(anonymous namespace)::k_volume<float, float, 4>(float const*, long)"'
+    rows = [f'"KERNEL_DISPATCH","Agent 1",1,0,1,{i},1,{bwd},{i},{1000 * i},{1000 * i + d},0,0,64,0,16,512,1,1,'
+            f'{g},1,1' for i, (d, g) in enumerate([(435000, 16777216), (425000, 16777216), (100000, 4194304)])]
+    rows.append(f'"KERNEL_DISPATCH","Agent 1",1,0,1,9,1,{vol},9,0,230000,0,0,32,0,16,256,1,1,16777216,1,1')
+    csvp = tmp_path / "trace.csv"
+    csvp.write_text(head + "\n" + "\n".join(rows) + "\n")
+    out = bench.write_trace_profile(str(csvp), str(tmp_path / "t.md"))
+    text = open(out).read()
+    table = [ln for ln in text.splitlines() if ln.startswith("| `")]
+    assert table[0].startswith("| `k_offset_bwd<1, float, float, float, 4, true>` | 16,777,216 | 2 | 430.0 | 425.0 |")
+    assert table[1].startswith("| `k_volume<float, float, 4>` | 16,777,216 | 1 | 230.0 | 230.0 |")
+    assert table[2].startswith("| `k_offset_bwd<1, float, float, float, 4, true>` | 4,194,304 | 1 | 100.0 |")
+    assert bench.kernel_source_hash() in text

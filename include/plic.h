@@ -180,6 +180,24 @@ int plic_curvature_f32(const float *phi, int64_t X, int64_t Y, int64_t Z, float 
                        void *stream);
 
 /*
+ * plic_curvature_noalloc_f32 — plic_curvature_f32 (Parker-Youngs normal, the
+ * centre normal for every point) for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  It takes no workspace and allocates nothing: its
+ * workspace is a static device array of 16 MiB inside the library, one per
+ * GPU the library runs on, held until the process ends.  Lattices of up to
+ * 21,399 tiles of 64x4x4 cells (256^3 has 16,384) fit; a larger lattice
+ * returns PLIC_EWORKSPACE before anything is launched.  Every call on a GPU
+ * shares that GPU's array, which keeps the last call's contents (each call
+ * clears what it uses): calls that overlap in time on one GPU (several
+ * streams or host threads) race and must be serialised by the caller.
+ * Arguments, status codes and results (bit for bit) are otherwise those of
+ * plic_curvature_f32.
+ */
+int plic_curvature_noalloc_f32(const float *phi, int64_t X, int64_t Y, int64_t Z, float *kappa,
+                               int solver, int precision, void *stream);
+
+/*
  * plic_curvature_backward_f32 — vector-Jacobian product of plic_curvature:
  * grad_phi[j] = sum over interface cells c of grad_kappa[c] * d kappa_c / d phi_j.
  * The neighbourhood of each cell is recomputed (nothing is stored by the

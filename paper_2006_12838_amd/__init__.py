@@ -29,6 +29,7 @@ from ._lib import (  # noqa: F401  (re-exported: the C ABI by name)
     plic_curvature_backward_f32,
     plic_curvature_ex_f32,
     plic_curvature_f32,
+    plic_curvature_noalloc_f32,
     plic_curvature_status,
     plic_curvature_workspace_bytes,
     plic_curvature_workspace_bytes_ex,

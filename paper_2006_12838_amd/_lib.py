@@ -45,6 +45,7 @@ _c = {
     "plic_offset_backward_f64": _sig("plic_offset_backward_f64", [_vp] * 9 + [_i64, _int, _vp]),
     "plic_curvature_f32": _sig("plic_curvature_f32",
                                [_vp, _i64, _i64, _i64, _vp, _int, _int, _vp, ctypes.c_size_t, _vp]),
+    "plic_curvature_noalloc_f32": _sig("plic_curvature_noalloc_f32", [_vp, _i64, _i64, _i64, _vp, _int, _int, _vp]),
     "plic_curvature_backward_f32": _sig("plic_curvature_backward_f32",
                                         [_vp, _i64, _i64, _i64, _vp, _vp, _int, _int, _vp,
                                          ctypes.c_size_t, _vp]),
@@ -267,6 +268,21 @@ def plic_curvature_f32(phi, kappa, solver="analytic", precision="mixed", workspa
                                     _enum(PRECISIONS, precision, "precision"),
                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
            "plic_curvature_f32")
+    return kappa
+
+
+def plic_curvature_noalloc_f32(phi, kappa, solver="analytic", precision="mixed"):
+    """plic_curvature_f32 without a workspace: the library's static 16 MiB
+    device array serves as one (lattices up to 21,399 tiles of 64x4x4 cells;
+    calls that overlap in time on one GPU race)."""
+    X, Y, Z = _lattice_dims(phi)
+    n = X * Y * Z
+    _same_device(phi, kappa)
+    _check(_c["plic_curvature_noalloc_f32"](_ptr(phi, torch.float32, n, "phi"), X, Y, Z,
+                                            _ptr(kappa, torch.float32, n, "kappa"),
+                                            _enum(SOLVERS, solver, "solver"),
+                                            _enum(PRECISIONS, precision, "precision"), _stream(phi)),
+           "plic_curvature_noalloc_f32")
     return kappa
 
 

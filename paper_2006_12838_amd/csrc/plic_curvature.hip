@@ -34,6 +34,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "plic_host.hpp"
 #include "plic_math.hpp"
 
@@ -1397,6 +1399,42 @@ int curvature_forward(const float* phi, int64_t X, int64_t Y, int64_t Z, float* 
     return launch_status();
 }
 
+// ---- the forward without a caller workspace ------------------------------------
+// A file-scope device array serves as the workspace of plic_curvature_noalloc_f32
+// (every GPU the library runs on holds its own copy, for the life of the
+// process).  Host code reaches it only through the address that
+// hipGetSymbolAddress returns on each device; the array's name in host code
+// is not a device address.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's scratch address, looked up once per device
+int scratch_for_current_device(void** ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_last_hip_error(static_cast<int>(e));
+        return PLIC_EHIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) return PLIC_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            set_last_hip_error(static_cast<int>(e != hipSuccess ? e : hipErrorInvalidSymbol));
+            return PLIC_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return PLIC_OK;
+}
+
 }  // namespace
 }  // namespace plic
 
@@ -1443,6 +1481,25 @@ int plic_curvature_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float*
                        int precision, void* workspace, size_t workspace_bytes, void* stream) {
     return plic_curvature_ex_f32(phi, X, Y, Z, kappa, solver, precision, PLIC_NORMAL_PY, 0, workspace,
                                  workspace_bytes, stream);
+}
+
+int plic_curvature_noalloc_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, float* kappa, int solver,
+                               int precision, void* stream) {
+    bool empty;
+    Grid g{};
+    if (!valid_curvature_solver(solver) || !valid_precision(precision)) return PLIC_EINVAL;
+    if (check_lattice(X, Y, Z, &empty, &g) != PLIC_OK) return PLIC_EINVAL;
+    const int64_t n = empty ? 0 : X * Y * Z;
+    if (!valid_array(phi, n) || !valid_array(kappa, n)) return PLIC_EINVAL;
+    const size_t nb = static_cast<size_t>(n) * sizeof(float);
+    if (overlap(phi, nb, kappa, nb)) return PLIC_EINVAL;
+    if (empty) return PLIC_OK;
+    if (fixed_bytes(g) > kScratchBytes) return PLIC_EWORKSPACE;          // beyond the static scratch
+    void* ws = nullptr;
+    const int rc = scratch_for_current_device(&ws);
+    if (rc != PLIC_OK) return rc;
+    return curvature_forward(phi, X, Y, Z, kappa, solver, precision, PLIC_NORMAL_PY, false, ws, kScratchBytes, g,
+                             static_cast<hipStream_t>(stream));
 }
 
 

@@ -156,6 +156,21 @@ def test_curvature_options_validation(lib):
     assert lib._lib.plic_curvature_workspace_bytes_ex(4, 4, 4, 2) == 0       # bad flag (C entry point)
 
 
+def test_curvature_noalloc_validation(lib):
+    """Refusals of the workspace-free forward happen on the host, before any
+    HIP call: bad enums and lattices, overlapping arrays, and a lattice whose
+    fixed part exceeds the static 16 MiB array (21,399 tiles of 64x4x4)."""
+    f = lib.raw("plic_curvature_noalloc_f32")
+    far = [k << 40 for k in (1, 2)]
+    assert f(None, 0, 5, 5, None, 0, 1, None) == 0                       # empty lattice
+    assert f(far[0], 8, 8, 8, far[1], 4, 1, None) == -1                  # Kawano's solver
+    assert f(far[0], 8, 8, 8, far[1], 0, 3, None) == -1                  # bad precision
+    assert f(far[0], -1, 8, 8, far[1], 0, 1, None) == -1                 # negative size
+    assert f(far[0], 8, 8, 8, far[0] + 64, 0, 1, None) == -1             # kappa overlaps phi
+    assert f(far[0], 8, 8, 8, far[1] + 2, 0, 1, None) == -1              # misaligned
+    assert f(far[0], 64 * 21399 + 1, 4, 4, far[1], 0, 1, None) == -3    # beyond the static array
+
+
 def test_curvature_status_validation(lib):
     """The status query rejects what it cannot read before any HIP call."""
     import ctypes

@@ -65,13 +65,15 @@ __device__ __forceinline__ bool is_iface(float p) { return p > 0.0f && p < 1.0f;
 
 // ---------------------------------------------------------------------------
 // LDL^T factorisation and solve of the symmetric 5x5 normal equations
-// (App. B.3).  The lower triangle of m holds M on entry and L on exit, the
-// diagonal holds D.  Only the leading N = min(5, #points) parameters are
-// fitted (reduced dimension, the rest stay 0); a pivot below pivot_rel times
-// the largest diagonal entry of the leading block drops its parameter.
+// (App. B.3).  The lower triangle of m holds M on entry and L on exit; dinv
+// holds the reciprocals of D (0 for a dropped parameter), so that the solves
+// (the fit and, in the backward, its adjoint) multiply instead of divide.
+// Only the leading N = min(5, #points) parameters are fitted (reduced
+// dimension, the rest stay 0); a pivot below pivot_rel times the largest
+// diagonal entry of the leading block drops its parameter.
 // ---------------------------------------------------------------------------
 template <class F>
-__device__ __forceinline__ void ldlt_factor(F (&m)[5][5], int N, bool (&act)[5]) {
+__device__ __forceinline__ void ldlt_factor(F (&m)[5][5], int N, bool (&act)[5], F (&dinv)[5]) {
     F maxd = F(0);
 #pragma unroll
     for (int j = 0; j < 5; ++j)
@@ -85,6 +87,7 @@ __device__ __forceinline__ void ldlt_factor(F (&m)[5][5], int N, bool (&act)[5])
         act[j] = (j < N) && (dj > tol) && (maxd > F(0));
         const F inv = act[j] ? F(1) / dj : F(0);
         m[j][j] = act[j] ? dj : F(0);
+        dinv[j] = inv;
 #pragma unroll
         for (int i = j + 1; i < 5; ++i) {
             F sij = m[i][j];
@@ -96,8 +99,8 @@ __device__ __forceinline__ void ldlt_factor(F (&m)[5][5], int N, bool (&act)[5])
 }
 
 template <class F>
-__device__ __forceinline__ void ldlt_solve(const F (&m)[5][5], const bool (&act)[5], const F (&rhs)[5],
-                                           F (&x)[5]) {
+__device__ __forceinline__ void ldlt_solve(const F (&m)[5][5], const bool (&act)[5], const F (&dinv)[5],
+                                           const F (&rhs)[5], F (&x)[5]) {
     F y[5];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
@@ -108,7 +111,7 @@ __device__ __forceinline__ void ldlt_solve(const F (&m)[5][5], const bool (&act)
     }
 #pragma unroll
     for (int j = 4; j >= 0; --j) {
-        F t = act[j] ? y[j] / m[j][j] : F(0);
+        F t = y[j] * dinv[j];
 #pragma unroll
         for (int i = j + 1; i < 5; ++i) t -= m[i][j] * x[i];
         x[j] = act[j] ? t : F(0);
@@ -126,30 +129,36 @@ __device__ __forceinline__ F kappa_of(const F (&a)[5]) {
 
 // ---------------------------------------------------------------------------
 // Per-group LDS scratch.  Reductions over the 26 neighbour lanes go through a
-// [26][20] staging tile: every lane writes its row, lane k sums column k in
+// [26][COLS] staging tile: every lane writes its row, lane k sums column k in
 // the fixed order l = 0..25 (so every call gives the same bits), lanes read
-// the column sums back.
+// the column sums back; a row wider than the tile goes through it in passes
+// of COLS columns (the same sums, the same bits).
 // ---------------------------------------------------------------------------
-template <class F>
+template <class F, int COLS = 20>
 struct alignas(16) GroupLds {
-    F stage[26][20];
+    F stage[26][COLS];
     F res[32];
 };
 
-template <class F, int NV>
-__device__ __forceinline__ void group_colsum(GroupLds<F>& L, int j, const F (&row)[NV], F (&sum)[NV]) {
-    if (j < 26) {
+template <class F, int NV, int COLS>
+__device__ __forceinline__ void group_colsum(GroupLds<F, COLS>& L, int j, const F (&row)[NV], F (&sum)[NV]) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) L.stage[j][k] = row[k];
-    }
-    __syncwarp();
-    if (j < NV) {
-        F acc = F(0);
+    for (int c0 = 0; c0 < NV; c0 += COLS) {
+        constexpr int W = COLS;
+        if (j < 26) {
 #pragma unroll
-        for (int l = 0; l < 26; ++l) acc += L.stage[l][j];
-        L.res[j] = acc;
+            for (int k = 0; k < W; ++k)
+                if (c0 + k < NV) L.stage[j][k] = row[c0 + k];
+        }
+        __syncwarp();
+        if (j < W && c0 + j < NV) {
+            F acc = F(0);
+#pragma unroll
+            for (int l = 0; l < 26; ++l) acc += L.stage[l][j];
+            L.res[c0 + j] = acc;
+        }
+        __syncwarp();
     }
-    __syncwarp();
 #pragma unroll
     for (int k = 0; k < NV; ++k) sum[k] = L.res[k];
     __syncwarp();
@@ -194,9 +203,9 @@ __device__ __forceinline__ void gradient27(const float* __restrict__ s, int c, i
     }
 }
 
-template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
+template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR, int COLS>
 __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, int sy, int sz, int j,
-                                            float gk, float* __restrict__ out, GroupLds<F>& L,
+                                            float gk, float* __restrict__ out, GroupLds<F, COLS>& L,
                                             int gx0 = 0, int gy0 = 0, int gz0 = 0, int X = 0, int Y = 0,
                                             int Z = 0) {
     using mt = M<T>;
@@ -293,7 +302,7 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
         for (int k = 0; k <= i; ++k) row[tri(i, k)] = Q[i] * Q[k];
         row[15 + i] = z * Q[i];
     }
-    group_colsum<F, 20>(L, j, row, sum);
+    group_colsum<F, 20, COLS>(L, j, row, sum);
     F m[5][5], b[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
@@ -302,9 +311,9 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
         for (int k = 0; k <= i; ++k) m[i][k] = sum[tri(i, k)];
     }
     bool act[5];
-    F a[5];
-    ldlt_factor<F>(m, npts < 5 ? npts : 5, act);
-    ldlt_solve<F>(m, act, b, a);
+    F a[5], dinv[5];
+    ldlt_factor<F>(m, npts < 5 ? npts : 5, act, dinv);
+    ldlt_solve<F>(m, act, dinv, b, a);
     const float kappa = float(kappa_of<F>(a));
     if constexpr (ADJ) {
         // d kappa / d(A,B,C,H,I), kappa = -(A(I^2+1) + B(H^2+1) - CHI) / W^(3/2)
@@ -322,7 +331,7 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
 #pragma unroll
         for (int i = 0; i < 5; ++i) abar[i] = act[i] ? abar[i] : F(0);
         F lam[5];
-        ldlt_solve<F>(m, act, abar, lam);          // M symmetric: lambda = M^-1 abar
+        ldlt_solve<F>(m, act, dinv, abar, lam);    // M symmetric: lambda = M^-1 abar
         // this lane's point: zbar = lam.Q, Qbar = lam (z - a.Q) - a (lam.Q)
         T phib = T(0);
         T hb0 = T(0), hb1 = T(0), hb2 = T(0);     // neighbour-normal variant: adjoint of this lane's h
@@ -379,7 +388,7 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
             L.res[25] = F(cc[0]); L.res[26] = F(cc[1]); L.res[27] = F(cc[2]);
         }
         F asum[10];
-        group_colsum<F, 10>(L, j, arow, asum);     // its barriers also publish res[25..27]
+        group_colsum<F, 10, COLS>(L, j, arow, asum);   // its barriers also publish res[25..27]
         const T c00 = T(L.res[25]), c01 = T(L.res[26]), c02 = T(L.res[27]);
         const T sbx0 = T(asum[0]), sbx1 = T(asum[1]), sbx2 = T(asum[2]);
         const T sz_ = T(asum[9]);
@@ -514,9 +523,10 @@ constexpr unsigned kRowLimitNbr = (1u << 30) / kRowFloatsNbr;
 constexpr size_t kDefaultRowsPerTileNbr = 64;
 
 // header words: [0] work items, [1] gather tiles, [2] overflow tiles,
-// [3] unused, [4] / [5] low / high word of the call's interface-cell count
+// [3] workgroup tickets of the one-pass row prefix, [4] / [5] low / high word
+// of the call's interface-cell count
 constexpr int kCounters = 6;
-constexpr int kCountLo = 4, kCountHi = 5;
+constexpr int kTicket = 3, kCountLo = 4, kCountHi = 5;
 
 struct Workspace {
     unsigned* counter;  // header words (kCounters)
@@ -532,9 +542,12 @@ struct Workspace {
     unsigned rows;      // contribution capacity
 };
 
-__global__ void k_curv_zero(unsigned* counter) {
-#pragma unroll
-    for (int i = 0; i < kCounters; ++i) counter[i] = 0u;
+// clears the header words and the first nstatus words of the overflow list
+// (the one-pass row prefix publishes its workgroup totals there)
+__global__ void k_curv_zero(unsigned* counter, unsigned* status, int nstatus) {
+    const int t = threadIdx.x;
+    if (t < kCounters) counter[t] = 0u;
+    for (int i = t; i < nstatus; i += blockDim.x) status[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -560,11 +573,9 @@ __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict_
         const bool yz_in = y >= 1 && y <= Y - 2 && z >= 1 && z <= Z - 2;
         const int64_t row = (static_cast<int64_t>(z) * Y + y) * X;
         if (VEC && x + 4 <= X) {
-            // phi is streamed once here: non-temporal load (the work items
-            // re-read the few interface neighbourhoods later)
-            typedef float f4 __attribute__((ext_vector_type(4)));
-            const f4 l4 = __builtin_nontemporal_load(reinterpret_cast<const f4*>(phi + row + x));
-            const float4 v = make_float4(l4[0], l4[1], l4[2], l4[3]);
+            // a plain load: with the non-temporal hint this scan measured slower
+            // (34 against 26 us at 256^3)
+            const float4 v = *reinterpret_cast<const float4*>(phi + row + x);
             *reinterpret_cast<float4*>(out + row + x) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -593,23 +604,34 @@ __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict_
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) total += wsum[w];
     const unsigned parts = (total + kPartCells - 1) / kPartCells;
-    if (t == 0) {
-        if (parts) {
-            // the call's interface-cell count, 64-bit from two words: the add
-            // that carries out of the low word bumps the high word
-            const unsigned old = atomicAdd(ws.counter + kCountLo, static_cast<unsigned>(total));
-            if (old + static_cast<unsigned>(total) < old) atomicAdd(ws.counter + kCountHi, 1u);
-            const unsigned base = atomicAdd(ws.counter, parts);
-            for (unsigned p = 0; p < parts; ++p) ws.items[base + p] = (static_cast<unsigned>(tile) << 7) | p;
+    if (t < 64) {                                         // the first wave writes the tile's records
+        // mask words and the set bits before each (exclusive scan over lanes 0..31)
+        const unsigned mw = t < kWords ? smask[t] : 0u, c = __popc(mw);
+        unsigned incl = c;
+#pragma unroll
+        for (int d = 1; d < kWords; d <<= 1) {
+            const unsigned o = __shfl_up(incl, d, 64);
+            if (t >= d) incl += o;
         }
-        if constexpr (!FWD) ws.flags[tile] = static_cast<unsigned>(total);  // rows are assigned from these counts
-        unsigned acc = 0u;
-        for (int w = 0; w < kWords; ++w) {
-            ws.prefix[tile * kWords + w] = acc;
-            acc += __popc(smask[w]);
+        if (t < kWords) {
+            ws.mask[tile * kWords + t] = mw;
+            ws.prefix[tile * kWords + t] = incl - c;
         }
+        unsigned base = 0u;
+        if (t == 0) {
+            if (parts) {
+                // the call's interface-cell count, 64-bit from two words: the add
+                // that carries out of the low word bumps the high word
+                const unsigned old = atomicAdd(ws.counter + kCountLo, static_cast<unsigned>(total));
+                if (old + static_cast<unsigned>(total) < old) atomicAdd(ws.counter + kCountHi, 1u);
+                base = atomicAdd(ws.counter, parts);
+            }
+            if constexpr (!FWD) ws.flags[tile] = static_cast<unsigned>(total);  // rows are assigned from these counts
+        }
+        base = __shfl(base, 0, 64);
+        for (unsigned p = static_cast<unsigned>(t); p < parts; p += 64u)
+            ws.items[base + p] = (static_cast<unsigned>(tile) << 7) | p;
     }
-    if (t < kWords) ws.mask[tile * kWords + t] = smask[t];
 }
 
 // Contribution rows in tile order: cbase[tile] = number of interface cells in
@@ -623,10 +645,30 @@ __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict_
 // Gather list and the first prefix pass, one tile per thread.  The list holds
 // every tile whose 3x3x3 tile neighbourhood has an interface cell (its cells
 // can receive a contribution); its order does not affect any result.
+// With ONEPASS (lattices of at most kOnePassBlocks workgroups of tiles) the
+// workgroups also finish the prefix themselves: each takes a ticket, which
+// orders it after every workgroup that took one before (those have started
+// and never wait before they publish), publishes its total in the overflow
+// list (cleared at the start of the call) with a ready bit, and adds up the
+// totals of the workgroups before it, one per lane of its first wave, waiting
+// for each to be published.  Otherwise the totals go to the overflow list for
+// the second pass.
+constexpr int kOnePassBlocks = 256;
+constexpr unsigned kPublished = 0x80000000u;                   // totals are at most 256 * 1024
+
+template <bool ONEPASS>
 __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx, int nty, int ntz, int ntiles) {
     __shared__ unsigned wsum[kThreads / 64];
+    __shared__ unsigned long long boff;
+    __shared__ int ticket;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int tile = blockIdx.x * kThreads + t;
+    int b = static_cast<int>(blockIdx.x);
+    if constexpr (ONEPASS) {
+        if (t == 0) ticket = static_cast<int>(atomicAdd(ws.counter + kTicket, 1u));
+        __syncthreads();
+        b = ticket;
+    }
+    const int tile = b * kThreads + t;
     bool act = false;
     unsigned c = 0u;
     if (tile < ntiles) {
@@ -661,8 +703,30 @@ __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx,
         woff += w < wave ? wsum[w] : 0u;
         total += wsum[w];
     }
-    if (tile < ntiles) ws.cbase[tile] = woff + incl - c;
-    if (t == 0) ws.over[blockIdx.x] = total;                  // at most 256 * 1024 = 2^18
+    if constexpr (ONEPASS) {
+        if (t == 0) __hip_atomic_store(ws.over + b, total | kPublished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (wave == 0) {
+            unsigned long long acc = 0ull;
+            for (int p = lane; p < b; p += 64) {
+                unsigned v;
+                do {
+                    v = __hip_atomic_load(ws.over + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } while (!(v & kPublished));
+                acc += v & ~kPublished;
+            }
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+            if (lane == 0) boff = acc;
+        }
+        __syncthreads();
+        if (tile < ntiles) {
+            const unsigned long long r = boff + woff + incl - c;
+            ws.cbase[tile] = static_cast<unsigned>(r < kRowCap ? r : kRowCap);
+        }
+    } else {
+        if (tile < ntiles) ws.cbase[tile] = woff + incl - c;
+        if (t == 0) ws.over[blockIdx.x] = total;              // at most 256 * 1024 = 2^18
+    }
 }
 
 // second prefix pass: workgroup b's offset is the sum of the totals of
@@ -731,17 +795,20 @@ __device__ __forceinline__ int thread_index_per_iteration() {
 
 // Waves per SIMD the work items are compiled for: the work is a chain of
 // dependent steps per cell, so concurrency sets the time.  Each count is the
-// largest that compiles without spilling (VGPRs at most 102 for 5 waves, 128
-// for 4, 168 for 3) and that the LDS allows (a forward with an FP64 fit holds
-// 36 KiB per workgroup: 4 waves).  In mixed precision the PLIC points are
-// FP32 with the FP64 island only near case boundaries, so the adjoint fits
-// 4 waves (3 with neighbour normals); in FP64 the adjoint of a trigonometric
-// root (analytic, SZ) needs more registers than that of an iterative one, and
-// the neighbour-normal variant more again.
+// largest that compiles without spilling (VGPRs at most 64 for 8 waves, 80
+// for 6, 128 for 4, 168 for 3) and that the LDS allows: a forward with an
+// FP32 fit holds 19 KiB per workgroup (8 waves; 7 for neighbour normals, whose
+// 5x5x5 fill levels add 4 KiB), the mixed-precision forward
+// 19.5 KiB with its halved FP64 staging tile (6 waves), an FP64 forward 36 KiB
+// (4).  In mixed precision the PLIC points are FP32 with the FP64 island only
+// near case boundaries, so the adjoint fits 4 waves (3 with neighbour
+// normals); in FP64 the adjoint of a trigonometric root (analytic, SZ) needs
+// more registers than that of an iterative one, and the neighbour-normal
+// variant more again.
 template <int SOLVER, class T, class U, bool ADJ, bool NBR>
 constexpr int items_waves() {
     const bool iter = SOLVER == kNewton || SOLVER == kNested;
-    if (!ADJ) return sizeof(U) == 4 ? 5 : 4;                              // FP64 fit: LDS allows 4
+    if (!ADJ) return sizeof(U) == 4 ? (NBR ? 7 : 8) : (sizeof(T) == 4 ? 6 : 4);   // LDS, as above
     if (sizeof(U) == 4) return 4;                                         // FP32
     if (sizeof(T) == 4) return NBR ? 3 : 4;                               // mixed
     return iter && !NBR ? 3 : 2;                                          // FP64
@@ -753,8 +820,12 @@ __global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, U, ADJ, NBR>())) 
                                                           float* __restrict__ kappa, Workspace ws, int X, int Y,
                                                           int Z, int ntx, int nty) {
     constexpr int H = NBR ? 2 : 1, W = 2 * H + 1, NB = W * W * W, C = (H * W + H) * W + H;
+    // the mixed-precision forward stages its FP64 rows in two passes of 10
+    // columns: 19.5 KiB of LDS per workgroup instead of 36, so its registers
+    // (at most 80) set the occupancy, 6 waves per SIMD
+    constexpr int COLS = (!ADJ && sizeof(F) == 8 && sizeof(T) == 4) ? 10 : 20;
     __shared__ float nbh[kGroups][NB];
-    __shared__ GroupLds<F> glds[kGroups];
+    __shared__ GroupLds<F, COLS> glds[kGroups];
     const unsigned nitems = *static_cast<volatile unsigned*>(ws.counter);
     for (unsigned item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int tid = thread_index_per_iteration(), grp = tid / kGroup, j = tid % kGroup;
@@ -792,11 +863,11 @@ __global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, U, ADJ, NBR>())) 
         const int64_t g = (static_cast<int64_t>(gz) * Y + gy) * X + gx;
         if constexpr (ADJ) {
             constexpr int ROWF = NBR ? kRowFloatsNbr : 27;
-            group_cell<SOLVER, T, U, F, true, NRM, NBR>(nbh[grp], C, W, W * W, j, gkap[g],
+            group_cell<SOLVER, T, U, F, true, NRM, NBR, COLS>(nbh[grp], C, W, W * W, j, gkap[g],
                                                         ws.contrib + static_cast<size_t>(row) * ROWF, glds[grp],
                                                         gx, gy, gz, X, Y, Z);
         } else {
-            const float kv = group_cell<SOLVER, T, U, F, false, NRM, NBR>(nbh[grp], C, W, W * W, j, 0.0f, nullptr,
+            const float kv = group_cell<SOLVER, T, U, F, false, NRM, NBR, COLS>(nbh[grp], C, W, W * W, j, 0.0f, nullptr,
                                                                          glds[grp], gx, gy, gz, X, Y, Z);
             if (j == 0) kappa[g] = kv;
         }
@@ -897,7 +968,7 @@ __global__ __launch_bounds__(kThreads) void k_curv_gather_fallback(const float* 
                     const int lx = ci % C_RX, ly = (ci / C_RX) % C_RY, lz = ci / (C_RX * C_RY);
                     const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
                     const float gk = gkap[(static_cast<int64_t>(gz) * Y + gy) * X + gx];
-                    group_cell<SOLVER, T, U, F, true, NRM, false>(s, ((lz + 1) * RY + (ly + 1)) * RX + (lx + 1),
+                    group_cell<SOLVER, T, U, F, true, NRM, false, 20>(s, ((lz + 1) * RY + (ly + 1)) * RX + (lx + 1),
                                                                   RX, RX * RY, j, gk, contrib[i], glds[grp]);
                 }
             }
@@ -1265,7 +1336,9 @@ Workspace carve(void* base, size_t bytes, const Grid& g, bool nbr = false) {
 template <bool FWD>
 void launch_scan(const float* phi, float* out, Workspace ws, int X, int Y, int Z, const Grid& g,
                  hipStream_t st) {
-    hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(1), 0, st, ws.counter);
+    const int nb = (g.ntiles + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(kThreads), 0, st, ws.counter, ws.over,
+                       nb <= kOnePassBlocks ? nb : 0);
     const bool vec = X % 4 == 0 && aligned(phi, 16) && aligned(out, 16);
     if (vec)
         hipLaunchKernelGGL((k_curv_scan<true, FWD>), dim3(g.ntiles), dim3(kThreads), 0, st, phi, out, ws, X, Y, Z, g.ntx, g.nty);
@@ -1277,11 +1350,16 @@ unsigned persistent_grid(int64_t items_max) {
     return static_cast<unsigned>(items_max < kPersistentBlocks ? items_max : kPersistentBlocks);
 }
 
-// gather list and contribution rows (two prefix passes)
+// gather list and contribution rows (one pass up to kOnePassBlocks workgroups
+// of tiles, else two prefix passes)
 void launch_rows(Workspace ws, const Grid& g, hipStream_t st) {
     const int nb = (g.ntiles + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_curv_dilate, dim3(nb), dim3(kThreads), 0, st, ws, g.ntx, g.nty, g.ntz, g.ntiles);
-    hipLaunchKernelGGL(k_curv_prefix, dim3(nb), dim3(kThreads), 0, st, ws, g.ntiles);
+    if (nb <= kOnePassBlocks) {
+        hipLaunchKernelGGL(k_curv_dilate<true>, dim3(nb), dim3(kThreads), 0, st, ws, g.ntx, g.nty, g.ntz, g.ntiles);
+    } else {
+        hipLaunchKernelGGL(k_curv_dilate<false>, dim3(nb), dim3(kThreads), 0, st, ws, g.ntx, g.nty, g.ntz, g.ntiles);
+        hipLaunchKernelGGL(k_curv_prefix, dim3(nb), dim3(kThreads), 0, st, ws, g.ntiles);
+    }
 }
 
 template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>

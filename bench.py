@@ -70,6 +70,8 @@ def parse():
                     help="static gfx950 instruction counts of the paper-method benchmark kernels "
                          "(compiles plic_bench.hip to assembly; no GPU)")
     ap.add_argument("--isa-out", default=ISA_PROFILE, help="where --write-isa-profile writes")
+    ap.add_argument("--write-valu-profile", metavar="OUT_MD",
+                    help="run only the VALU issue-rate probe (GPU) and write its table to OUT_MD")
     ap.add_argument("--write-trace-profile", metavar="TRACE_CSV",
                     help="summarise a rocprofv3 --kernel-trace run of this script (its "
                          "*_kernel_trace.csv) into --trace-out")
@@ -139,6 +141,45 @@ def measured_issue(kernel):
         return None
     return {"waves": int(m.group(1).replace(",", "")), "valu": float(m.group(2)), "trans_f32": float(m.group(3)),
             "trans_f64": float(m.group(4))}
+
+
+def write_valu_profile(out):
+    """The VALU probe on its own, at two loop lengths (the difference of the
+    two removes the launch and the chains' set-up), as a profile table."""
+    import torch
+
+    import paper_2006_12838_amd as P
+
+    dev = torch.device("cuda:0")
+    a = valu_ceiling(P, torch, dev, iters=200)
+    b = valu_ceiling(P, torch, dev, iters=800)
+    lines = [
+        "# VALU issue rates on gfx950 (MI355X): plic_bench_valu",
+        "",
+        "Command (from the repository root on an MI355X, ROCm 7.2):",
+        "",
+        "```",
+        "python3 bench.py --write-valu-profile profiles/valu_ceiling_gfx950.md",
+        "```",
+        "",
+        "2^20 threads (16 waves per SIMD), each issuing 32 x iters instructions of one kind in 8 independent "
+        "dependency chains with nothing else in the loop (checked in the kernel's ISA), timed with HIP "
+        "events against an iters = 0 launch, after a 10-launch warm-up of the clock.  Cycles per wavefront "
+        "instruction are at the nominal 2.4 GHz (1024 SIMDs).",
+        "",
+        "| instruction | lane-ops/s (iters 200) | lane-ops/s (iters 800) | cycles per wave instruction |",
+        "|---|---:|---:|---:|",
+    ]
+    names = {"fma_f32": "`v_fma_f32`", "fma_f64": "`v_fma_f64`", "sqrt_f32": "`v_sqrt_f32`",
+             "rsq_f32": "`v_rsq_f32`", "rcp_f32": "`v_rcp_f32`", "sin_f32": "`v_sin_f32`",
+             "exp_f32": "`v_exp_f32`", "log_f32": "`v_log_f32`", "rcp_f64": "`v_rcp_f64`",
+             "sqrt_f64": "`v_sqrt_f64`", "fma_sin_f32": "16 `v_fma_f32` + 16 `v_sin_f32`"}
+    for op in a:
+        lines.append(f"| {names.get(op, op)} | {a[op]['lane_ops_per_s']:.3g} | {b[op]['lane_ops_per_s']:.3g} | "
+                     f"{b[op]['cycles_per_wave_instr_at_2p4GHz']:.2f} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return out
 
 
 def valu_bound_ms(issue, ceiling):
@@ -832,6 +873,9 @@ def main():
         return
     if args.write_issue_profile:
         print(write_issue_profile(args.write_issue_profile, args.log2n, args.lattice, args.issue_out))
+        return
+    if args.write_valu_profile:
+        print(write_valu_profile(args.write_valu_profile))
         return
     if args.write_trace_profile:
         print(write_trace_profile(args.write_trace_profile, args.trace_out))

@@ -745,15 +745,16 @@ def _stats(err):
     return {"max_abs": float(err.max()), "rms": float(np.sqrt(np.mean(err * err)))}
 
 
-def precision_study(P, torch, dev, log2n=24, lattice=None, radius=40.0):
+def precision_study(P, torch, dev, log2n=24, lattice=None, radius=40.0, step_inputs=None):
     """The precision modes against the oracle (part of the CPU-baseline leg,
     the only part of this script that runs the oracle): 2^log2n near-degenerate
     problems (normals within 1e-4 rad of the axes and diagonals, fill levels
     within 1e-6 of 0, 1 and the case-boundary volumes) through every solver in
     FP32, mixed, FP64 arithmetic with FP32 storage, and FP64 storage, each with
-    its time and max / RMS |d0 - oracle|; and the curvature of the lattice in
-    each mode, with max / RMS |kappa - oracle| over the well-conditioned
-    interface cells."""
+    its time and max / RMS |d0 - oracle|; the step's own random problems in
+    FP32 and mixed (time, beside their error in error_vs_oracle); and the
+    curvature of the lattice in each mode, with max / RMS |kappa - oracle| over
+    the well-conditioned interface cells."""
     import numpy as np
     import oracle
     import workloads
@@ -781,6 +782,21 @@ def precision_study(P, torch, dev, log2n=24, lattice=None, radius=40.0):
                                                 "12 face-diagonal and 8 space-diagonal directions; V0 within "
                                                 "1e-6 of 0, 1 or a case-boundary volume",
                         "tolerance": {"fp32_storage": 1e-5, "f64": 1e-12}, "per_mode": rows}}
+    if step_inputs is not None:
+        # the step's own 2^26 random problems: FP32 against mixed, time only
+        # (their error against the oracle is error_vs_oracle of the CPU leg)
+        tn, out = step_inputs, torch.empty_like(step_inputs[3])
+        rand = {}
+        for solver in SOLVERS:
+            for mode in ("fp32", "mixed"):
+                ms = timed_reps(torch, stream, lambda: P.plic_offset_f32(*tn[:4], out, solver, mode), reps=5)
+                rand[f"{solver}/{mode}"] = {"ms": round(ms, 4)}
+            rand[f"{solver}/mixed"]["mixed_over_fp32"] = round(rand[f"{solver}/mixed"]["ms"] /
+                                                               rand[f"{solver}/fp32"]["ms"], 3)
+        res["random_problems"] = {"count": int(tn[3].numel()), "per_mode": rand}
+    for solver in SOLVERS:
+        rows[f"{solver}/mixed"]["mixed_over_fp32"] = round(rows[f"{solver}/mixed"]["ms"] /
+                                                           rows[f"{solver}/fp32"]["ms"], 3)
     if lattice is not None:
         phi = lattice
         kref, flags = oracle.curvature(phi, flags=True)
@@ -1033,7 +1049,7 @@ def main():
             return d0[: 1 << 21].cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(nx, ny, nz, V0, args.cpu_seconds, gpu_offset, phi)
         if not args.only:
-            out["precision_study"] = precision_study(P, torch, dev, 24, phi, args.radius)
+            out["precision_study"] = precision_study(P, torch, dev, 24, phi, args.radius, tn)
     print(json.dumps(out), flush=True)
 
 

@@ -241,14 +241,15 @@ def write_traffic_profile(fetch_csv, write_csv, log2n, lattice, out=TRAFFIC_PROF
         "Commands (from the repository root on an MI355X, ROCm 7.2), one counter per run:",
         "",
         "```",
+        "# $REPO: the repository root; $OUT: a directory for the profiler's output",
         "cd /tmp && export TMPDIR=/tmp",
         "K=" + ",".join(PMC_DISPATCHES),
-        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/pmc_FETCH_SIZE -o pmc -- "
+        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_FETCH_SIZE -o pmc -- "
         "python3 $REPO/bench.py --only $K --steps 1 --warmup 0 --no-cpu-baseline",
-        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $REPO/gpurun_out/pmc_WRITE_SIZE -o pmc -- "
+        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_WRITE_SIZE -o pmc -- "
         "python3 $REPO/bench.py --only $K --steps 1 --warmup 0 --no-cpu-baseline",
-        "python3 $REPO/bench.py --write-traffic-profile $REPO/gpurun_out/pmc_FETCH_SIZE/pmc_counter_collection.csv "
-        "$REPO/gpurun_out/pmc_WRITE_SIZE/pmc_counter_collection.csv --traffic-out <this file>",
+        "python3 $REPO/bench.py --write-traffic-profile $OUT/pmc_FETCH_SIZE/pmc_counter_collection.csv "
+        "$OUT/pmc_WRITE_SIZE/pmc_counter_collection.csv --traffic-out <this file>",
         "```",
         "",
         f"Calibration: a plain device copy of {4 * n:,} bytes (`copy`, torch's `copy_`) reads "
@@ -404,10 +405,11 @@ def write_trace_profile(trace_csv, out=None):
         "Command (from the repository root on an MI355X, ROCm 7.2):",
         "",
         "```",
+        "# $REPO: the repository root; $OUT: a directory for the profiler's output",
         "cd /tmp && export TMPDIR=/tmp",
-        "rocprofv3 --kernel-trace --stats --output-format csv -d $REPO/gpurun_out/prof -o bench -- "
-        "python3 $REPO/bench.py --no-cpu-baseline",
-        "python3 $REPO/bench.py --write-trace-profile $REPO/gpurun_out/prof/bench_kernel_trace.csv "
+        "rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/prof -o bench -- "
+        "python3 $REPO/bench.py --gpus 1 --steps 20 --warmup 5 --no-cpu-baseline",
+        "python3 $REPO/bench.py --write-trace-profile $OUT/prof/bench_kernel_trace.csv "
         "--trace-out <this file>",
         "```",
         "",
@@ -416,9 +418,9 @@ def write_trace_profile(trace_csv, out=None):
         "Dispatch durations from the kernel trace, grouped by kernel and launch size (work-items), so the "
         "step's launches (2^26 problems: `k_offset` and `k_volume` at 16,777,216 work-items, `k_offset_bwd` "
         "at 16,777,216) are apart from the same kernels on other sizes (the differentiation workload's "
-        "2^24 problems, the precision study).  One bench step launches every step kernel once (the "
-        "default 20 warm-up + 20 timed steps = 40 calls; the curvature scan and the counter reset run once "
-        "for the forward and once for the backward).  The secondary timings after the timed steps (VALU "
+        "2^24 problems, the precision study).  One bench step launches every step kernel once (5 warm-up "
+        "+ 20 timed steps = 25 calls; the curvature scan and the counter reset run "
+        "once for the forward and once for the backward).  The secondary timings after the timed steps (VALU "
         "probe `k_valu`, plane-sphere, Kawano's SZ, the FP64 solvers, the warm curvature and its variants, "
         "the 192^3 differentiation lattice, the paper-method benchmark `k_isolated`) appear with their own "
         "call counts.",
@@ -461,11 +463,12 @@ def write_issue_profile(sq_csv, log2n, lattice, out=ISSUE_PROFILE):
         "Command (from the repository root on an MI355X, ROCm 7.2):",
         "",
         "```",
+        "# $REPO: the repository root; $OUT: a directory for the profiler's output",
         "cd /tmp && export TMPDIR=/tmp",
         "K=" + ",".join(k for k in PMC_DISPATCHES if k != "copy"),
-        "rocprofv3 --pmc " + " ".join(ISSUE_COUNTERS) + " --output-format csv -d $REPO/gpurun_out/pmc_sq -o pmc -- "
+        "rocprofv3 --pmc " + " ".join(ISSUE_COUNTERS) + " --output-format csv -d $OUT/pmc_sq -o pmc -- "
         "python3 $REPO/bench.py --only $K --steps 1 --warmup 0 --no-cpu-baseline",
-        "python3 $REPO/bench.py --write-issue-profile $REPO/gpurun_out/pmc_sq/pmc_counter_collection.csv "
+        "python3 $REPO/bench.py --write-issue-profile $OUT/pmc_sq/pmc_counter_collection.csv "
         "--issue-out <this file>",
         "```",
         "",

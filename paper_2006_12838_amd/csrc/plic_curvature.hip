@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <vector>
 
 #include "plic_host.hpp"
 #include "plic_math.hpp"
@@ -523,10 +524,9 @@ constexpr unsigned kRowLimitNbr = (1u << 30) / kRowFloatsNbr;
 constexpr size_t kDefaultRowsPerTileNbr = 64;
 
 // header words: [0] work items, [1] gather tiles, [2] overflow tiles,
-// [3] workgroup tickets of the one-pass row prefix, [4] / [5] low / high word
-// of the call's interface-cell count
-constexpr int kCounters = 6;
-constexpr int kTicket = 3, kCountLo = 4, kCountHi = 5;
+// [3] workgroup tickets of the one-pass row prefix
+constexpr int kCounters = 4;
+constexpr int kTicket = 3;
 
 struct Workspace {
     unsigned* counter;  // header words (kCounters)
@@ -617,20 +617,19 @@ __global__ __launch_bounds__(kThreads) void k_curv_scan(const float* __restrict_
             ws.mask[tile * kWords + t] = mw;
             ws.prefix[tile * kWords + t] = incl - c;
         }
-        unsigned base = 0u;
-        if (t == 0) {
-            if (parts) {
-                // the call's interface-cell count, 64-bit from two words: the add
-                // that carries out of the low word bumps the high word
-                const unsigned old = atomicAdd(ws.counter + kCountLo, static_cast<unsigned>(total));
-                if (old + static_cast<unsigned>(total) < old) atomicAdd(ws.counter + kCountHi, 1u);
-                base = atomicAdd(ws.counter, parts);
-            }
-            if constexpr (!FWD) ws.flags[tile] = static_cast<unsigned>(total);  // rows are assigned from these counts
+        // the tile's interface count: the backward assigns rows from these,
+        // and plic_curvature_status sums them (no shared counter here: every
+        // atomic on one word serialises at the memory side)
+        if (t == 0) ws.flags[tile] = static_cast<unsigned>(total);
+        // only a tile with interface cells waits for an atomic's result (the
+        // wait also covers the block's stores); parts is uniform per block
+        if (parts) {
+            unsigned base = 0u;
+            if (t == 0) base = atomicAdd(ws.counter, parts);
+            base = __shfl(base, 0, 64);
+            for (unsigned p = static_cast<unsigned>(t); p < parts; p += 64u)
+                ws.items[base + p] = (static_cast<unsigned>(tile) << 7) | p;
         }
-        base = __shfl(base, 0, 64);
-        for (unsigned p = static_cast<unsigned>(t); p < parts; p += 64u)
-            ws.items[base + p] = (static_cast<unsigned>(tile) << 7) | p;
     }
 }
 
@@ -1630,18 +1629,21 @@ int plic_curvature_status(const void* workspace, size_t workspace_bytes, int64_t
     const bool nbr = neighbour_normals != 0;
     if (workspace_bytes < fixed_bytes(g) + (nbr ? kRowBytesNbr : 0)) return PLIC_EWORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    unsigned h[kCounters];
+    const Workspace ws = carve(const_cast<void*>(workspace), workspace_bytes, g, nbr);
+    // the call's interface count is the sum of the tiles' counts the scan wrote
+    std::vector<unsigned> flags(static_cast<size_t>(g.ntiles));
     hipError_t e = hipStreamSynchronize(st);
-    if (e == hipSuccess) e = hipMemcpy(h, workspace, sizeof(h), hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(flags.data(), ws.flags, flags.size() * sizeof(unsigned), hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
         set_last_hip_error(static_cast<int>(e));
         return PLIC_EHIP;
     }
-    const uint64_t cells = (static_cast<uint64_t>(h[kCountHi]) << 32) | h[kCountLo];
+    uint64_t cells = 0;
+    for (const unsigned f : flags) cells += f;
     const size_t row_bytes = nbr ? kRowBytesNbr : kRowBytes;
     if (interface_cells) *interface_cells = static_cast<int64_t>(cells);
     if (bytes_for_all_rows) *bytes_for_all_rows = fixed_bytes(g) + static_cast<size_t>(cells) * row_bytes;
-    const Workspace ws = carve(const_cast<void*>(workspace), workspace_bytes, g, nbr);
     return nbr && cells > ws.rows ? PLIC_EWORKSPACE : PLIC_OK;
 }
 

@@ -164,3 +164,34 @@ def test_autograd_forward_matches_raw(P, sphere):
     t = dev(sphere)
     k = P.curvature(t)
     assert np.array_equal(host(k), gpu_kappa(P, sphere))
+
+
+def interior_interface_count(phi):
+    """Interface cells as defined for the fit: 0 < phi < 1, not on the outer layer."""
+    inner = phi[1:-1, 1:-1, 1:-1]
+    return int(((inner > 0) & (inner < 1)).sum())
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_forward_status_and_count(P, precision):
+    """The status query after a forward reports the lattice's interface
+    count, on the 256^3 sphere, a lattice of one tile and one without
+    interface cells; repeated calls on one workspace give the same bits."""
+    cases = [workloads.sphere_lattice(N=256, R=40.0, seed=0)[0],
+             np.ascontiguousarray(workloads.sphere_lattice(N=12, R=3.0, seed=2)[0][4:8, 4:8, :]),
+             np.zeros((9, 10, 11), np.float32)]
+    for phi in cases:
+        Z, Y, X = phi.shape
+        t = dev(phi)
+        ws = torch.empty(P.plic_curvature_workspace_bytes(X, Y, Z), dtype=torch.uint8, device="cuda")
+        outs = []
+        for _ in range(3):
+            k = torch.empty_like(t)
+            P.plic_curvature_f32(t, k, "sz", precision, ws)
+            rc, cells, _ = P.plic_curvature_status(ws, X, Y, Z)
+            assert rc == 0, P.plic_status_string(rc)
+            assert cells == interior_interface_count(phi)
+            outs.append(host(k))
+        assert all(np.array_equal(outs[0], o) for o in outs[1:])
+        if cells == 0:
+            assert np.all(outs[0] == 0.0)

@@ -419,15 +419,17 @@ def write_trace_profile(trace_csv, out=None):
         "step's launches (2^26 problems: `k_offset` and `k_volume` at 16,777,216 work-items, `k_offset_bwd` "
         "at 16,777,216) are apart from the same kernels on other sizes (the differentiation workload's "
         "2^24 problems, the precision study).  One bench step launches every step kernel once (5 warm-up "
-        "+ 20 timed steps = 25 calls; the curvature scan and the counter reset run "
-        "once for the forward and once for the backward).  The secondary timings after the timed steps (VALU "
+        "+ 20 timed steps = 25 calls; the counter reset runs once for the forward and once for the "
+        "backward, the scan only for the forward: the step's backward reuses it).  The secondary timings after "
+        "the timed steps (VALU "
         "probe `k_valu`, plane-sphere, Kawano's SZ, the FP64 solvers, the warm curvature and its variants, "
         "the 192^3 differentiation lattice, the paper-method benchmark `k_isolated`) appear with their own "
         "call counts.",
         "",
         "Template arguments: `k_offset<solver, storage, bulk, cubic, problems per lane, whole blocks>`, "
         "`k_curv_items<solver, points, cubic, fit, backward, normal, neighbour normals>`, "
-        "`k_curv_gather_fallback<solver, points, cubic, fit, normal>`; solver 0 analytic, 1 optimized SZ, "
+        "`k_curv_gather_fallback<solver, points, cubic, fit, normal>`, "
+        "`k_curv_gather_direct<neighbour normals, normal, writes the zeros>`; solver 0 analytic, 1 optimized SZ, "
         "2 Newton-Raphson, 3 nested intervals, 4 Kawano's SZ; normal 0 Parker-Youngs.",
         "",
         "| kernel | work-items | calls | avg µs | min µs | share | VGPR | LDS B | scratch B |",
@@ -590,10 +592,14 @@ def curvature_warm(P, torch, tphi, tgk, kap, gphi, ws):
     256^3) stays in the 256 MB last-level cache, unlike in the step."""
     stream = torch.cuda.current_stream(tphi.device)
     fwd = timed_reps(torch, stream, lambda: P.plic_curvature_f32(tphi, kap, "analytic", "mixed", ws))
-    bwd = timed_reps(torch, stream, lambda: P.plic_curvature_backward_f32(tphi, tgk, gphi, "analytic", "mixed", ws))
+    # the workspace holds the forward's scan: the backward that reuses it, then
+    # the one that scans phi itself
+    bwd = timed_reps(torch, stream, lambda: P.plic_curvature_backward_reuse_f32(tphi, tgk, gphi, "analytic", "mixed",
+                                                                                "py", False, ws))
+    full = timed_reps(torch, stream, lambda: P.plic_curvature_backward_f32(tphi, tgk, gphi, "analytic", "mixed", ws))
     n = tphi.numel()
-    return {"fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4), "fwd_cells_per_s": n / (fwd * 1e-3),
-            "bwd_cells_per_s": n / (bwd * 1e-3)}
+    return {"fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4), "bwd_scanning_ms": round(full, 4),
+            "fwd_cells_per_s": n / (fwd * 1e-3), "bwd_cells_per_s": n / (bwd * 1e-3)}
 
 
 def curvature_variants(P, torch, tphi, tgk, kap, gphi, ws):
@@ -854,7 +860,8 @@ def differentiation(P, torch, dev, tn, log2n=24):
     Z, Y, X = phi.shape
     ws = torch.empty(P.plic_curvature_workspace_bytes(X, Y, Z), dtype=torch.uint8, device=dev)
     cf = timed_reps(torch, stream, lambda: P.plic_curvature_f32(tp, kap, "analytic", "mixed", ws))
-    cb = timed_reps(torch, stream, lambda: P.plic_curvature_backward_f32(tp, tg, gp, "analytic", "mixed", ws))
+    cb = timed_reps(torch, stream, lambda: P.plic_curvature_backward_reuse_f32(tp, tg, gp, "analytic", "mixed", "py",
+                                                                               False, ws))
     res["curvature"] = {"lattice": [192, 192, 192], "workload": "perturbed sphere R=50, l<=6, 5% amplitude",
                         "interface_cells": int(iface.sum()), "fwd_ms": round(cf, 4), "bwd_ms": round(cb, 4),
                         "fwd_bwd_cells_per_s": phi.size / ((cf + cb) * 1e-3),
@@ -940,8 +947,9 @@ def main():
                     lambda: P.plic_offset_backward_f32(*tn[:4], tn[4], *gout, "sz", "fp32"), N, "solves", 36))
     kernels.append(("curvature_fwd", lambda: P.plic_curvature_f32(tphi, kap, "analytic", "mixed", ws),
                     cells, "cells", 8))
+    # the backward follows its forward on the same workspace and reuses its scan
     kernels.append(("curvature_bwd",
-                    lambda: P.plic_curvature_backward_f32(tphi, tgk, gphi, "analytic", "mixed", ws),
+                    lambda: P.plic_curvature_backward_reuse_f32(tphi, tgk, gphi, "analytic", "mixed", "py", False, ws),
                     cells, "cells", 8))
     if args.only:
         keep = set(args.only.split(","))

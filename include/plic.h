@@ -14,7 +14,10 @@
  *
  * Common rules for every entry point
  *  - Array arguments are DEVICE pointers owned by the caller.  The library
- *    allocates nothing and keeps no state between calls.
+ *    allocates nothing and keeps no state between calls, with two stated
+ *    exceptions: the static device array of plic_curvature_noalloc_f32, and a
+ *    small host-side note, per curvature workspace address, of the phi and
+ *    lattice its last scan was for (plic_curvature_backward_reuse_f32).
  *  - Arrays are structure-of-arrays, one element per problem (or per lattice
  *    cell), naturally aligned (4 bytes for float, 8 for double).  Outputs may
  *    alias an input of the same element index only where stated.
@@ -274,6 +277,26 @@ int plic_curvature_backward_ex_f32(const float *phi, int64_t X, int64_t Y, int64
                                    const float *grad_kappa, float *grad_phi, int solver,
                                    int precision, int normal, int neighbour_normals,
                                    void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * plic_curvature_backward_reuse_f32 — plic_curvature_backward_ex_f32 after a
+ * forward (Sec. 4.2 and App. B; the derivative itself is not in the paper) on
+ * the same workspace: the interface scan's records that the forward left there
+ * (bitmasks, prefix counts, work items, tile counts; they depend on phi only)
+ * are used again instead of scanning phi a second time, as a training step's
+ * backward follows its forward.  The caller guarantees that phi's contents did
+ * not change since the last curvature call on `workspace` (forward or
+ * backward, any options) and that no other use of the workspace memory came
+ * between.  The library checks what it can see: when the last call it
+ * launched on this workspace address was not on the same phi address and
+ * lattice, this call scans phi as plic_curvature_backward_ex_f32 does.
+ * Arguments, status codes and results (bit for bit) as
+ * plic_curvature_backward_ex_f32.
+ */
+int plic_curvature_backward_reuse_f32(const float *phi, int64_t X, int64_t Y, int64_t Z,
+                                      const float *grad_kappa, float *grad_phi, int solver,
+                                      int precision, int normal, int neighbour_normals,
+                                      void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * plic_curvature_status — what the last curvature call (forward or backward,

@@ -27,6 +27,7 @@ from ._lib import (  # noqa: F401  (re-exported: the C ABI by name)
     plic_bench_valu,
     plic_curvature_backward_ex_f32,
     plic_curvature_backward_f32,
+    plic_curvature_backward_reuse_f32,
     plic_curvature_ex_f32,
     plic_curvature_f32,
     plic_curvature_noalloc_f32,
@@ -118,15 +119,21 @@ def volume(n, d0, precision: str = "fp32"):
 
 
 class PlicCurvature(torch.autograd.Function):
-    """kappa(phi) on a (Z, Y, X) lattice with the recomputing backward."""
+    """kappa(phi) on a (Z, Y, X) lattice with the recomputing backward.  The
+    forward's workspace is kept for the backward, which reuses its interface
+    scan (autograd's saved-tensor check rejects a phi changed in place)."""
 
     @staticmethod
     def forward(ctx, phi, solver="analytic", precision="mixed", normal="py", neighbour_normals=False):
         phi = phi.contiguous()
         kappa = torch.empty_like(phi)
-        plic_curvature_ex_f32(phi, kappa, solver, precision, normal, neighbour_normals)
+        Z, Y, X = phi.shape
+        ws = torch.empty(max(plic_curvature_workspace_bytes_ex(X, Y, Z, neighbour_normals), 1), dtype=torch.uint8,
+                         device=phi.device)
+        plic_curvature_ex_f32(phi, kappa, solver, precision, normal, neighbour_normals, ws)
         ctx.save_for_backward(phi)
         ctx.opts = (solver, precision, normal, neighbour_normals)
+        ctx.ws = ws
         return kappa
 
     @staticmethod
@@ -135,7 +142,8 @@ class PlicCurvature(torch.autograd.Function):
         solver, precision, normal, neighbour_normals = ctx.opts
         grad_phi = torch.empty_like(phi)
         plic_curvature_backward_ex_f32(phi, grad_kappa.contiguous(), grad_phi, solver, precision, normal,
-                                       neighbour_normals)
+                                       neighbour_normals, ctx.ws, reuse=True, grow=True)
+        ctx.ws = None
         return grad_phi, None, None, None, None
 
 

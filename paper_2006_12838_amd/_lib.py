@@ -61,6 +61,9 @@ _c = {
     "plic_curvature_backward_ex_f32": _sig("plic_curvature_backward_ex_f32",
                                            [_vp, _i64, _i64, _i64, _vp, _vp, _int, _int, _int, _int, _vp,
                                             ctypes.c_size_t, _vp]),
+    "plic_curvature_backward_reuse_f32": _sig("plic_curvature_backward_reuse_f32",
+                                              [_vp, _i64, _i64, _i64, _vp, _vp, _int, _int, _int, _int, _vp,
+                                               ctypes.c_size_t, _vp]),
 }
 _lib.plic_curvature_workspace_bytes.restype = ctypes.c_size_t
 _lib.plic_curvature_workspace_bytes.argtypes = [_i64, _i64, _i64]
@@ -287,28 +290,33 @@ def plic_curvature_noalloc_f32(phi, kappa, solver="analytic", precision="mixed")
 
 
 def plic_curvature_backward_ex_f32(phi, grad_kappa, grad_phi, solver="analytic", precision="mixed", normal="py",
-                                   neighbour_normals=False, workspace=None, check=True):
+                                   neighbour_normals=False, workspace=None, check=True, reuse=False, grow=False):
     """With neighbour_normals and check (the default), and outside graph
     capture, the call is followed by plic_curvature_status (one stream
     synchronisation): when the workspace held
     fewer rows than the lattice has interface cells, a workspace that holds
     them all is allocated and the call repeated if the workspace was the
-    library's own choice, and a RuntimeError is raised for a caller's
-    workspace (its grad_phi holds NaN where rows were missing)."""
+    library's own choice (or grow is set), and a RuntimeError is raised for a
+    caller's workspace (its grad_phi holds NaN where rows were missing).
+    reuse: plic_curvature_backward_reuse_f32 on the caller's workspace, which
+    holds the records of the last forward on this phi (phi unchanged since)."""
     X, Y, Z = _lattice_dims(phi)
     n = X * Y * Z
     _same_device(phi, grad_kappa, grad_phi)
-    own = workspace is None
+    if reuse and workspace is None:
+        raise ValueError("reuse needs the workspace of the forward call")
+    own = workspace is None or grow
     ws = _workspace(phi, workspace, X, Y, Z, neighbour_normals)
     for attempt in range(2):
-        _check(_c["plic_curvature_backward_ex_f32"](_ptr(phi, torch.float32, n, "phi"), X, Y, Z,
-                                                    _ptr(grad_kappa, torch.float32, n, "grad_kappa"),
-                                                    _ptr(grad_phi, torch.float32, n, "grad_phi"),
-                                                    _enum(SOLVERS, solver, "solver"),
-                                                    _enum(PRECISIONS, precision, "precision"),
-                                                    _enum(NORMALS, normal, "normal"), int(bool(neighbour_normals)),
-                                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
-               "plic_curvature_backward_ex_f32")
+        name = "plic_curvature_backward_reuse_f32" if reuse and attempt == 0 else "plic_curvature_backward_ex_f32"
+        _check(_c[name](_ptr(phi, torch.float32, n, "phi"), X, Y, Z,
+                        _ptr(grad_kappa, torch.float32, n, "grad_kappa"),
+                        _ptr(grad_phi, torch.float32, n, "grad_phi"),
+                        _enum(SOLVERS, solver, "solver"),
+                        _enum(PRECISIONS, precision, "precision"),
+                        _enum(NORMALS, normal, "normal"), int(bool(neighbour_normals)),
+                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(phi)),
+               name)
         # the status query synchronises the stream, which a stream under graph
         # capture may not do: there the caller sizes the workspace (and may
         # query plic_curvature_status after a replay)
@@ -322,6 +330,14 @@ def plic_curvature_backward_ex_f32(phi, grad_kappa, grad_phi, solver="analytic",
                                f"({cells} interface cells need {need} bytes, workspace has {ws.numel()})")
         ws = torch.empty(need, dtype=torch.uint8, device=phi.device)
     return grad_phi
+
+
+def plic_curvature_backward_reuse_f32(phi, grad_kappa, grad_phi, solver="analytic", precision="mixed",
+                                      normal="py", neighbour_normals=False, workspace=None, check=True):
+    """The backward on the workspace of the last forward on phi (its scan is
+    not repeated; see plic_curvature_backward_ex_f32 for check)."""
+    return plic_curvature_backward_ex_f32(phi, grad_kappa, grad_phi, solver, precision, normal, neighbour_normals,
+                                          workspace, check, reuse=True)
 
 
 def plic_curvature_backward_f32(phi, grad_kappa, grad_phi, solver="analytic", precision="mixed",

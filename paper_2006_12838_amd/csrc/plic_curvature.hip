@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "plic_host.hpp"
@@ -544,18 +545,20 @@ struct Workspace {
 
 // clears the header words and the first nstatus words of the overflow list
 // (the one-pass row prefix publishes its workgroup totals there)
-__global__ void k_curv_zero(unsigned* counter, unsigned* status, int nstatus) {
+// (from header word first on: a backward that reuses a forward's records
+// keeps its work item count, word 0)
+__global__ void k_curv_zero(unsigned* counter, int first, unsigned* status, int nstatus) {
     const int t = threadIdx.x;
-    if (t < kCounters) counter[t] = 0u;
+    if (t >= first && t < kCounters) counter[t] = 0u;
     for (int i = t; i < nstatus; i += blockDim.x) status[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
 // 1. streaming scan: zero output everywhere; the tile's interface bitmask and
 // the set bits before each of its words; one work item (tile << 7 | part) per
-// kPartCells interface cells of the tile.  The backward also records the
-// tile's interface count (its flag), from which the contribution rows are
-// assigned.  Thread t handles 4 consecutive cells along x, which are the cells
+// kPartCells interface cells of the tile; the tile's interface count (its
+// flag), from which the backward assigns contribution rows.  (A backward that
+// reuses a forward's records runs no scan: its gather writes the zeros.)  Thread t handles 4 consecutive cells along x, which are the cells
 // 4t .. 4t+3 of the tile in cell order (x fastest, then y, z).
 // ---------------------------------------------------------------------------
 template <bool VEC, bool FWD>
@@ -1087,15 +1090,40 @@ __device__ __forceinline__ unsigned source_row(const SourceMap& m, int cx, int c
 // NBR: the neighbour-normal variant's rows, plus each source's own-gradient
 // adjoint spread by the gradient weights of NRM; a tile with a source beyond
 // the store gets NaN on its band (that variant has no fallback)
-template <bool NBR, int NRM>
+// thread t's cells 4t .. 4t+3 of a tile (row t / 16 in cell order) set to
+// zero where bit k of keep is clear; vec: 16-byte stores are aligned
+__device__ __forceinline__ void zero_cells(float* __restrict__ gphi, int tile, unsigned keep, bool vec, int X,
+                                           int Y, int Z, int ntx, int nty) {
+    const int t = threadIdx.x;
+    const int gx = (tile % ntx) * TX + (t % (TX / 4)) * 4, gy = ((tile / ntx) % nty) * TY + (t / (TX / 4)) % TY,
+              gz = (tile / (ntx * nty)) * TZ + t / (TX / 4 * TY);
+    if (gx >= X || gy >= Y || gz >= Z) return;
+    float* o = gphi + (static_cast<int64_t>(gz) * Y + gy) * X + gx;
+    if (vec && keep == 0u) {
+        *reinterpret_cast<float4*>(o) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (gx + k < X && !((keep >> k) & 1u)) o[k] = 0.0f;
+    }
+}
+
+constexpr int kZeroBatch = kThreads / 32;     // tiles checked at a time by the zero fill
+
+// ZFILL: the call ran no scan (it reuses a forward's records), so nothing
+// zeroed grad_phi: the gather writes the zeros itself, on its tiles' cells off
+// the band and on every tile it does not gather
+template <bool NBR, int NRM, bool ZFILL>
 __global__ __launch_bounds__(kThreads, (NBR ? 5 : 8)) void k_curv_gather_direct(float* __restrict__ gphi, Workspace ws, int X,
-                                                                  int Y, int Z, int ntx, int nty, int ntz) {
+                                                                  int Y, int Z, int ntx, int nty, int ntz,
+                                                                  bool vec) {
     constexpr unsigned ROWF = NBR ? kRowFloatsNbr : 27;
     __shared__ SourceMap m;
     __shared__ unsigned short band[kTile];
     __shared__ unsigned long long brow[TY * TZ];
     __shared__ int bpref[TY * TZ];
     __shared__ int bcount;
+    __shared__ unsigned zact[kZeroBatch];
     const unsigned ntl = *static_cast<volatile unsigned*>(ws.counter + 1);
     for (unsigned it = blockIdx.x; it < ntl; it += gridDim.x) {
         const int tid = thread_index_per_iteration();
@@ -1279,7 +1307,39 @@ __global__ __launch_bounds__(kThreads, (NBR ? 5 : 8)) void k_curv_gather_direct(
             }
             if (__syncthreads_or(miss) && tid == 0) ws.over[atomicAdd(ws.counter + 2, 1u)] = static_cast<unsigned>(tile);
         }
+        // the tile's cells outside the band have a zero gradient; thread t
+        // takes cells 4t .. 4t+3, row t / 16.  After the sums' loads: loads and
+        // stores share one in-order counter, so stores issued before them
+        // would be waited for with them.
+        if constexpr (ZFILL)
+            zero_cells(gphi, tile, static_cast<unsigned>(brow[tid / (TX / 4)] >> ((tid % (TX / 4)) * 4)) & 0xFu, vec,
+                       X, Y, Z, ntx, nty);
         __syncthreads();                                             // LDS reused by the next tile
+    }
+    // Tiles with no interface cell in their 3x3x3 tile neighbourhood (those
+    // the gather list leaves out) have a zero gradient.  kZeroBatch tiles at a
+    // time: the 32 threads of group u check the 27 neighbours of tile u
+    // (the gather list's own test), then the workgroup zeroes the inactive ones.
+    if constexpr (!ZFILL) return;
+    const int ntiles = ntx * nty * ntz;
+    for (int b0 = static_cast<int>(blockIdx.x); b0 < ntiles; b0 += static_cast<int>(gridDim.x) * kZeroBatch) {
+        const int tid = threadIdx.x, u = tid / 32, q = tid % 32;
+        const int tile = b0 + u * static_cast<int>(gridDim.x);
+        bool act = false;
+        if (tile < ntiles && q < 27) {
+            const int ax = tile % ntx + q_dx(q), ay = (tile / ntx) % nty + q_dy(q), az = tile / (ntx * nty) + q_dz(q);
+            if (ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz)
+                act = ws.flags[(az * nty + ay) * ntx + ax] != 0u;
+        }
+        const unsigned long long bal = __ballot(act);
+        if (q == 0) zact[u] = static_cast<unsigned>((tid & 32) ? (bal >> 32) : (bal & 0xFFFFFFFFull)) != 0u;
+        __syncthreads();
+#pragma unroll 1
+        for (int uu = 0; uu < kZeroBatch; ++uu) {
+            const int tl = b0 + uu * static_cast<int>(gridDim.x);
+            if (tl < ntiles && !zact[uu]) zero_cells(gphi, tl, 0u, vec, X, Y, Z, ntx, nty);   // uniform test
+        }
+        __syncthreads();                                             // zact reused
     }
 }
 
@@ -1336,7 +1396,7 @@ template <bool FWD>
 void launch_scan(const float* phi, float* out, Workspace ws, int X, int Y, int Z, const Grid& g,
                  hipStream_t st) {
     const int nb = (g.ntiles + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(kThreads), 0, st, ws.counter, ws.over,
+    hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(kThreads), 0, st, ws.counter, 0, ws.over,
                        nb <= kOnePassBlocks ? nb : 0);
     const bool vec = X % 4 == 0 && aligned(phi, 16) && aligned(out, 16);
     if (vec)
@@ -1393,13 +1453,23 @@ void launch_fwd(int precision, int normal, bool nbr, const float* phi, float* ka
 // backward: adjoint work items (rows that fit), gather list, lean gather of
 // the stored rows (independent of solver and precision), then the fallback
 // gather that recomputes the rows that did not fit
+template <bool NBR, int NRM>
+void launch_gather(float* gp, Workspace ws, int X, int Y, int Z, const Grid& g, bool zfill, hipStream_t st) {
+    const bool vec = X % 4 == 0 && aligned(gp, 16);
+    if (zfill)
+        hipLaunchKernelGGL((k_curv_gather_direct<NBR, NRM, true>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0,
+                           st, gp, ws, X, Y, Z, g.ntx, g.nty, g.ntz, vec);
+    else
+        hipLaunchKernelGGL((k_curv_gather_direct<NBR, NRM, false>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0,
+                           st, gp, ws, X, Y, Z, g.ntx, g.nty, g.ntz, vec);
+}
+
 template <int SOLVER, class T, class U, class F, int NRM>
 void launch_bwd_t(const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y, int Z,
-                  const Grid& g, hipStream_t st) {
+                  const Grid& g, bool zfill, hipStream_t st) {
     launch_rows(ws, g, st);
     if (ws.rows > 0) launch_items<SOLVER, T, U, F, true, NRM, false>(phi, gk, nullptr, ws, X, Y, Z, g, st);
-    hipLaunchKernelGGL((k_curv_gather_direct<false, 0>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0, st, gp,
-                       ws, X, Y, Z, g.ntx, g.nty, g.ntz);
+    launch_gather<false, 0>(gp, ws, X, Y, Z, g, zfill, st);
     // usually empty.  Its registers and LDS allow one workgroup per CU, so a
     // grid of one per CU (256) runs in a single round, cheap when nothing
     // overflowed and as concurrent as any larger grid when something did
@@ -1413,36 +1483,35 @@ void launch_bwd_t(const float* phi, const float* gk, float* gp, Workspace ws, in
 // gather; there is no fallback (the entry point requires one row at least)
 template <int SOLVER, class T, class U, class F, int NRM>
 void launch_bwd_nbr_t(const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y, int Z,
-                      const Grid& g, hipStream_t st) {
+                      const Grid& g, bool zfill, hipStream_t st) {
     launch_rows(ws, g, st);
     launch_items<SOLVER, T, U, F, true, NRM, true>(phi, gk, nullptr, ws, X, Y, Z, g, st);
     hipLaunchKernelGGL(k_curv_hgather, dim3(persistent_grid(static_cast<int64_t>(g.ntiles) * kMaxParts)),
                        dim3(kThreads), 0, st, ws, X, Y, Z, g.ntx, g.nty);
-    hipLaunchKernelGGL((k_curv_gather_direct<true, NRM>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0, st, gp,
-                       ws, X, Y, Z, g.ntx, g.nty, g.ntz);
+    launch_gather<true, NRM>(gp, ws, X, Y, Z, g, zfill, st);
 }
 
 template <int SOLVER, class T, class U, class F>
 void launch_bwd_n(int normal, bool nbr, const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y,
-                  int Z, const Grid& g, hipStream_t st) {
+                  int Z, const Grid& g, bool zfill, hipStream_t st) {
     if (nbr) {
-        if (normal == kNormalCM) launch_bwd_nbr_t<SOLVER, T, U, F, kNormalCM>(phi, gk, gp, ws, X, Y, Z, g, st);
-        else launch_bwd_nbr_t<SOLVER, T, U, F, kNormalPY>(phi, gk, gp, ws, X, Y, Z, g, st);
+        if (normal == kNormalCM) launch_bwd_nbr_t<SOLVER, T, U, F, kNormalCM>(phi, gk, gp, ws, X, Y, Z, g, zfill, st);
+        else launch_bwd_nbr_t<SOLVER, T, U, F, kNormalPY>(phi, gk, gp, ws, X, Y, Z, g, zfill, st);
     } else {
-        if (normal == kNormalCM) launch_bwd_t<SOLVER, T, U, F, kNormalCM>(phi, gk, gp, ws, X, Y, Z, g, st);
-        else launch_bwd_t<SOLVER, T, U, F, kNormalPY>(phi, gk, gp, ws, X, Y, Z, g, st);
+        if (normal == kNormalCM) launch_bwd_t<SOLVER, T, U, F, kNormalCM>(phi, gk, gp, ws, X, Y, Z, g, zfill, st);
+        else launch_bwd_t<SOLVER, T, U, F, kNormalPY>(phi, gk, gp, ws, X, Y, Z, g, zfill, st);
     }
 }
 
 template <int SOLVER>
 void launch_bwd(int precision, int normal, bool nbr, const float* phi, const float* gk, float* gp, Workspace ws,
-                int X, int Y, int Z, const Grid& g, hipStream_t st) {
+                int X, int Y, int Z, const Grid& g, bool zfill, hipStream_t st) {
     if (precision == PLIC_FP32)
-        launch_bwd_n<SOLVER, float, float, float>(normal, nbr, phi, gk, gp, ws, X, Y, Z, g, st);
+        launch_bwd_n<SOLVER, float, float, float>(normal, nbr, phi, gk, gp, ws, X, Y, Z, g, zfill, st);
     else if (precision == PLIC_MIXED)
-        launch_bwd_n<SOLVER, float, double, double>(normal, nbr, phi, gk, gp, ws, X, Y, Z, g, st);
+        launch_bwd_n<SOLVER, float, double, double>(normal, nbr, phi, gk, gp, ws, X, Y, Z, g, zfill, st);
     else
-        launch_bwd_n<SOLVER, double, double, double>(normal, nbr, phi, gk, gp, ws, X, Y, Z, g, st);
+        launch_bwd_n<SOLVER, double, double, double>(normal, nbr, phi, gk, gp, ws, X, Y, Z, g, zfill, st);
 }
 
 // shared argument checks of the two entry points (the workspace's size is
@@ -1461,6 +1530,37 @@ int check_common(const float* phi, int64_t X, int64_t Y, int64_t Z, int solver, 
     return PLIC_OK;
 }
 
+// ---- which phi a workspace's scan records belong to -----------------------------
+// The scan's records (interface masks, prefix counts, work items, tile counts)
+// depend on phi and the lattice only.  The host notes, per workspace address,
+// the phi and lattice of the last call that scanned into it, so that
+// plic_curvature_backward_reuse_f32 skips the scan only when they match.  The
+// table is bounded (cleared when full: a miss only costs a scan).
+struct ScanRecord {
+    const float* phi;
+    int64_t X, Y, Z;
+};
+constexpr size_t kMaxRecords = 4096;
+std::mutex g_record_mutex;
+std::unordered_map<const void*, ScanRecord> g_records;
+
+void note_scan(const void* ws, const float* phi, int64_t X, int64_t Y, int64_t Z, bool ok) {
+    std::lock_guard<std::mutex> lock(g_record_mutex);
+    if (!ok) {
+        g_records.erase(ws);
+        return;
+    }
+    if (g_records.size() >= kMaxRecords && g_records.find(ws) == g_records.end()) g_records.clear();
+    g_records[ws] = ScanRecord{phi, X, Y, Z};
+}
+
+bool scanned_for(const void* ws, const float* phi, int64_t X, int64_t Y, int64_t Z) {
+    std::lock_guard<std::mutex> lock(g_record_mutex);
+    const auto it = g_records.find(ws);
+    return it != g_records.end() && it->second.phi == phi && it->second.X == X && it->second.Y == Y &&
+           it->second.Z == Z;
+}
+
 // the forward launches, after validation
 int curvature_forward(const float* phi, int64_t X, int64_t Y, int64_t Z, float* kappa, int solver, int precision,
                       int normal, bool nbr, void* workspace, size_t workspace_bytes, const Grid& g, hipStream_t st) {
@@ -1473,7 +1573,58 @@ int curvature_forward(const float* phi, int64_t X, int64_t Y, int64_t Z, float* 
         case kNested: launch_fwd<kNested>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
         default: launch_fwd<kAnalytic>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
     }
-    return launch_status();
+    const int rc = launch_status();
+    note_scan(workspace, phi, X, Y, Z, rc == PLIC_OK);
+    return rc;
+}
+
+// the backward, after the shared checks; reuse: skip the scan when the
+// workspace holds this phi's records
+int curvature_backward(const float* phi, int64_t X, int64_t Y, int64_t Z, const float* grad_kappa, float* grad_phi,
+                       int solver, int precision, int normal, int neighbour_normals, void* workspace,
+                       size_t workspace_bytes, void* stream, bool reuse) {
+    bool empty;
+    Grid g{};
+    int64_t n = 0;
+    if (check_common(phi, X, Y, Z, solver, precision, workspace, workspace_bytes, &empty, &g, &n) != PLIC_OK)
+        return PLIC_EINVAL;
+    if (!valid_normal(normal) || (neighbour_normals != 0 && neighbour_normals != 1)) return PLIC_EINVAL;
+    if (!valid_array(grad_kappa, n) || !valid_array(grad_phi, n)) return PLIC_EINVAL;
+    const size_t nb = static_cast<size_t>(n) * sizeof(float);
+    if (overlap(grad_phi, nb, phi, nb) || overlap(grad_phi, nb, grad_kappa, nb)) return PLIC_EINVAL;
+    if (!empty && (overlap(workspace, workspace_bytes, grad_phi, nb) ||
+                   overlap(workspace, workspace_bytes, grad_kappa, nb)))
+        return PLIC_EINVAL;
+    if (empty) return PLIC_OK;
+    // the neighbour-normal backward has no fallback: it needs one row at least
+    if (workspace_bytes < fixed_bytes(g) + (neighbour_normals ? kRowBytesNbr : 0)) return PLIC_EWORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool nbr = neighbour_normals != 0;
+    const Workspace ws = carve(workspace, workspace_bytes, g, nbr);
+    const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
+    const bool scan = !(reuse && scanned_for(workspace, phi, X, Y, Z));
+    if (scan) {
+        launch_scan<false>(phi, grad_phi, ws, x, y, z, g, st);
+    } else {
+        const int nb = (g.ntiles + kThreads - 1) / kThreads;
+        hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(kThreads), 0, st, ws.counter, 1, ws.over,
+                           nb <= kOnePassBlocks ? nb : 0);
+    }
+    switch (solver) {
+        case kSZ: launch_bwd<kSZ>(precision, normal, nbr, phi, grad_kappa, grad_phi, ws, x, y, z, g, !scan, st); break;
+        case kNewton:
+            launch_bwd<kNewton>(precision, normal, nbr, phi, grad_kappa, grad_phi, ws, x, y, z, g, !scan, st);
+            break;
+        case kNested:
+            launch_bwd<kNested>(precision, normal, nbr, phi, grad_kappa, grad_phi, ws, x, y, z, g, !scan, st);
+            break;
+        default:
+            launch_bwd<kAnalytic>(precision, normal, nbr, phi, grad_kappa, grad_phi, ws, x, y, z, g, !scan, st);
+            break;
+    }
+    const int rc = launch_status();
+    if (scan || rc != PLIC_OK) note_scan(workspace, phi, X, Y, Z, rc == PLIC_OK);
+    return rc;
 }
 
 // ---- the forward without a caller workspace ------------------------------------
@@ -1583,33 +1734,15 @@ int plic_curvature_noalloc_f32(const float* phi, int64_t X, int64_t Y, int64_t Z
 int plic_curvature_backward_ex_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, const float* grad_kappa,
                                    float* grad_phi, int solver, int precision, int normal, int neighbour_normals,
                                    void* workspace, size_t workspace_bytes, void* stream) {
-    bool empty;
-    Grid g{};
-    int64_t n = 0;
-    if (check_common(phi, X, Y, Z, solver, precision, workspace, workspace_bytes, &empty, &g, &n) != PLIC_OK)
-        return PLIC_EINVAL;
-    if (!valid_normal(normal) || (neighbour_normals != 0 && neighbour_normals != 1)) return PLIC_EINVAL;
-    if (!valid_array(grad_kappa, n) || !valid_array(grad_phi, n)) return PLIC_EINVAL;
-    const size_t nb = static_cast<size_t>(n) * sizeof(float);
-    if (overlap(grad_phi, nb, phi, nb) || overlap(grad_phi, nb, grad_kappa, nb)) return PLIC_EINVAL;
-    if (!empty && (overlap(workspace, workspace_bytes, grad_phi, nb) ||
-                   overlap(workspace, workspace_bytes, grad_kappa, nb)))
-        return PLIC_EINVAL;
-    if (empty) return PLIC_OK;
-    // the neighbour-normal backward has no fallback: it needs one row at least
-    if (workspace_bytes < fixed_bytes(g) + (neighbour_normals ? kRowBytesNbr : 0)) return PLIC_EWORKSPACE;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const bool nbr = neighbour_normals != 0;
-    const Workspace ws = carve(workspace, workspace_bytes, g, nbr);
-    const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
-    launch_scan<false>(phi, grad_phi, ws, x, y, z, g, st);
-    switch (solver) {
-        case kSZ: launch_bwd<kSZ>(precision, normal, nbr, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
-        case kNewton: launch_bwd<kNewton>(precision, normal, nbr, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
-        case kNested: launch_bwd<kNested>(precision, normal, nbr, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
-        default: launch_bwd<kAnalytic>(precision, normal, nbr, phi, grad_kappa, grad_phi, ws, x, y, z, g, st); break;
-    }
-    return launch_status();
+    return curvature_backward(phi, X, Y, Z, grad_kappa, grad_phi, solver, precision, normal, neighbour_normals,
+                              workspace, workspace_bytes, stream, false);
+}
+
+int plic_curvature_backward_reuse_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, const float* grad_kappa,
+                                      float* grad_phi, int solver, int precision, int normal, int neighbour_normals,
+                                      void* workspace, size_t workspace_bytes, void* stream) {
+    return curvature_backward(phi, X, Y, Z, grad_kappa, grad_phi, solver, precision, normal, neighbour_normals,
+                              workspace, workspace_bytes, stream, true);
 }
 
 int plic_curvature_backward_f32(const float* phi, int64_t X, int64_t Y, int64_t Z, const float* grad_kappa,

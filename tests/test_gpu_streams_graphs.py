@@ -1,7 +1,8 @@
 """The entry points run asynchronously on the caller's stream and record into
 a HIP graph: a side stream gives the same bits as the default stream, and a
 captured sequence (batched inversion, forward volume, curvature forward and
-backward, the neighbour-normal backward, all with caller-owned outputs and
+backward, the backward that reuses the forward's scan, the neighbour-normal
+backward, all with caller-owned outputs and
 workspaces) replays correctly several times with eager work and new inputs
 between the replays.  The curvature clears its counters with a kernel, not a
 memset, and sizes its launches on the host, so nothing in it depends on
@@ -58,6 +59,7 @@ def test_graph_replays_match_eager(P):
     kap = torch.empty_like(phi)
     gphi = torch.empty_like(phi)
     gnbr = torch.empty_like(phi)
+    greu = torch.empty_like(phi)
     ws = torch.empty(P.plic_curvature_workspace_bytes(48, 48, 48), dtype=torch.uint8, device="cuda")
     ws_nbr = torch.empty(P.plic_curvature_workspace_bytes_ex(48, 48, 48, True), dtype=torch.uint8, device="cuda")
 
@@ -71,6 +73,8 @@ def test_graph_replays_match_eager(P):
         P.plic_offset_f32(*sn, d0, "nested", "fp32")
         P.plic_volume_f32(sn[0], sn[1], sn[2], d0, vb, "fp32")
         P.plic_curvature_f32(phi, kap, "analytic", "mixed", ws)
+        # the backward that reuses the forward's scan (decided at capture: no scan in the graph)
+        P.plic_curvature_backward_reuse_f32(phi, gk, greu, "analytic", "mixed", "py", False, ws)
         P.plic_curvature_backward_f32(phi, gk, gphi, "analytic", "mixed", ws)
         P.plic_curvature_backward_ex_f32(phi, gk, gnbr, "analytic", "mixed", "py", True, ws_nbr)
 
@@ -90,11 +94,13 @@ def test_graph_replays_match_eager(P):
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        got = [x.clone() for x in (d0, vb, kap, gphi, gnbr)]
+        got = [x.clone() for x in (d0, vb, kap, gphi, gnbr, greu)]
+        assert torch.equal(got[5], got[3]), rep                # reusing and scanning backward: same bits
         # eager work between the replays, on the same buffers
         work()
         torch.cuda.synchronize()
-        for a, b, name in zip(got, (d0, vb, kap, gphi, gnbr), ("d0", "V0", "kappa", "grad_phi", "grad_phi_nbr")):
+        for a, b, name in zip(got, (d0, vb, kap, gphi, gnbr, greu),
+                              ("d0", "V0", "kappa", "grad_phi", "grad_phi_nbr", "grad_phi_reuse")):
             assert torch.equal(a.nan_to_num(7.0), b.nan_to_num(7.0)), (rep, name)
         assert int(torch.count_nonzero(kap).item()) > 500
         assert bool(torch.isfinite(gnbr).all()) and int(torch.count_nonzero(gnbr).item()) > 500

@@ -179,3 +179,25 @@ def test_trace_profile_summary(tmp_path):
     assert table[1].startswith("| `k_volume<float, float, 4>` | 16,777,216 | 1 | 230.0 | 230.0 |")
     assert table[2].startswith("| `k_offset_bwd<1, float, float, float, 4, true>` | 4,194,304 | 1 | 100.0 |")
     assert bench.kernel_source_hash() in text
+
+
+def test_traffic_profile_lists_the_dispatches_that_ran(tmp_path):
+    """A launch is summed over the dispatches that ran: the backward that
+    reuses the forward's scan has no scan dispatch, and is listed by the
+    others."""
+    log2n, n, lat = 10, 1 << 10, 8
+    kib = 4 * n / 1024
+    items = "void plic::(anonymous namespace)::k_curv_items<0, float, double, double, true, 0, false>(...)"
+    gather = "void plic::(anonymous namespace)::k_curv_gather_direct<false, 0, true>(...)"
+    fetch = [("__amd_rocclr_copyBuffer", kib), (items, 1.0), (gather, 2.0)]
+    write = [("__amd_rocclr_copyBuffer", kib), (items, 3.0), (gather, 4.0)]
+    fc, wc = tmp_path / "fetch.csv", tmp_path / "write.csv"
+    write_counters(fc, fetch)
+    write_counters(wc, write)
+    out = tmp_path / "traffic.md"
+    bench.write_traffic_profile(str(fc), str(wc), log2n, lat, str(out))
+    rows = {line.split("|")[1].strip(): line for line in out.read_text().splitlines() if line.startswith("| ")}
+    cells = [c.strip() for c in rows["curvature_bwd"].split("|")]
+    assert "k_curv_scan" not in cells[2] and "k_curv_items" in cells[2] and "k_curv_gather_direct" in cells[2]
+    assert int(cells[3].replace(",", "")) == 1024 * (1 + 2 + 3 + 4)          # copy factors are 1
+    assert float(cells[6].replace(",", "")) == 8 * lat ** 3                  # 8 B per cell

@@ -1536,29 +1536,44 @@ int check_common(const float* phi, int64_t X, int64_t Y, int64_t Z, int solver, 
 // the phi and lattice of the last call that scanned into it, so that
 // plic_curvature_backward_reuse_f32 skips the scan only when they match.  The
 // table is bounded (cleared when full: a miss only costs a scan).
+// clean: the last call was a forward, whose counter reset also cleared the
+// backward's counters and row-prefix totals (nothing in the forward writes
+// them afterwards), so a backward right after it needs no reset of its own
 struct ScanRecord {
     const float* phi;
     int64_t X, Y, Z;
+    bool clean;
 };
 constexpr size_t kMaxRecords = 4096;
 std::mutex g_record_mutex;
 std::unordered_map<const void*, ScanRecord> g_records;
 
-void note_scan(const void* ws, const float* phi, int64_t X, int64_t Y, int64_t Z, bool ok) {
+void note_scan(const void* ws, const float* phi, int64_t X, int64_t Y, int64_t Z, bool ok, bool clean) {
     std::lock_guard<std::mutex> lock(g_record_mutex);
     if (!ok) {
         g_records.erase(ws);
         return;
     }
     if (g_records.size() >= kMaxRecords && g_records.find(ws) == g_records.end()) g_records.clear();
-    g_records[ws] = ScanRecord{phi, X, Y, Z};
+    g_records[ws] = ScanRecord{phi, X, Y, Z, clean};
 }
 
-bool scanned_for(const void* ws, const float* phi, int64_t X, int64_t Y, int64_t Z) {
+// 0: no records of this phi; 1: records; 2: records and clean counters.  The
+// note turns unclean (a backward is about to use the counters).
+int take_scan(const void* ws, const float* phi, int64_t X, int64_t Y, int64_t Z) {
     std::lock_guard<std::mutex> lock(g_record_mutex);
     const auto it = g_records.find(ws);
-    return it != g_records.end() && it->second.phi == phi && it->second.X == X && it->second.Y == Y &&
-           it->second.Z == Z;
+    if (it == g_records.end() || it->second.phi != phi || it->second.X != X || it->second.Y != Y ||
+        it->second.Z != Z)
+        return 0;
+    const bool clean = it->second.clean;
+    it->second.clean = false;
+    return clean ? 2 : 1;
+}
+
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
 }
 
 // the forward launches, after validation
@@ -1574,7 +1589,7 @@ int curvature_forward(const float* phi, int64_t X, int64_t Y, int64_t Z, float* 
         default: launch_fwd<kAnalytic>(precision, normal, nbr, phi, kappa, ws, x, y, z, g, st); break;
     }
     const int rc = launch_status();
-    note_scan(workspace, phi, X, Y, Z, rc == PLIC_OK);
+    note_scan(workspace, phi, X, Y, Z, rc == PLIC_OK, true);
     return rc;
 }
 
@@ -1602,10 +1617,12 @@ int curvature_backward(const float* phi, int64_t X, int64_t Y, int64_t Z, const 
     const bool nbr = neighbour_normals != 0;
     const Workspace ws = carve(workspace, workspace_bytes, g, nbr);
     const int x = static_cast<int>(X), y = static_cast<int>(Y), z = static_cast<int>(Z);
-    const bool scan = !(reuse && scanned_for(workspace, phi, X, Y, Z));
+    const int rec = reuse ? take_scan(workspace, phi, X, Y, Z) : 0;
+    const bool scan = rec == 0;
     if (scan) {
         launch_scan<false>(phi, grad_phi, ws, x, y, z, g, st);
-    } else {
+    } else if (rec == 1 || capturing(st)) {
+        // (a captured graph may replay this backward without its forward)
         const int nb = (g.ntiles + kThreads - 1) / kThreads;
         hipLaunchKernelGGL(k_curv_zero, dim3(1), dim3(kThreads), 0, st, ws.counter, 1, ws.over,
                            nb <= kOnePassBlocks ? nb : 0);
@@ -1623,7 +1640,7 @@ int curvature_backward(const float* phi, int64_t X, int64_t Y, int64_t Z, const 
             break;
     }
     const int rc = launch_status();
-    if (scan || rc != PLIC_OK) note_scan(workspace, phi, X, Y, Z, rc == PLIC_OK);
+    if (scan || rc != PLIC_OK) note_scan(workspace, phi, X, Y, Z, rc == PLIC_OK, false);
     return rc;
 }
 

@@ -102,3 +102,24 @@ def test_autograd_reuses_and_matches(P, lattice):
     k = P.curvature(x, "analytic", "mixed")
     k.backward(tg)
     assert np.array_equal(host(x.grad), plain(P, tp, tg, "analytic", "mixed"))
+
+
+def test_reuse_repeated_and_after_a_scanning_backward(P, lattice):
+    """Right after its forward the reusing backward also skips the counter
+    reset (the forward's reset covered it); repeated, or after a scanning
+    backward on the workspace, it resets them: every call gives the same bits."""
+    phi, gk = lattice
+    tp, tg = dev(phi, gk)
+    ref = plain(P, tp, tg, "analytic", "mixed")
+    Z, Y, X = phi.shape
+    ws = torch.empty(P.plic_curvature_workspace_bytes(X, Y, Z), dtype=torch.uint8, device="cuda")
+    P.plic_curvature_f32(tp, torch.empty_like(tp), "analytic", "mixed", ws)
+    for k in range(3):
+        out = torch.full_like(tp, float("nan"))
+        P.plic_curvature_backward_reuse_f32(tp, tg, out, "analytic", "mixed", "py", False, ws)
+        assert np.array_equal(host(out), ref), k
+    out = torch.empty_like(tp)
+    P.plic_curvature_backward_f32(tp, tg, out, "analytic", "mixed", ws)
+    out = torch.full_like(tp, float("nan"))
+    P.plic_curvature_backward_reuse_f32(tp, tg, out, "analytic", "mixed", "py", False, ws)
+    assert np.array_equal(host(out), ref)

@@ -1110,13 +1110,40 @@ __device__ __forceinline__ void zero_cells(float* __restrict__ gphi, int tile, u
 
 constexpr int kZeroBatch = kThreads / 32;     // tiles checked at a time by the zero fill
 
+// Zero fill of a backward that ran no scan, tiles b0 .. b0 + kZeroBatch - 1:
+// those with no interface cell in their 3x3x3 tile neighbourhood (the ones the
+// gather list leaves out) get a zero gradient.  The 32 threads of group u
+// check the 27 neighbours of tile b0 + u (the gather list's own test), then the
+// workgroup zeroes the inactive ones.  zact: kZeroBatch words of LDS.
+__device__ __forceinline__ void zero_away_batch_at(float* __restrict__ gphi, const Workspace& ws, int b0, bool vec,
+                                                   int X, int Y, int Z, int ntx, int nty, int ntz, unsigned* zact) {
+    const int ntiles = ntx * nty * ntz;
+    const int tid = threadIdx.x, u = tid / 32, q = tid % 32;
+    const int tile = b0 + u;
+    bool act = false;
+    if (tile < ntiles && q < 27) {
+        const int ax = tile % ntx + q_dx(q), ay = (tile / ntx) % nty + q_dy(q), az = tile / (ntx * nty) + q_dz(q);
+        if (ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz)
+            act = ws.flags[(az * nty + ay) * ntx + ax] != 0u;
+    }
+    const unsigned long long bal = __ballot(act);
+    if (q == 0) zact[u] = static_cast<unsigned>((tid & 32) ? (bal >> 32) : (bal & 0xFFFFFFFFull)) != 0u;
+    __syncthreads();
+#pragma unroll 1
+    for (int uu = 0; uu < kZeroBatch; ++uu) {
+        const int tl = b0 + uu;
+        if (tl < ntiles && !zact[uu]) zero_cells(gphi, tl, 0u, vec, X, Y, Z, ntx, nty);   // uniform test
+    }
+}
+
 // ZFILL: the call ran no scan (it reuses a forward's records), so nothing
-// zeroed grad_phi: the gather writes the zeros itself, on its tiles' cells off
-// the band and on every tile it does not gather
+// zeroed grad_phi: the gather writes the zeros on its tiles' cells off the
+// band, and workgroups added past the first ngather zero the tiles it does not
+// gather, one batch of kZeroBatch tiles each
 template <bool NBR, int NRM, bool ZFILL>
 __global__ __launch_bounds__(kThreads, (NBR ? 5 : 8)) void k_curv_gather_direct(float* __restrict__ gphi, Workspace ws, int X,
                                                                   int Y, int Z, int ntx, int nty, int ntz,
-                                                                  bool vec) {
+                                                                  bool vec, unsigned ngather) {
     constexpr unsigned ROWF = NBR ? kRowFloatsNbr : 27;
     __shared__ SourceMap m;
     __shared__ unsigned short band[kTile];
@@ -1124,8 +1151,17 @@ __global__ __launch_bounds__(kThreads, (NBR ? 5 : 8)) void k_curv_gather_direct(
     __shared__ int bpref[TY * TZ];
     __shared__ int bcount;
     __shared__ unsigned zact[kZeroBatch];
+    if constexpr (ZFILL) {
+        // workgroups past the first ngather: one zero-fill batch each (they
+        // start as the gathering ones with fewer tiles finish)
+        if (blockIdx.x >= ngather) {
+            zero_away_batch_at(gphi, ws, static_cast<int>(blockIdx.x - ngather) * kZeroBatch, vec, X, Y, Z, ntx, nty,
+                               ntz, zact);
+            return;
+        }
+    }
     const unsigned ntl = *static_cast<volatile unsigned*>(ws.counter + 1);
-    for (unsigned it = blockIdx.x; it < ntl; it += gridDim.x) {
+    for (unsigned it = blockIdx.x; it < ntl; it += ngather) {
         const int tid = thread_index_per_iteration();
         const int tile = static_cast<int>(ws.tiles[it]);
         if (ws.rows == 0u) {                                         // nothing stored: all recomputed
@@ -1316,31 +1352,6 @@ __global__ __launch_bounds__(kThreads, (NBR ? 5 : 8)) void k_curv_gather_direct(
                        X, Y, Z, ntx, nty);
         __syncthreads();                                             // LDS reused by the next tile
     }
-    // Tiles with no interface cell in their 3x3x3 tile neighbourhood (those
-    // the gather list leaves out) have a zero gradient.  kZeroBatch tiles at a
-    // time: the 32 threads of group u check the 27 neighbours of tile u
-    // (the gather list's own test), then the workgroup zeroes the inactive ones.
-    if constexpr (!ZFILL) return;
-    const int ntiles = ntx * nty * ntz;
-    for (int b0 = static_cast<int>(blockIdx.x); b0 < ntiles; b0 += static_cast<int>(gridDim.x) * kZeroBatch) {
-        const int tid = threadIdx.x, u = tid / 32, q = tid % 32;
-        const int tile = b0 + u * static_cast<int>(gridDim.x);
-        bool act = false;
-        if (tile < ntiles && q < 27) {
-            const int ax = tile % ntx + q_dx(q), ay = (tile / ntx) % nty + q_dy(q), az = tile / (ntx * nty) + q_dz(q);
-            if (ax >= 0 && ax < ntx && ay >= 0 && ay < nty && az >= 0 && az < ntz)
-                act = ws.flags[(az * nty + ay) * ntx + ax] != 0u;
-        }
-        const unsigned long long bal = __ballot(act);
-        if (q == 0) zact[u] = static_cast<unsigned>((tid & 32) ? (bal >> 32) : (bal & 0xFFFFFFFFull)) != 0u;
-        __syncthreads();
-#pragma unroll 1
-        for (int uu = 0; uu < kZeroBatch; ++uu) {
-            const int tl = b0 + uu * static_cast<int>(gridDim.x);
-            if (tl < ntiles && !zact[uu]) zero_cells(gphi, tl, 0u, vec, X, Y, Z, ntx, nty);   // uniform test
-        }
-        __syncthreads();                                             // zact reused
-    }
 }
 
 // ---- launch helpers -----------------------------------------------------------
@@ -1456,12 +1467,15 @@ void launch_fwd(int precision, int normal, bool nbr, const float* phi, float* ka
 template <bool NBR, int NRM>
 void launch_gather(float* gp, Workspace ws, int X, int Y, int Z, const Grid& g, bool zfill, hipStream_t st) {
     const bool vec = X % 4 == 0 && aligned(gp, 16);
-    if (zfill)
-        hipLaunchKernelGGL((k_curv_gather_direct<NBR, NRM, true>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0,
-                           st, gp, ws, X, Y, Z, g.ntx, g.nty, g.ntz, vec);
-    else
-        hipLaunchKernelGGL((k_curv_gather_direct<NBR, NRM, false>), dim3(persistent_grid(g.ntiles)), dim3(kThreads), 0,
-                           st, gp, ws, X, Y, Z, g.ntx, g.nty, g.ntz, vec);
+    const unsigned ngather = persistent_grid(g.ntiles);
+    if (zfill) {
+        const unsigned nbatch = static_cast<unsigned>((g.ntiles + kZeroBatch - 1) / kZeroBatch);
+        hipLaunchKernelGGL((k_curv_gather_direct<NBR, NRM, true>), dim3(ngather + nbatch), dim3(kThreads), 0, st, gp,
+                           ws, X, Y, Z, g.ntx, g.nty, g.ntz, vec, ngather);
+    } else {
+        hipLaunchKernelGGL((k_curv_gather_direct<NBR, NRM, false>), dim3(ngather), dim3(kThreads), 0, st, gp, ws, X,
+                           Y, Z, g.ntx, g.nty, g.ntz, vec, ngather);
+    }
 }
 
 template <int SOLVER, class T, class U, class F, int NRM>

@@ -661,7 +661,9 @@ constexpr unsigned kPublished = 0x80000000u;                   // totals are at 
 template <bool ONEPASS>
 __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx, int nty, int ntz, int ntiles) {
     __shared__ unsigned wsum[kThreads / 64];
+    __shared__ unsigned wact[kThreads / 64];
     __shared__ unsigned long long boff;
+    __shared__ unsigned gbase;
     __shared__ int ticket;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     int b = static_cast<int>(blockIdx.x);
@@ -691,22 +693,23 @@ __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx,
     }
     if (lane == 63) wsum[wave] = incl;
     const unsigned long long bal = __ballot(act);
-    unsigned first = 0;
-    if (lane == 0 && bal) first = atomicAdd(ws.counter + 1, static_cast<unsigned>(__popcll(bal)));
-    first = __shfl(first, 0, 64);
-    if (act) {
-        const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
-        ws.tiles[first + __popcll(below)] = static_cast<unsigned>(tile);
-    }
+    if (lane == 0) wact[wave] = static_cast<unsigned>(__popcll(bal));
     __syncthreads();
-    unsigned woff = 0u, total = 0u;
+    unsigned woff = 0u, total = 0u, aoff = 0u, atotal = 0u;
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) {
         woff += w < wave ? wsum[w] : 0u;
         total += wsum[w];
+        aoff += w < wave ? wact[w] : 0u;
+        atotal += wact[w];
     }
+    // the gather list: one atomic per workgroup (the atomics on one word are
+    // served one at a time), taken after the total is published
     if constexpr (ONEPASS) {
-        if (t == 0) __hip_atomic_store(ws.over + b, total | kPublished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t == 0) {
+            __hip_atomic_store(ws.over + b, total | kPublished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            gbase = atotal ? atomicAdd(ws.counter + 1, atotal) : 0u;
+        }
         if (wave == 0) {
             unsigned long long acc = 0ull;
             for (int p = lane; p < b; p += 64) {
@@ -727,7 +730,15 @@ __global__ __launch_bounds__(kThreads) void k_curv_dilate(Workspace ws, int ntx,
         }
     } else {
         if (tile < ntiles) ws.cbase[tile] = woff + incl - c;
-        if (t == 0) ws.over[blockIdx.x] = total;              // at most 256 * 1024 = 2^18
+        if (t == 0) {
+            ws.over[blockIdx.x] = total;                      // at most 256 * 1024 = 2^18
+            gbase = atotal ? atomicAdd(ws.counter + 1, atotal) : 0u;
+        }
+        __syncthreads();
+    }
+    if (act) {
+        const unsigned long long below = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
+        ws.tiles[gbase + aoff + __popcll(below)] = static_cast<unsigned>(tile);
     }
 }
 

@@ -429,6 +429,124 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
 }
 
 // ---------------------------------------------------------------------------
+// The forward of one interface cell on a group of 16 lanes, four cells per
+// wavefront.  The normal, the frame, the fit and kappa are computed once per
+// group, so per cell they cost half of what they cost on 32 lanes; lane j
+// owns the points of slots j and j + 16 (slot s < 26: neighbour q(s), the 26
+// offsets other than the centre; slot 26: the centre), so each lane inverts at
+// most two PLIC problems.  The fit's sums run over the group's lanes in a
+// fixed order (each lane's two points first), so every call gives the same
+// bits.  s: the 3x3x3 fill levels in LDS, indexed by q.
+// ---------------------------------------------------------------------------
+constexpr int kQuad = 16;                       // lanes per interface cell
+constexpr int kQuads = kThreads / kQuad;        // cells in flight per workgroup
+
+template <class F, int COLS>
+struct alignas(16) QuadLds {
+    F stage[kQuad][COLS];
+    F res[24];                                  // 20 sums, the centre offset at 20
+};
+
+// sum over the group's 16 lanes of each of the NV entries of row, through a
+// [16][COLS] staging tile (lane k sums column k of each pass in lane order)
+template <class F, int NV, int COLS>
+__device__ __forceinline__ void quad_colsum(QuadLds<F, COLS>& L, int j, const F (&row)[NV], F (&sum)[NV]) {
+#pragma unroll
+    for (int c0 = 0; c0 < NV; c0 += COLS) {
+#pragma unroll
+        for (int k = 0; k < COLS; ++k)
+            if (c0 + k < NV) L.stage[j][k] = row[c0 + k];
+        __syncwarp();
+        if (j < COLS && c0 + j < NV) {
+            F acc = F(0);
+#pragma unroll
+            for (int l = 0; l < kQuad; ++l) acc += L.stage[l][j];
+            L.res[c0 + j] = acc;
+        }
+        __syncwarp();
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sum[k] = L.res[k];
+    __syncwarp();
+}
+
+// this lane's point of slot q (x, y in the frame, z along n), zero when q is
+// not an interface neighbour
+template <class T, class F>
+__device__ __forceinline__ void quad_point(int q, bool iface, T D, T D0, T bx0, T bx1, T bx2, T by0, T by1, T by2,
+                                           T n0, T n1, T n2, F& x, F& y, F& z) {
+    x = F(0); y = F(0); z = F(0);
+    if (iface) {
+        const T ex = T(q_dx(q)), ey = T(q_dy(q)), ez = T(q_dz(q));
+        x = F(ex * bx0 + ey * bx1 + ez * bx2);
+        y = F(ex * by0 + ey * by1 + ez * by2);
+        z = F(ex * n0 + ey * n1 + ez * n2 + (D - D0));
+    }
+}
+
+template <int SOLVER, class T, class U, class F, int NRM, int COLS>
+__device__ __forceinline__ float quad_cell(const float* __restrict__ s, int j, int lane, QuadLds<F, COLS>& L) {
+    using mt = M<T>;
+    T gx, gy, gz;
+    gradient27<NRM, T>(s, 13, 3, 9, gx, gy, gz);
+    const int qa = j < 13 ? j : j + 1;          // slot j: a neighbour
+    const int sb = j + kQuad;                   // slot j + 16: a neighbour below 26, the centre at 26
+    const bool nbb = sb < 26, centre = sb == 26;
+    const int qb = nbb ? sb + 1 : 13;
+    const float pa = s[qa], pb = (nbb || centre) ? s[qb] : 0.0f;
+    const bool ia = is_iface(pa), ib = nbb && is_iface(pb);
+    const int g0 = lane & 48;                   // this group's lanes in the wave
+    const int npts = __popcll((__ballot(ia) >> g0) & 0xFFFFull) + __popcll((__ballot(ib) >> g0) & 0xFFFFull);
+    const T gn2 = gx * gx + gy * gy + gz * gz;
+    if (!(gn2 >= T(1e-24))) return 0.0f;        // no usable normal (uniform per group)
+    const T ign = mt::rcp(mt::sqrt(gn2));
+    const T n0 = -gx * ign, n1 = -gy * ign, n2 = -gz * ign;
+    // local frame (Sec. 4.2), as in group_cell
+    T r0 = T(kR0), r1 = T(kR1), r2 = T(kR2);
+    T u0 = n1 * r2 - n2 * r1, u1 = n2 * r0 - n0 * r2, u2 = n0 * r1 - n1 * r0;
+    T un2 = u0 * u0 + u1 * u1 + u2 * u2;
+    if (un2 < T(1e-12)) {
+        r0 = T(kR1); r1 = T(kR2); r2 = T(kR0);
+        u0 = n1 * r2 - n2 * r1; u1 = n2 * r0 - n0 * r2; u2 = n0 * r1 - n1 * r0;
+        un2 = u0 * u0 + u1 * u1 + u2 * u2;
+    }
+    const T iun = mt::rcp(mt::sqrt(un2));
+    const T by0 = u0 * iun, by1 = u1 * iun, by2 = u2 * iun;
+    const T bx0 = by1 * n2 - by2 * n1, bx1 = by2 * n0 - by0 * n2, bx2 = by0 * n1 - by1 * n0;
+    // PLIC offsets of the two slots with the centre normal
+    T Da = T(0), Db = T(0);
+    if (ia) Da = offset<SOLVER, T, U>(n0, n1, n2, T(pa));
+    if (ib || centre) Db = offset<SOLVER, T, U>(n0, n1, n2, T(pb));
+    if (centre) L.res[20] = F(Db);
+    __syncwarp();
+    const T D0 = T(L.res[20]);
+    F xa, ya, za, xb, yb, zb;
+    quad_point<T, F>(qa, ia, Da, D0, bx0, bx1, bx2, by0, by1, by2, n0, n1, n2, xa, ya, za);
+    quad_point<T, F>(qb, ib, Db, D0, bx0, bx1, bx2, by0, by1, by2, n0, n1, n2, xb, yb, zb);
+    const F Qa[5] = {xa * xa, ya * ya, xa * ya, xa, ya}, Qb[5] = {xb * xb, yb * yb, xb * yb, xb, yb};
+    F row[20], sum[20];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+#pragma unroll
+        for (int k = 0; k <= i; ++k) row[tri(i, k)] = Qa[i] * Qa[k] + Qb[i] * Qb[k];
+        row[15 + i] = za * Qa[i] + zb * Qb[i];
+    }
+    quad_colsum<F, 20, COLS>(L, j, row, sum);
+    F m[5][5], b[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        b[i] = sum[15 + i];
+#pragma unroll
+        for (int k = 0; k <= i; ++k) m[i][k] = sum[tri(i, k)];
+    }
+    bool act[5];
+    F a[5], dinv[5];
+    ldlt_factor<F>(m, npts < 5 ? npts : 5, act, dinv);
+    ldlt_solve<F>(m, act, dinv, b, a);
+    return float(kappa_of<F>(a));
+}
+
+// ---------------------------------------------------------------------------
 // Fill levels of a box [x0-H, x0+TX+H) x ... into LDS, every load issued
 // before the first store (out-of-lattice cells read as 0).
 // ---------------------------------------------------------------------------
@@ -809,11 +927,11 @@ __device__ __forceinline__ int thread_index_per_iteration() {
 // Waves per SIMD the work items are compiled for: the work is a chain of
 // dependent steps per cell, so concurrency sets the time.  Each count is the
 // largest that compiles without spilling (VGPRs at most 64 for 8 waves, 80
-// for 6, 128 for 4, 168 for 3) and that the LDS allows: a forward with an
-// FP32 fit holds 19 KiB per workgroup (8 waves; 7 for neighbour normals, whose
-// 5x5x5 fill levels add 4 KiB), the mixed-precision forward
-// 19.5 KiB with its halved FP64 staging tile (6 waves), an FP64 forward 36 KiB
-// (4).  In mixed precision the PLIC points are FP32 with the FP64 island only
+// for 6, 128 for 4, 168 for 3) and that the LDS allows.  On 32 lanes per cell
+// the forward runs only with neighbour normals (the plain forward runs on 16
+// lanes, k_curv_quads): with an FP32 fit it holds 21.5 KiB per workgroup (7
+// waves, the 5x5x5 fill levels included), in mixed precision 22.5 KiB with
+// its halved FP64 staging tile (compiled for 6 waves), in FP64 38.5 KiB (4).  In mixed precision the PLIC points are FP32 with the FP64 island only
 // near case boundaries, so the adjoint fits 4 waves (3 with neighbour
 // normals); in FP64 the adjoint of a trigonometric root (analytic, SZ) needs
 // more registers than that of an iterative one, and the neighbour-normal
@@ -885,6 +1003,64 @@ __global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, U, ADJ, NBR>())) 
             if (j == 0) kappa[g] = kv;
         }
         __syncwarp();                                        // nbh and glds reused by the next cell
+    }
+}
+
+// The forward without neighbour normals on groups of 16 lanes: a workgroup
+// takes two work items at a time (its first two waves the first, the last two
+// the second), each 32-lane half of a wave finds its two cells from the tile's
+// bitmask, and each group of 16 stages its cell's 3x3x3 fill levels and runs
+// quad_cell.
+template <class T, class U>
+constexpr int quad_waves() {
+    return sizeof(T) == 4 ? 8 : 4;
+}
+
+template <int SOLVER, class T, class U, class F, int NRM>
+__global__ __launch_bounds__(kThreads, (quad_waves<T, U>())) void k_curv_quads(const float* __restrict__ phi,
+                                                                              float* __restrict__ kappa, Workspace ws,
+                                                                              int X, int Y, int Z, int ntx, int nty) {
+    constexpr int COLS = sizeof(F) == 8 ? 5 : 10;
+    __shared__ float nbh[kQuads][27];
+    __shared__ QuadLds<F, COLS> qlds[kQuads];
+    const unsigned nitems = *static_cast<volatile unsigned*>(ws.counter);
+    const unsigned npairs = (nitems + 1u) / 2u;
+    for (unsigned pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
+        const int tid = thread_index_per_iteration(), grp = tid / kQuad, j = tid % kQuad;
+        const int lane = tid & 63, l32 = tid & 31, half = tid & 32;
+        const unsigned item = 2u * pr + (tid >= kThreads / 2 ? 1u : 0u);
+        if (item >= nitems) continue;                        // uniform per pair of waves
+        const unsigned e = ws.items[item];
+        const int tile = static_cast<int>(e >> 7), part = static_cast<int>(e & 127u);
+        // the two ranks of this half-wave's groups among the tile's interface cells
+        const unsigned mw = ws.mask[tile * kWords + l32], pw = ws.prefix[tile * kWords + l32];
+        const unsigned n = __shfl(pw + __popc(mw), kWords - 1, 32);
+        const unsigned i0 = static_cast<unsigned>(part * kPartCells + (grp % 8) / 2 * 2);
+        int cl[2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const unsigned ui = i0 + r < n ? i0 + r : n - 1u;    // n >= 1: the tile has an item
+            const unsigned in_word = static_cast<unsigned>(__ballot(pw <= ui && ui < pw + __popc(mw)) >> half);
+            const int w = __ffs(static_cast<int>(in_word)) - 1;
+            const unsigned word = __shfl(mw, w, 32);
+            const unsigned k = ui - __shfl(pw, w, 32);
+            const bool hit = ((word >> l32) & 1u) && static_cast<unsigned>(__popc(word & ((1u << l32) - 1u))) == k;
+            const int b = __ffs(static_cast<int>(static_cast<unsigned>(__ballot(hit) >> half))) - 1;
+            cl[r] = w * 32 + b;
+        }
+        if (i0 + (grp & 1) >= n) continue;                   // uniform per group
+        const int c = (grp & 1) ? cl[1] : cl[0];
+        const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
+        const int gx = x0 + c % TX, gy = y0 + (c / TX) % TY, gz = z0 + c / (TX * TY);
+        for (int t = j; t < 27; t += kQuad) {
+            const int ax = gx + q_dx(t), ay = gy + q_dy(t), az = gz + q_dz(t);
+            nbh[grp][t] = (ax >= 0 && ax < X && ay >= 0 && ay < Y && az >= 0 && az < Z)
+                              ? phi[(static_cast<int64_t>(az) * Y + ay) * X + ax] : 0.0f;
+        }
+        __syncwarp();
+        const float kv = quad_cell<SOLVER, T, U, F, NRM, COLS>(nbh[grp], j, lane, qlds[grp]);
+        if (j == 0) kappa[(static_cast<int64_t>(gz) * Y + gy) * X + gx] = kv;
+        __syncwarp();                                        // nbh and qlds reused by the next pair
     }
 }
 
@@ -1451,16 +1627,22 @@ void launch_items(const float* phi, const float* gk, float* kappa, Workspace ws,
                        g.ntx, g.nty);
 }
 
+template <int SOLVER, class T, class U, class F, int NRM>
+void launch_quads(const float* phi, float* kappa, Workspace ws, int X, int Y, int Z, const Grid& g, hipStream_t st) {
+    const dim3 grid(persistent_grid(static_cast<int64_t>(g.ntiles) * kMaxParts)), block(kThreads);
+    hipLaunchKernelGGL((k_curv_quads<SOLVER, T, U, F, NRM>), grid, block, 0, st, phi, kappa, ws, X, Y, Z, g.ntx, g.nty);
+}
+
 // forward: precision picks the types, then the normal and the variant
 template <int SOLVER, class T, class U, class F>
 void launch_fwd_t(int normal, bool nbr, const float* phi, float* kappa, Workspace ws, int X, int Y, int Z,
                   const Grid& g, hipStream_t st) {
     if (normal == kNormalCM) {
         if (nbr) launch_items<SOLVER, T, U, F, false, kNormalCM, true>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
-        else launch_items<SOLVER, T, U, F, false, kNormalCM, false>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
+        else launch_quads<SOLVER, T, U, F, kNormalCM>(phi, kappa, ws, X, Y, Z, g, st);
     } else {
         if (nbr) launch_items<SOLVER, T, U, F, false, kNormalPY, true>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
-        else launch_items<SOLVER, T, U, F, false, kNormalPY, false>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
+        else launch_quads<SOLVER, T, U, F, kNormalPY>(phi, kappa, ws, X, Y, Z, g, st);
     }
 }
 

@@ -1020,7 +1020,7 @@ template <int SOLVER, class T, class U, class F, int NRM>
 __global__ __launch_bounds__(kThreads, (quad_waves<T, U>())) void k_curv_quads(const float* __restrict__ phi,
                                                                               float* __restrict__ kappa, Workspace ws,
                                                                               int X, int Y, int Z, int ntx, int nty) {
-    constexpr int COLS = sizeof(F) == 8 ? 5 : 10;
+    constexpr int COLS = 10;                                 // 2 passes; 25 KiB of LDS with an FP64 fit
     __shared__ float nbh[kQuads][27];
     __shared__ QuadLds<F, COLS> qlds[kQuads];
     const unsigned nitems = *static_cast<volatile unsigned*>(ws.counter);

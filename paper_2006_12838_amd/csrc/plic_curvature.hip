@@ -484,21 +484,35 @@ __device__ __forceinline__ void quad_point(int q, bool iface, T D, T D0, T bx0, 
     }
 }
 
-template <int SOLVER, class T, class U, class F, int NRM, int COLS>
-__device__ __forceinline__ float quad_cell(const float* __restrict__ s, int j, int lane, QuadLds<F, COLS>& L) {
+// One interface cell on a group of 16 lanes.  s: LDS fill levels, c: centre
+// index, sy/sz: LDS strides, j: lane in the group (0..15), lane: lane in the
+// wavefront.  Every lane of the group must call it; returns kappa.  With ADJ,
+// also writes out[q] = gk * d kappa / d phi_q (q = 0..26) from the lane that
+// owns q, with the interface mask, the PLIC cases and the active fit
+// parameters held fixed (the adjoint of group_cell's, on two slots per lane).
+template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, int COLS>
+__device__ __forceinline__ float quad_cell(const float* __restrict__ s, int c, int sy, int sz, int j, int lane,
+                                           float gk, float* __restrict__ out, QuadLds<F, COLS>& L) {
     using mt = M<T>;
     T gx, gy, gz;
-    gradient27<NRM, T>(s, 13, 3, 9, gx, gy, gz);
+    gradient27<NRM, T>(s, c, sy, sz, gx, gy, gz);
     const int qa = j < 13 ? j : j + 1;          // slot j: a neighbour
     const int sb = j + kQuad;                   // slot j + 16: a neighbour below 26, the centre at 26
     const bool nbb = sb < 26, centre = sb == 26;
     const int qb = nbb ? sb + 1 : 13;
-    const float pa = s[qa], pb = (nbb || centre) ? s[qb] : 0.0f;
+    const float pa = s[c + q_dz(qa) * sz + q_dy(qa) * sy + q_dx(qa)];
+    const float pb = (nbb || centre) ? s[c + q_dz(qb) * sz + q_dy(qb) * sy + q_dx(qb)] : 0.0f;
     const bool ia = is_iface(pa), ib = nbb && is_iface(pb);
     const int g0 = lane & 48;                   // this group's lanes in the wave
     const int npts = __popcll((__ballot(ia) >> g0) & 0xFFFFull) + __popcll((__ballot(ib) >> g0) & 0xFFFFull);
     const T gn2 = gx * gx + gy * gy + gz * gz;
-    if (!(gn2 >= T(1e-24))) return 0.0f;        // no usable normal (uniform per group)
+    if (!(gn2 >= T(1e-24))) {                   // no usable normal: kappa = 0 (uniform per group)
+        if constexpr (ADJ) {
+            out[qa] = 0.0f;
+            if (nbb || centre) out[qb] = 0.0f;
+        }
+        return 0.0f;
+    }
     const T ign = mt::rcp(mt::sqrt(gn2));
     const T n0 = -gx * ign, n1 = -gy * ign, n2 = -gz * ign;
     // local frame (Sec. 4.2), as in group_cell
@@ -543,7 +557,100 @@ __device__ __forceinline__ float quad_cell(const float* __restrict__ s, int j, i
     F a[5], dinv[5];
     ldlt_factor<F>(m, npts < 5 ? npts : 5, act, dinv);
     ldlt_solve<F>(m, act, dinv, b, a);
-    return float(kappa_of<F>(a));
+    const float kappa = float(kappa_of<F>(a));
+    if constexpr (ADJ) {
+        // d kappa / d(A,B,C,H,I), as in group_cell
+        const F A = a[0], B = a[1], C = a[2], H = a[3], I = a[4];
+        const F W = H * H + I * I + F(1);
+        const F iW32 = F(1) / (W * M<F>::sqrt(W));
+        const F num = A * (I * I + F(1)) + B * (H * H + F(1)) - C * H * I;
+        const F g = -F(gk);
+        F abar[5];
+        abar[0] = g * (I * I + F(1)) * iW32;
+        abar[1] = g * (H * H + F(1)) * iW32;
+        abar[2] = g * (-H * I) * iW32;
+        abar[3] = g * ((F(2) * B * H - C * I) * iW32 - F(3) * num * H * iW32 / W);
+        abar[4] = g * ((F(2) * A * I - C * H) * iW32 - F(3) * num * I * iW32 / W);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) abar[i] = act[i] ? abar[i] : F(0);
+        F lam[5];
+        ldlt_solve<F>(m, act, dinv, abar, lam);    // M symmetric: lambda = M^-1 abar
+        // each slot's point: zbar = lam.Q, Qbar = lam (z - a.Q) - a (lam.Q); the
+        // frame's adjoint rows of the two slots add up per lane
+        T phia = T(0), phibb = T(0);
+        F arow[10];
+#pragma unroll
+        for (int i = 0; i < 10; ++i) arow[i] = F(0);
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+            const bool on = sl == 0 ? ia : ib;
+            if (!on) continue;
+            const int q = sl == 0 ? qa : qb;
+            const F x = sl == 0 ? xa : xb, y = sl == 0 ? ya : yb, z = sl == 0 ? za : zb;
+            const T D = sl == 0 ? Da : Db;
+            const float p = sl == 0 ? pa : pb;
+            const F Q[5] = {x * x, y * y, x * y, x, y};
+            F zq = F(0), aQ = F(0);
+#pragma unroll
+            for (int i = 0; i < 5; ++i) { zq += lam[i] * Q[i]; aQ += a[i] * Q[i]; }
+            F Qbar[5];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) Qbar[i] = lam[i] * (z - aQ) - a[i] * zq;
+            const T xbar = T(F(2) * x * Qbar[0] + y * Qbar[2] + Qbar[3]);
+            const T ybar = T(F(2) * y * Qbar[1] + x * Qbar[2] + Qbar[4]);
+            const T zt = T(zq);
+            const T ex = T(q_dx(q)), ey = T(q_dy(q)), ez = T(q_dz(q));
+            T cq[3];
+            const T dv = offset_grad_from_d0<T>(n0, n1, n2, T(p), D, cq);   // 1/A, centroid
+            (sl == 0 ? phia : phibb) = zt * dv;
+            arow[0] += F(xbar * ex); arow[1] += F(xbar * ey); arow[2] += F(xbar * ez);
+            arow[3] += F(ybar * ex); arow[4] += F(ybar * ey); arow[5] += F(ybar * ez);
+            arow[6] += F(zt * (ex + cq[0])); arow[7] += F(zt * (ey + cq[1])); arow[8] += F(zt * (ez + cq[2]));
+            arow[9] += F(zt);
+        }
+        T dvc = T(0);
+        if (centre) {
+            T cc[3];
+            dvc = offset_grad_from_d0<T>(n0, n1, n2, T(pb), Db, cc);
+            L.res[21] = F(cc[0]); L.res[22] = F(cc[1]); L.res[23] = F(cc[2]);
+        }
+        F asum[10];
+        quad_colsum<F, 10, COLS>(L, j, arow, asum);   // its barriers also publish res[21..23]
+        const T c00 = T(L.res[21]), c01 = T(L.res[22]), c02 = T(L.res[23]);
+        const T sbx0 = T(asum[0]), sbx1 = T(asum[1]), sbx2 = T(asum[2]);
+        const T sz_ = T(asum[9]);
+        // the centre offset D0 enters every z with a minus sign
+        T nb0 = T(asum[6]) - sz_ * c00, nb1 = T(asum[7]) - sz_ * c01, nb2 = T(asum[8]) - sz_ * c02;
+        // b_x = b_y x n
+        const T yb0 = T(asum[3]) + (n1 * sbx2 - n2 * sbx1);
+        const T yb1 = T(asum[4]) + (n2 * sbx0 - n0 * sbx2);
+        const T yb2 = T(asum[5]) + (n0 * sbx1 - n1 * sbx0);
+        nb0 += sbx1 * by2 - sbx2 * by1;
+        nb1 += sbx2 * by0 - sbx0 * by2;
+        nb2 += sbx0 * by1 - sbx1 * by0;
+        // b_y = u / |u|, u = n x r
+        const T bd = by0 * yb0 + by1 * yb1 + by2 * yb2;
+        const T ub0 = (yb0 - by0 * bd) * iun, ub1 = (yb1 - by1 * bd) * iun, ub2 = (yb2 - by2 * bd) * iun;
+        nb0 += r1 * ub2 - r2 * ub1;
+        nb1 += r2 * ub0 - r0 * ub2;
+        nb2 += r0 * ub1 - r1 * ub0;
+        // n = -g / |g|
+        const T nd = n0 * nb0 + n1 * nb1 + n2 * nb2;
+        const T gb0 = -(nb0 - n0 * nd) * ign, gb1 = -(nb1 - n1 * nd) * ign, gb2 = -(nb2 - n2 * nd) * ign;
+        {
+            const T ex = T(q_dx(qa)), ey = T(q_dy(qa)), ez = T(q_dz(qa));
+            const int e2 = q_dx(qa) * q_dx(qa) + q_dy(qa) * q_dy(qa) + q_dz(qa) * q_dz(qa);
+            out[qa] = float(phia + T(nrm_weight<NRM>(e2)) * (ex * gb0 + ey * gb1 + ez * gb2));
+        }
+        if (nbb) {
+            const T ex = T(q_dx(qb)), ey = T(q_dy(qb)), ez = T(q_dz(qb));
+            const int e2 = q_dx(qb) * q_dx(qb) + q_dy(qb) * q_dy(qb) + q_dz(qb) * q_dz(qb);
+            out[qb] = float(phibb + T(nrm_weight<NRM>(e2)) * (ex * gb0 + ey * gb1 + ez * gb2));
+        }
+        if (centre) out[13] = float(-sz_ * dvc);
+        __syncwarp();                              // res is reused by the next cell
+    }
+    return kappa;
 }
 
 // ---------------------------------------------------------------------------
@@ -882,14 +989,16 @@ __global__ __launch_bounds__(kThreads) void k_curv_prefix(Workspace ws, int ntil
 }
 
 // ---------------------------------------------------------------------------
-// 2. work items: up to kPartCells interface cells of a tile, one 32-lane group
-// per cell.  The group finds its cell, the i-th interface cell of the tile in
-// cell order, from the tile's bitmask and prefix counts (two ballots), stages
-// the fill levels of its 3x3x3 neighbourhood (5x5x5 for the neighbour-normal
-// variant, which needs each neighbour's own 3x3x3) in LDS, and runs the cell.
-// Groups never wait for each other: no block barrier.  Forward: kappa.
-// Backward: the cell's 27 contributions gk * d kappa / d phi_q into its
-// contribution row (when it fits).
+// 2. work items: up to kPartCells interface cells of a tile.  Without
+// neighbour normals a cell runs on a group of 16 lanes (k_curv_quads, above);
+// the neighbour-normal variant, whose cells need their 5x5x5 neighbourhood
+// (each neighbour's own 3x3x3), runs a cell on a group of 32 lanes
+// (k_curv_items).  The group finds its cell, the i-th interface cell of the
+// tile in cell order, from the tile's bitmask and prefix counts (two
+// ballots), stages the cell's fill levels in LDS, and runs the cell.  Groups
+// never wait for each other: no block barrier.  Forward: kappa.  Backward:
+// the cell's contributions gk * d kappa / d phi_q into its contribution row
+// (when it fits).
 // ---------------------------------------------------------------------------
 
 // Lattice position of the interface cell of rank i (in cell order) of a
@@ -924,32 +1033,29 @@ __device__ __forceinline__ int thread_index_per_iteration() {
     return t;
 }
 
-// Waves per SIMD the work items are compiled for: the work is a chain of
-// dependent steps per cell, so concurrency sets the time.  Each count is the
-// largest that compiles without spilling (VGPRs at most 64 for 8 waves, 80
-// for 6, 128 for 4, 168 for 3) and that the LDS allows.  On 32 lanes per cell
-// the forward runs only with neighbour normals (the plain forward runs on 16
-// lanes, k_curv_quads): with an FP32 fit it holds 21.5 KiB per workgroup (7
-// waves, the 5x5x5 fill levels included), in mixed precision 22.5 KiB with
-// its halved FP64 staging tile (compiled for 6 waves), in FP64 38.5 KiB (4).  In mixed precision the PLIC points are FP32 with the FP64 island only
-// near case boundaries, so the adjoint fits 4 waves (3 with neighbour
-// normals); in FP64 the adjoint of a trigonometric root (analytic, SZ) needs
-// more registers than that of an iterative one, and the neighbour-normal
-// variant more again.
-template <int SOLVER, class T, class U, bool ADJ, bool NBR>
+// Waves per SIMD the 32-lane work items (the neighbour-normal variant) are
+// compiled for: the work is a chain of dependent steps per cell, so
+// concurrency sets the time.  Each count is the largest that compiles without
+// spilling (VGPRs at most 64 for 8 waves, 80 for 6, 128 for 4, 168 for 3) and
+// that the LDS allows: the forward with an FP32 fit holds 21.5 KiB per
+// workgroup (7 waves, the 5x5x5 fill levels included), in mixed precision
+// 22.5 KiB with its halved FP64 staging tile (compiled for 6 waves), in FP64
+// 38.5 KiB (4); the adjoint fits 4 waves in FP32, 3 in mixed precision (its
+// PLIC points are FP32 with the FP64 island only near case boundaries) and 2
+// in FP64.
+template <class T, class U, bool ADJ>
 constexpr int items_waves() {
-    const bool iter = SOLVER == kNewton || SOLVER == kNested;
-    if (!ADJ) return sizeof(U) == 4 ? (NBR ? 7 : 8) : (sizeof(T) == 4 ? 6 : 4);   // LDS, as above
+    if (!ADJ) return sizeof(U) == 4 ? 7 : (sizeof(T) == 4 ? 6 : 4);      // LDS, as above
     if (sizeof(U) == 4) return 4;                                         // FP32
-    if (sizeof(T) == 4) return NBR ? 3 : 4;                               // mixed
-    return iter && !NBR ? 3 : 2;                                          // FP64
+    return sizeof(T) == 4 ? 3 : 2;                                        // mixed, FP64
 }
 
 template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
-__global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, U, ADJ, NBR>())) void k_curv_items(const float* __restrict__ phi,
+__global__ __launch_bounds__(kThreads, (items_waves<T, U, ADJ>())) void k_curv_items(const float* __restrict__ phi,
                                                           const float* __restrict__ gkap,
                                                           float* __restrict__ kappa, Workspace ws, int X, int Y,
                                                           int Z, int ntx, int nty) {
+    static_assert(NBR, "cells without neighbour normals run on 16 lanes (k_curv_quads)");
     constexpr int H = NBR ? 2 : 1, W = 2 * H + 1, NB = W * W * W, C = (H * W + H) * W + H;
     // the mixed-precision forward stages its FP64 rows in two passes of 10
     // columns: 19.5 KiB of LDS per workgroup instead of 36, so its registers
@@ -1006,20 +1112,30 @@ __global__ __launch_bounds__(kThreads, (items_waves<SOLVER, T, U, ADJ, NBR>())) 
     }
 }
 
-// The forward without neighbour normals on groups of 16 lanes: a workgroup
+// The curvature without neighbour normals on groups of 16 lanes: a workgroup
 // takes two work items at a time (its first two waves the first, the last two
 // the second), each 32-lane half of a wave finds its two cells from the tile's
 // bitmask, and each group of 16 stages its cell's 3x3x3 fill levels and runs
-// quad_cell.
-template <class T, class U>
+// quad_cell; the forward writes kappa, the backward (ADJ) the cell's
+// contribution row when it fits the workspace.
+// waves per SIMD, the most that compile without spilling: the forward 8
+// (FP64: 4); the adjoint, which keeps two points' state per lane, 4 in FP32,
+// 3 in mixed precision, in FP64 3 for the iterative solvers and 2 for the
+// trigonometric ones
+template <int SOLVER, class T, class U, bool ADJ>
 constexpr int quad_waves() {
-    return sizeof(T) == 4 ? 8 : 4;
+    if (!ADJ) return sizeof(T) == 4 ? 8 : 4;
+    if (sizeof(U) == 4) return 4;
+    if (sizeof(T) == 4) return 3;
+    return (SOLVER == kNewton || SOLVER == kNested) ? 3 : 2;
 }
 
-template <int SOLVER, class T, class U, class F, int NRM>
-__global__ __launch_bounds__(kThreads, (quad_waves<T, U>())) void k_curv_quads(const float* __restrict__ phi,
-                                                                              float* __restrict__ kappa, Workspace ws,
-                                                                              int X, int Y, int Z, int ntx, int nty) {
+template <int SOLVER, class T, class U, class F, bool ADJ, int NRM>
+__global__ __launch_bounds__(kThreads, (quad_waves<SOLVER, T, U, ADJ>())) void k_curv_quads(const float* __restrict__ phi,
+                                                                                   const float* __restrict__ gkap,
+                                                                                   float* __restrict__ kappa,
+                                                                                   Workspace ws, int X, int Y, int Z,
+                                                                                   int ntx, int nty) {
     constexpr int COLS = 10;                                 // 2 passes; 25 KiB of LDS with an FP64 fit
     __shared__ float nbh[kQuads][27];
     __shared__ QuadLds<F, COLS> qlds[kQuads];
@@ -1048,7 +1164,13 @@ __global__ __launch_bounds__(kThreads, (quad_waves<T, U>())) void k_curv_quads(c
             const int b = __ffs(static_cast<int>(static_cast<unsigned>(__ballot(hit) >> half))) - 1;
             cl[r] = w * 32 + b;
         }
-        if (i0 + (grp & 1) >= n) continue;                   // uniform per group
+        const unsigned ic = i0 + (grp & 1);
+        if (ic >= n) continue;                               // uniform per group
+        unsigned row = 0u;
+        if constexpr (ADJ) {
+            row = ws.cbase[tile] + ic;
+            if (row >= ws.rows) continue;                    // uniform per group; the gather recomputes
+        }
         const int c = (grp & 1) ? cl[1] : cl[0];
         const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
         const int gx = x0 + c % TX, gy = y0 + (c / TX) % TY, gz = z0 + c / (TX * TY);
@@ -1058,8 +1180,15 @@ __global__ __launch_bounds__(kThreads, (quad_waves<T, U>())) void k_curv_quads(c
                               ? phi[(static_cast<int64_t>(az) * Y + ay) * X + ax] : 0.0f;
         }
         __syncwarp();
-        const float kv = quad_cell<SOLVER, T, U, F, NRM, COLS>(nbh[grp], j, lane, qlds[grp]);
-        if (j == 0) kappa[(static_cast<int64_t>(gz) * Y + gy) * X + gx] = kv;
+        const int64_t gi = (static_cast<int64_t>(gz) * Y + gy) * X + gx;
+        if constexpr (ADJ) {
+            quad_cell<SOLVER, T, U, F, true, NRM, COLS>(nbh[grp], 13, 3, 9, j, lane, gkap[gi],
+                                                        ws.contrib + static_cast<size_t>(row) * 27, qlds[grp]);
+        } else {
+            const float kv = quad_cell<SOLVER, T, U, F, false, NRM, COLS>(nbh[grp], 13, 3, 9, j, lane, 0.0f, nullptr,
+                                                                          qlds[grp]);
+            if (j == 0) kappa[gi] = kv;
+        }
         __syncwarp();                                        // nbh and qlds reused by the next pair
     }
 }
@@ -1104,8 +1233,8 @@ __global__ __launch_bounds__(kThreads) void k_curv_gather_fallback(const float* 
     __shared__ float contrib[kChunk][27];
     __shared__ unsigned crow[kChunk];
     __shared__ int wcount[kThreads / 64];
-    __shared__ GroupLds<F> glds[kGroups];
-    const int tid = threadIdx.x, grp = tid / kGroup, j = tid % kGroup;
+    __shared__ QuadLds<F, 10> qlds[kQuads];
+    const int tid = threadIdx.x, grp = tid / kQuad, j = tid % kQuad;
     for (int i = tid; i < C_REGION; i += kThreads) slot[i] = kNoSlot;
     const unsigned ntl = *static_cast<volatile unsigned*>(ws.counter + 2);
     for (unsigned it = blockIdx.x; it < ntl; it += gridDim.x) {
@@ -1151,14 +1280,14 @@ __global__ __launch_bounds__(kThreads) void k_curv_gather_fallback(const float* 
             }
             {
                 // rows that did not fit: recomputed, one group of lanes per cell
-                for (int i = grp; i < nc; i += kGroups) {
+                for (int i = grp; i < nc; i += kQuads) {
                     if (crow[i] < ws.rows) continue;                     // uniform per group
                     const int ci = cand[c0 + i];
                     const int lx = ci % C_RX, ly = (ci / C_RX) % C_RY, lz = ci / (C_RX * C_RY);
                     const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
                     const float gk = gkap[(static_cast<int64_t>(gz) * Y + gy) * X + gx];
-                    group_cell<SOLVER, T, U, F, true, NRM, false, 20>(s, ((lz + 1) * RY + (ly + 1)) * RX + (lx + 1),
-                                                                  RX, RX * RY, j, gk, contrib[i], glds[grp]);
+                    quad_cell<SOLVER, T, U, F, true, NRM, 10>(s, ((lz + 1) * RY + (ly + 1)) * RX + (lx + 1), RX,
+                                                              RX * RY, j, tid & 63, gk, contrib[i], qlds[grp]);
                 }
             }
             __syncthreads();
@@ -1627,10 +1756,12 @@ void launch_items(const float* phi, const float* gk, float* kappa, Workspace ws,
                        g.ntx, g.nty);
 }
 
-template <int SOLVER, class T, class U, class F, int NRM>
-void launch_quads(const float* phi, float* kappa, Workspace ws, int X, int Y, int Z, const Grid& g, hipStream_t st) {
+template <int SOLVER, class T, class U, class F, bool ADJ, int NRM>
+void launch_quads(const float* phi, const float* gk, float* kappa, Workspace ws, int X, int Y, int Z, const Grid& g,
+                  hipStream_t st) {
     const dim3 grid(persistent_grid(static_cast<int64_t>(g.ntiles) * kMaxParts)), block(kThreads);
-    hipLaunchKernelGGL((k_curv_quads<SOLVER, T, U, F, NRM>), grid, block, 0, st, phi, kappa, ws, X, Y, Z, g.ntx, g.nty);
+    hipLaunchKernelGGL((k_curv_quads<SOLVER, T, U, F, ADJ, NRM>), grid, block, 0, st, phi, gk, kappa, ws, X, Y, Z,
+                       g.ntx, g.nty);
 }
 
 // forward: precision picks the types, then the normal and the variant
@@ -1639,10 +1770,10 @@ void launch_fwd_t(int normal, bool nbr, const float* phi, float* kappa, Workspac
                   const Grid& g, hipStream_t st) {
     if (normal == kNormalCM) {
         if (nbr) launch_items<SOLVER, T, U, F, false, kNormalCM, true>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
-        else launch_quads<SOLVER, T, U, F, kNormalCM>(phi, kappa, ws, X, Y, Z, g, st);
+        else launch_quads<SOLVER, T, U, F, false, kNormalCM>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
     } else {
         if (nbr) launch_items<SOLVER, T, U, F, false, kNormalPY, true>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
-        else launch_quads<SOLVER, T, U, F, kNormalPY>(phi, kappa, ws, X, Y, Z, g, st);
+        else launch_quads<SOLVER, T, U, F, false, kNormalPY>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
     }
 }
 
@@ -1675,7 +1806,7 @@ template <int SOLVER, class T, class U, class F, int NRM>
 void launch_bwd_t(const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y, int Z,
                   const Grid& g, bool zfill, hipStream_t st) {
     launch_rows(ws, g, st);
-    if (ws.rows > 0) launch_items<SOLVER, T, U, F, true, NRM, false>(phi, gk, nullptr, ws, X, Y, Z, g, st);
+    if (ws.rows > 0) launch_quads<SOLVER, T, U, F, true, NRM>(phi, gk, nullptr, ws, X, Y, Z, g, st);
     launch_gather<false, 0>(gp, ws, X, Y, Z, g, zfill, st);
     // usually empty.  Its registers and LDS allow one workgroup per CU, so a
     // grid of one per CU (256) runs in a single round, cheap when nothing

@@ -187,7 +187,7 @@ def test_traffic_profile_lists_the_dispatches_that_ran(tmp_path):
     others."""
     log2n, n, lat = 10, 1 << 10, 8
     kib = 4 * n / 1024
-    items = "void plic::(anonymous namespace)::k_curv_items<0, float, double, double, true, 0, false>(...)"
+    items = "void plic::(anonymous namespace)::k_curv_quads<0, float, double, double, true, 0>(...)"
     gather = "void plic::(anonymous namespace)::k_curv_gather_direct<false, 0, true>(...)"
     fetch = [("__amd_rocclr_copyBuffer", kib), (items, 1.0), (gather, 2.0)]
     write = [("__amd_rocclr_copyBuffer", kib), (items, 3.0), (gather, 4.0)]
@@ -198,6 +198,6 @@ def test_traffic_profile_lists_the_dispatches_that_ran(tmp_path):
     bench.write_traffic_profile(str(fc), str(wc), log2n, lat, str(out))
     rows = {line.split("|")[1].strip(): line for line in out.read_text().splitlines() if line.startswith("| ")}
     cells = [c.strip() for c in rows["curvature_bwd"].split("|")]
-    assert "k_curv_scan" not in cells[2] and "k_curv_items" in cells[2] and "k_curv_gather_direct" in cells[2]
+    assert "k_curv_scan" not in cells[2] and "k_curv_quads" in cells[2] and "k_curv_gather_direct" in cells[2]
     assert int(cells[3].replace(",", "")) == 1024 * (1 + 2 + 3 + 4)          # copy factors are 1
     assert float(cells[6].replace(",", "")) == 8 * lat ** 3                  # 8 B per cell

@@ -195,3 +195,31 @@ def test_forward_status_and_count(P, precision):
         assert all(np.array_equal(outs[0], o) for o in outs[1:])
         if cells == 0:
             assert np.all(outs[0] == 0.0)
+
+
+def test_vanishing_gradient_cells(P, orc):
+    """Interface cells whose 26 neighbours all hold the same fill level have a
+    zero fill-level gradient, hence no normal: kappa = 0 there (the oracle's
+    rule |g| < 1e-12), and they pass nothing back in any backward (every
+    variant, the reusing one included) even with a unit upstream gradient."""
+    N = 24
+    phi = np.zeros((N, N, N), np.float32)
+    phi[6:18, 6:18, 6:18] = 0.5
+    inner = np.zeros_like(phi, dtype=bool)
+    inner[7:17, 7:17, 7:17] = True
+    for precision in PRECISIONS:
+        k = gpu_kappa(P, phi, "analytic", precision)
+        assert np.all(k[inner] == 0.0)
+        check_cells(orc, phi, k, precision, f"flat block {precision}")
+    t = dev(phi)
+    gk = torch.from_numpy(inner.astype(np.float32)).cuda()
+    for normal, nbr in (("py", False), ("cm", False), ("py", True)):
+        g = torch.full_like(t, float("nan"))
+        P.plic_curvature_backward_ex_f32(t, gk, g, "analytic", "mixed", normal, nbr)
+        assert int(torch.count_nonzero(g).item()) == 0, (normal, nbr)
+    ws = torch.empty(P.plic_curvature_workspace_bytes(N, N, N), dtype=torch.uint8, device="cuda")
+    kap = torch.empty_like(t)
+    P.plic_curvature_f32(t, kap, "analytic", "mixed", ws)
+    g = torch.full_like(t, float("nan"))
+    P.plic_curvature_backward_reuse_f32(t, gk, g, "analytic", "mixed", "py", False, ws)
+    assert int(torch.count_nonzero(g).item()) == 0

@@ -170,18 +170,19 @@ __device__ __forceinline__ void group_colsum(GroupLds<F, COLS>& L, int j, const 
 __host__ __device__ constexpr int tri(int i, int k) { return i * (i + 1) / 2 + k; }
 
 // ---------------------------------------------------------------------------
-// One interface cell on a group of 32 lanes.  s: LDS fill levels, c: centre
-// index, sy/sz: LDS strides, j: lane in the group (0..31).  Lane j < 26 owns
-// neighbour q(j) (the 26 offsets other than the centre), lane 26 the centre.
-// Every lane of the group must call it.  Returns kappa (same bits on every
-// lane).  With ADJ, also writes out[q] = gk * d kappa / d phi_q (q = 0..26)
-// from the lane that owns q, with the interface mask, the PLIC cases and the
-// active fit parameters held fixed.  With NBR (neighbour normals: each
-// interface neighbour's point from its own normal m = -h / |h|, h its 3^3
-// fill-level gradient), out[q] holds the derivative with every m held fixed,
-// and lane j also writes out[27 + 3j .. 29 + 3j] = gk * d kappa / d h of its
-// neighbour (zero where the neighbour keeps the centre normal); spreading that
-// over the neighbour's 3^3 is left to the gathers.
+// One interface cell of the neighbour-normal variant on a group of 32 lanes
+// (each interface neighbour's point from its own normal m = -h / |h|, h its
+// 3^3 fill-level gradient; cells without neighbour normals run on 16 lanes,
+// quad_cell below).  s: LDS fill levels, c: centre index, sy/sz: LDS strides,
+// j: lane in the group (0..31).  Lane j < 26 owns neighbour q(j) (the 26
+// offsets other than the centre), lane 26 the centre.  Every lane of the
+// group must call it.  Returns kappa (same bits on every lane).  With ADJ,
+// also writes out[q] = gk * d kappa / d phi_q (q = 0..26) from the lane that
+// owns q, with the interface mask, the PLIC cases, the active fit parameters
+// and every m held fixed, and lane j writes out[27 + 3j .. 29 + 3j] =
+// gk * d kappa / d h of its neighbour (zero where the neighbour keeps the
+// centre normal); spreading that over the neighbour's 3^3 is left to the
+// gathers.
 // ---------------------------------------------------------------------------
 // weight of neighbour offset e in the fill-level gradient (App. B.1):
 // Parker-Youngs 4 / 2 / 1 for |e|^2 = 1 / 2 / 3, centre of mass 1
@@ -205,7 +206,7 @@ __device__ __forceinline__ void gradient27(const float* __restrict__ s, int c, i
     }
 }
 
-template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR, int COLS>
+template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, int COLS>
 __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, int sy, int sz, int j,
                                             float gk, float* __restrict__ out, GroupLds<F, COLS>& L,
                                             int gx0 = 0, int gy0 = 0, int gz0 = 0, int X = 0, int Y = 0,
@@ -231,9 +232,7 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
         if constexpr (ADJ) {
             if (nbr) out[q] = 0.0f;
             if (centre) out[13] = 0.0f;
-            if constexpr (NBR) {
-                if (nbr) out[27 + 3 * j] = out[28 + 3 * j] = out[29 + 3 * j] = 0.0f;
-            }
+            if (nbr) out[27 + 3 * j] = out[28 + 3 * j] = out[29 + 3 * j] = 0.0f;
         }
         return 0.0f;
     }
@@ -258,7 +257,7 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
     T m0 = n0, m1 = n1, m2 = n2;
     bool own = false;                             // this lane's point uses its own normal
     T ihq = T(0);                                 // 1 / |h| of that normal's gradient
-    if constexpr (NBR) {
+    {
         // the neighbour's own 3^3 neighbourhood lies in the lattice
         const int ax = gx0 + dx, ay = gy0 + dy, az = gz0 + dz;
         const bool inside = ax >= 1 && ay >= 1 && az >= 1 && ax <= X - 2 && ay <= Y - 2 && az <= Z - 2;
@@ -282,19 +281,13 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
     // this lane's point (coordinate transformation of Sec. 4.2) and its row of
     // the normal equations: Q Q^T (lower triangle) and z Q
     F x = F(0), y = F(0), z = F(0);
-    T P0 = T(0), P1 = T(0), P2 = T(0);            // neighbour-normal variant: the point before the frame
+    T P0 = T(0), P1 = T(0), P2 = T(0);            // the point before the frame
     if (iface) {
-        if constexpr (NBR) {
-            // foot of the neighbour's own plane, e + D n_q - D0 n, in the frame
-            P0 = ex + D * m0 - D0 * n0; P1 = ey + D * m1 - D0 * n1; P2 = ez + D * m2 - D0 * n2;
-            x = F(P0 * bx0 + P1 * bx1 + P2 * bx2);
-            y = F(P0 * by0 + P1 * by1 + P2 * by2);
-            z = F(P0 * n0 + P1 * n1 + P2 * n2);
-        } else {
-            x = F(ex * bx0 + ey * bx1 + ez * bx2);
-            y = F(ex * by0 + ey * by1 + ez * by2);
-            z = F(ex * n0 + ey * n1 + ez * n2 + (D - D0));
-        }
+        // foot of the neighbour's own plane, e + D n_q - D0 n, in the frame
+        P0 = ex + D * m0 - D0 * n0; P1 = ey + D * m1 - D0 * n1; P2 = ez + D * m2 - D0 * n2;
+        x = F(P0 * bx0 + P1 * bx1 + P2 * bx2);
+        y = F(P0 * by0 + P1 * by1 + P2 * by2);
+        z = F(P0 * n0 + P1 * n1 + P2 * n2);
     }
     const F Q[5] = {x * x, y * y, x * y, x, y};
     F row[20], sum[20];
@@ -350,37 +343,27 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
             const T xb = T(F(2) * x * Qb[0] + y * Qb[2] + Qb[3]);
             const T yb = T(F(2) * y * Qb[1] + x * Qb[2] + Qb[4]);
             const T zt = T(zb);
-            if constexpr (NBR) {
-                // x = P.b_x, y = P.b_y, z = P.n with P = e + D m - D0 n, D = d0(phi_q, m)
-                const T Pb0 = xb * bx0 + yb * by0 + zt * n0;
-                const T Pb1 = xb * bx1 + yb * by1 + zt * n1;
-                const T Pb2 = xb * bx2 + yb * by2 + zt * n2;
-                T cq[3];
-                const T dv = offset_grad_from_d0<T>(m0, m1, m2, T(p), D, cq);   // 1/A, centroid for m
-                const T Db = Pb0 * m0 + Pb1 * m1 + Pb2 * m2;
-                const T mb0 = D * Pb0 + Db * cq[0], mb1 = D * Pb1 + Db * cq[1], mb2 = D * Pb2 + Db * cq[2];
-                phib = Db * dv;
-                arow[0] = F(xb * P0); arow[1] = F(xb * P1); arow[2] = F(xb * P2);
-                arow[3] = F(yb * P0); arow[4] = F(yb * P1); arow[5] = F(yb * P2);
-                // n enters through z = P.n, through -D0 n in P, and as m where the lane keeps it
-                arow[6] = F(zt * P0 - D0 * Pb0 + (own ? T(0) : mb0));
-                arow[7] = F(zt * P1 - D0 * Pb1 + (own ? T(0) : mb1));
-                arow[8] = F(zt * P2 - D0 * Pb2 + (own ? T(0) : mb2));
-                arow[9] = F(zt);
-                if (own) {                                   // m = -h / |h|: the adjoint of h
-                    const T md = m0 * mb0 + m1 * mb1 + m2 * mb2;
-                    hb0 = -(mb0 - m0 * md) * ihq;
-                    hb1 = -(mb1 - m1 * md) * ihq;
-                    hb2 = -(mb2 - m2 * md) * ihq;
-                }
-            } else {
-                T cq[3];
-                const T dv = offset_grad_from_d0<T>(n0, n1, n2, T(p), D, cq);   // 1/A, centroid
-                phib = zt * dv;
-                arow[0] = F(xb * ex); arow[1] = F(xb * ey); arow[2] = F(xb * ez);
-                arow[3] = F(yb * ex); arow[4] = F(yb * ey); arow[5] = F(yb * ez);
-                arow[6] = F(zt * (ex + cq[0])); arow[7] = F(zt * (ey + cq[1])); arow[8] = F(zt * (ez + cq[2]));
-                arow[9] = F(zt);
+            // x = P.b_x, y = P.b_y, z = P.n with P = e + D m - D0 n, D = d0(phi_q, m)
+            const T Pb0 = xb * bx0 + yb * by0 + zt * n0;
+            const T Pb1 = xb * bx1 + yb * by1 + zt * n1;
+            const T Pb2 = xb * bx2 + yb * by2 + zt * n2;
+            T cq[3];
+            const T dv = offset_grad_from_d0<T>(m0, m1, m2, T(p), D, cq);   // 1/A, centroid for m
+            const T Db = Pb0 * m0 + Pb1 * m1 + Pb2 * m2;
+            const T mb0 = D * Pb0 + Db * cq[0], mb1 = D * Pb1 + Db * cq[1], mb2 = D * Pb2 + Db * cq[2];
+            phib = Db * dv;
+            arow[0] = F(xb * P0); arow[1] = F(xb * P1); arow[2] = F(xb * P2);
+            arow[3] = F(yb * P0); arow[4] = F(yb * P1); arow[5] = F(yb * P2);
+            // n enters through z = P.n, through -D0 n in P, and as m where the lane keeps it
+            arow[6] = F(zt * P0 - D0 * Pb0 + (own ? T(0) : mb0));
+            arow[7] = F(zt * P1 - D0 * Pb1 + (own ? T(0) : mb1));
+            arow[8] = F(zt * P2 - D0 * Pb2 + (own ? T(0) : mb2));
+            arow[9] = F(zt);
+            if (own) {                                   // m = -h / |h|: the adjoint of h
+                const T md = m0 * mb0 + m1 * mb1 + m2 * mb2;
+                hb0 = -(mb0 - m0 * md) * ihq;
+                hb1 = -(mb1 - m1 * md) * ihq;
+                hb2 = -(mb2 - m2 * md) * ihq;
             }
         }
         T dvc = T(0);
@@ -414,14 +397,12 @@ __device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, 
         const T gb0 = -(nb0 - n0 * nd) * ign, gb1 = -(nb1 - n1 * nd) * ign, gb2 = -(nb2 - n2 * nd) * ign;
         if (nbr) out[q] = float(phib + w * (ex * gb0 + ey * gb1 + ez * gb2));
         if (centre) out[13] = float(-sz_ * dvc);
-        if constexpr (NBR) {
-            // the adjoint of neighbour q's own fill-level gradient, gathered later
-            // at that neighbour and spread over its 3^3 by the gradient's weights
-            if (nbr) {
-                out[27 + 3 * j] = float(hb0);
-                out[28 + 3 * j] = float(hb1);
-                out[29 + 3 * j] = float(hb2);
-            }
+        // the adjoint of neighbour q's own fill-level gradient, gathered later
+        // at that neighbour and spread over its 3^3 by the gradient's weights
+        if (nbr) {
+            out[27 + 3 * j] = float(hb0);
+            out[28 + 3 * j] = float(hb1);
+            out[29 + 3 * j] = float(hb2);
         }
         __syncwarp();                              // res is reused by the next cell
     }
@@ -1100,11 +1081,11 @@ __global__ __launch_bounds__(kThreads, (items_waves<T, U, ADJ>())) void k_curv_i
         const int64_t g = (static_cast<int64_t>(gz) * Y + gy) * X + gx;
         if constexpr (ADJ) {
             constexpr int ROWF = NBR ? kRowFloatsNbr : 27;
-            group_cell<SOLVER, T, U, F, true, NRM, NBR, COLS>(nbh[grp], C, W, W * W, j, gkap[g],
+            group_cell<SOLVER, T, U, F, true, NRM, COLS>(nbh[grp], C, W, W * W, j, gkap[g],
                                                         ws.contrib + static_cast<size_t>(row) * ROWF, glds[grp],
                                                         gx, gy, gz, X, Y, Z);
         } else {
-            const float kv = group_cell<SOLVER, T, U, F, false, NRM, NBR, COLS>(nbh[grp], C, W, W * W, j, 0.0f, nullptr,
+            const float kv = group_cell<SOLVER, T, U, F, false, NRM, COLS>(nbh[grp], C, W, W * W, j, 0.0f, nullptr,
                                                                          glds[grp], gx, gy, gz, X, Y, Z);
             if (j == 0) kappa[g] = kv;
         }

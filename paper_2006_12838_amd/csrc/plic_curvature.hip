@@ -537,6 +537,23 @@ __device__ __forceinline__ float quad_cell(const float* __restrict__ s, int c, i
     bool act[5];
     F a[5], dinv[5];
     ldlt_factor<F>(m, npts < 5 ? npts : 5, act, dinv);
+    // in mixed precision the adjoint's solve reads the factor back from LDS
+    // (the staging tile is free until the adjoint's own sums): the same values,
+    // and the registers that held them are free in between, so that adjoint
+    // fits 4 waves per SIMD (in FP32 and FP64 the occupancy does not change and
+    // the factor stays in registers)
+    constexpr bool FAC = ADJ && sizeof(T) == 4 && sizeof(F) == 8;
+    F* const fac = &L.stage[0][0];
+    if constexpr (FAC) {
+        if (j == 0) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+#pragma unroll
+                for (int k = 0; k < i; ++k) fac[tri(i, k)] = m[i][k];
+                fac[15 + i] = dinv[i];
+            }
+        }
+    }
     ldlt_solve<F>(m, act, dinv, b, a);
     const float kappa = float(kappa_of<F>(a));
     if constexpr (ADJ) {
@@ -555,7 +572,20 @@ __device__ __forceinline__ float quad_cell(const float* __restrict__ s, int c, i
 #pragma unroll
         for (int i = 0; i < 5; ++i) abar[i] = act[i] ? abar[i] : F(0);
         F lam[5];
-        ldlt_solve<F>(m, act, dinv, abar, lam);    // M symmetric: lambda = M^-1 abar
+        if constexpr (FAC) {
+            __syncwarp();
+            F lm[5][5], ld[5];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+#pragma unroll
+                for (int k = 0; k < i; ++k) lm[i][k] = fac[tri(i, k)];
+                lm[i][i] = F(0);                            // not read: the solve uses 1 / D
+                ld[i] = fac[15 + i];
+            }
+            ldlt_solve<F>(lm, act, ld, abar, lam);           // M symmetric: lambda = M^-1 abar
+        } else {
+            ldlt_solve<F>(m, act, dinv, abar, lam);
+        }
         // each slot's point: zbar = lam.Q, Qbar = lam (z - a.Q) - a (lam.Q); the
         // frame's adjoint rows of the two slots add up per lane
         T phia = T(0), phibb = T(0);
@@ -1100,14 +1130,13 @@ __global__ __launch_bounds__(kThreads, (items_waves<T, U, ADJ>())) void k_curv_i
 // quad_cell; the forward writes kappa, the backward (ADJ) the cell's
 // contribution row when it fits the workspace.
 // waves per SIMD, the most that compile without spilling: the forward 8
-// (FP64: 4); the adjoint, which keeps two points' state per lane, 4 in FP32,
-// 3 in mixed precision, in FP64 3 for the iterative solvers and 2 for the
+// (FP64: 4); the adjoint, which keeps two points' state per lane, 4 in FP32
+// and mixed precision, in FP64 3 for the iterative solvers and 2 for the
 // trigonometric ones
 template <int SOLVER, class T, class U, bool ADJ>
 constexpr int quad_waves() {
     if (!ADJ) return sizeof(T) == 4 ? 8 : 4;
-    if (sizeof(U) == 4) return 4;
-    if (sizeof(T) == 4) return 3;
+    if (sizeof(T) == 4) return 4;
     return (SOLVER == kNewton || SOLVER == kNested) ? 3 : 2;
 }
 

@@ -465,15 +465,54 @@ __device__ __forceinline__ void quad_point(int q, bool iface, T D, T D0, T bx0, 
     }
 }
 
+// neighbour-normal variant: the normal of slot q's plane, the neighbour's own
+// -h / |h| (h its 3^3 fill-level gradient) when it is an interface cell whose
+// 3^3 lies in the lattice and h does not vanish, else the centre normal that m
+// holds on entry (as in group_cell)
+template <int NRM, class T>
+__device__ __forceinline__ void own_normal(const float* __restrict__ s, int c, int sy, int sz, int q, bool iface,
+                                           int gx0, int gy0, int gz0, int X, int Y, int Z, T (&m)[3]) {
+    const int dx = q_dx(q), dy = q_dy(q), dz = q_dz(q);
+    const int ax = gx0 + dx, ay = gy0 + dy, az = gz0 + dz;
+    const bool inside = ax >= 1 && ay >= 1 && az >= 1 && ax <= X - 2 && ay <= Y - 2 && az <= Z - 2;
+    if (iface && inside) {
+        T hx, hy, hz;
+        gradient27<NRM, T>(s, c + dz * sz + dy * sy + dx, sy, sz, hx, hy, hz);
+        const T h2 = hx * hx + hy * hy + hz * hz;
+        if (h2 >= T(1e-24)) {
+            const T ih = M<T>::rcp(M<T>::sqrt(h2));
+            m[0] = -hx * ih; m[1] = -hy * ih; m[2] = -hz * ih;
+        }
+    }
+}
+
+// neighbour-normal variant: slot q's point, the foot of its own plane
+// e + D m - D0 n, in the frame (zero when q is not an interface neighbour)
+template <class T, class F>
+__device__ __forceinline__ void quad_point_own(int q, bool iface, T D, T D0, const T (&m)[3], T bx0, T bx1, T bx2,
+                                               T by0, T by1, T by2, T n0, T n1, T n2, F& x, F& y, F& z) {
+    x = F(0); y = F(0); z = F(0);
+    if (iface) {
+        const T P0 = T(q_dx(q)) + D * m[0] - D0 * n0, P1 = T(q_dy(q)) + D * m[1] - D0 * n1,
+                P2 = T(q_dz(q)) + D * m[2] - D0 * n2;
+        x = F(P0 * bx0 + P1 * bx1 + P2 * bx2);
+        y = F(P0 * by0 + P1 * by1 + P2 * by2);
+        z = F(P0 * n0 + P1 * n1 + P2 * n2);
+    }
+}
+
 // One interface cell on a group of 16 lanes.  s: LDS fill levels, c: centre
 // index, sy/sz: LDS strides, j: lane in the group (0..15), lane: lane in the
-// wavefront.  Every lane of the group must call it; returns kappa.  With ADJ,
+// wavefront.  NBR (forward only): each interface neighbour's point from its
+// own normal (gx0.. and X.. locate the cell in the lattice).  Every lane of the group must call it; returns kappa.  With ADJ,
 // also writes out[q] = gk * d kappa / d phi_q (q = 0..26) from the lane that
 // owns q, with the interface mask, the PLIC cases and the active fit
 // parameters held fixed (the adjoint of group_cell's, on two slots per lane).
-template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, int COLS>
+template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, int COLS, bool NBR = false>
 __device__ __forceinline__ float quad_cell(const float* __restrict__ s, int c, int sy, int sz, int j, int lane,
-                                           float gk, float* __restrict__ out, QuadLds<F, COLS>& L) {
+                                           float gk, float* __restrict__ out, QuadLds<F, COLS>& L, int gx0 = 0,
+                                           int gy0 = 0, int gz0 = 0, int X = 0, int Y = 0, int Z = 0) {
+    static_assert(!(ADJ && NBR), "the neighbour-normal adjoint runs on 32 lanes (group_cell)");
     using mt = M<T>;
     T gx, gy, gz;
     gradient27<NRM, T>(s, c, sy, sz, gx, gy, gz);
@@ -508,16 +547,30 @@ __device__ __forceinline__ float quad_cell(const float* __restrict__ s, int c, i
     const T iun = mt::rcp(mt::sqrt(un2));
     const T by0 = u0 * iun, by1 = u1 * iun, by2 = u2 * iun;
     const T bx0 = by1 * n2 - by2 * n1, bx1 = by2 * n0 - by0 * n2, bx2 = by0 * n1 - by1 * n0;
-    // PLIC offsets of the two slots with the centre normal
+    // PLIC offsets of the two slots with the centre normal (neighbour normals:
+    // each interface neighbour with its own)
     T Da = T(0), Db = T(0);
-    if (ia) Da = offset<SOLVER, T, U>(n0, n1, n2, T(pa));
-    if (ib || centre) Db = offset<SOLVER, T, U>(n0, n1, n2, T(pb));
-    if (centre) L.res[20] = F(Db);
-    __syncwarp();
-    const T D0 = T(L.res[20]);
     F xa, ya, za, xb, yb, zb;
-    quad_point<T, F>(qa, ia, Da, D0, bx0, bx1, bx2, by0, by1, by2, n0, n1, n2, xa, ya, za);
-    quad_point<T, F>(qb, ib, Db, D0, bx0, bx1, bx2, by0, by1, by2, n0, n1, n2, xb, yb, zb);
+    if constexpr (NBR) {
+        T ma[3] = {n0, n1, n2}, mb[3] = {n0, n1, n2};
+        own_normal<NRM, T>(s, c, sy, sz, qa, ia, gx0, gy0, gz0, X, Y, Z, ma);
+        own_normal<NRM, T>(s, c, sy, sz, qb, ib, gx0, gy0, gz0, X, Y, Z, mb);
+        if (ia) Da = offset<SOLVER, T, U>(ma[0], ma[1], ma[2], T(pa));
+        if (ib || centre) Db = offset<SOLVER, T, U>(mb[0], mb[1], mb[2], T(pb));
+        if (centre) L.res[20] = F(Db);
+        __syncwarp();
+        const T D0 = T(L.res[20]);
+        quad_point_own<T, F>(qa, ia, Da, D0, ma, bx0, bx1, bx2, by0, by1, by2, n0, n1, n2, xa, ya, za);
+        quad_point_own<T, F>(qb, ib, Db, D0, mb, bx0, bx1, bx2, by0, by1, by2, n0, n1, n2, xb, yb, zb);
+    } else {
+        if (ia) Da = offset<SOLVER, T, U>(n0, n1, n2, T(pa));
+        if (ib || centre) Db = offset<SOLVER, T, U>(n0, n1, n2, T(pb));
+        if (centre) L.res[20] = F(Db);
+        __syncwarp();
+        const T D0 = T(L.res[20]);
+        quad_point<T, F>(qa, ia, Da, D0, bx0, bx1, bx2, by0, by1, by2, n0, n1, n2, xa, ya, za);
+        quad_point<T, F>(qb, ib, Db, D0, bx0, bx1, bx2, by0, by1, by2, n0, n1, n2, xb, yb, zb);
+    }
     const F Qa[5] = {xa * xa, ya * ya, xa * ya, xa, ya}, Qb[5] = {xb * xb, yb * yb, xb * yb, xb, yb};
     F row[20], sum[20];
 #pragma unroll
@@ -1000,11 +1053,11 @@ __global__ __launch_bounds__(kThreads) void k_curv_prefix(Workspace ws, int ntil
 }
 
 // ---------------------------------------------------------------------------
-// 2. work items: up to kPartCells interface cells of a tile.  Without
-// neighbour normals a cell runs on a group of 16 lanes (k_curv_quads, above);
-// the neighbour-normal variant, whose cells need their 5x5x5 neighbourhood
-// (each neighbour's own 3x3x3), runs a cell on a group of 32 lanes
-// (k_curv_items).  The group finds its cell, the i-th interface cell of the
+// 2. work items: up to kPartCells interface cells of a tile.  A cell runs on a
+// group of 16 lanes (k_curv_quads, above), except in the neighbour-normal
+// adjoint, which runs a cell on a group of 32 lanes (k_curv_items); the
+// neighbour-normal variant stages each cell's 5x5x5 neighbourhood (each
+// neighbour's own 3x3x3).  The group finds its cell, the i-th interface cell of the
 // tile in cell order, from the tile's bitmask and prefix counts (two
 // ballots), stages the cell's fill levels in LDS, and runs the cell.  Groups
 // never wait for each other: no block barrier.  Forward: kappa.  Backward:
@@ -1044,19 +1097,14 @@ __device__ __forceinline__ int thread_index_per_iteration() {
     return t;
 }
 
-// Waves per SIMD the 32-lane work items (the neighbour-normal variant) are
+// Waves per SIMD the 32-lane work items (the neighbour-normal adjoint) are
 // compiled for: the work is a chain of dependent steps per cell, so
 // concurrency sets the time.  Each count is the largest that compiles without
-// spilling (VGPRs at most 64 for 8 waves, 80 for 6, 128 for 4, 168 for 3) and
-// that the LDS allows: the forward with an FP32 fit holds 21.5 KiB per
-// workgroup (7 waves, the 5x5x5 fill levels included), in mixed precision
-// 22.5 KiB with its halved FP64 staging tile (compiled for 6 waves), in FP64
-// 38.5 KiB (4); the adjoint fits 4 waves in FP32, 3 in mixed precision (its
-// PLIC points are FP32 with the FP64 island only near case boundaries) and 2
-// in FP64.
+// spilling (VGPRs at most 64 for 8 waves, 80 for 6, 128 for 4, 168 for 3):
+// 4 in FP32, 3 in mixed precision (its PLIC points are FP32 with the FP64
+// island only near case boundaries) and 2 in FP64.
 template <class T, class U, bool ADJ>
 constexpr int items_waves() {
-    if (!ADJ) return sizeof(U) == 4 ? 7 : (sizeof(T) == 4 ? 6 : 4);      // LDS, as above
     if (sizeof(U) == 4) return 4;                                         // FP32
     return sizeof(T) == 4 ? 3 : 2;                                        // mixed, FP64
 }
@@ -1066,12 +1114,9 @@ __global__ __launch_bounds__(kThreads, (items_waves<T, U, ADJ>())) void k_curv_i
                                                           const float* __restrict__ gkap,
                                                           float* __restrict__ kappa, Workspace ws, int X, int Y,
                                                           int Z, int ntx, int nty) {
-    static_assert(NBR, "cells without neighbour normals run on 16 lanes (k_curv_quads)");
-    constexpr int H = NBR ? 2 : 1, W = 2 * H + 1, NB = W * W * W, C = (H * W + H) * W + H;
-    // the mixed-precision forward stages its FP64 rows in two passes of 10
-    // columns: 19.5 KiB of LDS per workgroup instead of 36, so its registers
-    // (at most 80) set the occupancy, 6 waves per SIMD
-    constexpr int COLS = (!ADJ && sizeof(F) == 8 && sizeof(T) == 4) ? 10 : 20;
+    static_assert(ADJ && NBR, "the forward, and the adjoint without neighbour normals, run on 16 lanes (k_curv_quads)");
+    constexpr int H = 2, W = 2 * H + 1, NB = W * W * W, C = (H * W + H) * W + H;   // the 5x5x5 fill levels
+    constexpr int COLS = 20;
     __shared__ float nbh[kGroups][NB];
     __shared__ GroupLds<F, COLS> glds[kGroups];
     const unsigned nitems = *static_cast<volatile unsigned*>(ws.counter);
@@ -1081,11 +1126,8 @@ __global__ __launch_bounds__(kThreads, (items_waves<T, U, ADJ>())) void k_curv_i
         const unsigned e = ws.items[item];
         const int tile = static_cast<int>(e >> 7), part = static_cast<int>(e & 127u);
         const int i = part * kPartCells + grp;               // rank of this group's cell
-        unsigned row = 0u;
-        if constexpr (ADJ) {
-            row = ws.cbase[tile] + static_cast<unsigned>(i);
-            if (row >= ws.rows) continue;                    // uniform per group; the gather recomputes
-        }
+        const unsigned row = ws.cbase[tile] + static_cast<unsigned>(i);
+        if (row >= ws.rows) continue;                        // uniform per group; the gather then writes NaN on the band
         // tile_cell written out (through the call the mixed-precision adjoint
         // spills): lane j holds mask word j and the count of set bits before it
         const unsigned mw = ws.mask[tile * kWords + j], pw = ws.prefix[tile * kWords + j];
@@ -1109,16 +1151,9 @@ __global__ __launch_bounds__(kThreads, (items_waves<T, U, ADJ>())) void k_curv_i
         }
         __syncwarp();
         const int64_t g = (static_cast<int64_t>(gz) * Y + gy) * X + gx;
-        if constexpr (ADJ) {
-            constexpr int ROWF = NBR ? kRowFloatsNbr : 27;
-            group_cell<SOLVER, T, U, F, true, NRM, COLS>(nbh[grp], C, W, W * W, j, gkap[g],
-                                                        ws.contrib + static_cast<size_t>(row) * ROWF, glds[grp],
-                                                        gx, gy, gz, X, Y, Z);
-        } else {
-            const float kv = group_cell<SOLVER, T, U, F, false, NRM, COLS>(nbh[grp], C, W, W * W, j, 0.0f, nullptr,
-                                                                         glds[grp], gx, gy, gz, X, Y, Z);
-            if (j == 0) kappa[g] = kv;
-        }
+        group_cell<SOLVER, T, U, F, true, NRM, COLS>(nbh[grp], C, W, W * W, j, gkap[g],
+                                                     ws.contrib + static_cast<size_t>(row) * kRowFloatsNbr, glds[grp],
+                                                     gx, gy, gz, X, Y, Z);
         __syncwarp();                                        // nbh and glds reused by the next cell
     }
 }
@@ -1133,21 +1168,23 @@ __global__ __launch_bounds__(kThreads, (items_waves<T, U, ADJ>())) void k_curv_i
 // (FP64: 4); the adjoint, which keeps two points' state per lane, 4 in FP32
 // and mixed precision, in FP64 3 for the iterative solvers and 2 for the
 // trigonometric ones
-template <int SOLVER, class T, class U, bool ADJ>
+template <int SOLVER, class T, class U, bool ADJ, bool NBR>
 constexpr int quad_waves() {
     if (!ADJ) return sizeof(T) == 4 ? 8 : 4;
     if (sizeof(T) == 4) return 4;
     return (SOLVER == kNewton || SOLVER == kNested) ? 3 : 2;
 }
 
-template <int SOLVER, class T, class U, class F, bool ADJ, int NRM>
-__global__ __launch_bounds__(kThreads, (quad_waves<SOLVER, T, U, ADJ>())) void k_curv_quads(const float* __restrict__ phi,
+template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
+__global__ __launch_bounds__(kThreads, (quad_waves<SOLVER, T, U, ADJ, NBR>())) void k_curv_quads(const float* __restrict__ phi,
                                                                                    const float* __restrict__ gkap,
                                                                                    float* __restrict__ kappa,
                                                                                    Workspace ws, int X, int Y, int Z,
                                                                                    int ntx, int nty) {
     constexpr int COLS = 10;                                 // 2 passes; 25 KiB of LDS with an FP64 fit
-    __shared__ float nbh[kQuads][27];
+    // the cell's 3x3x3 fill levels (5x5x5 with neighbour normals)
+    constexpr int H = NBR ? 2 : 1, W = 2 * H + 1, NB = W * W * W, C = (H * W + H) * W + H;
+    __shared__ float nbh[kQuads][NB];
     __shared__ QuadLds<F, COLS> qlds[kQuads];
     const unsigned nitems = *static_cast<volatile unsigned*>(ws.counter);
     const unsigned npairs = (nitems + 1u) / 2u;
@@ -1184,19 +1221,20 @@ __global__ __launch_bounds__(kThreads, (quad_waves<SOLVER, T, U, ADJ>())) void k
         const int c = (grp & 1) ? cl[1] : cl[0];
         const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
         const int gx = x0 + c % TX, gy = y0 + (c / TX) % TY, gz = z0 + c / (TX * TY);
-        for (int t = j; t < 27; t += kQuad) {
-            const int ax = gx + q_dx(t), ay = gy + q_dy(t), az = gz + q_dz(t);
+        for (int t = j; t < NB; t += kQuad) {
+            const int ax = gx + t % W - H, ay = gy + (t / W) % W - H, az = gz + t / (W * W) - H;
             nbh[grp][t] = (ax >= 0 && ax < X && ay >= 0 && ay < Y && az >= 0 && az < Z)
                               ? phi[(static_cast<int64_t>(az) * Y + ay) * X + ax] : 0.0f;
         }
         __syncwarp();
         const int64_t gi = (static_cast<int64_t>(gz) * Y + gy) * X + gx;
         if constexpr (ADJ) {
-            quad_cell<SOLVER, T, U, F, true, NRM, COLS>(nbh[grp], 13, 3, 9, j, lane, gkap[gi],
+            quad_cell<SOLVER, T, U, F, true, NRM, COLS>(nbh[grp], C, W, W * W, j, lane, gkap[gi],
                                                         ws.contrib + static_cast<size_t>(row) * 27, qlds[grp]);
         } else {
-            const float kv = quad_cell<SOLVER, T, U, F, false, NRM, COLS>(nbh[grp], 13, 3, 9, j, lane, 0.0f, nullptr,
-                                                                          qlds[grp]);
+            const float kv = quad_cell<SOLVER, T, U, F, false, NRM, COLS, NBR>(nbh[grp], C, W, W * W, j, lane, 0.0f,
+                                                                               nullptr, qlds[grp], gx, gy, gz, X, Y,
+                                                                               Z);
             if (j == 0) kappa[gi] = kv;
         }
         __syncwarp();                                        // nbh and qlds reused by the next pair
@@ -1766,11 +1804,11 @@ void launch_items(const float* phi, const float* gk, float* kappa, Workspace ws,
                        g.ntx, g.nty);
 }
 
-template <int SOLVER, class T, class U, class F, bool ADJ, int NRM>
+template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR = false>
 void launch_quads(const float* phi, const float* gk, float* kappa, Workspace ws, int X, int Y, int Z, const Grid& g,
                   hipStream_t st) {
     const dim3 grid(persistent_grid(static_cast<int64_t>(g.ntiles) * kMaxParts)), block(kThreads);
-    hipLaunchKernelGGL((k_curv_quads<SOLVER, T, U, F, ADJ, NRM>), grid, block, 0, st, phi, gk, kappa, ws, X, Y, Z,
+    hipLaunchKernelGGL((k_curv_quads<SOLVER, T, U, F, ADJ, NRM, NBR>), grid, block, 0, st, phi, gk, kappa, ws, X, Y, Z,
                        g.ntx, g.nty);
 }
 
@@ -1779,10 +1817,10 @@ template <int SOLVER, class T, class U, class F>
 void launch_fwd_t(int normal, bool nbr, const float* phi, float* kappa, Workspace ws, int X, int Y, int Z,
                   const Grid& g, hipStream_t st) {
     if (normal == kNormalCM) {
-        if (nbr) launch_items<SOLVER, T, U, F, false, kNormalCM, true>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
+        if (nbr) launch_quads<SOLVER, T, U, F, false, kNormalCM, true>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
         else launch_quads<SOLVER, T, U, F, false, kNormalCM>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
     } else {
-        if (nbr) launch_items<SOLVER, T, U, F, false, kNormalPY, true>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
+        if (nbr) launch_quads<SOLVER, T, U, F, false, kNormalPY, true>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
         else launch_quads<SOLVER, T, U, F, false, kNormalPY>(phi, nullptr, kappa, ws, X, Y, Z, g, st);
     }
 }

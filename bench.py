@@ -203,8 +203,8 @@ PMC_DISPATCHES = {
     "offset_nested": ("k_offset<3, float, float, float, 4,",),
     "volume": ("k_volume<float, float, 4>",),
     "offset_backward_sz": ("k_offset_bwd<1, float, float, float, 4,",),
-    "curvature_fwd": ("k_curv_scan<true, true>", "k_curv_quads<0, float, double, double, false, 0>"),
-    "curvature_bwd": ("k_curv_scan<true, false>", "k_curv_quads<0, float, double, double, true, 0>",
+    "curvature_fwd": ("k_curv_scan<true, true>", "k_curv_quads<0, float, double, double, false, 0, false>"),
+    "curvature_bwd": ("k_curv_scan<true, false>", "k_curv_quads<0, float, double, double, true, 0, false>",
                       "k_curv_dilate", "k_curv_prefix", "k_curv_gather_direct",
                       "k_curv_gather_fallback<0, float, double, double, 0>"),
     "copy": ("__amd_rocclr_copyBuffer",),
@@ -432,7 +432,7 @@ def write_trace_profile(trace_csv, out=None):
         "",
         "Template arguments: `k_offset<solver, storage, bulk, cubic, problems per lane, whole blocks>`, "
         "`k_curv_items<solver, points, cubic, fit, backward, normal, neighbour normals>`, "
-        "`k_curv_quads<solver, points, cubic, fit, backward, normal>` (16 lanes per cell), "
+        "`k_curv_quads<solver, points, cubic, fit, backward, normal, neighbour normals>` (16 lanes per cell), "
         "`k_curv_gather_fallback<solver, points, cubic, fit, normal>`, "
         "`k_curv_gather_direct<neighbour normals, normal, writes the zeros>`; solver 0 analytic, 1 optimized SZ, "
         "2 Newton-Raphson, 3 nested intervals, 4 Kawano's SZ; normal 0 Parker-Youngs.",

@@ -187,7 +187,7 @@ def test_traffic_profile_lists_the_dispatches_that_ran(tmp_path):
     others."""
     log2n, n, lat = 10, 1 << 10, 8
     kib = 4 * n / 1024
-    items = "void plic::(anonymous namespace)::k_curv_quads<0, float, double, double, true, 0>(...)"
+    items = "void plic::(anonymous namespace)::k_curv_quads<0, float, double, double, true, 0, false>(...)"
     gather = "void plic::(anonymous namespace)::k_curv_gather_direct<false, 0, true>(...)"
     fetch = [("__amd_rocclr_copyBuffer", kib), (items, 1.0), (gather, 2.0)]
     write = [("__amd_rocclr_copyBuffer", kib), (items, 3.0), (gather, 4.0)]

@@ -11,12 +11,12 @@
 //     lists one work item per 8 interface cells of each tile; the backward
 //     also records each tile's interface count;
 //  3. a persistent kernel over the work list in which each interface cell is
-//     computed by a group of 32 lanes: the group finds its cell from the
-//     bitmask, stages its neighbourhood in LDS, and lane j takes neighbour j
-//     of the 3x3x3 neighbourhood (its PLIC offset, its row of the normal
-//     equations), lane 26 the centre.  Sums over the neighbours go through a
-//     small LDS tile and are added in a fixed order, so results are bitwise
-//     reproducible.
+//     computed by a group of 16 lanes: the group finds its cell from the
+//     bitmask, stages its neighbourhood in LDS, and lane j takes slots j and
+//     j + 16 of the 3x3x3 neighbourhood (their PLIC offsets and rows of the
+//     normal equations; slot 26 is the centre).  Sums over the neighbours go
+//     through a small LDS tile and are added in a fixed order, so results are
+//     bitwise reproducible.
 // The backward first assigns contribution rows by a prefix over the tiles'
 // interface counts in tile order and lists the tiles next to the interface;
 // the work items store each interface cell's 27 contributions in its row; a
@@ -129,61 +129,9 @@ __device__ __forceinline__ F kappa_of(const F (&a)[5]) {
     return -(A * (I * I + F(1)) + B * (H * H + F(1)) - C * H * I) / (w * M<F>::sqrt(w));
 }
 
-// ---------------------------------------------------------------------------
-// Per-group LDS scratch.  Reductions over the 26 neighbour lanes go through a
-// [26][COLS] staging tile: every lane writes its row, lane k sums column k in
-// the fixed order l = 0..25 (so every call gives the same bits), lanes read
-// the column sums back; a row wider than the tile goes through it in passes
-// of COLS columns (the same sums, the same bits).
-// ---------------------------------------------------------------------------
-template <class F, int COLS = 20>
-struct alignas(16) GroupLds {
-    F stage[26][COLS];
-    F res[32];
-};
-
-template <class F, int NV, int COLS>
-__device__ __forceinline__ void group_colsum(GroupLds<F, COLS>& L, int j, const F (&row)[NV], F (&sum)[NV]) {
-#pragma unroll
-    for (int c0 = 0; c0 < NV; c0 += COLS) {
-        constexpr int W = COLS;
-        if (j < 26) {
-#pragma unroll
-            for (int k = 0; k < W; ++k)
-                if (c0 + k < NV) L.stage[j][k] = row[c0 + k];
-        }
-        __syncwarp();
-        if (j < W && c0 + j < NV) {
-            F acc = F(0);
-#pragma unroll
-            for (int l = 0; l < 26; ++l) acc += L.stage[l][j];
-            L.res[c0 + j] = acc;
-        }
-        __syncwarp();
-    }
-#pragma unroll
-    for (int k = 0; k < NV; ++k) sum[k] = L.res[k];
-    __syncwarp();
-}
-
 // lower-triangle index of the 5x5 normal matrix
 __host__ __device__ constexpr int tri(int i, int k) { return i * (i + 1) / 2 + k; }
 
-// ---------------------------------------------------------------------------
-// One interface cell of the neighbour-normal variant on a group of 32 lanes
-// (each interface neighbour's point from its own normal m = -h / |h|, h its
-// 3^3 fill-level gradient; cells without neighbour normals run on 16 lanes,
-// quad_cell below).  s: LDS fill levels, c: centre index, sy/sz: LDS strides,
-// j: lane in the group (0..31).  Lane j < 26 owns neighbour q(j) (the 26
-// offsets other than the centre), lane 26 the centre.  Every lane of the
-// group must call it.  Returns kappa (same bits on every lane).  With ADJ,
-// also writes out[q] = gk * d kappa / d phi_q (q = 0..26) from the lane that
-// owns q, with the interface mask, the PLIC cases, the active fit parameters
-// and every m held fixed, and lane j writes out[27 + 3j .. 29 + 3j] =
-// gk * d kappa / d h of its neighbour (zero where the neighbour keeps the
-// centre normal); spreading that over the neighbour's 3^3 is left to the
-// gathers.
-// ---------------------------------------------------------------------------
 // weight of neighbour offset e in the fill-level gradient (App. B.1):
 // Parker-Youngs 4 / 2 / 1 for |e|^2 = 1 / 2 / 3, centre of mass 1
 template <int NRM>
@@ -206,218 +154,15 @@ __device__ __forceinline__ void gradient27(const float* __restrict__ s, int c, i
     }
 }
 
-template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, int COLS>
-__device__ __forceinline__ float group_cell(const float* __restrict__ s, int c, int sy, int sz, int j,
-                                            float gk, float* __restrict__ out, GroupLds<F, COLS>& L,
-                                            int gx0 = 0, int gy0 = 0, int gz0 = 0, int X = 0, int Y = 0,
-                                            int Z = 0) {
-    using mt = M<T>;
-    // fill-level gradient of the centre (App. B.1); every lane forms the same
-    // sum from the staged fill levels
-    T gx, gy, gz;
-    gradient27<NRM, T>(s, c, sy, sz, gx, gy, gz);
-    const bool nbr = j < 26;                      // lane owns neighbour q
-    const bool centre = j == 26;                  // lane owns the centre
-    const int q = nbr ? (j < 13 ? j : j + 1) : 13;
-    const int dx = nbr ? q_dx(q) : 0, dy = nbr ? q_dy(q) : 0, dz = nbr ? q_dz(q) : 0;
-    const float p = (nbr || centre) ? s[c + dz * sz + dy * sy + dx] : 0.0f;
-    const T ex = T(dx), ey = T(dy), ez = T(dz);
-    const int e2 = dx * dx + dy * dy + dz * dz;
-    const T w = nbr ? T(nrm_weight<NRM>(e2)) : T(0);
-    const bool iface = nbr && is_iface(p);
-    const unsigned long long bal = __ballot(iface);
-    const int npts = __popcll(bal & (0xffffffffull << (threadIdx.x & 32)));
-    const T gn2 = gx * gx + gy * gy + gz * gz;
-    if (!(gn2 >= T(1e-24))) {                     // no usable normal: kappa = 0
-        if constexpr (ADJ) {
-            if (nbr) out[q] = 0.0f;
-            if (centre) out[13] = 0.0f;
-            if (nbr) out[27 + 3 * j] = out[28 + 3 * j] = out[29 + 3 * j] = 0.0f;
-        }
-        return 0.0f;
-    }
-    const T ign = mt::rcp(mt::sqrt(gn2));
-    const T n0 = -gx * ign, n1 = -gy * ign, n2 = -gz * ign;
-    // local frame (Sec. 4.2): b_z = n, b_y = n x r / |n x r|, b_x = b_y x b_z
-    T r0 = T(kR0), r1 = T(kR1), r2 = T(kR2);
-    T u0 = n1 * r2 - n2 * r1, u1 = n2 * r0 - n0 * r2, u2 = n0 * r1 - n1 * r0;
-    T un2 = u0 * u0 + u1 * u1 + u2 * u2;
-    if (un2 < T(1e-12)) {                         // n parallel to r: use (r_y, r_z, r_x)
-        r0 = T(kR1); r1 = T(kR2); r2 = T(kR0);
-        u0 = n1 * r2 - n2 * r1; u1 = n2 * r0 - n0 * r2; u2 = n0 * r1 - n1 * r0;
-        un2 = u0 * u0 + u1 * u1 + u2 * u2;
-    }
-    const T iun = mt::rcp(mt::sqrt(un2));
-    const T by0 = u0 * iun, by1 = u1 * iun, by2 = u2 * iun;
-    const T bx0 = by1 * n2 - by2 * n1, bx1 = by2 * n0 - by0 * n2, bx2 = by0 * n1 - by1 * n0;
-    // PLIC offsets: neighbour lanes and the centre lane in parallel, with the
-    // centre normal (Sec. 4.2) or, in the neighbour-normal variant, each
-    // neighbour with its own normal (centre normal on the outer lattice layer
-    // or for a vanishing gradient)
-    T m0 = n0, m1 = n1, m2 = n2;
-    bool own = false;                             // this lane's point uses its own normal
-    T ihq = T(0);                                 // 1 / |h| of that normal's gradient
-    {
-        // the neighbour's own 3^3 neighbourhood lies in the lattice
-        const int ax = gx0 + dx, ay = gy0 + dy, az = gz0 + dz;
-        const bool inside = ax >= 1 && ay >= 1 && az >= 1 && ax <= X - 2 && ay <= Y - 2 && az <= Z - 2;
-        if (iface && inside) {
-            T hx, hy, hz;
-            gradient27<NRM, T>(s, c + dz * sz + dy * sy + dx, sy, sz, hx, hy, hz);
-            const T h2 = hx * hx + hy * hy + hz * hz;
-            if (h2 >= T(1e-24)) {
-                const T ih = mt::rcp(mt::sqrt(h2));
-                m0 = -hx * ih; m1 = -hy * ih; m2 = -hz * ih;
-                own = true;
-                ihq = ih;
-            }
-        }
-    }
-    T D = T(0);
-    if (iface || centre) D = offset<SOLVER, T, U>(m0, m1, m2, T(p));
-    if (centre) L.res[24] = F(D);
-    __syncwarp();
-    const T D0 = T(L.res[24]);
-    // this lane's point (coordinate transformation of Sec. 4.2) and its row of
-    // the normal equations: Q Q^T (lower triangle) and z Q
-    F x = F(0), y = F(0), z = F(0);
-    T P0 = T(0), P1 = T(0), P2 = T(0);            // the point before the frame
-    if (iface) {
-        // foot of the neighbour's own plane, e + D n_q - D0 n, in the frame
-        P0 = ex + D * m0 - D0 * n0; P1 = ey + D * m1 - D0 * n1; P2 = ez + D * m2 - D0 * n2;
-        x = F(P0 * bx0 + P1 * bx1 + P2 * bx2);
-        y = F(P0 * by0 + P1 * by1 + P2 * by2);
-        z = F(P0 * n0 + P1 * n1 + P2 * n2);
-    }
-    const F Q[5] = {x * x, y * y, x * y, x, y};
-    F row[20], sum[20];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-#pragma unroll
-        for (int k = 0; k <= i; ++k) row[tri(i, k)] = Q[i] * Q[k];
-        row[15 + i] = z * Q[i];
-    }
-    group_colsum<F, 20, COLS>(L, j, row, sum);
-    F m[5][5], b[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        b[i] = sum[15 + i];
-#pragma unroll
-        for (int k = 0; k <= i; ++k) m[i][k] = sum[tri(i, k)];
-    }
-    bool act[5];
-    F a[5], dinv[5];
-    ldlt_factor<F>(m, npts < 5 ? npts : 5, act, dinv);
-    ldlt_solve<F>(m, act, dinv, b, a);
-    const float kappa = float(kappa_of<F>(a));
-    if constexpr (ADJ) {
-        // d kappa / d(A,B,C,H,I), kappa = -(A(I^2+1) + B(H^2+1) - CHI) / W^(3/2)
-        const F A = a[0], B = a[1], C = a[2], H = a[3], I = a[4];
-        const F W = H * H + I * I + F(1);
-        const F iW32 = F(1) / (W * M<F>::sqrt(W));
-        const F num = A * (I * I + F(1)) + B * (H * H + F(1)) - C * H * I;
-        const F g = -F(gk);
-        F abar[5];
-        abar[0] = g * (I * I + F(1)) * iW32;
-        abar[1] = g * (H * H + F(1)) * iW32;
-        abar[2] = g * (-H * I) * iW32;
-        abar[3] = g * ((F(2) * B * H - C * I) * iW32 - F(3) * num * H * iW32 / W);
-        abar[4] = g * ((F(2) * A * I - C * H) * iW32 - F(3) * num * I * iW32 / W);
-#pragma unroll
-        for (int i = 0; i < 5; ++i) abar[i] = act[i] ? abar[i] : F(0);
-        F lam[5];
-        ldlt_solve<F>(m, act, dinv, abar, lam);    // M symmetric: lambda = M^-1 abar
-        // this lane's point: zbar = lam.Q, Qbar = lam (z - a.Q) - a (lam.Q)
-        T phib = T(0);
-        T hb0 = T(0), hb1 = T(0), hb2 = T(0);     // neighbour-normal variant: adjoint of this lane's h
-        F arow[10];
-#pragma unroll
-        for (int i = 0; i < 10; ++i) arow[i] = F(0);
-        if (iface) {
-            F zb = F(0), aQ = F(0);
-#pragma unroll
-            for (int i = 0; i < 5; ++i) { zb += lam[i] * Q[i]; aQ += a[i] * Q[i]; }
-            F Qb[5];
-#pragma unroll
-            for (int i = 0; i < 5; ++i) Qb[i] = lam[i] * (z - aQ) - a[i] * zb;
-            const T xb = T(F(2) * x * Qb[0] + y * Qb[2] + Qb[3]);
-            const T yb = T(F(2) * y * Qb[1] + x * Qb[2] + Qb[4]);
-            const T zt = T(zb);
-            // x = P.b_x, y = P.b_y, z = P.n with P = e + D m - D0 n, D = d0(phi_q, m)
-            const T Pb0 = xb * bx0 + yb * by0 + zt * n0;
-            const T Pb1 = xb * bx1 + yb * by1 + zt * n1;
-            const T Pb2 = xb * bx2 + yb * by2 + zt * n2;
-            T cq[3];
-            const T dv = offset_grad_from_d0<T>(m0, m1, m2, T(p), D, cq);   // 1/A, centroid for m
-            const T Db = Pb0 * m0 + Pb1 * m1 + Pb2 * m2;
-            const T mb0 = D * Pb0 + Db * cq[0], mb1 = D * Pb1 + Db * cq[1], mb2 = D * Pb2 + Db * cq[2];
-            phib = Db * dv;
-            arow[0] = F(xb * P0); arow[1] = F(xb * P1); arow[2] = F(xb * P2);
-            arow[3] = F(yb * P0); arow[4] = F(yb * P1); arow[5] = F(yb * P2);
-            // n enters through z = P.n, through -D0 n in P, and as m where the lane keeps it
-            arow[6] = F(zt * P0 - D0 * Pb0 + (own ? T(0) : mb0));
-            arow[7] = F(zt * P1 - D0 * Pb1 + (own ? T(0) : mb1));
-            arow[8] = F(zt * P2 - D0 * Pb2 + (own ? T(0) : mb2));
-            arow[9] = F(zt);
-            if (own) {                                   // m = -h / |h|: the adjoint of h
-                const T md = m0 * mb0 + m1 * mb1 + m2 * mb2;
-                hb0 = -(mb0 - m0 * md) * ihq;
-                hb1 = -(mb1 - m1 * md) * ihq;
-                hb2 = -(mb2 - m2 * md) * ihq;
-            }
-        }
-        T dvc = T(0);
-        if (centre) {
-            T cc[3];
-            dvc = offset_grad_from_d0<T>(n0, n1, n2, T(p), D, cc);
-            L.res[25] = F(cc[0]); L.res[26] = F(cc[1]); L.res[27] = F(cc[2]);
-        }
-        F asum[10];
-        group_colsum<F, 10, COLS>(L, j, arow, asum);   // its barriers also publish res[25..27]
-        const T c00 = T(L.res[25]), c01 = T(L.res[26]), c02 = T(L.res[27]);
-        const T sbx0 = T(asum[0]), sbx1 = T(asum[1]), sbx2 = T(asum[2]);
-        const T sz_ = T(asum[9]);
-        // the centre offset D0 enters every z with a minus sign
-        T nb0 = T(asum[6]) - sz_ * c00, nb1 = T(asum[7]) - sz_ * c01, nb2 = T(asum[8]) - sz_ * c02;
-        // b_x = b_y x n
-        const T yb0 = T(asum[3]) + (n1 * sbx2 - n2 * sbx1);
-        const T yb1 = T(asum[4]) + (n2 * sbx0 - n0 * sbx2);
-        const T yb2 = T(asum[5]) + (n0 * sbx1 - n1 * sbx0);
-        nb0 += sbx1 * by2 - sbx2 * by1;
-        nb1 += sbx2 * by0 - sbx0 * by2;
-        nb2 += sbx0 * by1 - sbx1 * by0;
-        // b_y = u / |u|, u = n x r
-        const T bd = by0 * yb0 + by1 * yb1 + by2 * yb2;
-        const T ub0 = (yb0 - by0 * bd) * iun, ub1 = (yb1 - by1 * bd) * iun, ub2 = (yb2 - by2 * bd) * iun;
-        nb0 += r1 * ub2 - r2 * ub1;
-        nb1 += r2 * ub0 - r0 * ub2;
-        nb2 += r0 * ub1 - r1 * ub0;
-        // n = -g / |g|
-        const T nd = n0 * nb0 + n1 * nb1 + n2 * nb2;
-        const T gb0 = -(nb0 - n0 * nd) * ign, gb1 = -(nb1 - n1 * nd) * ign, gb2 = -(nb2 - n2 * nd) * ign;
-        if (nbr) out[q] = float(phib + w * (ex * gb0 + ey * gb1 + ez * gb2));
-        if (centre) out[13] = float(-sz_ * dvc);
-        // the adjoint of neighbour q's own fill-level gradient, gathered later
-        // at that neighbour and spread over its 3^3 by the gradient's weights
-        if (nbr) {
-            out[27 + 3 * j] = float(hb0);
-            out[28 + 3 * j] = float(hb1);
-            out[29 + 3 * j] = float(hb2);
-        }
-        __syncwarp();                              // res is reused by the next cell
-    }
-    return kappa;
-}
-
 // ---------------------------------------------------------------------------
-// The forward of one interface cell on a group of 16 lanes, four cells per
-// wavefront.  The normal, the frame, the fit and kappa are computed once per
-// group, so per cell they cost half of what they cost on 32 lanes; lane j
-// owns the points of slots j and j + 16 (slot s < 26: neighbour q(s), the 26
-// offsets other than the centre; slot 26: the centre), so each lane inverts at
-// most two PLIC problems.  The fit's sums run over the group's lanes in a
-// fixed order (each lane's two points first), so every call gives the same
-// bits.  s: the 3x3x3 fill levels in LDS, indexed by q.
+// One interface cell on a group of 16 lanes, four cells per wavefront.  The
+// normal, the frame, the fit and kappa are computed once per group (every
+// lane forms the same values), so per cell they cost half of what they would
+// on 32 lanes; lane j owns the points of slots j and j + 16 (slot s < 26:
+// neighbour q(s), the 26 offsets other than the centre; slot 26: the centre),
+// so each lane inverts at most two PLIC problems.  The fit's sums run over
+// the group's lanes in a fixed order (each lane's two points first), so every
+// call gives the same bits.
 // ---------------------------------------------------------------------------
 constexpr int kQuad = 16;                       // lanes per interface cell
 constexpr int kQuads = kThreads / kQuad;        // cells in flight per workgroup
@@ -468,10 +213,11 @@ __device__ __forceinline__ void quad_point(int q, bool iface, T D, T D0, T bx0, 
 // neighbour-normal variant: the normal of slot q's plane, the neighbour's own
 // -h / |h| (h its 3^3 fill-level gradient) when it is an interface cell whose
 // 3^3 lies in the lattice and h does not vanish, else the centre normal that m
-// holds on entry (as in group_cell)
+// holds on entry (the rule of the oracle's variant)
 template <int NRM, class T>
 __device__ __forceinline__ void own_normal(const float* __restrict__ s, int c, int sy, int sz, int q, bool iface,
-                                           int gx0, int gy0, int gz0, int X, int Y, int Z, T (&m)[3]) {
+                                           int gx0, int gy0, int gz0, int X, int Y, int Z, T (&m)[3], bool& own,
+                                           T& ih_out) {
     const int dx = q_dx(q), dy = q_dy(q), dz = q_dz(q);
     const int ax = gx0 + dx, ay = gy0 + dy, az = gz0 + dz;
     const bool inside = ax >= 1 && ay >= 1 && az >= 1 && ax <= X - 2 && ay <= Y - 2 && az <= Z - 2;
@@ -482,6 +228,8 @@ __device__ __forceinline__ void own_normal(const float* __restrict__ s, int c, i
         if (h2 >= T(1e-24)) {
             const T ih = M<T>::rcp(M<T>::sqrt(h2));
             m[0] = -hx * ih; m[1] = -hy * ih; m[2] = -hz * ih;
+            own = true;
+            ih_out = ih;
         }
     }
 }
@@ -501,18 +249,21 @@ __device__ __forceinline__ void quad_point_own(int q, bool iface, T D, T D0, con
     }
 }
 
-// One interface cell on a group of 16 lanes.  s: LDS fill levels, c: centre
-// index, sy/sz: LDS strides, j: lane in the group (0..15), lane: lane in the
-// wavefront.  NBR (forward only): each interface neighbour's point from its
-// own normal (gx0.. and X.. locate the cell in the lattice).  Every lane of the group must call it; returns kappa.  With ADJ,
-// also writes out[q] = gk * d kappa / d phi_q (q = 0..26) from the lane that
-// owns q, with the interface mask, the PLIC cases and the active fit
-// parameters held fixed (the adjoint of group_cell's, on two slots per lane).
+// s: LDS fill levels, c: centre index, sy/sz: LDS strides, j: lane in the
+// group (0..15), lane: lane in the wavefront.  Every lane of the group must
+// call it; returns kappa (same bits on every lane).  With ADJ, also writes
+// out[q] = gk * d kappa / d phi_q (q = 0..26) from the lane that owns q, with
+// the interface mask, the PLIC cases and the active fit parameters held
+// fixed.  With NBR (neighbour normals: each interface neighbour's point from
+// its own normal m = -h / |h|; gx0.. and X.. locate the cell in the lattice),
+// out[q] holds the derivative with every m held fixed, and the owner of slot t
+// also writes out[27 + 3t .. 29 + 3t] = gk * d kappa / d h of its neighbour
+// (zero where the neighbour keeps the centre normal); spreading that over the
+// neighbour's 3^3 is left to the gathers.
 template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, int COLS, bool NBR = false>
 __device__ __forceinline__ float quad_cell(const float* __restrict__ s, int c, int sy, int sz, int j, int lane,
                                            float gk, float* __restrict__ out, QuadLds<F, COLS>& L, int gx0 = 0,
                                            int gy0 = 0, int gz0 = 0, int X = 0, int Y = 0, int Z = 0) {
-    static_assert(!(ADJ && NBR), "the neighbour-normal adjoint runs on 32 lanes (group_cell)");
     using mt = M<T>;
     T gx, gy, gz;
     gradient27<NRM, T>(s, c, sy, sz, gx, gy, gz);
@@ -530,12 +281,16 @@ __device__ __forceinline__ float quad_cell(const float* __restrict__ s, int c, i
         if constexpr (ADJ) {
             out[qa] = 0.0f;
             if (nbb || centre) out[qb] = 0.0f;
+            if constexpr (NBR) {
+                out[27 + 3 * j] = out[28 + 3 * j] = out[29 + 3 * j] = 0.0f;
+                if (nbb) out[27 + 3 * sb] = out[28 + 3 * sb] = out[29 + 3 * sb] = 0.0f;
+            }
         }
         return 0.0f;
     }
     const T ign = mt::rcp(mt::sqrt(gn2));
     const T n0 = -gx * ign, n1 = -gy * ign, n2 = -gz * ign;
-    // local frame (Sec. 4.2), as in group_cell
+    // local frame (Sec. 4.2): b_z = n, b_y = n x r / |n x r|, b_x = b_y x b_z
     T r0 = T(kR0), r1 = T(kR1), r2 = T(kR2);
     T u0 = n1 * r2 - n2 * r1, u1 = n2 * r0 - n0 * r2, u2 = n0 * r1 - n1 * r0;
     T un2 = u0 * u0 + u1 * u1 + u2 * u2;
@@ -549,17 +304,19 @@ __device__ __forceinline__ float quad_cell(const float* __restrict__ s, int c, i
     const T bx0 = by1 * n2 - by2 * n1, bx1 = by2 * n0 - by0 * n2, bx2 = by0 * n1 - by1 * n0;
     // PLIC offsets of the two slots with the centre normal (neighbour normals:
     // each interface neighbour with its own)
-    T Da = T(0), Db = T(0);
+    T Da = T(0), Db = T(0), D0;
     F xa, ya, za, xb, yb, zb;
+    T ma[3] = {n0, n1, n2}, mb[3] = {n0, n1, n2};     // neighbour normals: each slot's plane normal
+    bool owna = false, ownb = false;                  // the slot's point uses its own normal
+    T iha = T(0), ihb = T(0);                         // 1 / |h| of that normal's gradient
     if constexpr (NBR) {
-        T ma[3] = {n0, n1, n2}, mb[3] = {n0, n1, n2};
-        own_normal<NRM, T>(s, c, sy, sz, qa, ia, gx0, gy0, gz0, X, Y, Z, ma);
-        own_normal<NRM, T>(s, c, sy, sz, qb, ib, gx0, gy0, gz0, X, Y, Z, mb);
+        own_normal<NRM, T>(s, c, sy, sz, qa, ia, gx0, gy0, gz0, X, Y, Z, ma, owna, iha);
+        own_normal<NRM, T>(s, c, sy, sz, qb, ib, gx0, gy0, gz0, X, Y, Z, mb, ownb, ihb);
         if (ia) Da = offset<SOLVER, T, U>(ma[0], ma[1], ma[2], T(pa));
         if (ib || centre) Db = offset<SOLVER, T, U>(mb[0], mb[1], mb[2], T(pb));
         if (centre) L.res[20] = F(Db);
         __syncwarp();
-        const T D0 = T(L.res[20]);
+        D0 = T(L.res[20]);
         quad_point_own<T, F>(qa, ia, Da, D0, ma, bx0, bx1, bx2, by0, by1, by2, n0, n1, n2, xa, ya, za);
         quad_point_own<T, F>(qb, ib, Db, D0, mb, bx0, bx1, bx2, by0, by1, by2, n0, n1, n2, xb, yb, zb);
     } else {
@@ -567,7 +324,7 @@ __device__ __forceinline__ float quad_cell(const float* __restrict__ s, int c, i
         if (ib || centre) Db = offset<SOLVER, T, U>(n0, n1, n2, T(pb));
         if (centre) L.res[20] = F(Db);
         __syncwarp();
-        const T D0 = T(L.res[20]);
+        D0 = T(L.res[20]);
         quad_point<T, F>(qa, ia, Da, D0, bx0, bx1, bx2, by0, by1, by2, n0, n1, n2, xa, ya, za);
         quad_point<T, F>(qb, ib, Db, D0, bx0, bx1, bx2, by0, by1, by2, n0, n1, n2, xb, yb, zb);
     }
@@ -610,7 +367,7 @@ __device__ __forceinline__ float quad_cell(const float* __restrict__ s, int c, i
     ldlt_solve<F>(m, act, dinv, b, a);
     const float kappa = float(kappa_of<F>(a));
     if constexpr (ADJ) {
-        // d kappa / d(A,B,C,H,I), as in group_cell
+        // d kappa / d(A,B,C,H,I), kappa = -(A(I^2+1) + B(H^2+1) - CHI) / W^(3/2)
         const F A = a[0], B = a[1], C = a[2], H = a[3], I = a[4];
         const F W = H * H + I * I + F(1);
         const F iW32 = F(1) / (W * M<F>::sqrt(W));
@@ -642,6 +399,7 @@ __device__ __forceinline__ float quad_cell(const float* __restrict__ s, int c, i
         // each slot's point: zbar = lam.Q, Qbar = lam (z - a.Q) - a (lam.Q); the
         // frame's adjoint rows of the two slots add up per lane
         T phia = T(0), phibb = T(0);
+        T hba[3] = {T(0), T(0), T(0)}, hbb[3] = {T(0), T(0), T(0)};   // neighbour normals: adjoints of h
         F arow[10];
 #pragma unroll
         for (int i = 0; i < 10; ++i) arow[i] = F(0);
@@ -664,13 +422,43 @@ __device__ __forceinline__ float quad_cell(const float* __restrict__ s, int c, i
             const T ybar = T(F(2) * y * Qbar[1] + x * Qbar[2] + Qbar[4]);
             const T zt = T(zq);
             const T ex = T(q_dx(q)), ey = T(q_dy(q)), ez = T(q_dz(q));
-            T cq[3];
-            const T dv = offset_grad_from_d0<T>(n0, n1, n2, T(p), D, cq);   // 1/A, centroid
-            (sl == 0 ? phia : phibb) = zt * dv;
-            arow[0] += F(xbar * ex); arow[1] += F(xbar * ey); arow[2] += F(xbar * ez);
-            arow[3] += F(ybar * ex); arow[4] += F(ybar * ey); arow[5] += F(ybar * ez);
-            arow[6] += F(zt * (ex + cq[0])); arow[7] += F(zt * (ey + cq[1])); arow[8] += F(zt * (ez + cq[2]));
-            arow[9] += F(zt);
+            if constexpr (NBR) {
+                // x = P.b_x, y = P.b_y, z = P.n with P = e + D m - D0 n, D = d0(phi_q, m)
+                const T(&mm)[3] = sl == 0 ? ma : mb;
+                const bool own = sl == 0 ? owna : ownb;
+                const T P0 = ex + D * mm[0] - D0 * n0, P1 = ey + D * mm[1] - D0 * n1, P2 = ez + D * mm[2] - D0 * n2;
+                const T Pb0 = xbar * bx0 + ybar * by0 + zt * n0;
+                const T Pb1 = xbar * bx1 + ybar * by1 + zt * n1;
+                const T Pb2 = xbar * bx2 + ybar * by2 + zt * n2;
+                T cq[3];
+                const T dv = offset_grad_from_d0<T>(mm[0], mm[1], mm[2], T(p), D, cq);   // 1/A, centroid for m
+                const T Dbar = Pb0 * mm[0] + Pb1 * mm[1] + Pb2 * mm[2];
+                const T mb0 = D * Pb0 + Dbar * cq[0], mb1 = D * Pb1 + Dbar * cq[1], mb2 = D * Pb2 + Dbar * cq[2];
+                (sl == 0 ? phia : phibb) = Dbar * dv;
+                arow[0] += F(xbar * P0); arow[1] += F(xbar * P1); arow[2] += F(xbar * P2);
+                arow[3] += F(ybar * P0); arow[4] += F(ybar * P1); arow[5] += F(ybar * P2);
+                // n enters through z = P.n, through -D0 n in P, and as m where the slot keeps it
+                arow[6] += F(zt * P0 - D0 * Pb0 + (own ? T(0) : mb0));
+                arow[7] += F(zt * P1 - D0 * Pb1 + (own ? T(0) : mb1));
+                arow[8] += F(zt * P2 - D0 * Pb2 + (own ? T(0) : mb2));
+                arow[9] += F(zt);
+                if (own) {                                   // m = -h / |h|: the adjoint of h
+                    const T ih = sl == 0 ? iha : ihb;
+                    const T md = mm[0] * mb0 + mm[1] * mb1 + mm[2] * mb2;
+                    T(&hb)[3] = sl == 0 ? hba : hbb;
+                    hb[0] = -(mb0 - mm[0] * md) * ih;
+                    hb[1] = -(mb1 - mm[1] * md) * ih;
+                    hb[2] = -(mb2 - mm[2] * md) * ih;
+                }
+            } else {
+                T cq[3];
+                const T dv = offset_grad_from_d0<T>(n0, n1, n2, T(p), D, cq);   // 1/A, centroid
+                (sl == 0 ? phia : phibb) = zt * dv;
+                arow[0] += F(xbar * ex); arow[1] += F(xbar * ey); arow[2] += F(xbar * ez);
+                arow[3] += F(ybar * ex); arow[4] += F(ybar * ey); arow[5] += F(ybar * ez);
+                arow[6] += F(zt * (ex + cq[0])); arow[7] += F(zt * (ey + cq[1])); arow[8] += F(zt * (ez + cq[2]));
+                arow[9] += F(zt);
+            }
         }
         T dvc = T(0);
         if (centre) {
@@ -712,6 +500,14 @@ __device__ __forceinline__ float quad_cell(const float* __restrict__ s, int c, i
             out[qb] = float(phibb + T(nrm_weight<NRM>(e2)) * (ex * gb0 + ey * gb1 + ez * gb2));
         }
         if (centre) out[13] = float(-sz_ * dvc);
+        if constexpr (NBR) {
+            // the adjoints of the slots' own fill-level gradients, gathered later at
+            // those neighbours and spread over their 3^3 by the gradient's weights
+            out[27 + 3 * j] = float(hba[0]); out[28 + 3 * j] = float(hba[1]); out[29 + 3 * j] = float(hba[2]);
+            if (nbb) {
+                out[27 + 3 * sb] = float(hbb[0]); out[28 + 3 * sb] = float(hbb[1]); out[29 + 3 * sb] = float(hbb[2]);
+            }
+        }
         __syncwarp();                              // res is reused by the next cell
     }
     return kappa;
@@ -1053,16 +849,14 @@ __global__ __launch_bounds__(kThreads) void k_curv_prefix(Workspace ws, int ntil
 }
 
 // ---------------------------------------------------------------------------
-// 2. work items: up to kPartCells interface cells of a tile.  A cell runs on a
-// group of 16 lanes (k_curv_quads, above), except in the neighbour-normal
-// adjoint, which runs a cell on a group of 32 lanes (k_curv_items); the
-// neighbour-normal variant stages each cell's 5x5x5 neighbourhood (each
-// neighbour's own 3x3x3).  The group finds its cell, the i-th interface cell of the
-// tile in cell order, from the tile's bitmask and prefix counts (two
-// ballots), stages the cell's fill levels in LDS, and runs the cell.  Groups
-// never wait for each other: no block barrier.  Forward: kappa.  Backward:
-// the cell's contributions gk * d kappa / d phi_q into its contribution row
-// (when it fits).
+// 2. work items: up to kPartCells interface cells of a tile, each cell on a
+// group of 16 lanes (k_curv_quads; the neighbour-normal variant stages each
+// cell's 5x5x5 neighbourhood, for each neighbour's own 3x3x3).  The group
+// finds its cell, the i-th interface cell of the tile in cell order, from the
+// tile's bitmask and prefix counts (two ballots), stages the cell's fill
+// levels in LDS, and runs the cell.  Groups never wait for each other: no
+// block barrier.  Forward: kappa.  Backward: the cell's contributions
+// gk * d kappa / d phi_q into its contribution row (when it fits).
 // ---------------------------------------------------------------------------
 
 // Lattice position of the interface cell of rank i (in cell order) of a
@@ -1097,67 +891,6 @@ __device__ __forceinline__ int thread_index_per_iteration() {
     return t;
 }
 
-// Waves per SIMD the 32-lane work items (the neighbour-normal adjoint) are
-// compiled for: the work is a chain of dependent steps per cell, so
-// concurrency sets the time.  Each count is the largest that compiles without
-// spilling (VGPRs at most 64 for 8 waves, 80 for 6, 128 for 4, 168 for 3):
-// 4 in FP32, 3 in mixed precision (its PLIC points are FP32 with the FP64
-// island only near case boundaries) and 2 in FP64.
-template <class T, class U, bool ADJ>
-constexpr int items_waves() {
-    if (sizeof(U) == 4) return 4;                                         // FP32
-    return sizeof(T) == 4 ? 3 : 2;                                        // mixed, FP64
-}
-
-template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
-__global__ __launch_bounds__(kThreads, (items_waves<T, U, ADJ>())) void k_curv_items(const float* __restrict__ phi,
-                                                          const float* __restrict__ gkap,
-                                                          float* __restrict__ kappa, Workspace ws, int X, int Y,
-                                                          int Z, int ntx, int nty) {
-    static_assert(ADJ && NBR, "the forward, and the adjoint without neighbour normals, run on 16 lanes (k_curv_quads)");
-    constexpr int H = 2, W = 2 * H + 1, NB = W * W * W, C = (H * W + H) * W + H;   // the 5x5x5 fill levels
-    constexpr int COLS = 20;
-    __shared__ float nbh[kGroups][NB];
-    __shared__ GroupLds<F, COLS> glds[kGroups];
-    const unsigned nitems = *static_cast<volatile unsigned*>(ws.counter);
-    for (unsigned item = blockIdx.x; item < nitems; item += gridDim.x) {
-        const int tid = thread_index_per_iteration(), grp = tid / kGroup, j = tid % kGroup;
-        const int half = tid & 32;                           // this group's lanes in the wave
-        const unsigned e = ws.items[item];
-        const int tile = static_cast<int>(e >> 7), part = static_cast<int>(e & 127u);
-        const int i = part * kPartCells + grp;               // rank of this group's cell
-        const unsigned row = ws.cbase[tile] + static_cast<unsigned>(i);
-        if (row >= ws.rows) continue;                        // uniform per group; the gather then writes NaN on the band
-        // tile_cell written out (through the call the mixed-precision adjoint
-        // spills): lane j holds mask word j and the count of set bits before it
-        const unsigned mw = ws.mask[tile * kWords + j], pw = ws.prefix[tile * kWords + j];
-        const int n = static_cast<int>(__shfl(pw + __popc(mw), kWords - 1, kGroup));
-        if (i >= n) continue;                                // uniform per group
-        const unsigned ui = static_cast<unsigned>(i);
-        const unsigned in_word = static_cast<unsigned>(__ballot(pw <= ui && ui < pw + __popc(mw)) >> half);
-        const int w = __ffs(static_cast<int>(in_word)) - 1;
-        const unsigned word = __shfl(mw, w, kGroup);
-        const unsigned k = ui - __shfl(pw, w, kGroup);
-        const bool hit = ((word >> j) & 1u) && static_cast<unsigned>(__popc(word & ((1u << j) - 1u))) == k;
-        const int b = __ffs(static_cast<int>(static_cast<unsigned>(__ballot(hit) >> half))) - 1;
-        const int cl = w * 32 + b;
-        const int x0 = (tile % ntx) * TX, y0 = ((tile / ntx) % nty) * TY, z0 = (tile / (ntx * nty)) * TZ;
-        const int gx = x0 + cl % TX, gy = y0 + (cl / TX) % TY, gz = z0 + cl / (TX * TY);
-        // the neighbourhood's fill levels (outside the lattice: 0)
-        for (int t = j; t < NB; t += kGroup) {
-            const int ax = gx + t % W - H, ay = gy + (t / W) % W - H, az = gz + t / (W * W) - H;
-            nbh[grp][t] = (ax >= 0 && ax < X && ay >= 0 && ay < Y && az >= 0 && az < Z)
-                              ? phi[(static_cast<int64_t>(az) * Y + ay) * X + ax] : 0.0f;
-        }
-        __syncwarp();
-        const int64_t g = (static_cast<int64_t>(gz) * Y + gy) * X + gx;
-        group_cell<SOLVER, T, U, F, true, NRM, COLS>(nbh[grp], C, W, W * W, j, gkap[g],
-                                                     ws.contrib + static_cast<size_t>(row) * kRowFloatsNbr, glds[grp],
-                                                     gx, gy, gz, X, Y, Z);
-        __syncwarp();                                        // nbh and glds reused by the next cell
-    }
-}
-
 // The curvature without neighbour normals on groups of 16 lanes: a workgroup
 // takes two work items at a time (its first two waves the first, the last two
 // the second), each 32-lane half of a wave finds its two cells from the tile's
@@ -1166,13 +899,14 @@ __global__ __launch_bounds__(kThreads, (items_waves<T, U, ADJ>())) void k_curv_i
 // contribution row when it fits the workspace.
 // waves per SIMD, the most that compile without spilling: the forward 8
 // (FP64: 4); the adjoint, which keeps two points' state per lane, 4 in FP32
-// and mixed precision, in FP64 3 for the iterative solvers and 2 for the
-// trigonometric ones
+// and mixed precision (3 with neighbour normals), in FP64 3 for the iterative
+// solvers and 2 for the trigonometric ones and with neighbour normals
 template <int SOLVER, class T, class U, bool ADJ, bool NBR>
 constexpr int quad_waves() {
     if (!ADJ) return sizeof(T) == 4 ? 8 : 4;
-    if (sizeof(T) == 4) return 4;
-    return (SOLVER == kNewton || SOLVER == kNested) ? 3 : 2;
+    if (sizeof(U) == 4) return 4;                            // FP32
+    if (sizeof(T) == 4) return NBR ? 3 : 4;                  // mixed
+    return (!NBR && (SOLVER == kNewton || SOLVER == kNested)) ? 3 : 2;   // FP64
 }
 
 template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
@@ -1229,8 +963,10 @@ __global__ __launch_bounds__(kThreads, (quad_waves<SOLVER, T, U, ADJ, NBR>())) v
         __syncwarp();
         const int64_t gi = (static_cast<int64_t>(gz) * Y + gy) * X + gx;
         if constexpr (ADJ) {
-            quad_cell<SOLVER, T, U, F, true, NRM, COLS>(nbh[grp], C, W, W * W, j, lane, gkap[gi],
-                                                        ws.contrib + static_cast<size_t>(row) * 27, qlds[grp]);
+            constexpr int ROWF = NBR ? kRowFloatsNbr : 27;
+            quad_cell<SOLVER, T, U, F, true, NRM, COLS, NBR>(nbh[grp], C, W, W * W, j, lane, gkap[gi],
+                                                             ws.contrib + static_cast<size_t>(row) * ROWF, qlds[grp],
+                                                             gx, gy, gz, X, Y, Z);
         } else {
             const float kv = quad_cell<SOLVER, T, U, F, false, NRM, COLS, NBR>(nbh[grp], C, W, W * W, j, lane, 0.0f,
                                                                                nullptr, qlds[grp], gx, gy, gz, X, Y,
@@ -1796,14 +1532,6 @@ void launch_rows(Workspace ws, const Grid& g, hipStream_t st) {
     }
 }
 
-template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR>
-void launch_items(const float* phi, const float* gk, float* kappa, Workspace ws, int X, int Y, int Z,
-                  const Grid& g, hipStream_t st) {
-    const dim3 grid(persistent_grid(static_cast<int64_t>(g.ntiles) * kMaxParts)), block(kThreads);
-    hipLaunchKernelGGL((k_curv_items<SOLVER, T, U, F, ADJ, NRM, NBR>), grid, block, 0, st, phi, gk, kappa, ws, X, Y, Z,
-                       g.ntx, g.nty);
-}
-
 template <int SOLVER, class T, class U, class F, bool ADJ, int NRM, bool NBR = false>
 void launch_quads(const float* phi, const float* gk, float* kappa, Workspace ws, int X, int Y, int Z, const Grid& g,
                   hipStream_t st) {
@@ -1871,7 +1599,7 @@ template <int SOLVER, class T, class U, class F, int NRM>
 void launch_bwd_nbr_t(const float* phi, const float* gk, float* gp, Workspace ws, int X, int Y, int Z,
                       const Grid& g, bool zfill, hipStream_t st) {
     launch_rows(ws, g, st);
-    launch_items<SOLVER, T, U, F, true, NRM, true>(phi, gk, nullptr, ws, X, Y, Z, g, st);
+    launch_quads<SOLVER, T, U, F, true, NRM, true>(phi, gk, nullptr, ws, X, Y, Z, g, st);
     hipLaunchKernelGGL(k_curv_hgather, dim3(persistent_grid(static_cast<int64_t>(g.ntiles) * kMaxParts)),
                        dim3(kThreads), 0, st, ws, X, Y, Z, g.ntx, g.nty);
     launch_gather<true, NRM>(gp, ws, X, Y, Z, g, zfill, st);
